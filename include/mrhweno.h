@@ -1,0 +1,173 @@
+/*
+ * mrhweno.h -- C ABI of the MI355X (gfx950) moment-based multi-resolution
+ * HWENO library.
+ *
+ * The library advances the zeroth and first moments of hyperbolic
+ * conservation laws u_t + div f(u) = 0 on uniform 1D and 2D meshes with the
+ * moment-based multi-resolution HWENO scheme of Li, Shu and Qiu (arXiv
+ * 2201.12193):
+ *   - the state of each cell is its cell average and its first moments,
+ *     eq. (1D-moment) / (2D-moment), in the cell's reference coordinates;
+ *   - the semi-discrete scheme is eq. (1D-equ-int-approximation) /
+ *     (2D-equ-int-approximation) with the four-point Gauss-Lobatto
+ *     quadratures of eqs. (F), (integral1)-(integral3);
+ *   - point values come from the reconstruction algorithm (Step 1: nested
+ *     stencils q1..q4, smoothness indicators, WENO-Z nonlinear weights;
+ *     Step 2: KXRCF troubled-cell indicator, modification of the first
+ *     moments by the quartic of eq. (p0)/(vi), re-reconstruction);
+ *   - fluxes are HLLC for the Euler equations (eqs. f_HLLC, COEF, uLR_) and
+ *     Lax-Friedrichs for scalar Burgers;
+ *   - time stepping is the third-order TVD Runge-Kutta method (eq.
+ *     Runge-Kutta) at a CFL number (0.6 in the paper).
+ *
+ * Memory: every pointer documented as "device" is device memory owned by the
+ * caller; the library never allocates device memory and never copies between
+ * host and device inside a step.  Host pointers are read during the call
+ * only.  All entry points are asynchronous on the stream given at creation
+ * except mrhweno_sync, mrhweno_last_dt and mrhweno_create.
+ *
+ * Moment layout (FP64, structure of arrays, x fastest):
+ *   1D: U[comp][m][nx],       m = 0 (cell average), 1 (first moment)
+ *   2D: U[comp][m][ny][nx],   m = 0 (cell average), 1 (x moment), 2 (y moment)
+ * Components: Burgers (u); 1D Euler (rho, rho*mu, E); 2D Euler
+ * (rho, rho*mu, rho*nu, E).
+ *
+ * Errors: a negative status is returned for invalid arguments or a failing
+ * device call; mrhweno_last_error describes the most recent one.  A
+ * non-physical state met on the device (rho <= 0, p <= 0 or non-finite
+ * values in a cell average) is latched per instance: later steps of that
+ * instance do nothing, the state is rolled back to the last good step, and
+ * the next mrhweno_sync returns MRHWENO_ERR_NONPHYSICAL.
+ */
+#ifndef MRHWENO_H
+#define MRHWENO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mrhweno_ctx mrhweno_ctx;
+
+typedef enum {
+  MRHWENO_OK = 0,
+  MRHWENO_ERR_INVALID_ARG = -1,
+  MRHWENO_ERR_UNSUPPORTED = -2,
+  MRHWENO_ERR_DEVICE = -3,
+  MRHWENO_ERR_NONPHYSICAL = -4
+} mrhweno_status;
+
+typedef enum { MRHWENO_BURGERS_LF = 0, MRHWENO_EULER_HLLC = 1 } mrhweno_flux;
+typedef enum { MRHWENO_BC_PERIODIC = 0, MRHWENO_BC_TRANSMISSIVE = 1 } mrhweno_bc;
+/* Step 2 variants named as in the paper's Sec. 3: HWENO6 (no
+ * modification), HWENO6-M5-I (KXRCF-flagged cells), HWENO6-M5-NI (every
+ * cell); LEARNED uses the learned indicator with a KXRCF fallback band. */
+typedef enum {
+  MRHWENO_TC_NONE = 0,
+  MRHWENO_TC_KXRCF = 1,
+  MRHWENO_TC_ALL = 2,
+  MRHWENO_TC_LEARNED = 3
+} mrhweno_tc;
+/* Smoothness indicators of eq. (beta)/(2D-beta) taken on q_l (default; the
+ * reading under which Remark 1's expansion holds) or on p_l as printed. */
+typedef enum { MRHWENO_BETA_ON_Q = 0, MRHWENO_BETA_ON_P = 1 } mrhweno_beta;
+
+/* A problem posed as the paper poses it (Secs. 2.1, 2.2, 3). */
+typedef struct {
+  int dim;                 /* 1 or 2                                              */
+  int nx, ny;              /* cells (ny ignored in 1D); each >= 8                 */
+  double x0, x1, y0, y1;   /* domain; 2D requires square cells (dx == dy)        */
+  int bc_x, bc_y;          /* mrhweno_bc                                         */
+  int flux;                /* mrhweno_flux; ncomp = 1 (Burgers), 3 (1D Euler),
+                              4 (2D Euler)                                        */
+  double gamma_gas;        /* ratio of specific heats (Euler)                    */
+  double cfl;              /* CFL number, > 0                                     */
+  double t_final;          /* final time (may be +inf for a fixed step count)    */
+  double gamma_bar[4];     /* positive linear weights (paper: 1, 10, 100, 1000)  */
+  double eps;              /* epsilon of the nonlinear weights (paper: 1e-10)    */
+  int tc_mode;             /* mrhweno_tc                                         */
+  int beta_on;             /* mrhweno_beta                                       */
+} mrhweno_problem;
+
+/* Device workspace needed for n instances (bytes, 256-byte aligned pieces).
+ * Returns 0 if a problem is invalid. */
+size_t mrhweno_workspace_bytes(const mrhweno_problem* probs, int n_instances);
+
+/* Create a context for n instances that are advanced together.
+ *   probs        host array of n problems;
+ *   moments_dev  host array of n device pointers, one FP64 moment array per
+ *                instance (layout above); in/out: the current state is
+ *                returned there by mrhweno_sync;
+ *   workspace    device buffer of mrhweno_workspace_bytes(probs, n) bytes;
+ *   hip_stream   hipStream_t the library launches on (NULL = default);
+ *   out          receives the context (host object owned by the library).
+ * The initial time of every instance is 0. */
+mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n_instances,
+                              void* const* moments_dev, void* workspace_dev,
+                              void* hip_stream, mrhweno_ctx** out);
+
+/* Enqueue nsteps SSP-RK3 steps of every instance (asynchronous).  Each step
+ * takes dt from the CFL condition on U^n, clipped at t_final; an instance at
+ * t_final (or with a latched error) does not change. */
+mrhweno_status mrhweno_step(mrhweno_ctx* ctx, int nsteps);
+
+/* Wait for the stream, bring every instance's current state back into its
+ * moments_dev array, and report per-instance time (t_out, n doubles) and
+ * step count (steps_out, n longs); either may be NULL.  Returns
+ * MRHWENO_ERR_NONPHYSICAL if any instance latched a non-physical state. */
+mrhweno_status mrhweno_sync(mrhweno_ctx* ctx, double* t_out, long* steps_out);
+
+/* Set time and step counter of one instance (resume from a checkpoint). */
+mrhweno_status mrhweno_set_time(mrhweno_ctx* ctx, int instance, double t, long steps);
+
+/* dt of the most recent step of every instance (synchronises; n doubles). */
+mrhweno_status mrhweno_last_dt(mrhweno_ctx* ctx, double* dt_out);
+
+/* Steps 1-2 of the reconstruction algorithm once on a given state of
+ * instance `instance`:
+ *   moments_dev  device, the state (layout above), read only;
+ *   gl_dev       device, final Gauss-Lobatto values after Step 2:
+ *                1D [comp][4][nx], 2D [comp][16][ny][nx] with point
+ *                k + 4 l at (xi_k, eta_l), xi, eta in
+ *                {-1/2, -sqrt(5)/10, sqrt(5)/10, 1/2};
+ *   flags_dev    device uint8 [ny][nx] troubled-cell map, or NULL. */
+mrhweno_status mrhweno_reconstruct(mrhweno_ctx* ctx, int instance, const void* moments_dev,
+                                   void* gl_dev, void* flags_dev);
+
+/* Step 2.1 (troubled-cell indicator) once on a given state:
+ *   flags_dev  device uint8 [ny][nx];
+ *   aleph_dev  device FP64 [ny][nx][2]: numerator |J| and denominator
+ *              h^2 |dI^-| ||u|| of the KXRCF ratio (1D: h^2 ||u||), or NULL. */
+mrhweno_status mrhweno_flag(mrhweno_ctx* ctx, int instance, const void* moments_dev,
+                            void* flags_dev, void* aleph_dev);
+
+/* The semi-discrete operator L(U) once on a given state (same layout as the
+ * state), with the troubled-cell map of that evaluation in flags_dev (or
+ * NULL). */
+mrhweno_status mrhweno_residual(mrhweno_ctx* ctx, int instance, const void* moments_dev,
+                                void* residual_dev, void* flags_dev);
+
+/* Rows per work item of the 2D stage kernel and grid size (0 = one work
+ * group per work item) -- the launch shape the autotuner chooses. */
+mrhweno_status mrhweno_set_launch(mrhweno_ctx* ctx, int rows_2d, int grid_2d);
+
+/* Run nsteps steps launched one kernel at a time (no graph) with HIP events
+ * recorded on the context's stream between kernel classes, then
+ * synchronise.  ms_out (host, 4 floats) receives the summed device time of
+ * [0] wave-speed reductions and dt, [1] KXRCF face summaries, [2] flags,
+ * [3] stage kernels (reconstruction, fluxes, residual, RK combination);
+ * launches_out (host, 4 ints, or NULL) the number of launches of each.
+ * The state advances exactly as with mrhweno_step. */
+mrhweno_status mrhweno_profile(mrhweno_ctx* ctx, int nsteps, float* ms_out, int* launches_out);
+
+/* Most recent error message (thread-local when ctx is NULL). */
+const char* mrhweno_last_error(const mrhweno_ctx* ctx);
+
+/* Release the context (does not free caller memory). */
+void mrhweno_destroy(mrhweno_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRHWENO_H */

@@ -1,0 +1,262 @@
+"""CPU oracle of the moment-based multi-resolution HWENO scheme.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package; the GPU library
+never does.  The arithmetic lives in ``mrhweno_oracle.c`` (plain C, FP64,
+no FMA contraction); this module only marshals numpy arrays through ctypes.
+
+Parity status of each function is listed in ``ORACLE_PINS`` below; every
+function there is pinned by a ``-m "not gpu"`` test against what the paper
+or the mathematics fixes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mrhweno_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ORACLE_PINS = {
+    "step1_1d": "exactness of q2/q3/q4 on polynomial data; closed forms; eq. (pq); Remark 1; Table 1/3 orders",
+    "step1_2d": "exactness of the least-squares q2/q3/q4 on P2/P3/P5 data; eq. (2D-pq); D4 symmetry; Table 2/4 orders",
+    "modification": "eq. (vi) printed coefficients",
+    "kxrcf": "smooth/discontinuous scaling (Remark 2); inflow side of a moving step; Lax problem flags",
+    "hllc": "consistency, supersonic branches, stationary contact",
+    "residual": "conservation; free-stream preservation; convergence orders; Lax problem vs exact Riemann solution",
+    "rk3": "third-order temporal convergence",
+}
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, -ffp-contract=off, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Prob(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("system", C.c_int),
+                ("bc_x", C.c_int), ("bc_y", C.c_int), ("tc_mode", C.c_int), ("beta_on", C.c_int),
+                ("dx", C.c_double), ("dy", C.c_double), ("gamma", C.c_double),
+                ("gbar", C.c_double * 4), ("eps", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB)
+        D = C.POINTER(C.c_double)
+        B = C.POINTER(C.c_ubyte)
+        P = C.POINTER(_Prob)
+        L.orc_step1_1d.argtypes = [P, D, D, D, D, D]
+        L.orc_step1_2d.argtypes = [P, D, D, D, D, D, D]
+        L.orc_qmap_1d.argtypes = [C.c_int, D]
+        L.orc_modmap_1d.argtypes = [D]
+        L.orc_qmap_2d.argtypes = [C.c_int, D]
+        L.orc_qcoef_2d.argtypes = [C.c_int, D, D, D, D]
+        L.orc_monomials_2d.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_hllc.argtypes = [D, D, C.c_int, C.c_int, C.c_double, D]
+        L.orc_residual.argtypes = [P, D, D, B]
+        L.orc_reconstruct.argtypes = [P, D, D, B, D, D]
+        L.orc_wave_speeds.argtypes = [P, D, D]
+        L.orc_dt.argtypes = [P, D, C.c_double]
+        L.orc_dt.restype = C.c_double
+        L.orc_rk3_step.argtypes = [P, D, C.c_double, B]
+        L.orc_rk3_step_p.argtypes = [P, D, C.c_double, B, C.c_int]
+        L.orc_modify.argtypes = [P, D, B, D]
+        L.orc_residual_cell_2d.argtypes = [P, D, C.c_double, C.c_int, C.c_int, D]
+        L.orc_gl.argtypes = [D, D]
+        L.orc_max_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _bp(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.uint8 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_ubyte))
+
+
+def cprob(prob) -> _Prob:
+    p = _Prob()
+    p.dim, p.nx, p.ny = prob.dim, prob.nx, (prob.ny if prob.dim == 2 else 1)
+    p.system, p.bc_x, p.bc_y = prob.system, prob.bc_x, prob.bc_y
+    p.tc_mode = 1 if prob.tc_mode == 3 else prob.tc_mode
+    p.beta_on = prob.beta_on
+    p.dx, p.dy, p.gamma, p.eps = prob.dx, prob.dy, prob.gamma, prob.eps
+    for k in range(4):
+        p.gbar[k] = prob.gbar[k]
+    return p
+
+
+def _arr(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+# ---------------------------------------------------------------- per stencil
+def step1_1d(prob, ub, vb) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Step 1 (1D) for one component: returns (gl[4], weights[4], betas[4])."""
+    ub, vb = _arr(ub), _arr(vb)
+    gl, w, b = np.zeros(4), np.zeros(4), np.zeros(4)
+    lib().orc_step1_1d(C.byref(cprob(prob)), _dp(ub), _dp(vb), _dp(gl), _dp(w), _dp(b))
+    return gl, w, b
+
+
+def step1_2d(prob, ub, vb, wb) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Step 1 (2D) for one component; ub/vb/wb indexed by stencil label-1.
+    Returns (gl[16] with gl[k + 4 l] at (xi_k, eta_l), weights[4], betas[4])."""
+    ub, vb, wb = _arr(ub), _arr(vb), _arr(wb)
+    gl, w, b = np.zeros(16), np.zeros(4), np.zeros(4)
+    lib().orc_step1_2d(C.byref(cprob(prob)), _dp(ub), _dp(vb), _dp(wb), _dp(gl), _dp(w), _dp(b))
+    return gl, w, b
+
+
+def qmap_1d(level: int) -> np.ndarray:
+    deg = {2: 2, 3: 3, 4: 5}[level]
+    out = np.zeros((deg + 1, 6))
+    lib().orc_qmap_1d(level, _dp(out))
+    return out
+
+
+def modmap_1d() -> np.ndarray:
+    out = np.zeros(6)
+    lib().orc_modmap_1d(_dp(out))
+    return out
+
+
+def monomials_2d() -> Tuple[np.ndarray, np.ndarray]:
+    a = (C.c_int * 21)()
+    b = (C.c_int * 21)()
+    lib().orc_monomials_2d(a, b)
+    return np.array(a[:]), np.array(b[:])
+
+
+def qmap_2d(level: int) -> np.ndarray:
+    nco = {2: 6, 3: 10, 4: 21}[level]
+    out = np.zeros((nco, 27))
+    lib().orc_qmap_2d(level, _dp(out))
+    return out
+
+
+def qcoef_2d(level: int, ub, vb, wb) -> np.ndarray:
+    nco = {2: 6, 3: 10, 4: 21}[level]
+    out = np.zeros(nco)
+    lib().orc_qcoef_2d(level, _dp(_arr(ub)), _dp(_arr(vb)), _dp(_arr(wb)), _dp(out))
+    return out
+
+
+def hllc(uL, uR, gamma: float, direction: int = 0) -> np.ndarray:
+    uL, uR = _arr(uL), _arr(uR)
+    f = np.zeros(len(uL))
+    lib().orc_hllc(_dp(uL), _dp(uR), len(uL), direction, gamma, _dp(f))
+    return f
+
+
+# ---------------------------------------------------------------- whole grid
+def residual(prob, U) -> Tuple[np.ndarray, np.ndarray]:
+    """L(U) and the troubled-cell flags of the interior."""
+    U = _arr(U).reshape(prob.shape())
+    L = np.zeros_like(U)
+    flags = np.zeros(prob.ncell, dtype=np.uint8)
+    lib().orc_residual(C.byref(cprob(prob)), _dp(U), _dp(L), _bp(flags))
+    return L, flags.reshape(prob.shape()[2:])
+
+
+def reconstruct(prob, U):
+    """Final Gauss-Lobatto values (1D [comp][4][nx], 2D [comp][16][ny][nx]),
+    flags, and the KXRCF numerator and denominator."""
+    U = _arr(U).reshape(prob.shape())
+    npt = 4 if prob.dim == 1 else 16
+    gl = np.zeros((prob.ncomp, npt) + prob.shape()[2:])
+    flags = np.zeros(prob.ncell, dtype=np.uint8)
+    num = np.zeros(prob.ncell)
+    den = np.zeros(prob.ncell)
+    lib().orc_reconstruct(C.byref(cprob(prob)), _dp(U), _dp(gl), _bp(flags), _dp(num), _dp(den))
+    sh = prob.shape()[2:]
+    return gl, flags.reshape(sh), num.reshape(sh), den.reshape(sh)
+
+
+def wave_speeds(prob, U) -> Tuple[float, float]:
+    U = _arr(U).reshape(prob.shape())
+    out = np.zeros(2)
+    lib().orc_wave_speeds(C.byref(cprob(prob)), _dp(U), _dp(out))
+    return float(out[0]), float(out[1])
+
+
+def dt(prob, U, cfl: Optional[float] = None) -> float:
+    U = _arr(U).reshape(prob.shape())
+    return float(lib().orc_dt(C.byref(cprob(prob)), _dp(U), prob.cfl if cfl is None else cfl))
+
+
+def rk3_step(prob, U, dt_: float, want_flags: bool = False, persist: int = 1):
+    """One SSP-RK3 step; returns U^{n+1} (and the flags of the 3 stages)."""
+    U = _arr(U).reshape(prob.shape()).copy()
+    flags = np.zeros(3 * prob.ncell, dtype=np.uint8) if want_flags else None
+    lib().orc_rk3_step_p(C.byref(cprob(prob)), _dp(U), dt_, _bp(flags), persist)
+    if want_flags:
+        return U, flags.reshape((3,) + prob.shape()[2:])
+    return U
+
+
+def residual_cell_2d(prob, U, i: int, j: int, alpha: float = 0.0) -> np.ndarray:
+    """L(U) at one cell of a 2D grid, recomputed from scratch (for sampling)."""
+    out = np.zeros((prob.ncomp, 3))
+    lib().orc_residual_cell_2d(C.byref(cprob(prob)), _dp(U), alpha, i, j, _dp(out))
+    return out
+
+
+def modify(prob, U, flags) -> np.ndarray:
+    """Stage input with troubled cells' first moments replaced (Step 2.2)."""
+    U = _arr(U).reshape(prob.shape())
+    fl = np.ascontiguousarray(np.asarray(flags, dtype=np.uint8).ravel())
+    out = np.zeros_like(U)
+    lib().orc_modify(C.byref(cprob(prob)), _dp(U), _bp(fl), _dp(out))
+    return out
+
+
+def run(prob, U, t_final: Optional[float] = None, max_steps: int = 10 ** 9, dt_fn=None, persist: int = 1):
+    """March to t_final with the CFL time step (clipped at t_final)."""
+    T = prob.t_final if t_final is None else t_final
+    U = _arr(U).reshape(prob.shape()).copy()
+    t, steps = 0.0, 0
+    while t < T and steps < max_steps:
+        d = dt(prob, U) if dt_fn is None else dt_fn(prob, U)
+        d = min(d, T - t)
+        U = rk3_step(prob, U, d, persist=persist)
+        t += d
+        steps += 1
+    return U, t, steps
+
+
+def gl_rule():
+    x, w = np.zeros(4), np.zeros(4)
+    lib().orc_gl(_dp(x), _dp(w))
+    return x, w
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())

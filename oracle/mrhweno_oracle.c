@@ -1,0 +1,1289 @@
+/*
+ * mrhweno_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT PATH.
+ *
+ * A plain, slow, FP64 CPU implementation of the moment-based multi-resolution
+ * HWENO finite-volume scheme of Li, Shu & Qiu (arXiv:2201.12193), written
+ * from the paper so that the GPU library can be checked against it.  Only the
+ * test-suite, the smoke check and the CPU-baseline leg of the benchmark may
+ * load this library.  It shares no code, table or constant generator with the
+ * GPU path: every reconstruction map below is derived here numerically, at
+ * first use, from the moment conditions the paper states.
+ *
+ * Readings taken where the paper is silent or inconsistent (each is repeated
+ * at the place it is used):
+ *   R1  smoothness indicators beta_2..4 are taken on q_l (default) -- the
+ *       printed eq. (beta) names p_l, but Remark 1's expansion
+ *       beta_l = u'^2 dx^2 + O(dx^4) holds only for q_l; beta_on = 1 selects
+ *       the printed p_l reading.
+ *   R2  Euler systems are reconstructed component by component on the
+ *       conserved variables.
+ *   R3  the first-moment modification (Step 2.2) is Jacobi: modified moments
+ *       use the original neighbour moments; the modified moments are
+ *       internal to the spatial operator and never written back to U.
+ *   R4  a troubled cell has the first moments of all components modified.
+ *   R5  sf(z) = 1 if z > 0 else 0; the interface velocity is the mean of the
+ *       velocities of the two reconstructed face states (in 2D, the
+ *       Gauss-Lobatto-weighted average of that mean over the face).
+ *   R6  1D uses the printed boundary-point sum without 1/|dI^-|; 2D divides
+ *       by the inflow length |dI^-|; h = dx; the test is evaluated without
+ *       a division, |J| > h^2 |dI^-| ||u||, strictly (ties and no-inflow
+ *       cells are not troubled).
+ *   R7  2D tau_1 is the mean over the 6 unordered pairs.
+ *   R8  the 2D least-squares problems keep the centre cell average exact and
+ *       fit every other condition in the unweighted least-squares sense.
+ *   R9  the 2D smoothness indicator counts every multi-index once and uses
+ *       |I| = dx*dy with square cells, which makes it scale free.
+ *   R10 HLLC uses the printed PVRS estimates; 2D HLLC rotates the normal
+ *       velocity into the role of mu and carries the tangential momentum in
+ *       the star state; the four branches are tested in order.
+ *   R11 the scalar flux is global Lax-Friedrichs with alpha = max |f'(u)|
+ *       over the cell averages of the stage input.
+ *   R12 dt = cfl*dx/alpha (1D), cfl/(alpha_x/dx + alpha_y/dy) (2D), alpha
+ *       from the cell averages of U^n.
+ *   R13 transmissive ghosts: cell average copied from the nearest interior
+ *       cell, first moments zero; every step of the operator is applied to
+ *       ghost cells exactly as to interior cells.
+ *
+ * Coordinates: every polynomial lives in the target cell's reference
+ * coordinates xi = (x - x_i)/dx, eta = (y - y_j)/dy, so that cell (i+d) is
+ * [d - 1/2, d + 1/2] and the moments of eq. (1D-moment)/(2D-moment) are
+ * averages of u and of u*(xi - d) over it.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdint.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Problem description (the oracle's own struct; the product has its own)   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int dim;        /* 1 or 2                                                  */
+  int nx, ny;     /* cells; ny = 1 in 1D                                     */
+  int system;     /* 0 = scalar Burgers + Lax-Friedrichs, 1 = Euler + HLLC   */
+  int bc_x, bc_y; /* 0 = periodic, 1 = transmissive                          */
+  int tc_mode;    /* 0 = no modification (HWENO6), 1 = KXRCF (M5-I),
+                     2 = modify every cell (M5-NI)                           */
+  int beta_on;    /* 0 = beta on q_l (R1), 1 = beta on p_l as printed       */
+  double dx, dy;
+  double gamma;   /* ratio of specific heats (Euler)                         */
+  double gbar[4]; /* unnormalised linear weights, eq. (linear-weight)        */
+  double eps;     /* 1e-10 in eq. (w1_-LR) and eq. (non-linear-weight)       */
+} orc_problem;
+
+static int ncomp_of(const orc_problem* P) {
+  if (P->system == 0) return 1;
+  return P->dim == 1 ? 3 : 4;
+}
+
+/* Gauss-Lobatto nodes and weights on [-1/2, 1/2], eq. (F). */
+static double gl_node(int k) {
+  double s = sqrt(5.0) / 10.0;
+  static const int sg[4] = {-1, 0, 0, 1};
+  if (k == 0 || k == 3) return 0.5 * sg[k];
+  return k == 1 ? -s : s;
+}
+static double gl_weight(int k) { return (k == 0 || k == 3) ? 1.0 / 12.0 : 5.0 / 12.0; }
+
+/* ------------------------------------------------------------------------ */
+/* Small dense linear algebra: Gaussian elimination with partial pivoting in */
+/* long double, followed by iterative refinement, so that the maps derived  */
+/* below are accurate to the last bit of a double even though the KKT       */
+/* systems of the 2D least-squares problems are ill conditioned.            */
+/* Solves A X = B (A: n x n row-major, B: n x m row-major); X replaces B.   */
+/* ------------------------------------------------------------------------ */
+static int gauss_ld(int n, long double* A, int m, long double* B) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabsl(A[r * n + c]) > fabsl(A[piv * n + c])) piv = r;
+    if (A[piv * n + c] == 0.0L) return -1;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) { long double t = A[c * n + k]; A[c * n + k] = A[piv * n + k]; A[piv * n + k] = t; }
+      for (int k = 0; k < m; ++k) { long double t = B[c * m + k]; B[c * m + k] = B[piv * m + k]; B[piv * m + k] = t; }
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      long double f = A[r * n + c] / A[c * n + c];
+      if (f == 0.0L) continue;
+      for (int k = 0; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+      for (int k = 0; k < m; ++k) B[r * m + k] -= f * B[c * m + k];
+    }
+  }
+  for (int c = 0; c < n; ++c)
+    for (int k = 0; k < m; ++k) B[c * m + k] /= A[c * n + c];
+  return 0;
+}
+
+static int gauss_solve(int n, double* A, int m, double* B) {
+  long double* A0 = malloc(sizeof(long double) * n * n);
+  long double* W = malloc(sizeof(long double) * n * n);
+  long double* X = malloc(sizeof(long double) * n * m);
+  long double* R = malloc(sizeof(long double) * n * m);
+  for (int k = 0; k < n * n; ++k) A0[k] = W[k] = A[k];
+  for (int k = 0; k < n * m; ++k) X[k] = B[k];
+  int st = gauss_ld(n, W, m, X);
+  for (int it = 0; it < 3 && st == 0; ++it) {
+    /* residual R = B - A X, correction A D = R */
+    for (int r = 0; r < n; ++r)
+      for (int k = 0; k < m; ++k) {
+        long double acc = B[r * m + k];
+        for (int c = 0; c < n; ++c) acc -= A0[r * n + c] * X[c * m + k];
+        R[r * m + k] = acc;
+      }
+    for (int k = 0; k < n * n; ++k) W[k] = A0[k];
+    st = gauss_ld(n, W, m, R);
+    for (int k = 0; k < n * m; ++k) X[k] += R[k];
+  }
+  for (int k = 0; k < n * m; ++k) B[k] = (double)X[k];
+  free(A0); free(W); free(X); free(R);
+  return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Moments of monomials over the cell at offset d (reference coordinates).  */
+/* ------------------------------------------------------------------------ */
+static double ipow(double x, int n) { double r = 1.0; for (int k = 0; k < n; ++k) r *= x; return r; }
+/* average of s^n over [d-1/2, d+1/2] */
+static double mono_avg_direct(int n, int d) {
+  double a = d - 0.5, b = d + 0.5;
+  return (ipow(b, n + 1) - ipow(a, n + 1)) / (n + 1);
+}
+/* the same values tabulated once (n <= 11, d in -1..1) */
+static double g_avg_tab[12][3];
+static int g_avg_init = 0;
+static double mono_avg(int n, int d) {
+  if (n > 11 || d < -1 || d > 1) return mono_avg_direct(n, d);
+  if (!g_avg_init) {
+    for (int k = 0; k < 12; ++k)
+      for (int e = -1; e <= 1; ++e) g_avg_tab[k][e + 1] = mono_avg_direct(k, e);
+    g_avg_init = 1;
+  }
+  return g_avg_tab[n][d + 1];
+}
+/* first moments, average of s^n (s - d) over [d-1/2, d+1/2], and the
+   integrals above in long double, for building the least-squares systems
+   (their conditioning magnifies the rounding of the matrix entries) */
+static long double mono_avg_ld(int n, int d) {
+  long double a = d - 0.5L, b = d + 0.5L, pa = 1.0L, pb = 1.0L;
+  for (int k = 0; k <= n; ++k) { pa *= a; pb *= b; }
+  return (pb - pa) / (n + 1);
+}
+static long double mono_mom_ld(int n, int d) { return mono_avg_ld(n + 1, d) - d * mono_avg_ld(n, d); }
+
+/* ======================================================================== */
+/* 1D reconstruction maps, eq. (q): q_l as linear maps of the stencil data. */
+/* Data vector layout: (ubar_{i-1}, ubar_i, ubar_{i+1}, vbar_{i-1},         */
+/* vbar_i, vbar_{i+1}); map[l] is (deg_l+1) x 6, coefficients of xi^n.      */
+/* ======================================================================== */
+static int g_init1 = 0;
+static double M1q[5][6][6];   /* M1q[l][n][data] for l = 2, 3, 4 (degree 2, 3, 5) */
+static double M1mod[6];      /* Step 2.2 modified first moment, eq. (p0)/(vi)      */
+
+static void init_1d(void) {
+  if (g_init1) return;
+  (void)mono_avg(0, 0);
+  memset(M1q, 0, sizeof M1q);
+  /* conditions: (type, offset); type 0 = average, 1 = first moment */
+  const int deg[5] = {0, 0, 2, 3, 5};
+  const int nc[5] = {0, 1, 3, 4, 6};
+  const int ctype[5][6] = {{0}, {0}, {0, 0, 0}, {0, 0, 0, 1}, {0, 0, 0, 1, 1, 1}};
+  const int coff[5][6] = {{0}, {0}, {-1, 0, 1}, {-1, 0, 1, 0}, {-1, 0, 1, -1, 0, 1}};
+  /* data index of each condition in the 6-vector */
+  const int cdat[5][6] = {{0}, {0}, {0, 1, 2}, {0, 1, 2, 4}, {0, 1, 2, 3, 4, 5}};
+  for (int l = 2; l <= 4; ++l) {
+    int n = deg[l] + 1;               /* unknowns = conditions (square) */
+    long double A[36], B[36];
+    for (int r = 0; r < nc[l]; ++r) {
+      for (int p = 0; p < n; ++p)
+        A[r * n + p] = ctype[l][r] == 0 ? mono_avg_ld(p, coff[l][r]) : mono_mom_ld(p, coff[l][r]);
+      for (int c = 0; c < nc[l]; ++c) B[r * nc[l] + c] = (r == c) ? 1.0L : 0.0L;
+    }
+    gauss_ld(n, A, nc[l], B);
+    for (int p = 0; p < n; ++p)
+      for (int c = 0; c < nc[l]; ++c) M1q[l][p][cdat[l][c]] = (double)B[p * nc[l] + c];
+  }
+  /* Step 2.2, eq. (p0): quartic with averages on i-1, i, i+1 and first
+     moments on i-1, i+1; the modified vbar_i is its first moment on I_i. */
+  {
+    long double A[25], B[25];
+    const int ct[5] = {0, 0, 0, 1, 1}, co[5] = {-1, 0, 1, -1, 1};
+    for (int r = 0; r < 5; ++r) {
+      for (int p = 0; p < 5; ++p) A[r * 5 + p] = ct[r] == 0 ? mono_avg_ld(p, co[r]) : mono_mom_ld(p, co[r]);
+      for (int c = 0; c < 5; ++c) B[r * 5 + c] = (r == c) ? 1.0L : 0.0L;
+    }
+    gauss_ld(5, A, 5, B);
+    /* data order (u_{i-1}, u_i, u_{i+1}, v_{i-1}, v_{i+1}) -> 6-vector order */
+    const int dmap[5] = {0, 1, 2, 3, 5};
+    memset(M1mod, 0, sizeof M1mod);
+    for (int c = 0; c < 5; ++c) {
+      long double s = 0.0L;
+      for (int p = 0; p < 5; ++p) s += B[p * 5 + c] * mono_mom_ld(p, 0);
+      M1mod[dmap[c]] = (double)s;
+    }
+  }
+  g_init1 = 1;
+}
+
+/* value of a 1D polynomial (coefficients of xi^n, n < np) */
+static double peval1(const double* a, int np, double x) {
+  double s = 0.0;
+  for (int n = np - 1; n >= 0; --n) s = s * x + a[n];
+  return s;
+}
+
+/* beta of eq. (beta) in reference coordinates: the factor dx^{2a-1} and the
+   chain rule d/dx = (1/dx) d/dxi cancel, leaving
+   sum_{a=1..kappa} int_{-1/2}^{1/2} (r^{(a)}(xi))^2 dxi. */
+static double beta1d(const double* r, int np, int kappa) {
+  double d[6], tot = 0.0;
+  for (int n = 0; n < np; ++n) d[n] = r[n];
+  for (int a = 1; a <= kappa; ++a) {
+    for (int n = 0; n < np - 1; ++n) d[n] = (n + 1) * d[n + 1];  /* differentiate */
+    d[np - 1] = 0.0;
+    for (int m = 0; m < np; ++m)
+      for (int n = 0; n < np; ++n) tot += d[m] * d[n] * mono_avg(m + n, 0);
+  }
+  return tot;
+}
+
+/* Step 1 of the 1D reconstruction algorithm for one component:
+   data (ubar, vbar) on cells i-1, i, i+1 -> values at the four
+   Gauss-Lobatto points of I_i (eq. re-u).  wts/beta are optional outputs. */
+int orc_step1_1d(const orc_problem* P, const double* ub, const double* vb,
+                 double* gl, double* wts, double* betas) {
+  init_1d();
+  double dat[6] = {ub[0], ub[1], ub[2], vb[0], vb[1], vb[2]};
+  /* Step 1.1, eq. (q): q_1 .. q_4 as coefficient vectors of length 6 */
+  double q[5][6];
+  memset(q, 0, sizeof q);
+  q[1][0] = ub[1];
+  for (int l = 2; l <= 4; ++l)
+    for (int n = 0; n < 6; ++n) {
+      double s = 0.0;
+      for (int c = 0; c < 6; ++c) s += M1q[l][n][c] * dat[c];
+      q[l][n] = s;
+    }
+  /* eq. (linear-weight): gamma_{l1,l2} = gbar_{l1} / sum_{l<=l2} gbar_l */
+  double g[5][5];
+  for (int l2 = 1; l2 <= 4; ++l2) {
+    double S = 0.0;
+    for (int l = 1; l <= l2; ++l) S += P->gbar[l - 1];
+    for (int l1 = 1; l1 <= l2; ++l1) g[l1][l2] = P->gbar[l1 - 1] / S;
+  }
+  /* eq. (p): p_1 = q_1, p_l2 = q_l2/gamma_{l2,l2} - sum_{l<l2} gamma_{l,l2}/gamma_{l2,l2} p_l */
+  double p[5][6];
+  memset(p, 0, sizeof p);
+  for (int n = 0; n < 6; ++n) p[1][n] = q[1][n];
+  for (int l2 = 2; l2 <= 4; ++l2)
+    for (int n = 0; n < 6; ++n) {
+      double s = q[l2][n] / g[l2][l2];
+      for (int l = 1; l < l2; ++l) s -= g[l][l2] / g[l2][l2] * p[l][n];
+      p[l2][n] = s;
+    }
+  /* Step 1.2, eq. (beta): beta_2..4 with kappa = 2, 3, 5 (reading R1) */
+  double beta[5];
+  const int kappa[5] = {0, 0, 2, 3, 5};
+  for (int l = 2; l <= 4; ++l) beta[l] = beta1d(P->beta_on ? p[l] : q[l], 6, kappa[l]);
+  /* beta_1 through q_1L, q_1R, eqs. (q1-LR) .. (beta1) */
+  {
+    double bL = (ub[1] - ub[0]) * (ub[1] - ub[0]);
+    double bR = (ub[2] - ub[1]) * (ub[2] - ub[1]);
+    double tau1 = fabs(bR - bL) * fabs(bR - bL);
+    double wL = 0.5 * (1.0 + tau1 / (bL + P->eps));
+    double wR = 0.5 * (1.0 + tau1 / (bR + P->eps));
+    double oL = wL / (wL + wR), oR = wR / (wL + wR);
+    double d = oL * (ub[1] - ub[0]) + oR * (ub[2] - ub[1]);
+    beta[1] = d * d;
+  }
+  /* eqs. (non-linear-weight), (tau4) */
+  double tau4 = (fabs(beta[4] - beta[1]) + fabs(beta[4] - beta[2]) + fabs(beta[4] - beta[3])) / 3.0;
+  tau4 = tau4 * tau4;
+  double wb[5], ws = 0.0, w[5];
+  for (int l = 1; l <= 4; ++l) { wb[l] = g[l][4] * (1.0 + tau4 / (beta[l] + P->eps)); ws += wb[l]; }
+  for (int l = 1; l <= 4; ++l) w[l] = wb[l] / ws;
+  /* Step 1.3, eqs. (re-p), (re-u) */
+  double u[6];
+  for (int n = 0; n < 6; ++n) {
+    double s = 0.0;
+    for (int l = 1; l <= 4; ++l) s += w[l] * p[l][n];
+    u[n] = s;
+  }
+  for (int k = 0; k < 4; ++k) gl[k] = peval1(u, 6, gl_node(k));
+  if (wts) for (int l = 0; l < 4; ++l) wts[l] = w[l + 1];
+  if (betas) for (int l = 0; l < 4; ++l) betas[l] = beta[l + 1];
+  return 0;
+}
+
+/* Exported for the pins: coefficients of q_level (level 2..4) and of the
+   modified first moment (6-vector weights of (u-, u0, u+, v-, v0, v+)). */
+void orc_qmap_1d(int level, double* out /* (deg+1) x 6 */) {
+  init_1d();
+  const int deg[5] = {0, 0, 2, 3, 5};
+  for (int n = 0; n <= deg[level]; ++n)
+    for (int c = 0; c < 6; ++c) out[n * 6 + c] = M1q[level][n][c];
+}
+void orc_modmap_1d(double* out6) { init_1d(); memcpy(out6, M1mod, sizeof M1mod); }
+
+/* ======================================================================== */
+/* 2D reconstruction maps: constrained least squares (reading R8).          */
+/* Monomials xi^a eta^b, a+b <= 5, ordered by total degree, then a down.    */
+/* Stencil labels 1..9 (P:stencil figure) -> offsets (dx, dy):              */
+/* label = 1 + (dx+1) + 3 (dy+1).                                           */
+/* Data vector (27): ubar_1..9, vtil_1..9, wtil_1..9 (index 0..26).         */
+/* ======================================================================== */
+static int g_init2 = 0;
+static int mono_a[21], mono_b[21];
+static double M2q[5][21][27];  /* M2q[l][coef][data] for l = 2, 3, 4 */
+
+static void init_gram2(void);
+static int lab_dx(int lab) { return (lab - 1) % 3 - 1; }
+static int lab_dy(int lab) { return (lab - 1) / 3 - 1; }
+
+static long double cond_row_2d(int type, int lab, int a, int b) {
+  int dx = lab_dx(lab), dy = lab_dy(lab);
+  if (type == 0) return mono_avg_ld(a, dx) * mono_avg_ld(b, dy);
+  if (type == 1) return mono_mom_ld(a, dx) * mono_avg_ld(b, dy);
+  return mono_avg_ld(a, dx) * mono_mom_ld(b, dy);
+}
+
+static void build_lsq_2d(int level, int ncoef, int ncond, const int* types, const int* labs) {
+  /* minimise sum_{conditions except the centre average} (row.q - data)^2
+     subject to the centre average (label 5, type 0) holding exactly.
+     KKT system: [A^T A  c^T; c  0] [q; lambda] = [A^T d; d_c], built and
+     solved in long double with iterative refinement. */
+  int n = ncoef + 1;
+  long double* K = calloc((size_t)n * n, sizeof(long double));
+  long double* R = calloc((size_t)n * 27, sizeof(long double));
+  long double* W = calloc((size_t)n * n, sizeof(long double));
+  long double* X = calloc((size_t)n * 27, sizeof(long double));
+  long double* E = calloc((size_t)n * 27, sizeof(long double));
+  long double rows[32][21];
+  int ctr = -1;
+  for (int r = 0; r < ncond; ++r) {
+    for (int p = 0; p < ncoef; ++p) rows[r][p] = cond_row_2d(types[r], labs[r], mono_a[p], mono_b[p]);
+    if (types[r] == 0 && labs[r] == 5) ctr = r;
+  }
+  for (int r = 0; r < ncond; ++r) {
+    int didx = types[r] * 9 + (labs[r] - 1);
+    if (r == ctr) {
+      for (int p = 0; p < ncoef; ++p) { K[ncoef * n + p] = rows[r][p]; K[p * n + ncoef] = rows[r][p]; }
+      R[ncoef * 27 + didx] = 1.0L;
+      continue;
+    }
+    for (int p = 0; p < ncoef; ++p) {
+      for (int s = 0; s < ncoef; ++s) K[p * n + s] += rows[r][p] * rows[r][s];
+      R[p * 27 + didx] += rows[r][p];
+    }
+  }
+  for (int k = 0; k < n * n; ++k) W[k] = K[k];
+  for (int k = 0; k < n * 27; ++k) X[k] = R[k];
+  gauss_ld(n, W, 27, X);
+  for (int it = 0; it < 3; ++it) {
+    for (int r = 0; r < n; ++r)
+      for (int k = 0; k < 27; ++k) {
+        long double acc = R[r * 27 + k];
+        for (int c = 0; c < n; ++c) acc -= K[r * n + c] * X[c * 27 + k];
+        E[r * 27 + k] = acc;
+      }
+    for (int k = 0; k < n * n; ++k) W[k] = K[k];
+    gauss_ld(n, W, 27, E);
+    for (int k = 0; k < n * 27; ++k) X[k] += E[k];
+  }
+  for (int p = 0; p < ncoef; ++p)
+    for (int d = 0; d < 27; ++d) M2q[level][p][d] = (double)X[p * 27 + d];
+  free(K); free(R); free(W); free(X); free(E);
+}
+
+static void init_2d(void) {
+  if (g_init2) return;
+  (void)mono_avg(0, 0);
+  int k = 0;
+  for (int d = 0; d <= 5; ++d)
+    for (int a = d; a >= 0; --a) { mono_a[k] = a; mono_b[k] = d - a; ++k; }
+  memset(M2q, 0, sizeof M2q);
+  int types[32], labs[32], nc;
+  /* q_2, eq. (2D-q2): averages on labels 1..9 */
+  nc = 0;
+  for (int l = 1; l <= 9; ++l) { types[nc] = 0; labs[nc++] = l; }
+  build_lsq_2d(2, 6, nc, types, labs);
+  /* q_3, eq. (2D-q3): averages 1..9, vtil_5, wtil_5 */
+  types[nc] = 1; labs[nc++] = 5;
+  types[nc] = 2; labs[nc++] = 5;
+  build_lsq_2d(3, 10, nc, types, labs);
+  /* q_4, eq. (2D-q4): averages 1..9, vtil on 1,3,4,5,6,7,9, wtil on 1,2,3,5,7,8,9 */
+  nc = 0;
+  for (int l = 1; l <= 9; ++l) { types[nc] = 0; labs[nc++] = l; }
+  const int vl[7] = {1, 3, 4, 5, 6, 7, 9}, wl[7] = {1, 2, 3, 5, 7, 8, 9};
+  for (int l = 0; l < 7; ++l) { types[nc] = 1; labs[nc++] = vl[l]; }
+  for (int l = 0; l < 7; ++l) { types[nc] = 2; labs[nc++] = wl[l]; }
+  build_lsq_2d(4, 21, nc, types, labs);
+  init_gram2();
+  g_init2 = 1;
+}
+
+void orc_monomials_2d(int* a, int* b) {
+  init_2d();
+  for (int k = 0; k < 21; ++k) { a[k] = mono_a[k]; b[k] = mono_b[k]; }
+}
+void orc_qmap_2d(int level, double* out /* ncoef x 27 */) {
+  init_2d();
+  const int nco[5] = {0, 1, 6, 10, 21};
+  for (int p = 0; p < nco[level]; ++p)
+    for (int d = 0; d < 27; ++d) out[p * 27 + d] = M2q[level][p][d];
+}
+
+/* 2D polynomial helpers over the monomial list */
+static double peval2(const double* c, int nco, double x, double y) {
+  double s = 0.0;
+  for (int p = 0; p < nco; ++p) s += c[p] * ipow(x, mono_a[p]) * ipow(y, mono_b[p]);
+  return s;
+}
+/* eq. (2D-beta) in reference coordinates (reading R9): with |I| = dx dy and
+   dx = dy the factor |I|^{|alpha|-1} cancels the scaling of the derivative
+   and of the area element.  The sum over multi-indices of the integrals of
+   products of monomial derivatives is a fixed quadratic form per kappa;
+   it is tabulated at first use (gram2[kappa][p][s]). */
+static double gram2[6][21][21];
+static int g_gram2 = 0;
+static void init_gram2(void) {
+  memset(gram2, 0, sizeof gram2);
+  for (int kappa = 1; kappa <= 5; ++kappa)
+    for (int ax = 0; ax <= kappa; ++ax)
+      for (int ay = 0; ax + ay <= kappa; ++ay) {
+        if (ax + ay == 0) continue;
+        for (int p = 0; p < 21; ++p)
+          for (int s = 0; s < 21; ++s) {
+            int a1 = mono_a[p], b1 = mono_b[p], a2 = mono_a[s], b2 = mono_b[s];
+            if (a1 < ax || b1 < ay || a2 < ax || b2 < ay) continue;
+            double f = 1.0;
+            for (int t = 0; t < ax; ++t) f *= (double)(a1 - t) * (a2 - t);
+            for (int t = 0; t < ay; ++t) f *= (double)(b1 - t) * (b2 - t);
+            gram2[kappa][p][s] += f * mono_avg(a1 + a2 - 2 * ax, 0) * mono_avg(b1 + b2 - 2 * ay, 0);
+          }
+      }
+  g_gram2 = 1;
+}
+static double beta2d(const double* c, int nco, int kappa) {
+  double tot = 0.0;
+  for (int p = 0; p < nco; ++p)
+    for (int s = 0; s < nco; ++s) tot += c[p] * gram2[kappa][p][s] * c[s];
+  return tot;
+}
+
+/* Step 1 of the 2D reconstruction algorithm for one component.
+   ub/vb/wb hold ubar, vtil, wtil on stencil labels 1..9 (index label-1).
+   gl[k + 4 l] = u_{i,j}(xi_k, eta_l), k, l = 0..3 (eq. 2D-re-u). */
+int orc_step1_2d(const orc_problem* P, const double* ub, const double* vb, const double* wbv,
+                 double* gl, double* wts, double* betas) {
+  init_2d();
+  double dat[27];
+  for (int l = 0; l < 9; ++l) { dat[l] = ub[l]; dat[9 + l] = vb[l]; dat[18 + l] = wbv[l]; }
+  const int nco[5] = {0, 1, 6, 10, 21};
+  /* Step 1.1.1 - 1.1.4 */
+  double q[5][21];
+  memset(q, 0, sizeof q);
+  q[1][0] = ub[4];
+  for (int l = 2; l <= 4; ++l)
+    for (int p = 0; p < nco[l]; ++p) {
+      double s = 0.0;
+      for (int d = 0; d < 27; ++d) s += M2q[l][p][d] * dat[d];
+      q[l][p] = s;
+    }
+  /* Step 1.1.5, eq. (2D-p) with the linear weights of eq. (linear-weight) */
+  double g[5][5];
+  for (int l2 = 1; l2 <= 4; ++l2) {
+    double S = 0.0;
+    for (int l = 1; l <= l2; ++l) S += P->gbar[l - 1];
+    for (int l1 = 1; l1 <= l2; ++l1) g[l1][l2] = P->gbar[l1 - 1] / S;
+  }
+  double p[5][21];
+  memset(p, 0, sizeof p);
+  p[1][0] = q[1][0];
+  for (int l2 = 2; l2 <= 4; ++l2)
+    for (int n = 0; n < 21; ++n) {
+      double s = q[l2][n] / g[l2][l2];
+      for (int l = 1; l < l2; ++l) s -= g[l][l2] / g[l2][l2] * p[l][n];
+      p[l2][n] = s;
+    }
+  /* Step 1.2, eq. (2D-beta), kappa = 2, 3, 5 (readings R1, R9) */
+  double beta[5];
+  const int kappa[5] = {0, 0, 2, 3, 5};
+  for (int l = 2; l <= 4; ++l) beta[l] = beta2d(P->beta_on ? p[l] : q[l], 21, kappa[l]);
+  /* beta_1, eqs. (2D-q1-1234) .. (2D-beta1): q_1k are the linear
+     polynomials a + b xi + c eta through three cell averages */
+  {
+    const int tri[4][3] = {{4, 5, 8}, {5, 6, 8}, {2, 5, 6}, {2, 4, 5}};
+    double gx[4], gy[4], b1[4];
+    for (int k = 0; k < 4; ++k) {
+      double A[9], B[3];
+      for (int r = 0; r < 3; ++r) {
+        int lab = tri[k][r];
+        A[r * 3 + 0] = 1.0;
+        A[r * 3 + 1] = mono_avg(1, lab_dx(lab)) * mono_avg(0, lab_dy(lab));
+        A[r * 3 + 2] = mono_avg(0, lab_dx(lab)) * mono_avg(1, lab_dy(lab));
+        B[r] = ub[lab - 1];
+      }
+      gauss_solve(3, A, 1, B);
+      gx[k] = B[1];
+      gy[k] = B[2];
+      /* |I| |grad q_1k|^2 in reference coordinates */
+      b1[k] = gx[k] * gx[k] + gy[k] * gy[k];
+    }
+    double t = 0.0;
+    for (int k = 0; k < 4; ++k)
+      for (int l = k + 1; l < 4; ++l) t += fabs(b1[k] - b1[l]);
+    double tau1 = (t / 6.0) * (t / 6.0);
+    double wb1[4], s = 0.0;
+    for (int k = 0; k < 4; ++k) { wb1[k] = 0.25 * (1.0 + tau1 / (b1[k] + P->eps)); s += wb1[k]; }
+    double nx = 0.0, ny = 0.0;
+    for (int k = 0; k < 4; ++k) { nx += wb1[k] / s * gx[k]; ny += wb1[k] / s * gy[k]; }
+    beta[1] = nx * nx + ny * ny;
+  }
+  double tau4 = (fabs(beta[4] - beta[1]) + fabs(beta[4] - beta[2]) + fabs(beta[4] - beta[3])) / 3.0;
+  tau4 = tau4 * tau4;
+  double wbar[5], ws = 0.0, w[5];
+  for (int l = 1; l <= 4; ++l) { wbar[l] = g[l][4] * (1.0 + tau4 / (beta[l] + P->eps)); ws += wbar[l]; }
+  for (int l = 1; l <= 4; ++l) w[l] = wbar[l] / ws;
+  /* Step 1.3, eqs. (2D-re-p), (2D-re-u) */
+  double u[21];
+  for (int n = 0; n < 21; ++n) {
+    double s = 0.0;
+    for (int l = 1; l <= 4; ++l) s += w[l] * p[l][n];
+    u[n] = s;
+  }
+  for (int l = 0; l < 4; ++l)
+    for (int k = 0; k < 4; ++k) gl[k + 4 * l] = peval2(u, 21, gl_node(k), gl_node(l));
+  if (wts) for (int l = 0; l < 4; ++l) wts[l] = w[l + 1];
+  if (betas) for (int l = 0; l < 4; ++l) betas[l] = beta[l + 1];
+  return 0;
+}
+
+/* Coefficients of q_level for given stencil data (2D), for the pins. */
+void orc_qcoef_2d(int level, const double* ub, const double* vb, const double* wbv, double* out) {
+  init_2d();
+  const int nco[5] = {0, 1, 6, 10, 21};
+  double dat[27];
+  for (int l = 0; l < 9; ++l) { dat[l] = ub[l]; dat[9 + l] = vb[l]; dat[18 + l] = wbv[l]; }
+  for (int p = 0; p < nco[level]; ++p) {
+    double s = 0.0;
+    for (int d = 0; d < 27; ++d) s += M2q[level][p][d] * dat[d];
+    out[p] = s;
+  }
+}
+
+/* ======================================================================== */
+/* Physical fluxes and numerical fluxes                                      */
+/* ======================================================================== */
+/* Euler pressure from conserved variables (dim-aware: ncomp 3 or 4). */
+static double pressure(const double* u, int nc, double gam) {
+  double ke = u[1] * u[1];
+  if (nc == 4) ke += u[2] * u[2];
+  return (gam - 1.0) * (u[nc - 1] - 0.5 * ke / u[0]);
+}
+
+/* Physical flux in direction dir (0 = x, 1 = y), eq. (1D-Euler)/(2D-Euler). */
+static void euler_flux(const double* u, int nc, int dir, double gam, double* f) {
+  double p = pressure(u, nc, gam);
+  double vn = u[1 + dir] / u[0];
+  f[0] = u[1 + dir];
+  f[1] = u[1] * vn;
+  if (nc == 4) f[2] = u[2] * vn;
+  f[1 + dir] += p;
+  f[nc - 1] = vn * (u[nc - 1] + p);
+}
+
+/* HLLC flux of eqs. (f_HLLC), (COEF), (uLR_) with the printed PVRS p*, s*
+   (reading R10).  For nc = 4 the direction dir selects the normal. */
+void orc_hllc(const double* uL, const double* uR, int nc, int dir, double gam, double* f) {
+  int in = 1 + dir;            /* normal momentum component */
+  int it = (nc == 4) ? 2 - dir : -1; /* tangential momentum component */
+  double rL = uL[0], rR = uR[0];
+  double muL = uL[in] / rL, muR = uR[in] / rR;
+  double pL = pressure(uL, nc, gam), pR = pressure(uR, nc, gam);
+  double cL = sqrt(gam * pL / rL), cR = sqrt(gam * pR / rR);
+  double EL = uL[nc - 1], ER = uR[nc - 1];
+  double rs = (rL + rR) / 2.0, cs = (cL + cR) / 2.0;
+  double ps = (pL + pR + (muL - muR) * (cs * rs)) / 2.0;
+  double ss = (muL + muR + (pL - pR) / (cs * rs)) / 2.0;
+  double coefL = (ps <= pL) ? 1.0 : sqrt(1.0 + (gam + 1.0) * (ps / pL - 1.0) / (2.0 * gam));
+  double coefR = (ps <= pR) ? 1.0 : sqrt(1.0 + (gam + 1.0) * (ps / pR - 1.0) / (2.0 * gam));
+  double sL = muL - cL * coefL, sR = muR + cR * coefR;
+  double fL[4], fR[4];
+  euler_flux(uL, nc, dir, gam, fL);
+  euler_flux(uR, nc, dir, gam, fR);
+  /* ordered chain (reading R10): 0 <= sL -> f_L; 0 <= s* -> f*_L;
+     0 <= sR -> f*_R; otherwise f_R */
+  if (0.0 <= sL) { for (int c = 0; c < nc; ++c) f[c] = fL[c]; return; }
+  const double* uK;
+  double sK, muK, rK, pK, EK;
+  const double* fK;
+  if (0.0 <= ss) { uK = uL; sK = sL; muK = muL; rK = rL; pK = pL; EK = EL; fK = fL; }
+  else if (0.0 <= sR) { uK = uR; sK = sR; muK = muR; rK = rR; pK = pR; EK = ER; fK = fR; }
+  else { for (int c = 0; c < nc; ++c) f[c] = fR[c]; return; }
+  double fac = rK * (sK - muK) / (sK - ss);
+  double us[4];
+  us[0] = fac;
+  us[in] = fac * ss;
+  if (it >= 0) us[it] = fac * (uK[it] / rK);
+  us[nc - 1] = fac * (EK / rK + (ss - muK) * (ss + pK / (rK * (sK - muK))));
+  for (int c = 0; c < nc; ++c) f[c] = fK[c] + sK * (us[c] - uK[c]);
+}
+
+/* Scalar Burgers flux f(u) = u^2/2 with global Lax-Friedrichs (reading R11). */
+static double lf_flux(double a, double b, double alpha) {
+  return 0.5 * (0.5 * a * a + 0.5 * b * b - alpha * (b - a));
+}
+
+/* ======================================================================== */
+/* Grid access with ghost cells (reading R13)                               */
+/* U layout: U[((c * nm) + m) * ny * nx + j * nx + i], nm = dim + 1.         */
+/* ======================================================================== */
+typedef struct { const orc_problem* P; const double* U; int nc, nm; } grid_t;
+
+/* Moment m of component c at cell (i, j), any integer (i, j). */
+static double mom(const grid_t* G, int c, int m, int i, int j) {
+  const orc_problem* P = G->P;
+  int zero = 0;
+  if (i < 0 || i >= P->nx) {
+    if (P->bc_x == 0) i = ((i % P->nx) + P->nx) % P->nx;
+    else { zero = 1; i = i < 0 ? 0 : P->nx - 1; }
+  }
+  if (P->dim == 2 && (j < 0 || j >= P->ny)) {
+    if (P->bc_y == 0) j = ((j % P->ny) + P->ny) % P->ny;
+    else { zero = 1; j = j < 0 ? 0 : P->ny - 1; }
+  }
+  if (P->dim == 1) j = 0;
+  if (zero && m > 0) return 0.0;
+  return G->U[((size_t)(c * G->nm + m) * P->ny + j) * P->nx + i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1D spatial operator on an extended range of cells                        */
+/* ------------------------------------------------------------------------ */
+/* Step 2.2, eq. (vi), applied with the oracle's own p_0 map (reading R3). */
+static double modified_v1(const grid_t* G, int c, int i) {
+  double d[6] = {mom(G, c, 0, i - 1, 0), mom(G, c, 0, i, 0), mom(G, c, 0, i + 1, 0),
+                 mom(G, c, 1, i - 1, 0), mom(G, c, 1, i, 0), mom(G, c, 1, i + 1, 0)};
+  double s = 0.0;
+  for (int k = 0; k < 6; ++k) s += M1mod[k] * d[k];
+  return s;
+}
+
+/* velocity used by the KXRCF indicator at a point (Remark 2) */
+static double kx_velocity(const orc_problem* P, const double* upt, int dir) {
+  if (P->system == 0) return upt[0];           /* f'(u) = u (and g'(u) = u) */
+  return upt[1 + dir] / upt[0];
+}
+
+/* Work arrays for the 1D operator: ranges include R ghost cells each side. */
+#define R1G 4
+typedef struct {
+  int n, nc;
+  double* g0;      /* [cell][comp][4] Step-1 values of the original field   */
+  double* gf;      /* [cell][comp][4] final values after Step 2             */
+  unsigned char* fl;
+  double* anum;    /* KXRCF numerator |J|                                   */
+  double* aden;    /* KXRCF denominator h^2 ||u||                           */
+} work1_t;
+
+static void op1d_values(const orc_problem* P, const double* U, work1_t* W) {
+  init_1d();
+  grid_t G = {P, U, ncomp_of(P), 2};
+  int n = P->nx, nc = G.nc;
+  int lo = -R1G + 1, hi = n + R1G - 1;          /* g0 on [lo, hi) */
+  W->n = n;
+  W->nc = nc;
+  /* Step 1 on the original field */
+#pragma omp parallel for schedule(static)
+  for (int i = lo; i < hi; ++i)
+    for (int c = 0; c < nc; ++c) {
+      double ub[3] = {mom(&G, c, 0, i - 1, 0), mom(&G, c, 0, i, 0), mom(&G, c, 0, i + 1, 0)};
+      double vb[3] = {mom(&G, c, 1, i - 1, 0), mom(&G, c, 1, i, 0), mom(&G, c, 1, i + 1, 0)};
+      orc_step1_1d(P, ub, vb, &W->g0[(((size_t)(i - lo)) * nc + c) * 4], NULL, NULL);
+    }
+  /* Step 2.1: KXRCF (eq. KXRCF with eq. line-integral-average) on the
+     indicator variable, component 0, for cells [lo+1, hi-1) */
+#pragma omp parallel for schedule(static)
+  for (int i = lo + 1; i < hi - 1; ++i) {
+    const double* own = &W->g0[((size_t)(i - lo)) * nc * 4];
+    const double* lef = &W->g0[((size_t)(i - 1 - lo)) * nc * 4];
+    const double* rig = &W->g0[((size_t)(i + 1 - lo)) * nc * 4];
+    int f = 0;
+    double num = 0.0, den = 0.0;
+    if (P->tc_mode == 2) f = 1;
+    else if (P->tc_mode == 1) {
+      double ptO[4] = {0, 0, 0, 0}, ptN[4] = {0, 0, 0, 0};
+      /* left face x_{i-1/2}: u^+ = own left value, u^- = left neighbour's right value */
+      for (int c = 0; c < nc; ++c) { ptO[c] = own[c * 4 + 0]; ptN[c] = lef[c * 4 + 3]; }
+      double vl = 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
+      double jl = ptO[0] - ptN[0];
+      /* right face x_{i+1/2}: u^- = own right value, u^+ = right neighbour's left value */
+      for (int c = 0; c < nc; ++c) { ptO[c] = own[c * 4 + 3]; ptN[c] = rig[c * 4 + 0]; }
+      double vr = 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
+      double jr = ptO[0] - ptN[0];
+      double J = jl * (vl > 0.0 ? 1.0 : 0.0) + jr * (-vr > 0.0 ? 1.0 : 0.0);
+      double nrm = 0.0;
+      for (int k = 0; k < 4; ++k) if (fabs(own[k]) > nrm) nrm = fabs(own[k]);
+      num = fabs(J);
+      den = P->dx * P->dx * nrm;     /* h^{(l+1)/3} with l = 5 */
+      f = num > den;
+    }
+    W->fl[i - lo] = (unsigned char)f;
+    W->anum[i - lo] = num;
+    W->aden[i - lo] = den;
+  }
+  /* Steps 2.2 and 2.3 for cells [lo+2, hi-2) */
+#pragma omp parallel for schedule(static)
+  for (int i = lo + 2; i < hi - 2; ++i) {
+    for (int c = 0; c < nc; ++c) {
+      double* out = &W->gf[(((size_t)(i - lo)) * nc + c) * 4];
+      if (!W->fl[i - lo]) {
+        memcpy(out, &W->g0[(((size_t)(i - lo)) * nc + c) * 4], 4 * sizeof(double));
+        continue;
+      }
+      double ub[3], vb[3];
+      for (int d = -1; d <= 1; ++d) {
+        ub[d + 1] = mom(&G, c, 0, i + d, 0);
+        vb[d + 1] = W->fl[i + d - lo] ? modified_v1(&G, c, i + d) : mom(&G, c, 1, i + d, 0);
+      }
+      orc_step1_1d(P, ub, vb, out, NULL, NULL);
+    }
+  }
+}
+
+static int work1_alloc(const orc_problem* P, work1_t* W) {
+  int nc = ncomp_of(P);
+  size_t ncell = (size_t)P->nx + 2 * R1G;
+  W->g0 = calloc(ncell * nc * 4, sizeof(double));
+  W->gf = calloc(ncell * nc * 4, sizeof(double));
+  W->fl = calloc(ncell, 1);
+  W->anum = calloc(ncell, sizeof(double));
+  W->aden = calloc(ncell, sizeof(double));
+  return (W->g0 && W->gf && W->fl && W->anum && W->aden) ? 0 : -1;
+}
+static void work1_free(work1_t* W) { free(W->g0); free(W->gf); free(W->fl); free(W->anum); free(W->aden); }
+
+static double lf_alpha(const orc_problem* P, const double* U) {
+  /* reading R11: alpha = max |f'(ubar)| over the cells of the stage input */
+  double a = 0.0;
+  size_t n = (size_t)P->nx * P->ny;
+  for (size_t k = 0; k < n; ++k) if (fabs(U[k]) > a) a = fabs(U[k]);
+  return a;
+}
+
+/* L(U) of eq. (1D-equ-int-approximation), eq. (F) */
+static void residual_1d(const orc_problem* P, const double* U, double* L, unsigned char* flags) {
+  work1_t W;
+  work1_alloc(P, &W);
+  op1d_values(P, U, &W);
+  int n = P->nx, nc = ncomp_of(P);
+  int lo = -R1G + 1;
+  double alpha = P->system == 0 ? lf_alpha(P, U) : 0.0;
+  /* fluxes at faces x_{i-1/2}, i = 0..n */
+  double* fh = calloc((size_t)(n + 1) * nc, sizeof(double));
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i <= n; ++i) {
+    const double* lef = &W.gf[((size_t)(i - 1 - lo)) * nc * 4];
+    const double* rig = &W.gf[((size_t)(i - lo)) * nc * 4];
+    double uL[4], uR[4];
+    for (int c = 0; c < nc; ++c) { uL[c] = lef[c * 4 + 3]; uR[c] = rig[c * 4 + 0]; }
+    if (P->system == 0) fh[i] = lf_flux(uL[0], uR[0], alpha);
+    else orc_hllc(uL, uR, nc, 0, P->gamma, &fh[(size_t)i * nc]);
+  }
+#pragma omp parallel for schedule(static)
+  for (int i = 0; i < n; ++i) {
+    const double* own = &W.gf[((size_t)(i - lo)) * nc * 4];
+    /* F_i = sum_l omega_l f(u(x_l^GL)), eq. (F) */
+    double F[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 4; ++k) {
+      double pt[4], f[4];
+      for (int c = 0; c < nc; ++c) pt[c] = own[c * 4 + k];
+      if (P->system == 0) f[0] = 0.5 * pt[0] * pt[0];
+      else euler_flux(pt, nc, 0, P->gamma, f);
+      for (int c = 0; c < nc; ++c) F[c] += gl_weight(k) * f[c];
+    }
+    for (int c = 0; c < nc; ++c) {
+      double fm = fh[(size_t)i * nc + c], fp = fh[(size_t)(i + 1) * nc + c];
+      L[((size_t)(c * 2 + 0)) * n + i] = -(fp - fm) / P->dx;
+      L[((size_t)(c * 2 + 1)) * n + i] = -(fp + fm) / (2.0 * P->dx) + F[c] / P->dx;
+    }
+    if (flags) flags[i] = W.fl[i - lo];
+  }
+  free(fh);
+  work1_free(&W);
+}
+
+/* ------------------------------------------------------------------------ */
+/* 2D spatial operator                                                       */
+/* ------------------------------------------------------------------------ */
+#define R2G 4
+typedef struct {
+  int nx, ny, nc, ex, ey;  /* extended sizes */
+  double* g0;              /* [cell][comp][16] */
+  double* gf;
+  unsigned char* fl;
+  double* anum;
+  double* aden;
+} work2_t;
+
+static size_t w2idx(const work2_t* W, int i, int j) { return (size_t)(j + R2G) * W->ex + (i + R2G); }
+
+static void gather2(const grid_t* G, int c, int i, int j, double* ub, double* vb, double* wb) {
+  for (int lab = 1; lab <= 9; ++lab) {
+    int ii = i + lab_dx(lab), jj = j + lab_dy(lab);
+    ub[lab - 1] = mom(G, c, 0, ii, jj);
+    vb[lab - 1] = mom(G, c, 1, ii, jj);
+    wb[lab - 1] = mom(G, c, 2, ii, jj);
+  }
+}
+
+/* Step 2.2 in 2D: dimension by dimension with the 1D map (reading R3). */
+static void modified_vw2(const grid_t* G, int c, int i, int j, double* v, double* w) {
+  double dx[6] = {mom(G, c, 0, i - 1, j), mom(G, c, 0, i, j), mom(G, c, 0, i + 1, j),
+                  mom(G, c, 1, i - 1, j), mom(G, c, 1, i, j), mom(G, c, 1, i + 1, j)};
+  double dy[6] = {mom(G, c, 0, i, j - 1), mom(G, c, 0, i, j), mom(G, c, 0, i, j + 1),
+                  mom(G, c, 2, i, j - 1), mom(G, c, 2, i, j), mom(G, c, 2, i, j + 1)};
+  double sv = 0.0, sw = 0.0;
+  for (int k = 0; k < 6; ++k) { sv += M1mod[k] * dx[k]; sw += M1mod[k] * dy[k]; }
+  *v = sv;
+  *w = sw;
+}
+
+/* KXRCF in 2D, eqs. (KXRCF_), (line-integral-average_), readings R5, R6. */
+static void kxrcf_2d(const orc_problem* P, const work2_t* W, int i, int j,
+                     unsigned char* flag, double* num_out, double* den_out) {
+  int nc = W->nc;
+  const double* own = &W->g0[w2idx(W, i, j) * nc * 16];
+  const double* nb[4] = {&W->g0[w2idx(W, i - 1, j) * nc * 16], &W->g0[w2idx(W, i + 1, j) * nc * 16],
+                         &W->g0[w2idx(W, i, j - 1) * nc * 16], &W->g0[w2idx(W, i, j + 1) * nc * 16]};
+  /* faces: 0 = left (x_{i-1/2}), 1 = right, 2 = bottom (y_{j-1/2}), 3 = top.
+     own point index and neighbour point index for the m-th face point */
+  double J = 0.0, len = 0.0;
+  for (int f = 0; f < 4; ++f) {
+    double jump = 0.0, vel = 0.0;
+    int dir = f / 2;
+    double flen = dir == 0 ? P->dy : P->dx;
+    for (int m = 0; m < 4; ++m) {
+      int po, pn;
+      if (f == 0) { po = 0 + 4 * m; pn = 3 + 4 * m; }
+      else if (f == 1) { po = 3 + 4 * m; pn = 0 + 4 * m; }
+      else if (f == 2) { po = m + 0; pn = m + 12; }
+      else { po = m + 12; pn = m + 0; }
+      double ptO[4] = {0, 0, 0, 0}, ptN[4] = {0, 0, 0, 0};
+      for (int c = 0; c < nc; ++c) { ptO[c] = own[c * 16 + po]; ptN[c] = nb[f][c * 16 + pn]; }
+      jump += flen * gl_weight(m) * (ptO[0] - ptN[0]);
+      vel += gl_weight(m) * 0.5 * (kx_velocity(P, ptO, dir) + kx_velocity(P, ptN, dir));
+    }
+    /* inflow: left/bottom if v > 0, right/top if v < 0 (sf of the printed signs) */
+    double arg = (f == 0 || f == 2) ? vel : -vel;
+    if (arg > 0.0) { J += jump; len += flen; }
+  }
+  double nrm = 0.0;
+  for (int k = 0; k < 16; ++k) if (fabs(own[k]) > nrm) nrm = fabs(own[k]);
+  double num = fabs(J), den = P->dx * P->dx * len * nrm;
+  *flag = (unsigned char)(num > den);
+  *num_out = num;
+  *den_out = den;
+}
+
+static void op2d_values(const orc_problem* P, const double* U, work2_t* W) {
+  init_1d();
+  init_2d();
+  grid_t G = {P, U, ncomp_of(P), 3};
+  int nc = G.nc;
+  /* g0 for cells [-3, n+3), flags [-2, n+2), final values [-1, n+1) */
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int j = -3; j < P->ny + 3; ++j)
+    for (int i = -3; i < P->nx + 3; ++i)
+      for (int c = 0; c < nc; ++c) {
+        double ub[9], vb[9], wb[9];
+        gather2(&G, c, i, j, ub, vb, wb);
+        orc_step1_2d(P, ub, vb, wb, &W->g0[(w2idx(W, i, j) * nc + c) * 16], NULL, NULL);
+      }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int j = -2; j < P->ny + 2; ++j)
+    for (int i = -2; i < P->nx + 2; ++i) {
+      size_t k = w2idx(W, i, j);
+      if (P->tc_mode == 0) { W->fl[k] = 0; continue; }
+      if (P->tc_mode == 2) { W->fl[k] = 1; continue; }
+      kxrcf_2d(P, W, i, j, &W->fl[k], &W->anum[k], &W->aden[k]);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int j = -1; j < P->ny + 1; ++j)
+    for (int i = -1; i < P->nx + 1; ++i) {
+      size_t k = w2idx(W, i, j);
+      for (int c = 0; c < nc; ++c) {
+        double* out = &W->gf[(k * nc + c) * 16];
+        if (!W->fl[k]) { memcpy(out, &W->g0[(k * nc + c) * 16], 16 * sizeof(double)); continue; }
+        /* Step 2.3: Step 1 again on the modified field (reading R3, R4) */
+        double ub[9], vb[9], wb[9];
+        gather2(&G, c, i, j, ub, vb, wb);
+        for (int lab = 1; lab <= 9; ++lab) {
+          int ii = i + lab_dx(lab), jj = j + lab_dy(lab);
+          if (W->fl[w2idx(W, ii, jj)]) modified_vw2(&G, c, ii, jj, &vb[lab - 1], &wb[lab - 1]);
+        }
+        orc_step1_2d(P, ub, vb, wb, out, NULL, NULL);
+      }
+    }
+}
+
+static int work2_alloc(const orc_problem* P, work2_t* W) {
+  W->nx = P->nx; W->ny = P->ny; W->nc = ncomp_of(P);
+  W->ex = P->nx + 2 * R2G; W->ey = P->ny + 2 * R2G;
+  size_t ncell = (size_t)W->ex * W->ey;
+  W->g0 = calloc(ncell * W->nc * 16, sizeof(double));
+  W->gf = calloc(ncell * W->nc * 16, sizeof(double));
+  W->fl = calloc(ncell, 1);
+  W->anum = calloc(ncell, sizeof(double));
+  W->aden = calloc(ncell, sizeof(double));
+  return (W->g0 && W->gf && W->fl && W->anum && W->aden) ? 0 : -1;
+}
+static void work2_free(work2_t* W) { free(W->g0); free(W->gf); free(W->fl); free(W->anum); free(W->aden); }
+
+/* numerical flux at a face point; dir 0 = x face (f-hat), 1 = y face (g-hat) */
+static void num_flux(const orc_problem* P, const double* uL, const double* uR, int dir,
+                     double alpha, double* f) {
+  if (P->system == 0) { f[0] = lf_flux(uL[0], uR[0], alpha); return; }
+  orc_hllc(uL, uR, ncomp_of(P), dir, P->gamma, f);
+}
+
+/* L(U) of eq. (2D-equ-int-approximation) with the quadratures of eqs.
+   (integral1)-(integral3). */
+static void residual_2d(const orc_problem* P, const double* U, double* L, unsigned char* flags) {
+  work2_t W;
+  work2_alloc(P, &W);
+  op2d_values(P, U, &W);
+  int nx = P->nx, ny = P->ny, nc = W.nc;
+  double alpha = P->system == 0 ? lf_alpha(P, U) : 0.0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double* own = &W.gf[w2idx(&W, i, j) * nc * 16];
+      const double* lef = &W.gf[w2idx(&W, i - 1, j) * nc * 16];
+      const double* rig = &W.gf[w2idx(&W, i + 1, j) * nc * 16];
+      const double* bot = &W.gf[w2idx(&W, i, j - 1) * nc * 16];
+      const double* top = &W.gf[w2idx(&W, i, j + 1) * nc * 16];
+      /* face sums: X0 = sum_l w_l fhat, X1 = sum_l w_l eta_l fhat (x faces);
+         Y0 = sum_k w_k ghat, Y1 = sum_k w_k xi_k ghat (y faces) */
+      double XL0[4] = {0}, XL1[4] = {0}, XR0[4] = {0}, XR1[4] = {0};
+      double YB0[4] = {0}, YB1[4] = {0}, YT0[4] = {0}, YT1[4] = {0};
+      for (int m = 0; m < 4; ++m) {
+        double a[4], b[4], f[4];
+        double wm = gl_weight(m), xm = gl_node(m);
+        /* left face x_{i-1/2}, eta_m: left state from cell i-1 (xi = 1/2) */
+        for (int c = 0; c < nc; ++c) { a[c] = lef[c * 16 + 3 + 4 * m]; b[c] = own[c * 16 + 0 + 4 * m]; }
+        num_flux(P, a, b, 0, alpha, f);
+        for (int c = 0; c < nc; ++c) { XL0[c] += wm * f[c]; XL1[c] += wm * xm * f[c]; }
+        /* right face x_{i+1/2} */
+        for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + 3 + 4 * m]; b[c] = rig[c * 16 + 0 + 4 * m]; }
+        num_flux(P, a, b, 0, alpha, f);
+        for (int c = 0; c < nc; ++c) { XR0[c] += wm * f[c]; XR1[c] += wm * xm * f[c]; }
+        /* bottom face y_{j-1/2}, xi_m */
+        for (int c = 0; c < nc; ++c) { a[c] = bot[c * 16 + m + 12]; b[c] = own[c * 16 + m]; }
+        num_flux(P, a, b, 1, alpha, f);
+        for (int c = 0; c < nc; ++c) { YB0[c] += wm * f[c]; YB1[c] += wm * xm * f[c]; }
+        /* top face y_{j+1/2} */
+        for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + m + 12]; b[c] = top[c * 16 + m]; }
+        num_flux(P, a, b, 1, alpha, f);
+        for (int c = 0; c < nc; ++c) { YT0[c] += wm * f[c]; YT1[c] += wm * xm * f[c]; }
+      }
+      /* volume terms F_ij, G_ij, eq. (integral1) */
+      double F[4] = {0}, Gv[4] = {0};
+      for (int l = 0; l < 4; ++l)
+        for (int k = 0; k < 4; ++k) {
+          double pt[4], f[4], g[4];
+          for (int c = 0; c < nc; ++c) pt[c] = own[c * 16 + k + 4 * l];
+          if (P->system == 0) { f[0] = 0.5 * pt[0] * pt[0]; g[0] = f[0]; }
+          else { euler_flux(pt, nc, 0, P->gamma, f); euler_flux(pt, nc, 1, P->gamma, g); }
+          for (int c = 0; c < nc; ++c) {
+            F[c] += gl_weight(k) * gl_weight(l) * f[c];
+            Gv[c] += gl_weight(k) * gl_weight(l) * g[c];
+          }
+        }
+      size_t plane = (size_t)nx * ny, cell = (size_t)j * nx + i;
+      for (int c = 0; c < nc; ++c) {
+        double du = -(XR0[c] - XL0[c]) / P->dx - (YT0[c] - YB0[c]) / P->dy;
+        double dv = -(XR0[c] + XL0[c]) / (2.0 * P->dx) + F[c] / P->dx - (YT1[c] - YB1[c]) / P->dy;
+        double dw = -(XR1[c] - XL1[c]) / P->dx - (YT0[c] + YB0[c]) / (2.0 * P->dy) + Gv[c] / P->dy;
+        L[(c * 3 + 0) * plane + cell] = du;
+        L[(c * 3 + 1) * plane + cell] = dv;
+        L[(c * 3 + 2) * plane + cell] = dw;
+      }
+      if (flags) flags[cell] = W.fl[w2idx(&W, i, j)];
+    }
+  work2_free(&W);
+}
+
+/* ======================================================================== */
+/* Exported whole-grid entry points                                          */
+/* ======================================================================== */
+int orc_ncomp(const orc_problem* P) { return ncomp_of(P); }
+
+/* L(U); flags (optional) receive the troubled-cell map of the interior. */
+int orc_residual(const orc_problem* P, const double* U, double* L, unsigned char* flags) {
+  if (P->dim == 1) residual_1d(P, U, L, flags);
+  else residual_2d(P, U, L, flags);
+  return 0;
+}
+
+/* Final Gauss-Lobatto values after Step 2 (1D [comp][4][n], 2D
+   [comp][16][ny][nx]), troubled-cell flags, and the KXRCF numerator |J| and
+   denominator (h^2 ||u|| in 1D, h^2 |dI^-| ||u|| in 2D). */
+int orc_reconstruct(const orc_problem* P, const double* U, double* gl, unsigned char* flags,
+                    double* anum, double* aden) {
+  int nc = ncomp_of(P);
+  if (P->dim == 1) {
+    work1_t W;
+    work1_alloc(P, &W);
+    op1d_values(P, U, &W);
+    int n = P->nx, lo = -R1G + 1;
+    for (int i = 0; i < n; ++i) {
+      for (int c = 0; c < nc; ++c)
+        for (int k = 0; k < 4; ++k)
+          if (gl) gl[((size_t)c * 4 + k) * n + i] = W.gf[(((size_t)(i - lo)) * nc + c) * 4 + k];
+      if (flags) flags[i] = W.fl[i - lo];
+      if (anum) anum[i] = W.anum[i - lo];
+      if (aden) aden[i] = W.aden[i - lo];
+    }
+    work1_free(&W);
+  } else {
+    work2_t W;
+    work2_alloc(P, &W);
+    op2d_values(P, U, &W);
+    size_t plane = (size_t)P->nx * P->ny;
+    for (int j = 0; j < P->ny; ++j)
+      for (int i = 0; i < P->nx; ++i) {
+        size_t k = w2idx(&W, i, j), cell = (size_t)j * P->nx + i;
+        for (int c = 0; c < nc; ++c)
+          for (int p = 0; p < 16; ++p)
+            if (gl) gl[((size_t)c * 16 + p) * plane + cell] = W.gf[(k * nc + c) * 16 + p];
+        if (flags) flags[cell] = W.fl[k];
+        if (anum) anum[cell] = W.anum[k];
+        if (aden) aden[cell] = W.aden[k];
+      }
+    work2_free(&W);
+  }
+  return 0;
+}
+
+/* Maximum wave speeds from the cell averages (reading R12).  For Burgers
+   ax = ay = max |ubar|.  Returns ax in out[0], ay in out[1]. */
+int orc_wave_speeds(const orc_problem* P, const double* U, double* out) {
+  int nc = ncomp_of(P), nm = P->dim + 1;
+  size_t plane = (size_t)P->nx * P->ny;
+  double ax = 0.0, ay = 0.0;
+  for (size_t k = 0; k < plane; ++k) {
+    if (P->system == 0) {
+      double a = fabs(U[k]);
+      if (a > ax) ax = a;
+      if (a > ay) ay = a;
+      continue;
+    }
+    double u[4];
+    for (int c = 0; c < nc; ++c) u[c] = U[(size_t)c * nm * plane + k];
+    double p = pressure(u, nc, P->gamma);
+    double cs = sqrt(P->gamma * p / u[0]);
+    double sx = fabs(u[1] / u[0]) + cs;
+    if (sx > ax) ax = sx;
+    if (nc == 4) { double sy = fabs(u[2] / u[0]) + cs; if (sy > ay) ay = sy; }
+  }
+  out[0] = ax;
+  out[1] = ay;
+  return 0;
+}
+
+/* dt of reading R12 (unclipped). */
+double orc_dt(const orc_problem* P, const double* U, double cfl) {
+  double a[2];
+  orc_wave_speeds(P, U, a);
+  if (P->dim == 1) return cfl * P->dx / a[0];
+  return cfl / (a[0] / P->dx + a[1] / P->dy);
+}
+
+/* Stage input with the first moments of troubled cells replaced by their
+   modified values (Step 2.2, Jacobi from the unmodified input). */
+int orc_modify(const orc_problem* P, const double* U, const unsigned char* flags, double* Ut) {
+  init_1d();
+  int nc = ncomp_of(P), nm = P->dim + 1;
+  size_t plane = (size_t)P->nx * P->ny;
+  memcpy(Ut, U, (size_t)nc * nm * plane * sizeof(double));
+  grid_t G = {P, U, nc, nm};
+  for (int j = 0; j < P->ny; ++j)
+    for (int i = 0; i < P->nx; ++i) {
+      size_t cell = (size_t)j * P->nx + i;
+      if (!flags[cell]) continue;
+      for (int c = 0; c < nc; ++c) {
+        if (P->dim == 1) {
+          Ut[(size_t)(c * 2 + 1) * plane + cell] = modified_v1(&G, c, i);
+        } else {
+          double v, w;
+          modified_vw2(&G, c, i, j, &v, &w);
+          Ut[(size_t)(c * 3 + 1) * plane + cell] = v;
+          Ut[(size_t)(c * 3 + 2) * plane + cell] = w;
+        }
+      }
+    }
+  return 0;
+}
+
+/* One step of the third-order TVD Runge-Kutta method, eq. (Runge-Kutta).
+   U is overwritten with U^{n+1}; flags (optional, 3 x cells) receive the
+   troubled-cell map of every stage.  persist selects how the modified
+   first moments enter the stage combination:
+     0: not at all (the modification is internal to L);
+     1: every stage input, U^n included, is replaced by its modified state;
+     2: stage inputs are replaced, U^n in the later stages is the original. */
+int orc_rk3_step_p(const orc_problem* P, double* U, double dt, unsigned char* flags, int persist) {
+  size_t n = (size_t)ncomp_of(P) * (P->dim + 1) * P->nx * P->ny;
+  size_t cells = (size_t)P->nx * P->ny;
+  double* U1 = malloc(n * sizeof(double));
+  double* U2 = malloc(n * sizeof(double));
+  double* L = malloc(n * sizeof(double));
+  double* Ut = malloc(n * sizeof(double));
+  double* Un = malloc(n * sizeof(double));
+  unsigned char* fl = malloc(cells);
+  orc_residual(P, U, L, fl);
+  if (flags) memcpy(flags, fl, cells);
+  if (persist) orc_modify(P, U, fl, Ut); else memcpy(Ut, U, n * sizeof(double));
+  if (persist == 1) memcpy(Un, Ut, n * sizeof(double)); else memcpy(Un, U, n * sizeof(double));
+  for (size_t k = 0; k < n; ++k) U1[k] = Ut[k] + dt * L[k];
+  orc_residual(P, U1, L, fl);
+  if (flags) memcpy(flags + cells, fl, cells);
+  if (persist) orc_modify(P, U1, fl, Ut); else memcpy(Ut, U1, n * sizeof(double));
+  for (size_t k = 0; k < n; ++k) U2[k] = 3.0 / 4.0 * Un[k] + 1.0 / 4.0 * Ut[k] + 1.0 / 4.0 * dt * L[k];
+  orc_residual(P, U2, L, fl);
+  if (flags) memcpy(flags + 2 * cells, fl, cells);
+  if (persist) orc_modify(P, U2, fl, Ut); else memcpy(Ut, U2, n * sizeof(double));
+  for (size_t k = 0; k < n; ++k) U[k] = 1.0 / 3.0 * Un[k] + 2.0 / 3.0 * Ut[k] + 2.0 / 3.0 * dt * L[k];
+  free(U1); free(U2); free(L); free(Ut); free(Un); free(fl);
+  return 0;
+}
+
+int orc_rk3_step(const orc_problem* P, double* U, double dt, unsigned char* flags) {
+  return orc_rk3_step_p(P, U, dt, flags, 1);
+}
+
+/* ======================================================================== */
+/* Per-cell evaluation (for sampled checks on large grids): recomputes the  */
+/* whole dependency cone of one cell with no caching.                       */
+/* ======================================================================== */
+static void g0_cell2(const grid_t* G, int i, int j, double* out /* nc x 16 */) {
+  for (int c = 0; c < G->nc; ++c) {
+    double ub[9], vb[9], wb[9];
+    gather2(G, c, i, j, ub, vb, wb);
+    orc_step1_2d(G->P, ub, vb, wb, &out[c * 16], NULL, NULL);
+  }
+}
+
+/* flag of cell (i, j) computed from scratch */
+static int flag_cell2(const grid_t* G, int i, int j) {
+  const orc_problem* P = G->P;
+  if (P->tc_mode == 0) return 0;
+  if (P->tc_mode == 2) return 1;
+  /* a 3x3 work2_t window centred on (i, j) */
+  work2_t W;
+  W.nc = G->nc;
+  W.ex = 1 + 2 * R2G;  /* indices -R2G..R2G around the centre */
+  W.ey = W.ex;
+  size_t ncell = (size_t)W.ex * W.ey;
+  W.g0 = calloc(ncell * W.nc * 16, sizeof(double));
+  const int off[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+  for (int k = 0; k < 5; ++k)
+    g0_cell2(G, i + off[k][0], j + off[k][1], &W.g0[w2idx(&W, off[k][0], off[k][1]) * W.nc * 16]);
+  /* kxrcf_2d indexes relative to (0,0) of the window */
+  unsigned char f;
+  double num, den;
+  orc_problem Q = *P;
+  kxrcf_2d(&Q, &W, 0, 0, &f, &num, &den);
+  free(W.g0);
+  return f;
+}
+
+static void final_cell2(const grid_t* G, int i, int j, double* out /* nc x 16 */) {
+  if (!flag_cell2(G, i, j)) { g0_cell2(G, i, j, out); return; }
+  int fl[9];
+  for (int lab = 1; lab <= 9; ++lab) fl[lab - 1] = flag_cell2(G, i + lab_dx(lab), j + lab_dy(lab));
+  for (int c = 0; c < G->nc; ++c) {
+    double ub[9], vb[9], wb[9];
+    gather2(G, c, i, j, ub, vb, wb);
+    for (int lab = 1; lab <= 9; ++lab)
+      if (fl[lab - 1]) modified_vw2(G, c, i + lab_dx(lab), j + lab_dy(lab), &vb[lab - 1], &wb[lab - 1]);
+    orc_step1_2d(G->P, ub, vb, wb, &out[c * 16], NULL, NULL);
+  }
+}
+
+/* L(U) at the single cell (i, j) of a 2D grid (alpha: Lax-Friedrichs
+   constant for Burgers, ignored for Euler).  out: nc x 3. */
+int orc_residual_cell_2d(const orc_problem* P, const double* U, double alpha, int i, int j, double* out) {
+  init_1d();
+  init_2d();
+  grid_t G = {P, U, ncomp_of(P), 3};
+  int nc = G.nc;
+  double own[64], lef[64], rig[64], bot[64], top[64];
+  final_cell2(&G, i, j, own);
+  final_cell2(&G, i - 1, j, lef);
+  final_cell2(&G, i + 1, j, rig);
+  final_cell2(&G, i, j - 1, bot);
+  final_cell2(&G, i, j + 1, top);
+  double XL0[4] = {0}, XL1[4] = {0}, XR0[4] = {0}, XR1[4] = {0};
+  double YB0[4] = {0}, YB1[4] = {0}, YT0[4] = {0}, YT1[4] = {0};
+  for (int m = 0; m < 4; ++m) {
+    double a[4], b[4], f[4];
+    double wm = gl_weight(m), xm = gl_node(m);
+    for (int c = 0; c < nc; ++c) { a[c] = lef[c * 16 + 3 + 4 * m]; b[c] = own[c * 16 + 0 + 4 * m]; }
+    num_flux(P, a, b, 0, alpha, f);
+    for (int c = 0; c < nc; ++c) { XL0[c] += wm * f[c]; XL1[c] += wm * xm * f[c]; }
+    for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + 3 + 4 * m]; b[c] = rig[c * 16 + 0 + 4 * m]; }
+    num_flux(P, a, b, 0, alpha, f);
+    for (int c = 0; c < nc; ++c) { XR0[c] += wm * f[c]; XR1[c] += wm * xm * f[c]; }
+    for (int c = 0; c < nc; ++c) { a[c] = bot[c * 16 + m + 12]; b[c] = own[c * 16 + m]; }
+    num_flux(P, a, b, 1, alpha, f);
+    for (int c = 0; c < nc; ++c) { YB0[c] += wm * f[c]; YB1[c] += wm * xm * f[c]; }
+    for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + m + 12]; b[c] = top[c * 16 + m]; }
+    num_flux(P, a, b, 1, alpha, f);
+    for (int c = 0; c < nc; ++c) { YT0[c] += wm * f[c]; YT1[c] += wm * xm * f[c]; }
+  }
+  double F[4] = {0}, Gv[4] = {0};
+  for (int l = 0; l < 4; ++l)
+    for (int k = 0; k < 4; ++k) {
+      double pt[4], f[4], g[4];
+      for (int c = 0; c < nc; ++c) pt[c] = own[c * 16 + k + 4 * l];
+      if (P->system == 0) { f[0] = 0.5 * pt[0] * pt[0]; g[0] = f[0]; }
+      else { euler_flux(pt, nc, 0, P->gamma, f); euler_flux(pt, nc, 1, P->gamma, g); }
+      for (int c = 0; c < nc; ++c) {
+        F[c] += gl_weight(k) * gl_weight(l) * f[c];
+        Gv[c] += gl_weight(k) * gl_weight(l) * g[c];
+      }
+    }
+  for (int c = 0; c < nc; ++c) {
+    out[c * 3 + 0] = -(XR0[c] - XL0[c]) / P->dx - (YT0[c] - YB0[c]) / P->dy;
+    out[c * 3 + 1] = -(XR0[c] + XL0[c]) / (2.0 * P->dx) + F[c] / P->dx - (YT1[c] - YB1[c]) / P->dy;
+    out[c * 3 + 2] = -(XR1[c] - XL1[c]) / P->dx - (YT0[c] + YB0[c]) / (2.0 * P->dy) + Gv[c] / P->dy;
+  }
+  return 0;
+}
+
+/* Gauss-Lobatto nodes and weights of eq. (F), for the pins. */
+void orc_gl(double* x, double* w) {
+  for (int k = 0; k < 4; ++k) { x[k] = gl_node(k); w[k] = gl_weight(k); }
+}
+
+int orc_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

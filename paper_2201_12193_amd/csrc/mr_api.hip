@@ -1,0 +1,568 @@
+/* Host side of the MR-HWENO C ABI (include/mrhweno.h): validation,
+ * workspace layout, work lists, hipGraph capture of one SSP-RK3 step,
+ * state hand-back and the one-off probes (reconstruct / flag / residual). */
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mrhweno.h"
+#include "mr_types.h"
+
+extern "C" {
+hipError_t mr_launch_reduce(hipStream_t, mr_inst*, const mr_tile1*, int, int);
+hipError_t mr_launch_finalize(hipStream_t, mr_inst*, int, int);
+hipError_t mr_launch_summary(hipStream_t, int, int, mr_inst*, const mr_tile1*, int, int);
+hipError_t mr_launch_flags(hipStream_t, int, mr_inst*, const mr_tile1*, int, int);
+hipError_t mr_launch_stage1(hipStream_t, int, int, mr_inst*, const mr_tile1*, int, int, int);
+hipError_t mr_launch_stage2(hipStream_t, int, int, mr_inst*, const mr_tile2*, int, int, int);
+hipError_t mr_launch_values(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, double*);
+}
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kFHalo = 2;   /* flags: final values of cells -1..n need flags -2..n+1 */
+constexpr int kSHalo = 3;   /* summaries: flags of cells -2..n+1 need summaries -3..n+2 */
+constexpr int kMinRows = 8; /* smallest 2D strip height the work lists are sized for */
+
+thread_local std::string g_err;
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+int ncomp_of(const mrhweno_problem& p) { return p.flux == MRHWENO_BURGERS_LF ? 1 : (p.dim == 1 ? 3 : 4); }
+long long plane_of(const mrhweno_problem& p) { return (long long)p.nx * (p.dim == 2 ? p.ny : 1); }
+size_t state_bytes(const mrhweno_problem& p) { return sizeof(double) * ncomp_of(p) * (p.dim + 1) * plane_of(p); }
+int ext(int n, int h) { return n + 2 * h; }
+int fex(const mrhweno_problem& p) { return ext(p.nx, kFHalo); }
+int fey(const mrhweno_problem& p) { return p.dim == 2 ? ext(p.ny, kFHalo) : 1; }
+int sex(const mrhweno_problem& p) { return ext(p.nx, kSHalo); }
+int sey(const mrhweno_problem& p) { return p.dim == 2 ? ext(p.ny, kSHalo) : 1; }
+int nsumm(const mrhweno_problem& p) { return p.dim == 1 ? 5 : 9; }
+bool needs_summ(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_KXRCF || p.tc_mode == MRHWENO_TC_LEARNED; }
+int strip_cells(const mrhweno_problem& p) { return kBlock / ncomp_of(p); }   /* 2D strip width incl. ring */
+
+std::string validate(const mrhweno_problem& p) {
+  if (p.dim != 1 && p.dim != 2) return "dim must be 1 or 2";
+  if (p.nx < 8 || (p.dim == 2 && p.ny < 8)) return "grid must have at least 8 cells per direction";
+  if (!(p.x1 > p.x0) || (p.dim == 2 && !(p.y1 > p.y0))) return "empty domain";
+  if (p.flux != MRHWENO_BURGERS_LF && p.flux != MRHWENO_EULER_HLLC) return "unknown flux";
+  if (p.bc_x < 0 || p.bc_x > 1 || (p.dim == 2 && (p.bc_y < 0 || p.bc_y > 1))) return "unknown boundary condition";
+  if (p.flux == MRHWENO_EULER_HLLC && !(p.gamma_gas > 1.0)) return "gamma_gas must exceed 1";
+  if (!(p.cfl > 0.0) || !(p.t_final > 0.0)) return "cfl and t_final must be positive";
+  for (int l = 0; l < 4; ++l)
+    if (!(p.gamma_bar[l] > 0.0) || !std::isfinite(p.gamma_bar[l])) return "linear weights must be positive";
+  if (!(p.eps > 0.0)) return "eps must be positive";
+  if (p.tc_mode < 0 || p.tc_mode > 3) return "unknown troubled-cell mode";
+  if (p.beta_on != 0 && p.beta_on != 1) return "unknown beta_on";
+  if (p.dim == 2) {
+    const double dx = (p.x1 - p.x0) / p.nx, dy = (p.y1 - p.y0) / p.ny;
+    if (std::fabs(dx - dy) > 1e-12 * std::max(dx, dy)) return "2D cells must be square (dx == dy)";
+  }
+  if (plane_of(p) > (1ll << 31) - 1) return "grid too large";
+  return "";
+}
+
+/* workspace layout, computed identically for sizing and for creation */
+struct Layout {
+  size_t insts = 0, tiles1 = 0, tiles2 = 0, probe_tiles = 0, probe_aleph = 0, total = 0;
+  std::vector<size_t> buf1, buf2, fl0, fl1, summ;
+  size_t n_tiles1 = 0, n_tiles2 = 0, n_probe_tiles = 0;
+};
+
+int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+Layout layout(const mrhweno_problem* P, int n) {
+  Layout L;
+  size_t off = 0;
+  L.insts = off;
+  off += al(sizeof(mr_inst) * (n + 1));
+  /* per-cell work items: reduce (plane), summary (extended), flags (extended),
+     values (plane), 1D stage (block tiles) */
+  size_t t1 = 0, t2 = 0, tmax = 0;
+  for (int q = 0; q < n; ++q) {
+    const auto& p = P[q];
+    size_t a = ceil_div(plane_of(p), kBlock) + ceil_div((long long)sex(p) * sey(p), kBlock) +
+               ceil_div((long long)fex(p) * fey(p), kBlock) + ceil_div(plane_of(p), kBlock);
+    if (p.dim == 1) a += ceil_div(p.nx, kBlock - 2);
+    else t2 += (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows);
+    t1 += a;
+    tmax = std::max(tmax, a + (p.dim == 2 ? (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) : 0));
+  }
+  L.n_tiles1 = t1;
+  L.n_tiles2 = t2;
+  L.n_probe_tiles = tmax;
+  L.tiles1 = off;
+  off += al(sizeof(mr_tile1) * std::max<size_t>(t1, 1));
+  L.tiles2 = off;
+  off += al(sizeof(mr_tile2) * std::max<size_t>(t2, 1));
+  L.probe_tiles = off;
+  off += al(sizeof(mr_tile2) * (tmax + 32));
+  long long maxplane = 1;
+  for (int q = 0; q < n; ++q) maxplane = std::max(maxplane, plane_of(P[q]));
+  L.probe_aleph = off;
+  off += al(sizeof(double) * 2 * maxplane);
+  for (int q = 0; q < n; ++q) {
+    const auto& p = P[q];
+    L.buf1.push_back(off); off += al(state_bytes(p));
+    L.buf2.push_back(off); off += al(state_bytes(p));
+    L.fl0.push_back(off); off += al((size_t)fex(p) * fey(p));
+    L.fl1.push_back(off); off += al((size_t)fex(p) * fey(p));
+    L.summ.push_back(off);
+    if (needs_summ(p)) off += al(sizeof(double) * nsumm(p) * (size_t)sex(p) * sey(p));
+  }
+  L.total = off;
+  return L;
+}
+
+/* host-side description of one launch group (instances sharing a kernel) */
+struct Group {
+  int dim, nc, bp;
+  bool any_summ = false, any_lf = false;
+  std::vector<int> insts;
+  int t_summ = 0, n_summ = 0, t_flag = 0, n_flag = 0, t_st1 = 0, n_st1 = 0;
+  int t_st2 = 0, n_st2 = 0;
+};
+
+}  // namespace
+
+struct mrhweno_ctx {
+  int n = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Layout L;
+  std::vector<mrhweno_problem> probs;
+  std::vector<mr_inst> h;       /* host mirror of the descriptors */
+  mr_inst* d = nullptr;
+  mr_tile1* t1 = nullptr;
+  mr_tile2* t2 = nullptr;
+  int t_reduce = 0, n_reduce = 0;
+  std::vector<Group> groups;
+  std::vector<mr_tile1> h_t1;
+  std::vector<mr_tile2> h_t2;
+  int rows2 = 32, grid2 = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool any_lf = false;
+  std::string err;
+};
+
+static mrhweno_status fail(mrhweno_ctx* c, mrhweno_status s, const std::string& m) {
+  g_err = m;
+  if (c) c->err = m;
+  return s;
+}
+
+#define MR_CHECK(ctx, expr)                                                           \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(ctx, MRHWENO_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+static void fill_wconst(const mrhweno_problem& p, mr_wconst& W) {
+  double S[4];
+  double s = 0.0;
+  for (int l = 0; l < 4; ++l) { s += p.gamma_bar[l]; S[l] = s; }
+  for (int l = 0; l < 4; ++l) W.g4[l] = p.gamma_bar[l] / S[3];
+  for (int l = 0; l < 4; ++l) W.sg[l] = S[l] / p.gamma_bar[l];
+  for (int l = 0; l < 3; ++l) W.sgn[l] = S[l] / p.gamma_bar[l + 1];
+  W.eps = p.eps;
+}
+
+/* per-cell work items over `count` cells starting at 0 */
+static void add_cells(std::vector<mr_tile1>& v, int inst, long long count) {
+  for (long long s = 0; s < count; s += kBlock)
+    v.push_back(mr_tile1{inst, (int)s, (int)std::min<long long>(kBlock, count - s), 0});
+}
+
+static void build_lists(mrhweno_ctx* c) {
+  c->h_t1.clear();
+  c->h_t2.clear();
+  const int n = c->n;
+  c->t_reduce = 0;
+  for (int q = 0; q < n; ++q) add_cells(c->h_t1, q, plane_of(c->probs[q]));
+  c->n_reduce = (int)c->h_t1.size();
+  for (auto& g : c->groups) {
+    g.t_summ = (int)c->h_t1.size();
+    for (int q : g.insts)
+      if (needs_summ(c->probs[q])) add_cells(c->h_t1, q, (long long)sex(c->probs[q]) * sey(c->probs[q]));
+    g.n_summ = (int)c->h_t1.size() - g.t_summ;
+    g.t_flag = (int)c->h_t1.size();
+    for (int q : g.insts) add_cells(c->h_t1, q, (long long)fex(c->probs[q]) * fey(c->probs[q]));
+    g.n_flag = (int)c->h_t1.size() - g.t_flag;
+    g.t_st1 = (int)c->h_t1.size();
+    if (g.dim == 1)
+      for (int q : g.insts)
+        for (int s = 0; s < c->probs[q].nx; s += kBlock - 2)
+          c->h_t1.push_back(mr_tile1{q, s, std::min(kBlock - 2, c->probs[q].nx - s), 0});
+    g.n_st1 = (int)c->h_t1.size() - g.t_st1;
+    g.t_st2 = (int)c->h_t2.size();
+    if (g.dim == 2) {
+      /* largest instances first so the tail of the launch is short */
+      std::vector<int> order = g.insts;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return plane_of(c->probs[a]) > plane_of(c->probs[b]); });
+      for (int q : order) {
+        const auto& p = c->probs[q];
+        const int w = strip_cells(p) - 2;
+        const int rows = std::max(kMinRows, c->rows2);
+        for (int y0 = 0; y0 < p.ny; y0 += rows)
+          for (int x0 = 0; x0 < p.nx; x0 += w)
+            c->h_t2.push_back(mr_tile2{q, x0, y0, std::min(rows, p.ny - y0)});
+      }
+    }
+    g.n_st2 = (int)c->h_t2.size() - g.t_st2;
+  }
+}
+
+static mrhweno_status upload_lists(mrhweno_ctx* c) {
+  MR_CHECK(c, hipMemcpy(c->t1, c->h_t1.data(), sizeof(mr_tile1) * std::max<size_t>(c->h_t1.size(), 1) , hipMemcpyHostToDevice));
+  if (!c->h_t2.empty())
+    MR_CHECK(c, hipMemcpy(c->t2, c->h_t2.data(), sizeof(mr_tile2) * c->h_t2.size(), hipMemcpyHostToDevice));
+  return MRHWENO_OK;
+}
+
+/* Event hooks of the profiling mode: called between kernel classes. */
+struct mr_prof {
+  hipEvent_t ev[64];
+  int cls[64];
+  int n = 0;
+};
+
+static hipError_t mark(mrhweno_ctx* c, mr_prof* P, int cls) {
+  if (!P) return hipSuccess;
+  if (P->n >= 64) return hipErrorInvalidValue;
+  P->cls[P->n] = cls;
+  return hipEventRecord(P->ev[P->n++], c->stream);
+}
+
+/* the kernels of one SSP-RK3 step, in order; with P, an event is recorded
+   after every kernel class (class ids: 0 reduce/dt, 1 summary, 2 flags,
+   3 stage) */
+static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
+  hipError_t e;
+  hipStream_t s = c->stream;
+  if ((e = mark(c, P, -1)) != hipSuccess) return e;
+  if ((e = mr_launch_reduce(s, c->d, c->t1 + c->t_reduce, c->n_reduce, 0)) != hipSuccess) return e;
+  if ((e = mr_launch_finalize(s, c->d, c->n, 0)) != hipSuccess) return e;
+  if ((e = mark(c, P, 0)) != hipSuccess) return e;
+  for (int st = 0; st < 3; ++st) {
+    if (st > 0 && c->any_lf) {
+      if ((e = mr_launch_reduce(s, c->d, c->t1 + c->t_reduce, c->n_reduce, st)) != hipSuccess) return e;
+      if ((e = mark(c, P, 0)) != hipSuccess) return e;
+    }
+    bool any = false;
+    for (auto& g : c->groups)
+      if (g.any_summ) {
+        any = true;
+        if ((e = mr_launch_summary(s, g.dim, g.bp, c->d, c->t1 + g.t_summ, g.n_summ, st)) != hipSuccess) return e;
+      }
+    if (any && (e = mark(c, P, 1)) != hipSuccess) return e;
+    for (auto& g : c->groups)
+      if ((e = mr_launch_flags(s, g.dim, c->d, c->t1 + g.t_flag, g.n_flag, st)) != hipSuccess) return e;
+    if ((e = mark(c, P, 2)) != hipSuccess) return e;
+    for (auto& g : c->groups) {
+      if (g.dim == 1) e = mr_launch_stage1(s, g.nc, g.bp, c->d, c->t1 + g.t_st1, g.n_st1, st, 0);
+      else e = mr_launch_stage2(s, g.nc, g.bp, c->d, c->t2 + g.t_st2, g.n_st2, st, c->grid2);
+      if (e != hipSuccess) return e;
+    }
+    if ((e = mark(c, P, 3)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static mrhweno_status rebuild_graph(mrhweno_ctx* c) {
+  if (c->exec) { (void)hipGraphExecDestroy(c->exec); c->exec = nullptr; }
+  if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+  if (!c->stream) return MRHWENO_OK;   /* the legacy default stream cannot be captured */
+  MR_CHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = enqueue_step(c);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+  if (e != hipSuccess) return fail(c, MRHWENO_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+  if (e2 != hipSuccess) return fail(c, MRHWENO_ERR_DEVICE, std::string("end capture: ") + hipGetErrorString(e2));
+  c->graph = g;
+  MR_CHECK(c, hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0));
+  return MRHWENO_OK;
+}
+
+extern "C" {
+
+size_t mrhweno_workspace_bytes(const mrhweno_problem* probs, int n) {
+  if (!probs || n <= 0) return 0;
+  for (int q = 0; q < n; ++q)
+    if (!validate(probs[q]).empty()) return 0;
+  return layout(probs, n).total;
+}
+
+mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* moments_dev,
+                              void* workspace_dev, void* hip_stream, mrhweno_ctx** out) {
+  if (!out) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!probs || n <= 0 || !moments_dev || !workspace_dev)
+    return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL argument or no instances");
+  for (int q = 0; q < n; ++q) {
+    std::string m = validate(probs[q]);
+    if (!m.empty()) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "instance " + std::to_string(q) + ": " + m);
+    if (!moments_dev[q]) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL moments for instance " + std::to_string(q));
+    if ((reinterpret_cast<uintptr_t>(moments_dev[q]) & 7) != 0)
+      return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "moments must be 8-byte aligned");
+  }
+  if ((reinterpret_cast<uintptr_t>(workspace_dev) & 255) != 0)
+    return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  auto* c = new mrhweno_ctx();
+  c->n = n;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace_dev;
+  c->probs.assign(probs, probs + n);
+  c->L = layout(probs, n);
+  c->d = (mr_inst*)(c->ws + c->L.insts);
+  c->t1 = (mr_tile1*)(c->ws + c->L.tiles1);
+  c->t2 = (mr_tile2*)(c->ws + c->L.tiles2);
+  c->h.resize(n + 1);
+  for (int q = 0; q < n; ++q) {
+    const auto& p = probs[q];
+    mr_inst& I = c->h[q];
+    std::memset(&I, 0, sizeof I);
+    I.dim = p.dim; I.nx = p.nx; I.ny = p.dim == 2 ? p.ny : 1; I.nc = ncomp_of(p);
+    I.flux = p.flux; I.bcx = p.bc_x; I.bcy = p.dim == 2 ? p.bc_y : 0;
+    I.tc = p.tc_mode; I.beta_on = p.beta_on;
+    I.fhalo = kFHalo; I.shalo = kSHalo;
+    I.fex = fex(p); I.fey = fey(p); I.sex = sex(p); I.sey = sey(p);
+    I.plane = plane_of(p);
+    I.dx = (p.x1 - p.x0) / p.nx;
+    I.dy = p.dim == 2 ? (p.y1 - p.y0) / p.ny : 1.0;
+    I.gam = p.gamma_gas; I.cfl = p.cfl; I.t_final = p.t_final;
+    I.band_lo = 0.2; I.band_hi = 0.8;
+    fill_wconst(p, I.W);
+    I.buf[0] = (double*)moments_dev[q];
+    I.buf[1] = (double*)(c->ws + c->L.buf1[q]);
+    I.buf[2] = (double*)(c->ws + c->L.buf2[q]);
+    I.flags[0] = (unsigned char*)(c->ws + c->L.fl0[q]);
+    I.flags[1] = (unsigned char*)(c->ws + c->L.fl1[q]);
+    I.summ = needs_summ(p) ? (double*)(c->ws + c->L.summ[q]) : nullptr;
+    I.aleph = nullptr;
+    I.cur = 0;
+    if (p.flux == MRHWENO_BURGERS_LF) c->any_lf = true;
+  }
+  std::memset(&c->h[n], 0, sizeof(mr_inst));
+  /* launch groups */
+  for (int q = 0; q < n; ++q) {
+    const auto& p = probs[q];
+    const int nc = ncomp_of(p);
+    Group* gp = nullptr;
+    for (auto& g : c->groups)
+      if (g.dim == p.dim && g.nc == nc && g.bp == p.beta_on) gp = &g;
+    if (!gp) { c->groups.push_back(Group{p.dim, nc, p.beta_on}); gp = &c->groups.back(); }
+    gp->insts.push_back(q);
+    gp->any_summ |= needs_summ(p);
+  }
+  build_lists(c);
+  mrhweno_status st;
+  if (hipMemcpy(c->d, c->h.data(), sizeof(mr_inst) * (n + 1), hipMemcpyHostToDevice) != hipSuccess) {
+    delete c;
+    return fail(nullptr, MRHWENO_ERR_DEVICE, "descriptor upload failed");
+  }
+  if ((st = upload_lists(c)) != MRHWENO_OK || (st = rebuild_graph(c)) != MRHWENO_OK) {
+    std::string m = c->err;
+    mrhweno_destroy(c);
+    return fail(nullptr, st, m);
+  }
+  *out = c;
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_set_launch(mrhweno_ctx* c, int rows_2d, int grid_2d) {
+  if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
+  if (rows_2d < kMinRows || rows_2d > 4096 || grid_2d < 0)
+    return fail(c, MRHWENO_ERR_INVALID_ARG, "rows_2d must be in [8, 4096], grid_2d >= 0");
+  MR_CHECK(c, hipStreamSynchronize(c->stream));
+  c->rows2 = rows_2d;
+  c->grid2 = grid_2d;
+  build_lists(c);
+  mrhweno_status st = upload_lists(c);
+  if (st != MRHWENO_OK) return st;
+  return rebuild_graph(c);
+}
+
+mrhweno_status mrhweno_step(mrhweno_ctx* c, int nsteps) {
+  if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
+  if (nsteps < 0) return fail(c, MRHWENO_ERR_INVALID_ARG, "nsteps < 0");
+  for (int k = 0; k < nsteps; ++k) {
+    if (c->exec) MR_CHECK(c, hipGraphLaunch(c->exec, c->stream));
+    else MR_CHECK(c, enqueue_step(c));
+  }
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_profile(mrhweno_ctx* c, int nsteps, float* ms_out, int* launches_out) {
+  if (!c || !ms_out || nsteps < 0) return fail(c, MRHWENO_ERR_INVALID_ARG, "bad argument");
+  for (int k = 0; k < 4; ++k) { ms_out[k] = 0.0f; if (launches_out) launches_out[k] = 0; }
+  mr_prof P;
+  for (int k = 0; k < 64; ++k) MR_CHECK(c, hipEventCreate(&P.ev[k]));
+  mrhweno_status st = MRHWENO_OK;
+  for (int it = 0; it < nsteps && st == MRHWENO_OK; ++it) {
+    P.n = 0;
+    hipError_t e = enqueue_step(c, &P);
+    if (e != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, std::string("profile: ") + hipGetErrorString(e)); break; }
+    if (hipEventSynchronize(P.ev[P.n - 1]) != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, "event sync"); break; }
+    for (int k = 1; k < P.n; ++k) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, P.ev[k - 1], P.ev[k]) != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, "event time"); break; }
+      ms_out[P.cls[k]] += ms;
+      if (launches_out) launches_out[P.cls[k]] += 1;
+    }
+  }
+  for (int k = 0; k < 64; ++k) (void)hipEventDestroy(P.ev[k]);
+  return st;
+}
+
+static mrhweno_status pull(mrhweno_ctx* c) {
+  MR_CHECK(c, hipStreamSynchronize(c->stream));
+  MR_CHECK(c, hipMemcpy(c->h.data(), c->d, sizeof(mr_inst) * c->n, hipMemcpyDeviceToHost));
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_sync(mrhweno_ctx* c, double* t_out, long* steps_out) {
+  if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
+  mrhweno_status st = pull(c);
+  if (st != MRHWENO_OK) return st;
+  bool bad = false;
+  for (int q = 0; q < c->n; ++q) {
+    mr_inst& I = c->h[q];
+    if (I.cur != 0) {
+      MR_CHECK(c, hipMemcpyAsync(I.buf[0], I.buf[I.cur], state_bytes(c->probs[q]), hipMemcpyDeviceToDevice, c->stream));
+      I.cur = 0;
+      MR_CHECK(c, hipMemcpyAsync(&c->d[q].cur, &I.cur, sizeof(int), hipMemcpyHostToDevice, c->stream));
+      MR_CHECK(c, hipStreamSynchronize(c->stream));
+    }
+    if (t_out) t_out[q] = I.t;
+    if (steps_out) steps_out[q] = (long)I.steps;
+    bad |= I.err != 0;
+  }
+  if (bad) return fail(c, MRHWENO_ERR_NONPHYSICAL, "non-physical or non-finite state met; rolled back to the last good step");
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_set_time(mrhweno_ctx* c, int q, double t, long steps) {
+  if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
+  if (q < 0 || q >= c->n || !(t >= 0.0) || steps < 0) return fail(c, MRHWENO_ERR_INVALID_ARG, "bad instance, time or step count");
+  mrhweno_status st = pull(c);
+  if (st != MRHWENO_OK) return st;
+  c->h[q].t = t;
+  c->h[q].steps = steps;
+  c->h[q].err = 0;
+  c->h[q].rolled = 0;
+  MR_CHECK(c, hipMemcpy(&c->d[q], &c->h[q], sizeof(mr_inst), hipMemcpyHostToDevice));
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_last_dt(mrhweno_ctx* c, double* dt_out) {
+  if (!c || !dt_out) return fail(c, MRHWENO_ERR_INVALID_ARG, "NULL argument");
+  mrhweno_status st = pull(c);
+  if (st != MRHWENO_OK) return st;
+  for (int q = 0; q < c->n; ++q) dt_out[q] = c->h[q].dt;
+  return MRHWENO_OK;
+}
+
+/* kind: 0 = reconstruct, 1 = flag, 2 = residual */
+static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, void* flags, void* aleph, int kind) {
+  if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
+  if (q < 0 || q >= c->n || !U) return fail(c, MRHWENO_ERR_INVALID_ARG, "bad instance or NULL state");
+  if (kind != 1 && !out) return fail(c, MRHWENO_ERR_INVALID_ARG, "NULL output");
+  mrhweno_status st = pull(c);   /* the probe reuses the instance's scratch planes */
+  if (st != MRHWENO_OK) return st;
+  const auto& p = c->probs[q];
+  mr_inst I = c->h[q];
+  I.buf[0] = (double*)U;
+  I.cur = 0;
+  I.p_in[0] = (const double*)U;
+  I.p_un = (const double*)U;
+  I.p_out[0] = (double*)out;
+  I.active = 1; I.err = 0; I.rolled = 0;
+  I.amax[0] = I.amax[1] = 0ull;
+  I.lfa[0] = I.lfa[1] = I.lfa[2] = 0ull;
+  I.dt = 0.0;
+  double* al_buf = (double*)(c->ws + c->L.probe_aleph);
+  I.aleph = aleph ? al_buf : nullptr;
+  /* probe with tc = LEARNED falls back to KXRCF for the flags */
+  const int slot = c->n;
+  std::vector<mr_tile1> t1;
+  add_cells(t1, slot, plane_of(p));
+  const int n_red = (int)t1.size();
+  const int t_sum = (int)t1.size();
+  if (needs_summ(p)) add_cells(t1, slot, (long long)sex(p) * sey(p));
+  const int n_sum = (int)t1.size() - t_sum;
+  const int t_flg = (int)t1.size();
+  add_cells(t1, slot, (long long)fex(p) * fey(p));
+  const int n_flg = (int)t1.size() - t_flg;
+  const int t_val = (int)t1.size();
+  add_cells(t1, slot, plane_of(p));
+  const int n_val = (int)t1.size() - t_val;
+  const int t_st = (int)t1.size();
+  std::vector<mr_tile2> t2;
+  if (p.dim == 1) {
+    for (int s = 0; s < p.nx; s += kBlock - 2) t1.push_back(mr_tile1{slot, s, std::min(kBlock - 2, p.nx - s), 0});
+  } else {
+    const int w = strip_cells(p) - 2;
+    for (int y0 = 0; y0 < p.ny; y0 += 32)
+      for (int x0 = 0; x0 < p.nx; x0 += w) t2.push_back(mr_tile2{slot, x0, y0, std::min(32, p.ny - y0)});
+  }
+  const int n_st = (int)t1.size() - t_st;
+  mr_tile1* d1 = (mr_tile1*)(c->ws + c->L.probe_tiles);
+  if (t1.size() + t2.size() + 16 > c->L.n_probe_tiles + 32) return fail(c, MRHWENO_ERR_DEVICE, "probe list overflow");
+  /* the probe area holds the 1D list followed by the 2D list */
+  MR_CHECK(c, hipMemcpy(&c->d[slot], &I, sizeof(mr_inst), hipMemcpyHostToDevice));
+  MR_CHECK(c, hipMemcpy(d1, t1.data(), sizeof(mr_tile1) * t1.size(), hipMemcpyHostToDevice));
+  mr_tile2* d2 = (mr_tile2*)((char*)d1 + al(sizeof(mr_tile1) * t1.size()));
+  if (!t2.empty()) MR_CHECK(c, hipMemcpy(d2, t2.data(), sizeof(mr_tile2) * t2.size(), hipMemcpyHostToDevice));
+  hipStream_t s = c->stream;
+  MR_CHECK(c, mr_launch_reduce(s, c->d, d1, n_red, 0));
+  MR_CHECK(c, mr_launch_finalize(s, c->d + slot, 1, 1));
+  MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, c->d, d1 + t_sum, n_sum, 3));
+  MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));
+  const int nc = ncomp_of(p);
+  if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + t_val, n_val, (double*)out));
+  if (kind == 2) {
+    if (p.dim == 1) MR_CHECK(c, mr_launch_stage1(s, nc, p.beta_on, c->d, d1 + t_st, n_st, 3, 0));
+    else MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, c->d, d2, (int)t2.size(), 3, 0));
+  }
+  if (flags)
+    MR_CHECK(c, hipMemcpy2DAsync(flags, p.nx, I.flags[0] + (size_t)(p.dim == 2 ? kFHalo : 0) * I.fex + kFHalo, I.fex,
+                                 p.nx, p.dim == 2 ? p.ny : 1, hipMemcpyDeviceToDevice, s));
+  if (aleph)
+    MR_CHECK(c, hipMemcpyAsync(aleph, al_buf, sizeof(double) * 2 * plane_of(p), hipMemcpyDeviceToDevice, s));
+  MR_CHECK(c, hipStreamSynchronize(s));
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_reconstruct(mrhweno_ctx* c, int q, const void* U, void* gl, void* flags) {
+  return probe(c, q, U, gl, flags, nullptr, 0);
+}
+mrhweno_status mrhweno_flag(mrhweno_ctx* c, int q, const void* U, void* flags, void* aleph) {
+  if (!flags) return fail(c, MRHWENO_ERR_INVALID_ARG, "NULL flags");
+  return probe(c, q, U, nullptr, flags, aleph, 1);
+}
+mrhweno_status mrhweno_residual(mrhweno_ctx* c, int q, const void* U, void* R, void* flags) {
+  return probe(c, q, U, R, flags, nullptr, 2);
+}
+
+const char* mrhweno_last_error(const mrhweno_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_err.c_str();
+}
+
+void mrhweno_destroy(mrhweno_ctx* c) {
+  if (!c) return;
+  if (c->exec) (void)hipGraphExecDestroy(c->exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  delete c;
+}
+
+}  /* extern "C" */

@@ -1,0 +1,248 @@
+/* Device building blocks of the MR-HWENO operator (gfx950, FP64).
+ *
+ * Reconstruction (Step 1 of the 1D and 2D reconstruction algorithms),
+ * nonlinear weights, physical fluxes, HLLC and Lax-Friedrichs numerical
+ * fluxes, and ghost-cell indexing.  The linear parts (least-squares maps,
+ * smoothness-indicator quadratic forms, Gauss-Lobatto evaluation) come from
+ * recon_gen.h.
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include "mr_types.h"
+#include "recon_gen.h"
+
+#define MR_INL __device__ __forceinline__
+/* reconstruction and flux helpers also compile for the host, so that the
+   kernel arithmetic can be exercised in a CPU build */
+#define MR_HD __host__ __device__ __forceinline__
+
+/* Gauss-Lobatto weights and nodes on [-1/2, 1/2], eq. (F). */
+#define MR_W0 (1.0 / 12.0)
+#define MR_W1 (5.0 / 12.0)
+#define MR_S5 0x1.c9f25c5bfedd9p-3 /* sqrt(5)/10 */
+
+MR_INL double glw(int k) { return (k == 0 || k == 3) ? MR_W0 : MR_W1; }
+MR_INL double gln(int k) {
+  return k == 0 ? -0.5 : (k == 1 ? -MR_S5 : (k == 2 ? MR_S5 : 0.5));
+}
+
+/* ------------------------------------------------------------------ ghosts */
+/* Index of cell i in [0, n) under the boundary condition; *zero is set when
+ * the cell is a transmissive ghost (first moments vanish there).  Offsets up
+ * to one period either side are folded; anything further is clamped (such
+ * cells never feed an output). */
+MR_INL int mr_fold(int i, int n, int bc, bool* zero) {
+  if (i >= 0 && i < n) return i;
+  if (bc == 0) {
+    if (i < 0) i += n;
+    else i -= n;
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+  }
+  *zero = true;
+  return i < 0 ? 0 : n - 1;
+}
+
+/* ------------------------------------------------------------ nonlinear weights */
+/* 1D Step 1 for one component, data on cells i-1, i, i+1 -> 4 GL values. */
+template <bool BETA_P>
+MR_HD void mr_recon1d(double um, double u0, double up, double vm, double v0, double vp,
+                       const mr_wconst& W, double out[4]) {
+  double q2[3], q3[4], q4[6];
+  mr1_maps(um, u0, up, vm, v0, vp, q2, q3, q4);
+  double b2, b3, b4;
+  if (!BETA_P) {
+    b2 = mr1_beta_k2(q2);
+    b3 = mr1_beta_k3(q3);
+    b4 = mr1_beta_k5(q4);
+  } else {
+    /* p_l = (S_l q_l - S_{l-1} q_{l-1}) / gbar_l, eq. (p) */
+    double p2[3], p3[4], p4[6];
+    for (int k = 0; k < 3; ++k) p2[k] = W.sg[1] * q2[k] - (k == 0 ? W.sgn[0] * u0 : 0.0);
+    for (int k = 0; k < 4; ++k) p3[k] = W.sg[2] * q3[k] - (k < 3 ? W.sgn[1] * q2[k] : 0.0);
+    for (int k = 0; k < 6; ++k) p4[k] = W.sg[3] * q4[k] - (k < 4 ? W.sgn[2] * q3[k] : 0.0);
+    b2 = mr1_beta_k2(p2);
+    b3 = mr1_beta_k3(p3);
+    b4 = mr1_beta_k5(p4);
+  }
+  /* beta_1 from the two one-sided linear fits, eqs. (q1-LR)-(beta1) */
+  const double dL = u0 - um, dR = up - u0;
+  const double bL = dL * dL, bR = dR * dR;
+  const double tdiff = bR - bL;
+  const double tau1 = tdiff * tdiff;
+  const double wL = 0.5 * (1.0 + tau1 / (bL + W.eps));
+  const double wR = 0.5 * (1.0 + tau1 / (bR + W.eps));
+  const double dn = (wL * dL + wR * dR) / (wL + wR);
+  const double b1 = dn * dn;
+  /* eqs. (tau4), (non-linear-weight) */
+  double tau4 = (fabs(b4 - b1) + fabs(b4 - b2) + fabs(b4 - b3)) * (1.0 / 3.0);
+  tau4 = tau4 * tau4;
+  const double o1 = W.g4[0] * (1.0 + tau4 / (b1 + W.eps));
+  const double o2 = W.g4[1] * (1.0 + tau4 / (b2 + W.eps));
+  const double o3 = W.g4[2] * (1.0 + tau4 / (b3 + W.eps));
+  const double o4 = W.g4[3] * (1.0 + tau4 / (b4 + W.eps));
+  const double rs = 1.0 / (o1 + o2 + o3 + o4);
+  const double w1 = o1 * rs, w2 = o2 * rs, w3 = o3 * rs, w4 = o4 * rs;
+  /* u = sum_l w_l p_l = sum_l c_l q_l, eq. (re-p) */
+  const double c1 = w1 - w2 * W.sgn[0];
+  const double c2 = w2 * W.sg[1] - w3 * W.sgn[1];
+  const double c3 = w3 * W.sg[2] - w4 * W.sgn[2];
+  const double c4 = w4 * W.sg[3];
+  double C[6];
+  C[0] = c1 * u0 + c2 * q2[0] + c3 * q3[0] + c4 * q4[0];
+  C[1] = c2 * q2[1] + c3 * q3[1] + c4 * q4[1];
+  C[2] = c2 * q2[2] + c3 * q3[2] + c4 * q4[2];
+  C[3] = c3 * q3[3] + c4 * q4[3];
+  C[4] = c4 * q4[4];
+  C[5] = c4 * q4[5];
+  mr1_eval(C, out);
+}
+
+/* 2D Step 1 for one component; u/v/w indexed by stencil label - 1
+ * (label = 1 + (dx+1) + 3 (dy+1)).  out[k + 4 l] at (xi_k, eta_l). */
+template <bool BETA_P>
+MR_HD void mr_recon2d(const double u[9], const double v[9], const double w[9],
+                       const mr_wconst& W, double out[16]) {
+  double q2[6], q3[10], q4[21];
+  mr2_maps(u, v, w, q2, q3, q4);
+  double b2, b3, b4;
+  if (!BETA_P) {
+    b2 = mr2_beta_k2(q2);
+    b3 = mr2_beta_k3(q3);
+    b4 = mr2_beta_k5(q4);
+  } else {
+    double p2[6], p3[10], p4[21];
+    for (int k = 0; k < 6; ++k) p2[k] = W.sg[1] * q2[k] - (k == 0 ? W.sgn[0] * u[4] : 0.0);
+    for (int k = 0; k < 10; ++k) p3[k] = W.sg[2] * q3[k] - (k < 6 ? W.sgn[1] * q2[k] : 0.0);
+    for (int k = 0; k < 21; ++k) p4[k] = W.sg[3] * q4[k] - (k < 10 ? W.sgn[2] * q3[k] : 0.0);
+    b2 = mr2_beta_k2(p2);
+    b3 = mr2_beta_k3(p3);
+    b4 = mr2_beta_k5(p4);
+  }
+  /* beta_1 from the four three-cell linear fits, eqs. (2D-q1-1234)-(2D-beta1) */
+  const double u5 = u[4];
+  const double gxl = u5 - u[3], gxr = u[5] - u5, gyb = u5 - u[1], gyt = u[7] - u5;
+  const double xl2 = gxl * gxl, xr2 = gxr * gxr, yb2 = gyb * gyb, yt2 = gyt * gyt;
+  const double e11 = xl2 + yt2, e12 = xr2 + yt2, e13 = xr2 + yb2, e14 = xl2 + yb2;
+  double tau1 = (fabs(e11 - e12) + fabs(e11 - e13) + fabs(e11 - e14) + fabs(e12 - e13) +
+                 fabs(e12 - e14) + fabs(e13 - e14)) * (1.0 / 6.0);
+  tau1 = tau1 * tau1;
+  const double a11 = 0.25 * (1.0 + tau1 / (e11 + W.eps));
+  const double a12 = 0.25 * (1.0 + tau1 / (e12 + W.eps));
+  const double a13 = 0.25 * (1.0 + tau1 / (e13 + W.eps));
+  const double a14 = 0.25 * (1.0 + tau1 / (e14 + W.eps));
+  const double ra = 1.0 / (a11 + a12 + a13 + a14);
+  const double gx = ((a11 + a14) * gxl + (a12 + a13) * gxr) * ra;
+  const double gy = ((a11 + a12) * gyt + (a13 + a14) * gyb) * ra;
+  const double b1 = gx * gx + gy * gy;
+  double tau4 = (fabs(b4 - b1) + fabs(b4 - b2) + fabs(b4 - b3)) * (1.0 / 3.0);
+  tau4 = tau4 * tau4;
+  const double o1 = W.g4[0] * (1.0 + tau4 / (b1 + W.eps));
+  const double o2 = W.g4[1] * (1.0 + tau4 / (b2 + W.eps));
+  const double o3 = W.g4[2] * (1.0 + tau4 / (b3 + W.eps));
+  const double o4 = W.g4[3] * (1.0 + tau4 / (b4 + W.eps));
+  const double rs = 1.0 / (o1 + o2 + o3 + o4);
+  const double w1 = o1 * rs, w2 = o2 * rs, w3 = o3 * rs, w4 = o4 * rs;
+  const double c1 = w1 - w2 * W.sgn[0];
+  const double c2 = w2 * W.sg[1] - w3 * W.sgn[1];
+  const double c3 = w3 * W.sg[2] - w4 * W.sgn[2];
+  const double c4 = w4 * W.sg[3];
+  double C[21];
+  C[0] = c1 * u5 + c2 * q2[0] + c3 * q3[0] + c4 * q4[0];
+#pragma unroll
+  for (int k = 1; k < 6; ++k) C[k] = c2 * q2[k] + c3 * q3[k] + c4 * q4[k];
+#pragma unroll
+  for (int k = 6; k < 10; ++k) C[k] = c3 * q3[k] + c4 * q4[k];
+#pragma unroll
+  for (int k = 10; k < 21; ++k) C[k] = c4 * q4[k];
+  mr2_eval(C, out);
+}
+
+/* ------------------------------------------------------------------ fluxes */
+/* Euler pressure; NC = 3 (1D) or 4 (2D). */
+template <int NC>
+MR_INL double mr_pressure(const double* u, double gam) {
+  double m2 = u[1] * u[1];
+  if (NC == 4) m2 += u[2] * u[2];
+  return (gam - 1.0) * (u[NC - 1] - 0.5 * m2 / u[0]);
+}
+
+/* physical Euler flux in direction D (0 = x, 1 = y), eqs. (1D-Euler), (2D-Euler) */
+template <int NC, int D>
+MR_HD void mr_euler_flux(const double* u, double gam, double* f) {
+  const double r = 1.0 / u[0];
+  const double vn = u[1 + D] * r;
+  double m2 = u[1] * u[1];
+  if (NC == 4) m2 += u[2] * u[2];
+  const double p = (gam - 1.0) * (u[NC - 1] - 0.5 * m2 * r);
+  f[0] = u[1 + D];
+  f[1] = u[1] * vn;
+  if (NC == 4) f[2] = u[2] * vn;
+  f[1 + D] += p;
+  f[NC - 1] = vn * (u[NC - 1] + p);
+}
+
+/* HLLC flux of eqs. (f_HLLC), (COEF), (uLR_) with the printed PVRS star
+ * estimates; in 2D the normal direction D plays the role of mu and the
+ * tangential momentum is carried in the star state.  Branches in the order
+ * 0 <= sL, 0 <= s*, 0 <= sR, else. */
+template <int NC, int D>
+MR_HD void mr_hllc(const double* uL, const double* uR, double gam, double* f) {
+  constexpr int N = 1 + D;
+  constexpr int T = (NC == 4) ? 2 - D : 1;
+  const double rL = uL[0], rR = uR[0];
+  const double irL = 1.0 / rL, irR = 1.0 / rR;
+  const double muL = uL[N] * irL, muR = uR[N] * irR;
+  double m2L = uL[1] * uL[1], m2R = uR[1] * uR[1];
+  if (NC == 4) { m2L += uL[2] * uL[2]; m2R += uR[2] * uR[2]; }
+  const double EL = uL[NC - 1], ER = uR[NC - 1];
+  const double pL = (gam - 1.0) * (EL - 0.5 * m2L * irL);
+  const double pR = (gam - 1.0) * (ER - 0.5 * m2R * irR);
+  const double cL = sqrt(gam * pL * irL), cR = sqrt(gam * pR * irR);
+  const double rs = 0.5 * (rL + rR), cs = 0.5 * (cL + cR);
+  const double crs = cs * rs;
+  const double ps = 0.5 * (pL + pR + (muL - muR) * crs);
+  const double ss = 0.5 * (muL + muR + (pL - pR) / crs);
+  const double k1 = (gam + 1.0) / (2.0 * gam);
+  const double coefL = (ps <= pL) ? 1.0 : sqrt(1.0 + k1 * (ps / pL - 1.0));
+  const double coefR = (ps <= pR) ? 1.0 : sqrt(1.0 + k1 * (ps / pR - 1.0));
+  const double sL = muL - cL * coefL, sR = muR + cR * coefR;
+  /* ordered branch chain: 0 <= sL -> f_L; 0 <= s* -> f*_L; 0 <= sR -> f*_R; f_R */
+  const int br = (0.0 <= sL) ? 0 : ((0.0 <= ss) ? 1 : ((0.0 <= sR) ? 2 : 3));
+  const bool left = br <= 1;
+  const double* uK = left ? uL : uR;
+  const double sK = left ? sL : sR;
+  const double muK = left ? muL : muR;
+  const double rK = left ? rL : rR;
+  const double irK = left ? irL : irR;
+  const double pK = left ? pL : pR;
+  const double EK = left ? EL : ER;
+  double fK[NC];
+  fK[0] = uK[N];
+  fK[1] = uK[1] * muK;
+  if (NC == 4) fK[2] = uK[2] * muK;
+  fK[N] += pK;
+  fK[NC - 1] = muK * (EK + pK);
+  if (br == 0 || br == 3) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) f[c] = fK[c];
+    return;
+  }
+  const double dsK = sK - muK;
+  const double fac = rK * dsK / (sK - ss);
+  double us[NC];
+  us[0] = fac;
+  us[N] = fac * ss;
+  if (NC == 4) us[T] = fac * (uK[T] * irK);
+  us[NC - 1] = fac * (EK * irK + (ss - muK) * (ss + pK / (rK * dsK)));
+#pragma unroll
+  for (int c = 0; c < NC; ++c) f[c] = fK[c] + sK * (us[c] - uK[c]);
+}
+
+/* Burgers' f(u) = u^2/2 with global Lax-Friedrichs. */
+MR_HD double mr_lf(double a, double b, double alpha) {
+  return 0.5 * (0.5 * a * a + 0.5 * b * b - alpha * (b - a));
+}
+
+/* bits <-> double for order-preserving max of non-negative doubles */
+MR_INL unsigned long long mr_dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
+MR_INL double mr_bitsd(unsigned long long b) { return __longlong_as_double((long long)b); }

@@ -1,0 +1,208 @@
+"""Python binding of libmrhweno.so (argument marshalling only).
+
+Every step of the scheme runs in the library's HIP kernels; PyTorch only
+provides device memory (tensors) and the HIP stream.  The names follow the
+C ABI in include/mrhweno.h.  There is no fallback: if the shared library is
+missing or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import List, Optional, Sequence, Tuple
+
+from .inputs import Problem
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmrhweno.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_UNSUPPORTED = -2
+ERR_DEVICE = -3
+ERR_NONPHYSICAL = -4
+
+EXPORTS = ["mrhweno_workspace_bytes", "mrhweno_create", "mrhweno_step", "mrhweno_sync",
+           "mrhweno_set_time", "mrhweno_last_dt", "mrhweno_reconstruct", "mrhweno_flag",
+           "mrhweno_residual", "mrhweno_set_launch", "mrhweno_profile", "mrhweno_last_error",
+           "mrhweno_destroy"]
+
+
+class MrProblem(C.Structure):
+    _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
+                ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
+                ("bc_x", C.c_int), ("bc_y", C.c_int), ("flux", C.c_int),
+                ("gamma_gas", C.c_double), ("cfl", C.c_double), ("t_final", C.c_double),
+                ("gamma_bar", C.c_double * 4), ("eps", C.c_double),
+                ("tc_mode", C.c_int), ("beta_on", C.c_int)]
+
+
+def to_c(p: Problem) -> MrProblem:
+    c = MrProblem()
+    c.dim, c.nx, c.ny = p.dim, p.nx, (p.ny if p.dim == 2 else 1)
+    c.x0, c.x1, c.y0, c.y1 = p.x0, p.x1, p.y0, p.y1
+    c.bc_x, c.bc_y, c.flux = p.bc_x, p.bc_y, p.system
+    c.gamma_gas, c.cfl = p.gamma, p.cfl
+    c.t_final = p.t_final if math.isfinite(p.t_final) else float("inf")
+    for k in range(4):
+        c.gamma_bar[k] = p.gbar[k]
+    c.eps, c.tc_mode, c.beta_on = p.eps, p.tc_mode, p.beta_on
+    return c
+
+
+_lib = None
+
+
+class MrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mrhweno status {status}: {msg}")
+        self.status = status
+
+
+def lib():
+    """Load libmrhweno.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        vp, PP = C.c_void_p, C.POINTER(MrProblem)
+        L.mrhweno_workspace_bytes.argtypes = [PP, C.c_int]
+        L.mrhweno_workspace_bytes.restype = C.c_size_t
+        L.mrhweno_create.argtypes = [PP, C.c_int, C.POINTER(vp), vp, vp, C.POINTER(vp)]
+        L.mrhweno_step.argtypes = [vp, C.c_int]
+        L.mrhweno_sync.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_long)]
+        L.mrhweno_set_time.argtypes = [vp, C.c_int, C.c_double, C.c_long]
+        L.mrhweno_last_dt.argtypes = [vp, C.POINTER(C.c_double)]
+        L.mrhweno_reconstruct.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.mrhweno_flag.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.mrhweno_residual.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.mrhweno_set_launch.argtypes = [vp, C.c_int, C.c_int]
+        L.mrhweno_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int)]
+        L.mrhweno_last_error.argtypes = [vp]
+        L.mrhweno_last_error.restype = C.c_char_p
+        L.mrhweno_destroy.argtypes = [vp]
+        L.mrhweno_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _check(ctx, status: int) -> None:
+    if status != OK:
+        msg = lib().mrhweno_last_error(ctx)
+        raise MrError(status, msg.decode() if msg else "")
+
+
+def workspace_bytes(problems: Sequence[Problem]) -> int:
+    arr = (MrProblem * len(problems))(*[to_c(p) for p in problems])
+    return int(lib().mrhweno_workspace_bytes(arr, len(problems)))
+
+
+class Solver:
+    """A batch of instances advanced together (mrhweno_create .. destroy).
+
+    moments: list of float64 CUDA tensors, one per problem, with the layout
+    Problem.shape(); they are read and written in place (the current state
+    is handed back by sync())."""
+
+    def __init__(self, problems: Sequence[Problem], moments, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the MR-HWENO library runs on the device only")
+        self.problems = list(problems)
+        self.moments = list(moments)
+        for p, m in zip(self.problems, self.moments):
+            if m.dtype != torch.float64 or not m.is_cuda or not m.is_contiguous() or tuple(m.shape) != p.shape():
+                raise ValueError("moments must be contiguous float64 CUDA tensors of shape Problem.shape()")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        n = len(self.problems)
+        self._cp = (MrProblem * n)(*[to_c(p) for p in self.problems])
+        nbytes = int(lib().mrhweno_workspace_bytes(self._cp, n))
+        if nbytes == 0:
+            raise MrError(ERR_INVALID_ARG, lib().mrhweno_last_error(None).decode())
+        # 256-byte aligned device workspace owned by torch
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.moments[0].device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        ptrs = (C.c_void_p * n)(*[m.data_ptr() for m in self.moments])
+        ctx = C.c_void_p()
+        torch.cuda.synchronize()
+        _check(None, lib().mrhweno_create(self._cp, n, ptrs, C.c_void_p(self._ws_ptr),
+                                          C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+        self.ctx = ctx
+
+    def step(self, nsteps: int = 1) -> None:
+        _check(self.ctx, lib().mrhweno_step(self.ctx, int(nsteps)))
+
+    def sync(self, raise_on_error: bool = True) -> Tuple[List[float], List[int], int]:
+        n = len(self.problems)
+        t = (C.c_double * n)()
+        s = (C.c_long * n)()
+        st = lib().mrhweno_sync(self.ctx, t, s)
+        if st != OK and (raise_on_error or st != ERR_NONPHYSICAL):
+            _check(self.ctx, st)
+        return list(t), list(s), st
+
+    def set_time(self, instance: int, t: float, steps: int) -> None:
+        _check(self.ctx, lib().mrhweno_set_time(self.ctx, instance, float(t), int(steps)))
+
+    def last_dt(self) -> List[float]:
+        n = len(self.problems)
+        d = (C.c_double * n)()
+        _check(self.ctx, lib().mrhweno_last_dt(self.ctx, d))
+        return list(d)
+
+    def set_launch(self, rows_2d: int, grid_2d: int = 0) -> None:
+        _check(self.ctx, lib().mrhweno_set_launch(self.ctx, int(rows_2d), int(grid_2d)))
+
+    def profile(self, nsteps: int):
+        """Advance nsteps with per-kernel-class HIP event timing.  Returns
+        (ms[4], launches[4]) for [reduce/dt, summary, flags, stage]."""
+        ms = (C.c_float * 4)()
+        nl = (C.c_int * 4)()
+        _check(self.ctx, lib().mrhweno_profile(self.ctx, int(nsteps), ms, nl))
+        return list(ms), list(nl)
+
+    # -------------------------------------------------------------- probes
+    def reconstruct(self, instance: int, U):
+        import torch
+        torch.cuda.synchronize()
+        p = self.problems[instance]
+        npt = 4 if p.dim == 1 else 16
+        gl = torch.empty((p.ncomp, npt) + p.shape()[2:], dtype=torch.float64, device=U.device)
+        fl = torch.empty(p.shape()[2:], dtype=torch.uint8, device=U.device)
+        _check(self.ctx, lib().mrhweno_reconstruct(self.ctx, instance, C.c_void_p(U.data_ptr()),
+                                                   C.c_void_p(gl.data_ptr()), C.c_void_p(fl.data_ptr())))
+        return gl, fl
+
+    def flag(self, instance: int, U):
+        import torch
+        torch.cuda.synchronize()
+        p = self.problems[instance]
+        fl = torch.empty(p.shape()[2:], dtype=torch.uint8, device=U.device)
+        al = torch.empty(p.shape()[2:] + (2,), dtype=torch.float64, device=U.device)
+        _check(self.ctx, lib().mrhweno_flag(self.ctx, instance, C.c_void_p(U.data_ptr()),
+                                            C.c_void_p(fl.data_ptr()), C.c_void_p(al.data_ptr())))
+        return fl, al
+
+    def residual(self, instance: int, U):
+        import torch
+        torch.cuda.synchronize()
+        p = self.problems[instance]
+        R = torch.empty(p.shape(), dtype=torch.float64, device=U.device)
+        fl = torch.empty(p.shape()[2:], dtype=torch.uint8, device=U.device)
+        _check(self.ctx, lib().mrhweno_residual(self.ctx, instance, C.c_void_p(U.data_ptr()),
+                                                C.c_void_p(R.data_ptr()), C.c_void_p(fl.data_ptr())))
+        return R, fl
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            lib().mrhweno_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,55 @@
+"""The C-ABI library loads and exports every entry point include/mrhweno.h
+declares; host-side argument validation works without a GPU."""
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+from paper_2201_12193_amd import inputs as I
+from paper_2201_12193_amd import mrhweno as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mrhweno.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mrhweno_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_names():
+    assert _declared() == sorted(M.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = M.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_workspace_bytes_validates_problems():
+    good = I.Problem(dim=2, nx=64, ny=64)
+    assert M.workspace_bytes([good]) > 0
+    bad = [I.Problem(dim=3, nx=64), I.Problem(dim=2, nx=4, ny=64), I.Problem(dim=2, nx=64, ny=32),
+           good.replace(cfl=0.0), good.replace(gbar=(1, -1, 1, 1)), good.replace(eps=0.0),
+           good.replace(tc_mode=7), I.Problem(dim=1, nx=64, gamma=1.0)]
+    for b in bad:
+        assert M.workspace_bytes([b]) == 0, b
+    assert M.workspace_bytes([good, bad[0]]) == 0
+    # the workspace grows with the batch
+    assert M.workspace_bytes([good, good]) > M.workspace_bytes([good])
+
+
+def test_create_rejects_bad_arguments_on_the_host():
+    lib = M.lib()
+    ctx = C.c_void_p()
+    p = (M.MrProblem * 1)(M.to_c(I.Problem(dim=1, nx=64)))
+    st = lib.mrhweno_create(p, 1, None, None, None, C.byref(ctx))
+    assert st == M.ERR_INVALID_ARG and not ctx.value
+    assert b"NULL" in lib.mrhweno_last_error(None)
+    ptrs = (C.c_void_p * 1)(C.c_void_p(0x1000))
+    st = lib.mrhweno_create(p, 1, ptrs, C.c_void_p(0x1001), None, C.byref(ctx))   # misaligned workspace
+    assert st == M.ERR_INVALID_ARG
+    assert lib.mrhweno_step(None, 1) == M.ERR_INVALID_ARG

@@ -1,0 +1,152 @@
+"""GPU (through the C ABI) vs CPU oracle, element by element on seeded inputs.
+
+Tolerances: FP64 values within 1e-12 of the component's zeroth-moment scale
+per step (residuals: the same bound divided by the CFL time step); troubled-
+cell flags bit-exact except at near-ties of the KXRCF test, which must stay
+below a handful and are reported."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_12193_amd import inputs as I
+from tests.parity_util import comp_scale, rel_state_err, flag_mismatch
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def _solver(prob, U):
+    import torch
+    from paper_2201_12193_amd.mrhweno import Solver
+    Ut = torch.from_numpy(np.ascontiguousarray(U)).to(_dev())
+    return Solver([prob], [Ut]), Ut
+
+
+def _cases():
+    out = []
+    prob, U, _ = I.burgers_smooth_1d(seed=3, n=200)
+    out.append(("burgers1d_n200", prob, U))
+    prob, U, _ = I.euler_riemann_1d(seed=5, n=1000)
+    out.append(("euler1d_riemann_n1000", prob, U))
+    prob, U, _ = I.euler_quadrants_2d(seed=7, n=70, nq=2)
+    out.append(("euler2d_quadrants_70", prob, U))
+    prob, U = I.example_burgers_2d(66)
+    out.append(("burgers2d_66", prob, U))
+    return out
+
+
+CASES = _cases()
+
+
+def _advance_oracle(prob, U, steps):
+    for _ in range(steps):
+        U = oracle.rk3_step(prob, U, oracle.dt(prob, U))
+    return U
+
+
+@pytest.mark.parametrize("name,prob,U", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("tc", [I.TC_KXRCF, I.TC_ALL, I.TC_NONE])
+def test_residual_and_reconstruct(name, prob, U, tc):
+    prob = prob.replace(tc_mode=tc)
+    # a developed state with troubled cells: a few oracle steps first
+    U = _advance_oracle(prob, U, 3 if prob.dim == 2 else 10)
+    s, Ut = _solver(prob, U)
+    import torch
+    Uin = torch.from_numpy(U).to(_dev())
+    R, fl = s.residual(0, Uin)
+    gl, fl2 = s.reconstruct(0, Uin)
+    fl3, al = s.flag(0, Uin)
+    R, fl, gl, fl2, fl3 = R.cpu().numpy(), fl.cpu().numpy(), gl.cpu().numpy(), fl2.cpu().numpy(), fl3.cpu().numpy()
+    Lref, flref = oracle.residual(prob, U)
+    glref, flref2, num, den = oracle.reconstruct(prob, U)
+    sc = comp_scale(prob, U)
+    dt = oracle.dt(prob, U)
+    bad, ties = flag_mismatch(fl, flref, num, den)
+    assert bad == 0 and ties <= 2, (bad, ties)
+    assert np.array_equal(fl, fl2) and np.array_equal(fl, fl3)
+    if tc == I.TC_KXRCF:
+        al = al.cpu().numpy()
+        # the KXRCF ratio numerator/denominator agree with the oracle
+        assert np.allclose(al[..., 1], den, rtol=1e-12, atol=1e-300)
+        # |J| is a cancellation of O(1) face values (times dy in 2D)
+        jscale = sc[0] * (prob.dy if prob.dim == 2 else 1.0)
+        assert np.allclose(al[..., 0], num, rtol=0, atol=1e-12 * jscale)
+    dgl = np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc
+    assert dgl.max() <= TOL, dgl
+    dR = np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)
+    assert dR.max() <= TOL, dR
+    s.close()
+
+
+@pytest.mark.parametrize("name,prob,U", CASES, ids=[c[0] for c in CASES])
+def test_steps_per_step_parity(name, prob, U):
+    """Every step from the GPU's own state: GPU step vs oracle step with the
+    GPU's dt (dt itself must equal the oracle's bit for bit)."""
+    s, Ut = _solver(prob, U)
+    sc = comp_scale(prob, U)
+    nsteps = 12 if prob.dim == 1 else 4
+    prev = U.copy()
+    for k in range(nsteps):
+        s.step(1)
+        dt = s.last_dt()[0]
+        s.sync()
+        got = Ut.cpu().numpy()
+        assert dt == oracle.dt(prob, prev), (k, dt, oracle.dt(prob, prev))
+        ref = oracle.rk3_step(prob, prev, dt)
+        e = rel_state_err(prob, got, ref, sc)
+        assert e <= TOL, (k, e)
+        prev = got
+    s.close()
+
+
+def test_dt_bitwise_and_time_clipping():
+    prob, U, _ = I.burgers_smooth_1d(seed=11, n=200)
+    s, Ut = _solver(prob, U)
+    s.step(1)
+    assert s.last_dt()[0] == oracle.dt(prob, U)
+    # run to the end: the final step is clipped so that t == t_final exactly
+    s.step(200)
+    t, steps, _ = s.sync()
+    assert t[0] == prob.t_final
+    n_before = steps[0]
+    s.step(3)  # no-ops once t == t_final
+    t2, steps2, _ = s.sync()
+    assert steps2[0] == n_before and t2[0] == prob.t_final
+    s.close()
+
+
+def test_beta_on_p_switch():
+    prob, U, _ = I.euler_quadrants_2d(seed=9, n=40, nq=2)
+    prob = prob.replace(beta_on=I.BETA_ON_P)
+    import torch
+    s, Ut = _solver(prob, U)
+    R, fl = s.residual(0, torch.from_numpy(U).to(_dev()))
+    Lref, flref = oracle.residual(prob, U)
+    sc = comp_scale(prob, U)
+    dR = np.abs(R.cpu().numpy() - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / oracle.dt(prob, U))
+    assert dR.max() <= TOL
+    s.close()
+
+
+def test_transmissive_2d():
+    prob, U, _ = I.euler_quadrants_2d(seed=13, n=40, nq=2)
+    prob = prob.replace(bc_x=I.TRANSMISSIVE, bc_y=I.TRANSMISSIVE)
+    s, Ut = _solver(prob, U)
+    sc = comp_scale(prob, U)
+    prev = U.copy()
+    for k in range(3):
+        s.step(1)
+        dt = s.last_dt()[0]
+        s.sync()
+        got = Ut.cpu().numpy()
+        ref = oracle.rk3_step(prob, prev, dt)
+        assert rel_state_err(prob, got, ref, sc) <= TOL
+        prev = got
+    s.close()
