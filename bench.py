@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2048)
     ap.add_argument("--rows", type=int, default=0, help="2D strip height (0: autotuned/default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     return ap.parse_args()
 
 
@@ -91,6 +93,14 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     t, steps, _ = s.sync()
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ncell = prob.ncell
     cell_updates = ncell * 3 * args.steps
     value = cell_updates / wall

@@ -339,6 +339,8 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     I.dx = (p.x1 - p.x0) / p.nx;
     I.dy = p.dim == 2 ? (p.y1 - p.y0) / p.ny : 1.0;
     I.gam = p.gamma_gas; I.cfl = p.cfl; I.t_final = p.t_final;
+    I.rdx = 1.0 / I.dx;
+    I.rdy = 1.0 / I.dy;
     I.band_lo = 0.2; I.band_hi = 0.8;
     fill_wconst(p, I.W);
     I.buf[0] = (double*)moments_dev[q];

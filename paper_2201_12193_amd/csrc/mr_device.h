@@ -64,22 +64,26 @@ MR_HD void mr_recon1d(double um, double u0, double up, double vm, double v0, dou
     b3 = mr1_beta_k3(p3);
     b4 = mr1_beta_k5(p4);
   }
-  /* beta_1 from the two one-sided linear fits, eqs. (q1-LR)-(beta1) */
+  /* beta_1 from the two one-sided linear fits, eqs. (q1-LR)-(beta1).
+     With d = beta + eps, gamma (1 + tau/d) normalised over the set equals
+     gamma (d + tau) prod_{other} d normalised: one division per set. */
   const double dL = u0 - um, dR = up - u0;
   const double bL = dL * dL, bR = dR * dR;
   const double tdiff = bR - bL;
   const double tau1 = tdiff * tdiff;
-  const double wL = 0.5 * (1.0 + tau1 / (bL + W.eps));
-  const double wR = 0.5 * (1.0 + tau1 / (bR + W.eps));
-  const double dn = (wL * dL + wR * dR) / (wL + wR);
+  const double eL = bL + W.eps, eR = bR + W.eps;
+  const double aL = (eL + tau1) * eR, aR = (eR + tau1) * eL;
+  const double dn = (aL * dL + aR * dR) / (aL + aR);
   const double b1 = dn * dn;
   /* eqs. (tau4), (non-linear-weight) */
   double tau4 = (fabs(b4 - b1) + fabs(b4 - b2) + fabs(b4 - b3)) * (1.0 / 3.0);
   tau4 = tau4 * tau4;
-  const double o1 = W.g4[0] * (1.0 + tau4 / (b1 + W.eps));
-  const double o2 = W.g4[1] * (1.0 + tau4 / (b2 + W.eps));
-  const double o3 = W.g4[2] * (1.0 + tau4 / (b3 + W.eps));
-  const double o4 = W.g4[3] * (1.0 + tau4 / (b4 + W.eps));
+  const double d1 = b1 + W.eps, d2 = b2 + W.eps, d3 = b3 + W.eps, d4 = b4 + W.eps;
+  const double p12 = d1 * d2, p34 = d3 * d4;
+  const double o1 = W.g4[0] * (d1 + tau4) * (d2 * p34);
+  const double o2 = W.g4[1] * (d2 + tau4) * (d1 * p34);
+  const double o3 = W.g4[2] * (d3 + tau4) * (p12 * d4);
+  const double o4 = W.g4[3] * (d4 + tau4) * (p12 * d3);
   const double rs = 1.0 / (o1 + o2 + o3 + o4);
   const double w1 = o1 * rs, w2 = o2 * rs, w3 = o3 * rs, w4 = o4 * rs;
   /* u = sum_l w_l p_l = sum_l c_l q_l, eq. (re-p) */
@@ -126,20 +130,25 @@ MR_HD void mr_recon2d(const double u[9], const double v[9], const double w[9],
   double tau1 = (fabs(e11 - e12) + fabs(e11 - e13) + fabs(e11 - e14) + fabs(e12 - e13) +
                  fabs(e12 - e14) + fabs(e13 - e14)) * (1.0 / 6.0);
   tau1 = tau1 * tau1;
-  const double a11 = 0.25 * (1.0 + tau1 / (e11 + W.eps));
-  const double a12 = 0.25 * (1.0 + tau1 / (e12 + W.eps));
-  const double a13 = 0.25 * (1.0 + tau1 / (e13 + W.eps));
-  const double a14 = 0.25 * (1.0 + tau1 / (e14 + W.eps));
+  /* normalised 1/4 (1 + tau1 / d_k) with one division (see the 1D case) */
+  const double f1 = e11 + W.eps, f2 = e12 + W.eps, f3 = e13 + W.eps, f4 = e14 + W.eps;
+  const double r12 = f1 * f2, r34 = f3 * f4;
+  const double a11 = (f1 + tau1) * (f2 * r34);
+  const double a12 = (f2 + tau1) * (f1 * r34);
+  const double a13 = (f3 + tau1) * (r12 * f4);
+  const double a14 = (f4 + tau1) * (r12 * f3);
   const double ra = 1.0 / (a11 + a12 + a13 + a14);
   const double gx = ((a11 + a14) * gxl + (a12 + a13) * gxr) * ra;
   const double gy = ((a11 + a12) * gyt + (a13 + a14) * gyb) * ra;
   const double b1 = gx * gx + gy * gy;
   double tau4 = (fabs(b4 - b1) + fabs(b4 - b2) + fabs(b4 - b3)) * (1.0 / 3.0);
   tau4 = tau4 * tau4;
-  const double o1 = W.g4[0] * (1.0 + tau4 / (b1 + W.eps));
-  const double o2 = W.g4[1] * (1.0 + tau4 / (b2 + W.eps));
-  const double o3 = W.g4[2] * (1.0 + tau4 / (b3 + W.eps));
-  const double o4 = W.g4[3] * (1.0 + tau4 / (b4 + W.eps));
+  const double d1 = b1 + W.eps, d2 = b2 + W.eps, d3 = b3 + W.eps, d4 = b4 + W.eps;
+  const double p12 = d1 * d2, p34 = d3 * d4;
+  const double o1 = W.g4[0] * (d1 + tau4) * (d2 * p34);
+  const double o2 = W.g4[1] * (d2 + tau4) * (d1 * p34);
+  const double o3 = W.g4[2] * (d3 + tau4) * (p12 * d4);
+  const double o4 = W.g4[3] * (d4 + tau4) * (p12 * d3);
   const double rs = 1.0 / (o1 + o2 + o3 + o4);
   const double w1 = o1 * rs, w2 = o2 * rs, w3 = o3 * rs, w4 = o4 * rs;
   const double c1 = w1 - w2 * W.sgn[0];
@@ -181,6 +190,15 @@ MR_HD void mr_euler_flux(const double* u, double gam, double* f) {
   f[NC - 1] = vn * (u[NC - 1] + p);
 }
 
+/* physical fluxes f (x) and g (y) of the 2D Euler equations at one point */
+MR_HD void mr_euler_fg(const double* u, double gam, double* f, double* g) {
+  const double r = 1.0 / u[0];
+  const double vx = u[1] * r, vy = u[2] * r;
+  const double p = (gam - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) * r);
+  f[0] = u[1]; f[1] = u[1] * vx + p; f[2] = u[2] * vx; f[3] = vx * (u[3] + p);
+  g[0] = u[2]; g[1] = u[1] * vy; g[2] = u[2] * vy + p; g[3] = vy * (u[3] + p);
+}
+
 /* HLLC flux of eqs. (f_HLLC), (COEF), (uLR_) with the printed PVRS star
  * estimates; in 2D the normal direction D plays the role of mu and the
  * tangential momentum is carried in the star state.  Branches in the order
@@ -201,7 +219,7 @@ MR_HD void mr_hllc(const double* uL, const double* uR, double gam, double* f) {
   const double rs = 0.5 * (rL + rR), cs = 0.5 * (cL + cR);
   const double crs = cs * rs;
   const double ps = 0.5 * (pL + pR + (muL - muR) * crs);
-  const double ss = 0.5 * (muL + muR + (pL - pR) / crs);
+  const double ss = 0.5 * (muL + muR + (pL - pR) / crs);   /* s* of the printed PVRS */
   const double k1 = (gam + 1.0) / (2.0 * gam);
   const double coefL = (ps <= pL) ? 1.0 : sqrt(1.0 + k1 * (ps / pL - 1.0));
   const double coefR = (ps <= pR) ? 1.0 : sqrt(1.0 + k1 * (ps / pR - 1.0));
@@ -228,12 +246,16 @@ MR_HD void mr_hllc(const double* uL, const double* uR, double gam, double* f) {
     return;
   }
   const double dsK = sK - muK;
-  const double fac = rK * dsK / (sK - ss);
+  /* rho_K (s_K - mu_K) / (s_K - s*) and p_K / (rho_K (s_K - mu_K)) share one
+     reciprocal */
+  const double rd = rK * dsK, den = sK - ss;
+  const double inv = 1.0 / (den * rd);
+  const double fac = rd * rd * inv;
   double us[NC];
   us[0] = fac;
   us[N] = fac * ss;
   if (NC == 4) us[T] = fac * (uK[T] * irK);
-  us[NC - 1] = fac * (EK * irK + (ss - muK) * (ss + pK / (rK * dsK)));
+  us[NC - 1] = fac * (EK * irK + (ss - muK) * (ss + pK * den * inv));
 #pragma unroll
   for (int c = 0; c < NC; ++c) f[c] = fK[c] + sK * (us[c] - uK[c]);
 }

@@ -128,9 +128,53 @@ MR_INL void mr_physflux(const double* u, double gam, double* f) {
 /* Max wave speeds over the cell averages of the stage input (reading: dt
  * from U^n; Lax-Friedrichs alpha from every stage input), plus the
  * non-physical-state check.  One work item = up to MR_BLOCK cells. */
-__global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
+/* block-wide max of (ax, ay), result valid in thread 0 */
+MR_INL void mr_block_max2(double* ax, double* ay, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    *ax = fmax(*ax, __shfl_xor(*ax, o));
+    *ay = fmax(*ay, __shfl_xor(*ay, o));
+  }
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) { sh[2 * w] = *ax; sh[2 * w + 1] = *ay; }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 1; k < MR_BLOCK / 64; ++k) { *ax = fmax(*ax, sh[2 * k]); *ay = fmax(*ay, sh[2 * k + 1]); }
+}
+
+/* Each work group takes a contiguous run of `chunk` work items, keeps a
+ * running max per instance and publishes it with one atomic per instance
+ * run (max is exact, so the result does not depend on the order). */
+__global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_tile1* tiles, int ntiles,
+                                                     int stage, int chunk) {
 #pragma clang fp contract(off)
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  __shared__ double sh[2 * (MR_BLOCK / 64)];
+  const int t0 = blockIdx.x * chunk, t1 = min(ntiles, t0 + chunk);
+  int cur = -1;
+  double ax = 0.0, ay = 0.0;
+  int bad = 0;
+  for (int t = t0; t <= t1; ++t) {
+    const int inst = (t < t1) ? tiles[t].inst : -2;
+    if (inst != cur && cur >= 0) {
+      /* flush the finished instance (uniform across the block) */
+      mr_inst& J = insts[cur];
+      const int anybad = __syncthreads_or(bad);
+      mr_block_max2(&ax, &ay, sh);
+      if (threadIdx.x == 0) {
+        if (stage == 0) {
+          atomicMax(&J.amax[0], mr_dbits(ax));
+          atomicMax(&J.amax[1], mr_dbits(ay));
+          if (anybad) atomicOr(&J.err, 1);
+        } else {
+          atomicMax(&J.lfa[stage], mr_dbits(ax));
+        }
+      }
+      ax = ay = 0.0;
+      bad = 0;
+    }
+    cur = inst;
+    if (t >= t1) break;
     const mr_tile1 tl = tiles[t];
     mr_inst& I = insts[tl.inst];
     const double* U;
@@ -142,16 +186,14 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
       U = I.p_out[stage - 1];
     }
     const int k = tl.start + (int)threadIdx.x;
-    double ax = 0.0, ay = 0.0;
-    int bad = 0;
     if (k < tl.start + tl.count) {
       const long long P = I.plane;
       const int nm = I.dim + 1;
       if (I.flux == 0) {
         const double a = fabs(U[k]);
-        ax = a;
-        ay = a;
-        bad = !(a <= 1.0e300);
+        ax = fmax(ax, a);
+        ay = fmax(ay, a);
+        bad |= !(a <= 1.0e300);
       } else {
         double u[4];
         for (int c = 0; c < I.nc; ++c) u[c] = U[(long long)c * nm * P + k];
@@ -159,27 +201,11 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
         if (I.nc == 4) ke += u[2] * u[2];
         const double p = (I.gam - 1.0) * (u[I.nc - 1] - 0.5 * ke / u[0]);
         const double cs = sqrt(I.gam * p / u[0]);
-        ax = fabs(u[1] / u[0]) + cs;
-        if (I.nc == 4) ay = fabs(u[2] / u[0]) + cs;
-        bad = !(u[0] > 0.0) || !(p > 0.0) || !(ax <= 1.0e300) || !(ay <= 1.0e300);
-        if (bad) { ax = 0.0; ay = 0.0; }
-      }
-    }
-    /* wavefront max, then one atomic per wave (max is exact, so the result
-       does not depend on the order) */
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      ax = fmax(ax, __shfl_xor(ax, o));
-      ay = fmax(ay, __shfl_xor(ay, o));
-    }
-    const unsigned long long anybad = __ballot(bad);
-    if ((threadIdx.x & 63) == 0) {
-      if (stage == 0) {
-        atomicMax(&I.amax[0], mr_dbits(ax));
-        atomicMax(&I.amax[1], mr_dbits(ay));
-        if (anybad) atomicOr(&I.err, 1);
-      } else {
-        atomicMax(&I.lfa[stage], mr_dbits(ax));
+        const double sx = fabs(u[1] / u[0]) + cs;
+        const double sy = (I.nc == 4) ? fabs(u[2] / u[0]) + cs : 0.0;
+        const int b = !(u[0] > 0.0) || !(p > 0.0) || !(sx <= 1.0e300) || !(sy <= 1.0e300);
+        bad |= b;
+        if (!b) { ax = fmax(ax, sx); ay = fmax(ay, sy); }
       }
     }
   }
@@ -550,21 +576,46 @@ MR_INL double mr_rs(const double (&a)[NC], int k) {
 
 /* 2D stage kernel.  A work group owns a strip of CW = 256/NC consecutive
  * cells in x (two of them ring cells) and sweeps it upward over `rows` rows
- * plus one ring row below and one above.  With NC = 4 the four lanes of a
- * cell each reconstruct one conserved component, then each lane takes one
- * row eta_r of the cell's 4x4 Gauss-Lobatto grid for the volume integrals,
- * the left-face flux at eta_r and the bottom-face flux at xi_r.  Face values
- * of the neighbour to the left come from LDS, those of the row below from
- * the previous sweep step; the top-face flux of a row is the bottom-face
- * flux of the next one, so the residual of row j is completed while row j+1
- * is processed.  mode 0..2 = RK stage, 3 = write L(U). */
+ * plus one ring row below and one above.
+ *
+ * Moments: the rows y-2..y+2 of the strip (plus two columns each side) sit
+ * in an LDS ring of five rows; each value is loaded from HBM once per work
+ * group, with the boundary condition applied when it is loaded, and the
+ * row needed next is fetched into registers while the current row is
+ * computed.  Flags of rows y-1..y+1 sit in a three-row LDS ring.
+ *
+ * With NC = 4 the four lanes of a cell each reconstruct one conserved
+ * component, then each lane takes one row eta_r of the cell's 4x4
+ * Gauss-Lobatto grid for the volume integrals, the left-face flux at eta_r
+ * and the bottom-face flux at xi_r.  The top-face flux of a row is the
+ * bottom-face flux of the next one, so the residual of row j is completed
+ * while row j+1 is processed.  mode 0..2 = RK stage, 3 = write L(U). */
+template <int NC>
+struct mr2_lds {
+  static constexpr int CW = MR_BLOCK / NC;   /* strip cells incl. ring */
+  static constexpr int XW = CW + 4;          /* staged columns */
+  static constexpr int NP = 3 * NC;          /* staged planes */
+  double mom[5][NP][XW];
+  unsigned char flg[3][XW];
+  double val[CW * NC * 16];
+  double top[CW * NC * 4];
+  double fs[CW * NC * 2];
+};
+
+/* one staged element: plane q (= 3 c + m) of row y, column col of the strip */
+MR_INL double mr2_stage_ld(const mr_grid& g, int q, int x, int y) {
+  return mr_ld(g, q / 3, q % 3, x, y);
+}
+
 template <int NC, bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, const mr_tile2* tiles, int ntiles, int mode) {
-  constexpr int CW = MR_BLOCK / NC;
-  __shared__ double s_val[CW * NC * 16];
-  __shared__ double s_top[CW * NC * 4];
-  __shared__ double s_fs[CW * NC * 2];
-  const int cs = threadIdx.x / NC, k = threadIdx.x % NC;
+  using S = mr2_lds<NC>;
+  constexpr int CW = S::CW, XW = S::XW, NP = S::NP;
+  constexpr int NE = (NP * XW + MR_BLOCK - 1) / MR_BLOCK;   /* staged values per thread per row */
+  __shared__ S sh;
+  const int tid = threadIdx.x;
+  const int cs = tid / NC, k = tid % NC;
+  const int comp = (NC == 1) ? 0 : k;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile2 tl = tiles[t];
     const mr_inst& I = insts[tl.inst];
@@ -573,25 +624,82 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
     const mr_grid g{I.p_in[st], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
     const mr_grid gn{I.p_un, I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
     const unsigned char* fl = I.flags[(mode == 0 || mode == 3) ? 0 : 1];
-    const double dx = I.dx, dy = I.dy, dt = I.dt, gam = I.gam;
+    const double rdx = I.rdx, rdy = I.rdy, dt = I.dt, gam = I.gam;
     const double alpha = (NC == 1) ? mr_bitsd(I.lfa[st]) : 0.0;
     double* O = I.p_out[st];
     const long long P = I.plane;
+    const int xs0 = tl.x0 - 3;                 /* strip column 0 */
     const int x = tl.x0 - 1 + cs;
     const bool outx = cs >= 1 && cs <= CW - 2 && x < I.nx;
-    const int comp = (NC == 1) ? 0 : k;
-    /* carried from the previous row: partial residual (without the top
-       face), bottom-face sums, and the modified stage-input moments */
+    /* ---- prologue: moment rows y0-3 .. y0+1, flag rows y0-2 .. y0 ---- */
+    for (int r = tl.y0 - 3; r <= tl.y0 + 1; ++r) {
+      const int sl = ((r % 5) + 5) % 5;
+      for (int e = tid; e < NP * XW; e += MR_BLOCK)
+        sh.mom[sl][e / XW][e % XW] = mr2_stage_ld(g, e / XW, xs0 + e % XW, r);
+    }
+    for (int r = tl.y0 - 2; r <= tl.y0; ++r) {
+      const int sl = ((r % 3) + 3) % 3;
+      for (int e = tid; e < XW; e += MR_BLOCK)
+        sh.flg[sl][e] = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + e, r);
+    }
+    __syncthreads();
     double pAu = 0.0, pAv = 0.0, pAw = 0.0, pB0 = 0.0, pB1 = 0.0, pU = 0.0, pV = 0.0, pW = 0.0;
     for (int jr = -1; jr <= tl.rows; ++jr) {
       const int y = tl.y0 + jr;
-      /* ---- Steps 1, 2.2, 2.3: component `comp` of cell (x, y) ---- */
+      /* prefetch moment row y+3 and flag row y+2 (stored after this row) */
+      double pre[NE];
+      unsigned char pref = 0;
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * MR_BLOCK;
+        pre[q] = (e < NP * XW) ? mr2_stage_ld(g, e / XW, xs0 + e % XW, y + 3) : 0.0;
+      }
+      if (tid < XW) pref = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + tid, y + 2);
+      /* ---- Steps 1, 2.2, 2.3 for component `comp` of cell (x, y) ---- */
       double cu, cv, cw;
       {
-        double val[16];
-        mr2_cell_values<BP>(g, I, fl, comp, x, y, val, &cu, &cv, &cw);
+        const int rm = ((y - 1) % 5 + 5) % 5, r0 = ((y % 5) + 5) % 5, rp = ((y + 1) % 5 + 5) % 5;
+        const int fm = ((y - 1) % 3 + 3) % 3, f0 = ((y % 3) + 3) % 3, fp = ((y + 1) % 3 + 3) % 3;
+        const int c0 = cs + 2;                    /* staged column of cell x */
+        const int rr[3] = {rm, r0, rp}, ff[3] = {fm, f0, fp};
+        double u[9], v[9], w[9];
+        int fs[9];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) s_val[(cs * NC + comp) * 16 + q] = val[q];
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            const int l = dx + 3 * dy;
+            u[l] = sh.mom[rr[dy]][3 * comp + 0][c0 + dx - 1];
+            v[l] = sh.mom[rr[dy]][3 * comp + 1][c0 + dx - 1];
+            w[l] = sh.mom[rr[dy]][3 * comp + 2][c0 + dx - 1];
+            fs[l] = sh.flg[ff[dy]][c0 + dx - 1];
+          }
+        if (fs[4]) {
+          /* troubled cell: first moments of the troubled cells of the
+             stencil modified from the unmodified input (Jacobi) */
+          const int r2m = ((y - 2) % 5 + 5) % 5, r2p = ((y + 2) % 5 + 5) % 5;
+          const int rrr[5] = {r2m, rm, r0, rp, r2p};
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+              const int l = dx + 3 * dy;
+              if (!fs[l]) continue;
+              const int cc = c0 + dx - 1;
+              const int rw = rrr[dy + 1];
+              v[l] = mr_modified_moment(sh.mom[rw][3 * comp][cc - 1], sh.mom[rw][3 * comp][cc + 1],
+                                        sh.mom[rw][3 * comp + 1][cc - 1], sh.mom[rw][3 * comp + 1][cc + 1]);
+              w[l] = mr_modified_moment(sh.mom[rrr[dy]][3 * comp][cc], sh.mom[rrr[dy + 2]][3 * comp][cc],
+                                        sh.mom[rrr[dy]][3 * comp + 2][cc], sh.mom[rrr[dy + 2]][3 * comp + 2][cc]);
+            }
+        }
+        cu = u[4];
+        cv = v[4];
+        cw = w[4];
+        double val[16];
+        mr_recon2d<BP>(u, v, w, I.W, val);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sh.val[(cs * NC + comp) * 16 + q] = val[q];
       }
       __syncthreads();
       /* ---- volume integrals and the fluxes this lane owns ---- */
@@ -603,38 +711,37 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
       for (int rr = 0; rr < 4 / NC; ++rr) {
         const int r = (NC == 1) ? rr : k;
         const double wr = glw(r), er = gln(r);
-        double s4[4][NC];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-          for (int c = 0; c < NC; ++c) s4[q][c] = s_val[(cs * NC + c) * 16 + q + 4 * r];
         if (body) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            double f[NC], gg[NC];
-            mr_physflux<NC, 0>(s4[q], gam, f);
-            mr_physflux<NC, 1>(s4[q], gam, gg);
+            double pt[NC], f[NC], gg[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pt[c] = sh.val[(cs * NC + c) * 16 + q + 4 * r];
+            if (NC == 4) mr_euler_fg(pt, gam, f, gg);
+            else { f[0] = 0.5 * pt[0] * pt[0]; gg[0] = f[0]; }
             const double wq = glw(q) * wr;
 #pragma unroll
             for (int c = 0; c < NC; ++c) { F[c] += wq * f[c]; G[c] += wq * gg[c]; }
           }
           if (cs >= 1) {
-            double a[NC], fh[NC];
+            double a[NC], b[NC], fh[NC];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) a[c] = s_val[((cs - 1) * NC + c) * 16 + 3 + 4 * r];
-            mr_numflux<NC, 0>(a, s4[0], gam, alpha, fh);
+            for (int c = 0; c < NC; ++c) {
+              a[c] = sh.val[((cs - 1) * NC + c) * 16 + 3 + 4 * r];
+              b[c] = sh.val[(cs * NC + c) * 16 + 4 * r];
+            }
+            mr_numflux<NC, 0>(a, b, gam, alpha, fh);
 #pragma unroll
             for (int c = 0; c < NC; ++c) { XL0[c] += wr * fh[c]; XL1[c] += wr * er * fh[c]; }
           }
         }
         if (jr >= 0) {
-          double a[NC], gh[NC];
+          double a[NC], b[NC], gh[NC];
 #pragma unroll
-          for (int c = 0; c < NC; ++c) a[c] = s_top[(cs * NC + c) * 4 + r];
-          /* s4[0] holds (xi_0, eta_r); the bottom face needs (xi_r, eta_0) */
-          double b[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) b[c] = s_val[(cs * NC + c) * 16 + r];
+          for (int c = 0; c < NC; ++c) {
+            a[c] = sh.top[(cs * NC + c) * 4 + r];
+            b[c] = sh.val[(cs * NC + c) * 16 + r];
+          }
           mr_numflux<NC, 1>(a, b, gam, alpha, gh);
 #pragma unroll
           for (int c = 0; c < NC; ++c) { YB0[c] += wr * gh[c]; YB1[c] += wr * er * gh[c]; }
@@ -644,19 +751,29 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
       const double fF = mr_rs<NC>(F, k), fG = mr_rs<NC>(G, k);
       const double xl0 = mr_rs<NC>(XL0, k), xl1 = mr_rs<NC>(XL1, k);
       const double yb0 = mr_rs<NC>(YB0, k), yb1 = mr_rs<NC>(YB1, k);
-      s_fs[(cs * NC + comp) * 2 + 0] = xl0;
-      s_fs[(cs * NC + comp) * 2 + 1] = xl1;
+      sh.fs[(cs * NC + comp) * 2 + 0] = xl0;
+      sh.fs[(cs * NC + comp) * 2 + 1] = xl1;
       __syncthreads();
-      /* the row below has consumed s_top; store this row's top trace */
+      /* the row below has consumed its top trace; store this row's */
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        s_top[(cs * NC + comp) * 4 + q] = s_val[(cs * NC + comp) * 16 + 12 + q];
+        sh.top[(cs * NC + comp) * 4 + q] = sh.val[(cs * NC + comp) * 16 + 12 + q];
+      /* ring slots of rows y-2 (moments) and y-1 (flags) are free now */
+      {
+        const int sl = ((y + 3) % 5 + 5) % 5;
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          const int e = tid + q * MR_BLOCK;
+          if (e < NP * XW) sh.mom[sl][e / XW][e % XW] = pre[q];
+        }
+        if (tid < XW) sh.flg[((y + 2) % 3 + 3) % 3][tid] = pref;
+      }
       /* ---- finish the row below: its top face is this row's bottom face ---- */
       if (jr >= 1 && outx) {
         const int yp = y - 1;
-        const double Lu = pAu - (yb0 - pB0) / dy;
-        const double Lv = pAv - (yb1 - pB1) / dy;
-        const double Lw = pAw - (yb0 + pB0) / (2.0 * dy);
+        const double Lu = pAu - (yb0 - pB0) * rdy;
+        const double Lv = pAv - (yb1 - pB1) * rdy;
+        const double Lw = pAw - (yb0 + pB0) * (0.5 * rdy);
         double r0, r1, r2;
         if (mode == 3) { r0 = Lu; r1 = Lv; r2 = Lw; }
         else if (mode == 0) { r0 = pU + dt * Lu; r1 = pV + dt * Lv; r2 = pW + dt * Lw; }
@@ -675,11 +792,11 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
       }
       /* ---- this row's partial residual (all but the top face) ---- */
       if (cs + 1 < CW) {
-        const double xr0 = s_fs[((cs + 1) * NC + comp) * 2 + 0];
-        const double xr1 = s_fs[((cs + 1) * NC + comp) * 2 + 1];
-        pAu = -(xr0 - xl0) / dx;
-        pAv = -(xr0 + xl0) / (2.0 * dx) + fF / dx;
-        pAw = -(xr1 - xl1) / dx + fG / dy;
+        const double xr0 = sh.fs[((cs + 1) * NC + comp) * 2 + 0];
+        const double xr1 = sh.fs[((cs + 1) * NC + comp) * 2 + 1];
+        pAu = -(xr0 - xl0) * rdx;
+        pAv = -(xr0 + xl0) * (0.5 * rdx) + fF * rdx;
+        pAw = -(xr1 - xl1) * rdx + fG * rdy;
       }
       pB0 = yb0;
       pB1 = yb1;
@@ -714,7 +831,9 @@ extern "C" {
 
 hipError_t mr_launch_reduce(hipStream_t s, mr_inst* d, const mr_tile1* t, int nt, int stage) {
   if (nt <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
+  const int chunk = nt > 2048 ? (nt + 2047) / 2048 : 1;
+  const int grid = (nt + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(MR_BLOCK), 0, s, d, t, nt, stage, chunk);
   return hipGetLastError();
 }
 

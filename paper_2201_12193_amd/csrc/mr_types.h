@@ -32,6 +32,7 @@ struct mr_inst {
   int sex, sey;     /* summary plane extents                                   */
   long long plane;  /* nx * ny                                                 */
   double dx, dy, gam, cfl, t_final;
+  double rdx, rdy;            /* 1/dx, 1/dy                                    */
   double band_lo, band_hi;  /* learned-indicator uncertainty band              */
   mr_wconst W;
   double* buf[3];             /* state rotation; buf[0] = caller's moments     */
