@@ -100,6 +100,8 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
+        a.sum()                      # read-only pass over 1 GiB
+        torch.cuda.synchronize()
         del a, b
     ncell = prob.ncell
     cell_updates = ncell * 3 * args.steps

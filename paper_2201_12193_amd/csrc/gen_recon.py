@@ -36,6 +36,20 @@ R = sp.Rational
 
 
 # ------------------------------------------------------------ helpers
+import struct
+
+# FP64 constants that an instruction cannot encode directly (their low 32
+# bits are not zero) are collected into one table: on the device the table
+# is copied into LDS once per work group and read with broadcast LDS loads,
+# instead of being rebuilt in scalar registers at every use.
+_KTAB = []
+_KIDX = {}
+
+
+def _encodable(f: float) -> bool:
+    return (struct.unpack("<Q", struct.pack("<d", f))[0] & 0xFFFFFFFF) == 0
+
+
 def lit(x) -> str:
     x = sp.nsimplify(x)
     if x.is_Rational:
@@ -44,7 +58,13 @@ def lit(x) -> str:
         f = float(sp.N(x, 60))
     if f == 0.0:
         return "0.0"
-    return f.hex()
+    if _encodable(f):
+        return f.hex()
+    a = abs(f)
+    if a not in _KIDX:
+        _KIDX[a] = len(_KTAB)
+        _KTAB.append(a)
+    return ("-" if f < 0 else "") + f"MR_KT({_KIDX[a]})"
 
 
 def mono_avg(n, d):
@@ -462,15 +482,25 @@ def emit_mod(lines):
 
 
 def main():
+    body = []
+    emit_mod(body)
+    emit_1d(body)
+    emit_2d(body)
     lines = ["/* Generated by gen_recon.py -- do not edit. */",
              "#pragma once",
              "#ifndef MR_DEV",
              "#define MR_DEV __host__ __device__ __attribute__((always_inline))",
              "#endif",
-             ""]
-    emit_mod(lines)
-    emit_1d(lines)
-    emit_2d(lines)
+             f"#define MR_NKT {len(_KTAB)}",
+             "/* constants the instructions cannot encode; MR_KT(i) reads entry i",
+             "   (the including file defines MR_KT and the table storage) */",
+             "#define MR_KT_VALUES \\"]
+    for k in range(0, len(_KTAB), 4):
+        lines.append("  " + ", ".join(v.hex() for v in _KTAB[k:k + 4]) + ", \\")
+    lines.append("  0.0")
+    lines.append("MR_KT_DECLARE")
+    lines.append("")
+    lines.extend(body)
     sys.stdout.write("\n".join(lines) + "\n")
 
 

@@ -1,0 +1,125 @@
+/* Helpers shared by the kernel translation units of the MR-HWENO library. */
+#pragma once
+#include "mr_device.h"
+
+#define MR_BLOCK 256
+/* occupancy target for the reconstruction kernels: the compiler schedules
+   for at most 512 / MR_WAVES VGPRs per lane instead of the whole file */
+#ifndef MR_WAVES
+#define MR_WAVES 2
+#endif
+#define MR_OCC __attribute__((amdgpu_waves_per_eu(MR_WAVES)))
+
+/* =================================================================== helpers */
+struct mr_grid {
+  const double* U;  /* state base: comp c, moment m plane at U + (c*nm + m)*P */
+  long long P;
+  int nx, ny, bcx, bcy, nm;
+};
+
+/* moment m of component c at cell (i, j) with ghost handling */
+MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
+  bool z = false;
+  const int ii = mr_fold(i, g.nx, g.bcx, &z);
+  const int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &z) : 0;
+  if (z && m > 0) return 0.0;
+  return g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
+}
+
+/* flag of cell (i, j) from an extended plane with halo h (clamped) */
+MR_INL int mr_flag(const unsigned char* fl, int ex, int ey, int h, int i, int j) {
+  int a = i + h, b = j + h;
+  a = a < 0 ? 0 : (a >= ex ? ex - 1 : a);
+  b = b < 0 ? 0 : (b >= ey ? ey - 1 : b);
+  return fl[(long long)b * ex + a];
+}
+
+/* ----------------------------------------------------- 2D stencil + Step 1 */
+/* Final Gauss-Lobatto values of component c of cell (x, y): Step 1 on the
+ * stage input, or, for a troubled cell, Step 1 again with the first moments
+ * of the troubled cells of its stencil replaced (Steps 2.2, 2.3).
+ * ve/we receive the cell's own (possibly modified) first moments. */
+/* Steps 2.2/2.3 input: first moments of the troubled cells of the stencil of
+ * (x, y) replaced by their modified values (Jacobi, from the unmodified
+ * stage input). */
+MR_INL void mr2_modify_stencil(const mr_grid& g, int c, int x, int y, const int* fs,
+                               double* v, double* w) {
+#pragma unroll
+  for (int l = 0; l < 9; ++l) {
+    if (!fs[l]) continue;
+    const int xs = x + l % 3 - 1, ys = y + l / 3 - 1;
+    v[l] = mr_modified_moment(mr_ld(g, c, 0, xs - 1, ys), mr_ld(g, c, 0, xs + 1, ys),
+                              mr_ld(g, c, 1, xs - 1, ys), mr_ld(g, c, 1, xs + 1, ys));
+    w[l] = mr_modified_moment(mr_ld(g, c, 0, xs, ys - 1), mr_ld(g, c, 0, xs, ys + 1),
+                              mr_ld(g, c, 2, xs, ys - 1), mr_ld(g, c, 2, xs, ys + 1));
+  }
+}
+
+/* Final Gauss-Lobatto values of component c of cell (x, y): Step 1 on the
+ * stage input, or, for a troubled cell, Step 1 again with the first moments
+ * of the troubled cells of its stencil replaced (Steps 2.2, 2.3).
+ * ue/ve/we receive the cell's own (possibly modified) moments. */
+template <bool BP>
+MR_INL void mr2_cell_values(const mr_grid& g, const mr_inst& I, const unsigned char* fl,
+                            int c, int x, int y, double out[16], double* ue, double* ve, double* we) {
+  double u[9], v[9], w[9];
+  int fs[9];
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int l = (dx + 1) + 3 * (dy + 1);
+      u[l] = mr_ld(g, c, 0, x + dx, y + dy);
+      v[l] = mr_ld(g, c, 1, x + dx, y + dy);
+      w[l] = mr_ld(g, c, 2, x + dx, y + dy);
+      fs[l] = mr_flag(fl, I.fex, I.fey, I.fhalo, x + dx, y + dy);
+    }
+  if (fs[4]) mr2_modify_stencil(g, c, x, y, fs, v, w);
+  *ue = u[4];
+  *ve = v[4];
+  *we = w[4];
+  mr_recon2d<BP>(u, v, w, I.W, out);
+}
+
+/* U^n with the stage-1 modification applied at cell (x, y), component c */
+MR_INL void mr2_un_mod(const mr_grid& g, const unsigned char* fl1, const mr_inst& I,
+                       int c, int x, int y, double* u, double* v, double* w) {
+  *u = mr_ld(g, c, 0, x, y);
+  if (mr_flag(fl1, I.fex, I.fey, I.fhalo, x, y)) {
+    *v = mr_modified_moment(mr_ld(g, c, 0, x - 1, y), mr_ld(g, c, 0, x + 1, y),
+                            mr_ld(g, c, 1, x - 1, y), mr_ld(g, c, 1, x + 1, y));
+    *w = mr_modified_moment(mr_ld(g, c, 0, x, y - 1), mr_ld(g, c, 0, x, y + 1),
+                            mr_ld(g, c, 2, x, y - 1), mr_ld(g, c, 2, x, y + 1));
+  } else {
+    *v = mr_ld(g, c, 1, x, y);
+    *w = mr_ld(g, c, 2, x, y);
+  }
+}
+
+template <int NC, int D>
+MR_INL void mr_numflux(const double* a, const double* b, double gam, double alpha, double* f) {
+  if (NC == 1) f[0] = mr_lf(a[0], b[0], alpha);
+  else mr_hllc<NC, D>(a, b, gam, f);
+}
+
+template <int NC, int D>
+MR_INL void mr_physflux(const double* u, double gam, double* f) {
+  if (NC == 1) f[0] = 0.5 * u[0] * u[0];
+  else mr_euler_flux<NC, D>(u, gam, f);
+}
+
+/* reduce-scatter over the NC lanes of a cell: lane k receives sum_r a_r[k] */
+template <int NC>
+MR_INL double mr_rs(const double (&a)[NC], int k) {
+  if (NC == 1) return a[0];
+  const bool hi = (k & 2) != 0;
+  const double s0 = hi ? a[0] : a[2], s1 = hi ? a[1] : a[3];
+  const double k0 = hi ? a[2] : a[0], k1 = hi ? a[3] : a[1];
+  const double b0 = k0 + __shfl_xor(s0, 2);
+  const double b1 = k1 + __shfl_xor(s1, 2);
+  const bool odd = (k & 1) != 0;
+  const double s = odd ? b0 : b1, kk = odd ? b1 : b0;
+  return kk + __shfl_xor(s, 1);
+}
+
+/* 2D final Gauss-Lobatto values of interior cells: gl[(c*16 + p)*plane + cell]. */

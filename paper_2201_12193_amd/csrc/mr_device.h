@@ -9,7 +9,34 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include "mr_types.h"
+
+/* Constant table of the generated reconstruction code (the FP64 constants
+ * that an instruction cannot encode).  A translation unit that defines
+ * MR_KT_IN_LDS copies it into LDS once per work group (mr_kt_fill) and reads
+ * it from there, which keeps the constants out of the scalar registers of
+ * its large kernels; elsewhere the entries fold into literals. */
+#define MR_KT_MAX 128
+#if defined(__HIP_DEVICE_COMPILE__) && defined(MR_KT_IN_LDS)
+#define MR_KT(i) (mr_kt_lds[i])
+#define MR_KT_DECLARE                                            \
+  __constant__ double mr_kt_dev[MR_NKT + 1] = {MR_KT_VALUES};    \
+  __shared__ double mr_kt_lds[MR_KT_MAX];
+#else
+#define MR_KT(i) (mr_kt_lit[i])
+#define MR_KT_DECLARE static constexpr double mr_kt_lit[MR_NKT + 1] = {MR_KT_VALUES};
+#endif
 #include "recon_gen.h"
+static_assert(MR_NKT <= MR_KT_MAX, "constant table larger than its LDS slot");
+
+#if defined(__HIP_DEVICE_COMPILE__) && defined(MR_KT_IN_LDS)
+/* copy the constant table into LDS; call at kernel entry by every thread */
+__device__ __forceinline__ void mr_kt_fill() {
+  for (int i = threadIdx.x; i < MR_NKT; i += blockDim.x) mr_kt_lds[i] = mr_kt_dev[i];
+  __syncthreads();
+}
+#else
+__device__ __forceinline__ void mr_kt_fill() {}
+#endif
 
 #define MR_INL __device__ __forceinline__
 /* reconstruction and flux helpers also compile for the host, so that the

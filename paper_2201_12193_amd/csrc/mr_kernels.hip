@@ -16,113 +16,7 @@
  * modification of U^n made in the first stage is reapplied on the fly in
  * stages two and three from the stage-1 flags.
  */
-#include "mr_device.h"
-
-#define MR_BLOCK 256
-/* occupancy target for the reconstruction kernels: the compiler schedules
-   for at most 512 / MR_WAVES VGPRs per lane instead of the whole file */
-#ifndef MR_WAVES
-#define MR_WAVES 2
-#endif
-#define MR_OCC __attribute__((amdgpu_waves_per_eu(MR_WAVES)))
-
-/* =================================================================== helpers */
-struct mr_grid {
-  const double* U;  /* state base: comp c, moment m plane at U + (c*nm + m)*P */
-  long long P;
-  int nx, ny, bcx, bcy, nm;
-};
-
-/* moment m of component c at cell (i, j) with ghost handling */
-MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
-  bool z = false;
-  const int ii = mr_fold(i, g.nx, g.bcx, &z);
-  const int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &z) : 0;
-  if (z && m > 0) return 0.0;
-  return g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
-}
-
-/* flag of cell (i, j) from an extended plane with halo h (clamped) */
-MR_INL int mr_flag(const unsigned char* fl, int ex, int ey, int h, int i, int j) {
-  int a = i + h, b = j + h;
-  a = a < 0 ? 0 : (a >= ex ? ex - 1 : a);
-  b = b < 0 ? 0 : (b >= ey ? ey - 1 : b);
-  return fl[(long long)b * ex + a];
-}
-
-/* ----------------------------------------------------- 2D stencil + Step 1 */
-/* Final Gauss-Lobatto values of component c of cell (x, y): Step 1 on the
- * stage input, or, for a troubled cell, Step 1 again with the first moments
- * of the troubled cells of its stencil replaced (Steps 2.2, 2.3).
- * ve/we receive the cell's own (possibly modified) first moments. */
-/* Steps 2.2/2.3 input: first moments of the troubled cells of the stencil of
- * (x, y) replaced by their modified values (Jacobi, from the unmodified
- * stage input). */
-MR_INL void mr2_modify_stencil(const mr_grid& g, int c, int x, int y, const int* fs,
-                               double* v, double* w) {
-#pragma unroll
-  for (int l = 0; l < 9; ++l) {
-    if (!fs[l]) continue;
-    const int xs = x + l % 3 - 1, ys = y + l / 3 - 1;
-    v[l] = mr_modified_moment(mr_ld(g, c, 0, xs - 1, ys), mr_ld(g, c, 0, xs + 1, ys),
-                              mr_ld(g, c, 1, xs - 1, ys), mr_ld(g, c, 1, xs + 1, ys));
-    w[l] = mr_modified_moment(mr_ld(g, c, 0, xs, ys - 1), mr_ld(g, c, 0, xs, ys + 1),
-                              mr_ld(g, c, 2, xs, ys - 1), mr_ld(g, c, 2, xs, ys + 1));
-  }
-}
-
-/* Final Gauss-Lobatto values of component c of cell (x, y): Step 1 on the
- * stage input, or, for a troubled cell, Step 1 again with the first moments
- * of the troubled cells of its stencil replaced (Steps 2.2, 2.3).
- * ue/ve/we receive the cell's own (possibly modified) moments. */
-template <bool BP>
-MR_INL void mr2_cell_values(const mr_grid& g, const mr_inst& I, const unsigned char* fl,
-                            int c, int x, int y, double out[16], double* ue, double* ve, double* we) {
-  double u[9], v[9], w[9];
-  int fs[9];
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy)
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) {
-      const int l = (dx + 1) + 3 * (dy + 1);
-      u[l] = mr_ld(g, c, 0, x + dx, y + dy);
-      v[l] = mr_ld(g, c, 1, x + dx, y + dy);
-      w[l] = mr_ld(g, c, 2, x + dx, y + dy);
-      fs[l] = mr_flag(fl, I.fex, I.fey, I.fhalo, x + dx, y + dy);
-    }
-  if (fs[4]) mr2_modify_stencil(g, c, x, y, fs, v, w);
-  *ue = u[4];
-  *ve = v[4];
-  *we = w[4];
-  mr_recon2d<BP>(u, v, w, I.W, out);
-}
-
-/* U^n with the stage-1 modification applied at cell (x, y), component c */
-MR_INL void mr2_un_mod(const mr_grid& g, const unsigned char* fl1, const mr_inst& I,
-                       int c, int x, int y, double* u, double* v, double* w) {
-  *u = mr_ld(g, c, 0, x, y);
-  if (mr_flag(fl1, I.fex, I.fey, I.fhalo, x, y)) {
-    *v = mr_modified_moment(mr_ld(g, c, 0, x - 1, y), mr_ld(g, c, 0, x + 1, y),
-                            mr_ld(g, c, 1, x - 1, y), mr_ld(g, c, 1, x + 1, y));
-    *w = mr_modified_moment(mr_ld(g, c, 0, x, y - 1), mr_ld(g, c, 0, x, y + 1),
-                            mr_ld(g, c, 2, x, y - 1), mr_ld(g, c, 2, x, y + 1));
-  } else {
-    *v = mr_ld(g, c, 1, x, y);
-    *w = mr_ld(g, c, 2, x, y);
-  }
-}
-
-template <int NC, int D>
-MR_INL void mr_numflux(const double* a, const double* b, double gam, double alpha, double* f) {
-  if (NC == 1) f[0] = mr_lf(a[0], b[0], alpha);
-  else mr_hllc<NC, D>(a, b, gam, f);
-}
-
-template <int NC, int D>
-MR_INL void mr_physflux(const double* u, double gam, double* f) {
-  if (NC == 1) f[0] = 0.5 * u[0] * u[0];
-  else mr_euler_flux<NC, D>(u, gam, f);
-}
+#include "mr_common.h"
 
 /* ================================================================ reduction */
 /* Max wave speeds over the cell averages of the stage input (reading: dt
@@ -273,6 +167,7 @@ __global__ void k_finalize(mr_inst* insts, int n, int probe) {
  * x_{i-1/2}, 3: velocity at x_{i+1/2}, 4: max |u| over the 4 GL points. */
 template <bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
+  mr_kt_fill();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
     const mr_inst& I = insts[tl.inst];
@@ -340,6 +235,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_ti
  * mode 3 = write L(U) (input p_in[0], output p_out[0]). */
 template <int NC, bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, const mr_tile1* tiles, int ntiles, int mode) {
+  mr_kt_fill();
   __shared__ double s_tr[MR_BLOCK * NC];
   __shared__ double s_fl[MR_BLOCK * NC];
   const int cs = threadIdx.x;
@@ -430,6 +326,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
 /* 1D final Gauss-Lobatto values of interior cells: gl[(c*4 + k)*nx + i]. */
 template <int NC, bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, const mr_tile1* tiles, int ntiles, double* gl) {
+  mr_kt_fill();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
     const mr_inst& I = insts[tl.inst];
@@ -462,6 +359,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, con
  * over the 16 points. */
 template <bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_summary(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
+  mr_kt_fill();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
     const mr_inst& I = insts[tl.inst];
@@ -560,257 +458,9 @@ __global__ __launch_bounds__(MR_BLOCK) void k2_flags(mr_inst* insts, const mr_ti
   }
 }
 
-/* reduce-scatter over the NC lanes of a cell: lane k receives sum_r a_r[k] */
-template <int NC>
-MR_INL double mr_rs(const double (&a)[NC], int k) {
-  if (NC == 1) return a[0];
-  const bool hi = (k & 2) != 0;
-  const double s0 = hi ? a[0] : a[2], s1 = hi ? a[1] : a[3];
-  const double k0 = hi ? a[2] : a[0], k1 = hi ? a[3] : a[1];
-  const double b0 = k0 + __shfl_xor(s0, 2);
-  const double b1 = k1 + __shfl_xor(s1, 2);
-  const bool odd = (k & 1) != 0;
-  const double s = odd ? b0 : b1, kk = odd ? b1 : b0;
-  return kk + __shfl_xor(s, 1);
-}
-
-/* 2D stage kernel.  A work group owns a strip of CW = 256/NC consecutive
- * cells in x (two of them ring cells) and sweeps it upward over `rows` rows
- * plus one ring row below and one above.
- *
- * Moments: the rows y-2..y+2 of the strip (plus two columns each side) sit
- * in an LDS ring of five rows; each value is loaded from HBM once per work
- * group, with the boundary condition applied when it is loaded, and the
- * row needed next is fetched into registers while the current row is
- * computed.  Flags of rows y-1..y+1 sit in a three-row LDS ring.
- *
- * With NC = 4 the four lanes of a cell each reconstruct one conserved
- * component, then each lane takes one row eta_r of the cell's 4x4
- * Gauss-Lobatto grid for the volume integrals, the left-face flux at eta_r
- * and the bottom-face flux at xi_r.  The top-face flux of a row is the
- * bottom-face flux of the next one, so the residual of row j is completed
- * while row j+1 is processed.  mode 0..2 = RK stage, 3 = write L(U). */
-template <int NC>
-struct mr2_lds {
-  static constexpr int CW = MR_BLOCK / NC;   /* strip cells incl. ring */
-  static constexpr int XW = CW + 4;          /* staged columns */
-  static constexpr int NP = 3 * NC;          /* staged planes */
-  double mom[5][NP][XW];
-  unsigned char flg[3][XW];
-  double val[CW * NC * 16];
-  double top[CW * NC * 4];
-  double fs[CW * NC * 2];
-};
-
-/* one staged element: plane q (= 3 c + m) of row y, column col of the strip */
-MR_INL double mr2_stage_ld(const mr_grid& g, int q, int x, int y) {
-  return mr_ld(g, q / 3, q % 3, x, y);
-}
-
-template <int NC, bool BP>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, const mr_tile2* tiles, int ntiles, int mode) {
-  using S = mr2_lds<NC>;
-  constexpr int CW = S::CW, XW = S::XW, NP = S::NP;
-  constexpr int NE = (NP * XW + MR_BLOCK - 1) / MR_BLOCK;   /* staged values per thread per row */
-  __shared__ S sh;
-  const int tid = threadIdx.x;
-  const int cs = tid / NC, k = tid % NC;
-  const int comp = (NC == 1) ? 0 : k;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const mr_tile2 tl = tiles[t];
-    const mr_inst& I = insts[tl.inst];
-    if (mode < 3 && !I.active) continue;
-    const int st = mode == 3 ? 0 : mode;
-    const mr_grid g{I.p_in[st], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    const mr_grid gn{I.p_un, I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    const unsigned char* fl = I.flags[(mode == 0 || mode == 3) ? 0 : 1];
-    const double rdx = I.rdx, rdy = I.rdy, dt = I.dt, gam = I.gam;
-    const double alpha = (NC == 1) ? mr_bitsd(I.lfa[st]) : 0.0;
-    double* O = I.p_out[st];
-    const long long P = I.plane;
-    const int xs0 = tl.x0 - 3;                 /* strip column 0 */
-    const int x = tl.x0 - 1 + cs;
-    const bool outx = cs >= 1 && cs <= CW - 2 && x < I.nx;
-    /* ---- prologue: moment rows y0-3 .. y0+1, flag rows y0-2 .. y0 ---- */
-    for (int r = tl.y0 - 3; r <= tl.y0 + 1; ++r) {
-      const int sl = ((r % 5) + 5) % 5;
-      for (int e = tid; e < NP * XW; e += MR_BLOCK)
-        sh.mom[sl][e / XW][e % XW] = mr2_stage_ld(g, e / XW, xs0 + e % XW, r);
-    }
-    for (int r = tl.y0 - 2; r <= tl.y0; ++r) {
-      const int sl = ((r % 3) + 3) % 3;
-      for (int e = tid; e < XW; e += MR_BLOCK)
-        sh.flg[sl][e] = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + e, r);
-    }
-    __syncthreads();
-    double pAu = 0.0, pAv = 0.0, pAw = 0.0, pB0 = 0.0, pB1 = 0.0, pU = 0.0, pV = 0.0, pW = 0.0;
-    for (int jr = -1; jr <= tl.rows; ++jr) {
-      const int y = tl.y0 + jr;
-      /* prefetch moment row y+3 and flag row y+2 (stored after this row) */
-      double pre[NE];
-      unsigned char pref = 0;
-#pragma unroll
-      for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * MR_BLOCK;
-        pre[q] = (e < NP * XW) ? mr2_stage_ld(g, e / XW, xs0 + e % XW, y + 3) : 0.0;
-      }
-      if (tid < XW) pref = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + tid, y + 2);
-      /* ---- Steps 1, 2.2, 2.3 for component `comp` of cell (x, y) ---- */
-      double cu, cv, cw;
-      {
-        const int rm = ((y - 1) % 5 + 5) % 5, r0 = ((y % 5) + 5) % 5, rp = ((y + 1) % 5 + 5) % 5;
-        const int fm = ((y - 1) % 3 + 3) % 3, f0 = ((y % 3) + 3) % 3, fp = ((y + 1) % 3 + 3) % 3;
-        const int c0 = cs + 2;                    /* staged column of cell x */
-        const int rr[3] = {rm, r0, rp}, ff[3] = {fm, f0, fp};
-        double u[9], v[9], w[9];
-        int fs[9];
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-          for (int dx = 0; dx < 3; ++dx) {
-            const int l = dx + 3 * dy;
-            u[l] = sh.mom[rr[dy]][3 * comp + 0][c0 + dx - 1];
-            v[l] = sh.mom[rr[dy]][3 * comp + 1][c0 + dx - 1];
-            w[l] = sh.mom[rr[dy]][3 * comp + 2][c0 + dx - 1];
-            fs[l] = sh.flg[ff[dy]][c0 + dx - 1];
-          }
-        if (fs[4]) {
-          /* troubled cell: first moments of the troubled cells of the
-             stencil modified from the unmodified input (Jacobi) */
-          const int r2m = ((y - 2) % 5 + 5) % 5, r2p = ((y + 2) % 5 + 5) % 5;
-          const int rrr[5] = {r2m, rm, r0, rp, r2p};
-#pragma unroll
-          for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-              const int l = dx + 3 * dy;
-              if (!fs[l]) continue;
-              const int cc = c0 + dx - 1;
-              const int rw = rrr[dy + 1];
-              v[l] = mr_modified_moment(sh.mom[rw][3 * comp][cc - 1], sh.mom[rw][3 * comp][cc + 1],
-                                        sh.mom[rw][3 * comp + 1][cc - 1], sh.mom[rw][3 * comp + 1][cc + 1]);
-              w[l] = mr_modified_moment(sh.mom[rrr[dy]][3 * comp][cc], sh.mom[rrr[dy + 2]][3 * comp][cc],
-                                        sh.mom[rrr[dy]][3 * comp + 2][cc], sh.mom[rrr[dy + 2]][3 * comp + 2][cc]);
-            }
-        }
-        cu = u[4];
-        cv = v[4];
-        cw = w[4];
-        double val[16];
-        mr_recon2d<BP>(u, v, w, I.W, val);
-#pragma unroll
-        for (int q = 0; q < 16; ++q) sh.val[(cs * NC + comp) * 16 + q] = val[q];
-      }
-      __syncthreads();
-      /* ---- volume integrals and the fluxes this lane owns ---- */
-      double F[NC], G[NC], XL0[NC], XL1[NC], YB0[NC], YB1[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) F[c] = G[c] = XL0[c] = XL1[c] = YB0[c] = YB1[c] = 0.0;
-      const bool body = jr >= 0 && jr < tl.rows;
-#pragma unroll
-      for (int rr = 0; rr < 4 / NC; ++rr) {
-        const int r = (NC == 1) ? rr : k;
-        const double wr = glw(r), er = gln(r);
-        if (body) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            double pt[NC], f[NC], gg[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) pt[c] = sh.val[(cs * NC + c) * 16 + q + 4 * r];
-            if (NC == 4) mr_euler_fg(pt, gam, f, gg);
-            else { f[0] = 0.5 * pt[0] * pt[0]; gg[0] = f[0]; }
-            const double wq = glw(q) * wr;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) { F[c] += wq * f[c]; G[c] += wq * gg[c]; }
-          }
-          if (cs >= 1) {
-            double a[NC], b[NC], fh[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-              a[c] = sh.val[((cs - 1) * NC + c) * 16 + 3 + 4 * r];
-              b[c] = sh.val[(cs * NC + c) * 16 + 4 * r];
-            }
-            mr_numflux<NC, 0>(a, b, gam, alpha, fh);
-#pragma unroll
-            for (int c = 0; c < NC; ++c) { XL0[c] += wr * fh[c]; XL1[c] += wr * er * fh[c]; }
-          }
-        }
-        if (jr >= 0) {
-          double a[NC], b[NC], gh[NC];
-#pragma unroll
-          for (int c = 0; c < NC; ++c) {
-            a[c] = sh.top[(cs * NC + c) * 4 + r];
-            b[c] = sh.val[(cs * NC + c) * 16 + r];
-          }
-          mr_numflux<NC, 1>(a, b, gam, alpha, gh);
-#pragma unroll
-          for (int c = 0; c < NC; ++c) { YB0[c] += wr * gh[c]; YB1[c] += wr * er * gh[c]; }
-        }
-      }
-      /* lane k collects component k's sums */
-      const double fF = mr_rs<NC>(F, k), fG = mr_rs<NC>(G, k);
-      const double xl0 = mr_rs<NC>(XL0, k), xl1 = mr_rs<NC>(XL1, k);
-      const double yb0 = mr_rs<NC>(YB0, k), yb1 = mr_rs<NC>(YB1, k);
-      sh.fs[(cs * NC + comp) * 2 + 0] = xl0;
-      sh.fs[(cs * NC + comp) * 2 + 1] = xl1;
-      __syncthreads();
-      /* the row below has consumed its top trace; store this row's */
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        sh.top[(cs * NC + comp) * 4 + q] = sh.val[(cs * NC + comp) * 16 + 12 + q];
-      /* ring slots of rows y-2 (moments) and y-1 (flags) are free now */
-      {
-        const int sl = ((y + 3) % 5 + 5) % 5;
-#pragma unroll
-        for (int q = 0; q < NE; ++q) {
-          const int e = tid + q * MR_BLOCK;
-          if (e < NP * XW) sh.mom[sl][e / XW][e % XW] = pre[q];
-        }
-        if (tid < XW) sh.flg[((y + 2) % 3 + 3) % 3][tid] = pref;
-      }
-      /* ---- finish the row below: its top face is this row's bottom face ---- */
-      if (jr >= 1 && outx) {
-        const int yp = y - 1;
-        const double Lu = pAu - (yb0 - pB0) * rdy;
-        const double Lv = pAv - (yb1 - pB1) * rdy;
-        const double Lw = pAw - (yb0 + pB0) * (0.5 * rdy);
-        double r0, r1, r2;
-        if (mode == 3) { r0 = Lu; r1 = Lv; r2 = Lw; }
-        else if (mode == 0) { r0 = pU + dt * Lu; r1 = pV + dt * Lv; r2 = pW + dt * Lw; }
-        else {
-          const double a = mode == 1 ? 0.75 : 1.0 / 3.0, b = mode == 1 ? 0.25 : 2.0 / 3.0;
-          double un, vn, wn;
-          mr2_un_mod(gn, I.flags[0], I, comp, x, yp, &un, &vn, &wn);
-          r0 = a * un + b * pU + b * dt * Lu;
-          r1 = a * vn + b * pV + b * dt * Lv;
-          r2 = a * wn + b * pW + b * dt * Lw;
-        }
-        const long long cell = (long long)yp * I.nx + x;
-        O[(long long)(comp * 3 + 0) * P + cell] = r0;
-        O[(long long)(comp * 3 + 1) * P + cell] = r1;
-        O[(long long)(comp * 3 + 2) * P + cell] = r2;
-      }
-      /* ---- this row's partial residual (all but the top face) ---- */
-      if (cs + 1 < CW) {
-        const double xr0 = sh.fs[((cs + 1) * NC + comp) * 2 + 0];
-        const double xr1 = sh.fs[((cs + 1) * NC + comp) * 2 + 1];
-        pAu = -(xr0 - xl0) * rdx;
-        pAv = -(xr0 + xl0) * (0.5 * rdx) + fF * rdx;
-        pAw = -(xr1 - xl1) * rdx + fG * rdy;
-      }
-      pB0 = yb0;
-      pB1 = yb1;
-      pU = cu;
-      pV = cv;
-      pW = cw;
-      __syncthreads();
-    }
-  }
-}
-
-/* 2D final Gauss-Lobatto values of interior cells: gl[(c*16 + p)*plane + cell]. */
 template <int NC, bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_values(mr_inst* insts, const mr_tile1* tiles, int ntiles, double* gl) {
+  mr_kt_fill();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
     const mr_inst& I = insts[tl.inst];
@@ -869,17 +519,6 @@ hipError_t mr_launch_stage1(hipStream_t s, int nc, int bp, mr_inst* d, const mr_
   else if (nc == 3) { if (bp) MR_L1(3, true); else MR_L1(3, false); }
   else return hipErrorInvalidValue;
 #undef MR_L1
-  return hipGetLastError();
-}
-
-hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, mr_inst* d, const mr_tile2* t, int nt, int mode, int grid) {
-  if (nt <= 0) return hipSuccess;
-  const dim3 G(grid > 0 && grid < nt ? grid : nt), B(MR_BLOCK);
-#define MR_L2(NC_, BP_) hipLaunchKernelGGL((k2_stage<NC_, BP_>), G, B, 0, s, d, t, nt, mode)
-  if (nc == 1) { if (bp) MR_L2(1, true); else MR_L2(1, false); }
-  else if (nc == 4) { if (bp) MR_L2(4, true); else MR_L2(4, false); }
-  else return hipErrorInvalidValue;
-#undef MR_L2
   return hipGetLastError();
 }
 

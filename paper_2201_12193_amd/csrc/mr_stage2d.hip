@@ -1,0 +1,261 @@
+/* The 2D stage kernel (its own translation unit: it keeps the constant
+ * table of the reconstruction in LDS, see mr_device.h). */
+#define MR_KT_IN_LDS 1
+#include "mr_common.h"
+
+/* 2D stage kernel.  A work group owns a strip of CW = 256/NC consecutive
+ * cells in x (two of them ring cells) and sweeps it upward over `rows` rows
+ * plus one ring row below and one above.
+ *
+ * Moments: the rows y-2..y+2 of the strip (plus two columns each side) sit
+ * in an LDS ring of five rows; each value is loaded from HBM once per work
+ * group, with the boundary condition applied when it is loaded, and the
+ * row needed next is fetched into registers while the current row is
+ * computed.  Flags of rows y-1..y+1 sit in a three-row LDS ring.
+ *
+ * With NC = 4 the four lanes of a cell each reconstruct one conserved
+ * component, then each lane takes one row eta_r of the cell's 4x4
+ * Gauss-Lobatto grid for the volume integrals, the left-face flux at eta_r
+ * and the bottom-face flux at xi_r.  The top-face flux of a row is the
+ * bottom-face flux of the next one, so the residual of row j is completed
+ * while row j+1 is processed.  mode 0..2 = RK stage, 3 = write L(U). */
+template <int NC>
+struct mr2_lds {
+  static constexpr int CW = MR_BLOCK / NC;   /* strip cells incl. ring */
+  static constexpr int XW = CW + 4;          /* staged columns */
+  static constexpr int NP = 3 * NC;          /* staged planes */
+  /* point-major layouts with padded strides: the lanes of one access
+     (cells cs, roles/components k) fall on distinct LDS banks */
+  static constexpr int CS = CW + 4;          /* component stride */
+  static constexpr int VS = NC * CS + 1;     /* point stride of val */
+  static constexpr int TS = NC * CS + 4;     /* point stride of top */
+  static constexpr int FS = NC * CS;         /* stride of fs */
+  double mom[3][NP][XW];
+  unsigned char flg[3][XW];
+  double val[16 * VS];
+  double top[4 * TS];
+  double fs[2 * FS];
+};
+
+/* one staged element: plane q (= 3 c + m) of row y, column col of the strip */
+MR_INL double mr2_stage_ld(const mr_grid& g, int q, int x, int y) {
+  return mr_ld(g, q / 3, q % 3, x, y);
+}
+
+MR_INL int mr_mod3(int y) { return ((y % 3) + 3) % 3; }
+
+template <int NC, bool BP>
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, const mr_tile2* tiles, int ntiles, int mode) {
+  mr_kt_fill();
+  using S = mr2_lds<NC>;
+  constexpr int CW = S::CW, XW = S::XW, NP = S::NP, CS = S::CS, VS = S::VS, TS = S::TS, FS = S::FS;
+  constexpr int NE = (NP * XW + MR_BLOCK - 1) / MR_BLOCK;   /* staged values per thread per row */
+  __shared__ S sh;
+  const int tid = threadIdx.x;
+  const int cs = tid / NC, k = tid % NC;
+  const int comp = (NC == 1) ? 0 : k;
+#define VAL(p, c, cell) sh.val[(p) * VS + (c) * CS + (cell)]
+#define TOP(q, c, cell) sh.top[(q) * TS + (c) * CS + (cell)]
+#define FSM(m, c, cell) sh.fs[(m) * FS + (c) * CS + (cell)]
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const mr_tile2 tl = tiles[t];
+    const mr_inst& I = insts[tl.inst];
+    if (mode < 3 && !I.active) continue;
+    const int st = mode == 3 ? 0 : mode;
+    const mr_grid g{I.p_in[st], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const mr_grid gn{I.p_un, I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const unsigned char* fl = I.flags[(mode == 0 || mode == 3) ? 0 : 1];
+    const double rdx = I.rdx, rdy = I.rdy, dt = I.dt, gam = I.gam;
+    const double alpha = (NC == 1) ? mr_bitsd(I.lfa[st]) : 0.0;
+    double* O = I.p_out[st];
+    const long long P = I.plane;
+    const int xs0 = tl.x0 - 3;                 /* strip column 0 */
+    const int x = tl.x0 - 1 + cs;
+    const bool outx = cs >= 1 && cs <= CW - 2 && x < I.nx;
+    /* ---- prologue: moment and flag rows y0-2 .. y0 ---- */
+    for (int r = tl.y0 - 2; r <= tl.y0; ++r) {
+      const int sl = mr_mod3(r);
+      for (int e = tid; e < NP * XW; e += MR_BLOCK)
+        sh.mom[sl][e / XW][e % XW] = mr2_stage_ld(g, e / XW, xs0 + e % XW, r);
+      for (int e = tid; e < XW; e += MR_BLOCK)
+        sh.flg[sl][e] = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + e, r);
+    }
+    __syncthreads();
+    double pAu = 0.0, pAv = 0.0, pAw = 0.0, pB0 = 0.0, pB1 = 0.0, pU = 0.0, pV = 0.0, pW = 0.0;
+    for (int jr = -1; jr <= tl.rows; ++jr) {
+      const int y = tl.y0 + jr;
+      /* prefetch moment and flag row y+2 (stored once row y-1 is consumed) */
+      double pre[NE];
+      unsigned char pref = 0;
+#pragma unroll
+      for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * MR_BLOCK;
+        pre[q] = (e < NP * XW) ? mr2_stage_ld(g, e / XW, xs0 + e % XW, y + 2) : 0.0;
+      }
+      if (tid < XW) pref = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + tid, y + 2);
+      /* ---- Steps 1, 2.2, 2.3 for component `comp` of cell (x, y) ---- */
+      double cu, cv, cw;
+      {
+        const int rr[3] = {mr_mod3(y - 1), mr_mod3(y), mr_mod3(y + 1)};
+        const int c0 = cs + 2;                    /* staged column of cell x */
+        double u[9], v[9], w[9];
+        int fs[9];
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            const int l = dx + 3 * dy;
+            u[l] = sh.mom[rr[dy]][3 * comp + 0][c0 + dx - 1];
+            v[l] = sh.mom[rr[dy]][3 * comp + 1][c0 + dx - 1];
+            w[l] = sh.mom[rr[dy]][3 * comp + 2][c0 + dx - 1];
+            fs[l] = sh.flg[rr[dy]][c0 + dx - 1];
+          }
+        if (fs[4]) {
+          /* troubled cell: first moments of the troubled cells of the
+             stencil modified from the unmodified input (Jacobi); rows
+             y +- 2 come from global memory (rare path) */
+#pragma unroll
+          for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+              const int l = dx + 3 * dy;
+              if (!fs[l]) continue;
+              const int cc = c0 + dx - 1;
+              const int rw = rr[dy];
+              v[l] = mr_modified_moment(sh.mom[rw][3 * comp][cc - 1], sh.mom[rw][3 * comp][cc + 1],
+                                        sh.mom[rw][3 * comp + 1][cc - 1], sh.mom[rw][3 * comp + 1][cc + 1]);
+              const double ub = dy == 0 ? mr_ld(g, comp, 0, x + dx - 1, y - 2) : sh.mom[rr[dy - 1]][3 * comp][cc];
+              const double wb = dy == 0 ? mr_ld(g, comp, 2, x + dx - 1, y - 2) : sh.mom[rr[dy - 1]][3 * comp + 2][cc];
+              const double ut = dy == 2 ? mr_ld(g, comp, 0, x + dx - 1, y + 2) : sh.mom[rr[dy + 1]][3 * comp][cc];
+              const double wt = dy == 2 ? mr_ld(g, comp, 2, x + dx - 1, y + 2) : sh.mom[rr[dy + 1]][3 * comp + 2][cc];
+              w[l] = mr_modified_moment(ub, ut, wb, wt);
+            }
+        }
+        cu = u[4];
+        cv = v[4];
+        cw = w[4];
+        double val[16];
+        mr_recon2d<BP>(u, v, w, I.W, val);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) VAL(q, comp, cs) = val[q];
+      }
+      __syncthreads();
+      /* the moment/flag slot of row y-1 is consumed: store row y+2 */
+      {
+        const int sl = mr_mod3(y + 2);
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+          const int e = tid + q * MR_BLOCK;
+          if (e < NP * XW) sh.mom[sl][e / XW][e % XW] = pre[q];
+        }
+        if (tid < XW) sh.flg[sl][tid] = pref;
+      }
+      /* ---- volume integrals and the fluxes this lane owns ---- */
+      double F[NC], G[NC], XL0[NC], XL1[NC], YB0[NC], YB1[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) F[c] = G[c] = XL0[c] = XL1[c] = YB0[c] = YB1[c] = 0.0;
+      const bool body = jr >= 0 && jr < tl.rows;
+#pragma unroll
+      for (int rr = 0; rr < 4 / NC; ++rr) {
+        const int r = (NC == 1) ? rr : k;
+        const double wr = glw(r), er = gln(r);
+        if (body) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double pt[NC], f[NC], gg[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pt[c] = VAL(q + 4 * r, c, cs);
+            if (NC == 4) mr_euler_fg(pt, gam, f, gg);
+            else { f[0] = 0.5 * pt[0] * pt[0]; gg[0] = f[0]; }
+            const double wq = glw(q) * wr;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) { F[c] += wq * f[c]; G[c] += wq * gg[c]; }
+          }
+          if (cs >= 1) {
+            double a[NC], b[NC], fh[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+              a[c] = VAL(3 + 4 * r, c, cs - 1);
+              b[c] = VAL(4 * r, c, cs);
+            }
+            mr_numflux<NC, 0>(a, b, gam, alpha, fh);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) { XL0[c] += wr * fh[c]; XL1[c] += wr * er * fh[c]; }
+          }
+        }
+        if (jr >= 0) {
+          double a[NC], b[NC], gh[NC];
+#pragma unroll
+          for (int c = 0; c < NC; ++c) {
+            a[c] = TOP(r, c, cs);
+            b[c] = VAL(r, c, cs);
+          }
+          mr_numflux<NC, 1>(a, b, gam, alpha, gh);
+#pragma unroll
+          for (int c = 0; c < NC; ++c) { YB0[c] += wr * gh[c]; YB1[c] += wr * er * gh[c]; }
+        }
+      }
+      /* lane k collects component k's sums */
+      const double fF = mr_rs<NC>(F, k), fG = mr_rs<NC>(G, k);
+      const double xl0 = mr_rs<NC>(XL0, k), xl1 = mr_rs<NC>(XL1, k);
+      const double yb0 = mr_rs<NC>(YB0, k), yb1 = mr_rs<NC>(YB1, k);
+      FSM(0, comp, cs) = xl0;
+      FSM(1, comp, cs) = xl1;
+      __syncthreads();
+      /* the row below has consumed its top trace; store this row's */
+#pragma unroll
+      for (int q = 0; q < 4; ++q) TOP(q, comp, cs) = VAL(12 + q, comp, cs);
+      /* ---- finish the row below: its top face is this row's bottom face ---- */
+      if (jr >= 1 && outx) {
+        const int yp = y - 1;
+        const double Lu = pAu - (yb0 - pB0) * rdy;
+        const double Lv = pAv - (yb1 - pB1) * rdy;
+        const double Lw = pAw - (yb0 + pB0) * (0.5 * rdy);
+        double r0, r1, r2;
+        if (mode == 3) { r0 = Lu; r1 = Lv; r2 = Lw; }
+        else if (mode == 0) { r0 = pU + dt * Lu; r1 = pV + dt * Lv; r2 = pW + dt * Lw; }
+        else {
+          const double a = mode == 1 ? 0.75 : 1.0 / 3.0, b = mode == 1 ? 0.25 : 2.0 / 3.0;
+          double un, vn, wn;
+          mr2_un_mod(gn, I.flags[0], I, comp, x, yp, &un, &vn, &wn);
+          r0 = a * un + b * pU + b * dt * Lu;
+          r1 = a * vn + b * pV + b * dt * Lv;
+          r2 = a * wn + b * pW + b * dt * Lw;
+        }
+        const long long cell = (long long)yp * I.nx + x;
+        O[(long long)(comp * 3 + 0) * P + cell] = r0;
+        O[(long long)(comp * 3 + 1) * P + cell] = r1;
+        O[(long long)(comp * 3 + 2) * P + cell] = r2;
+      }
+      /* ---- this row's partial residual (all but the top face) ---- */
+      if (cs + 1 < CW) {
+        const double xr0 = FSM(0, comp, cs + 1);
+        const double xr1 = FSM(1, comp, cs + 1);
+        pAu = -(xr0 - xl0) * rdx;
+        pAv = -(xr0 + xl0) * (0.5 * rdx) + fF * rdx;
+        pAw = -(xr1 - xl1) * rdx + fG * rdy;
+      }
+      pB0 = yb0;
+      pB1 = yb1;
+      pU = cu;
+      pV = cv;
+      pW = cw;
+      __syncthreads();
+    }
+  }
+#undef VAL
+#undef TOP
+#undef FSM
+}
+
+extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, mr_inst* d, const mr_tile2* t, int nt, int mode, int grid) {
+  if (nt <= 0) return hipSuccess;
+  const dim3 G(grid > 0 && grid < nt ? grid : nt), B(MR_BLOCK);
+#define MR_L2(NC_, BP_) hipLaunchKernelGGL((k2_stage<NC_, BP_>), G, B, 0, s, d, t, nt, mode)
+  if (nc == 1) { if (bp) MR_L2(1, true); else MR_L2(1, false); }
+  else if (nc == 4) { if (bp) MR_L2(4, true); else MR_L2(4, false); }
+  else return hipErrorInvalidValue;
+#undef MR_L2
+  return hipGetLastError();
+}
+
