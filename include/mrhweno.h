@@ -152,6 +152,17 @@ mrhweno_status mrhweno_residual(mrhweno_ctx* ctx, int instance, const void* mome
  * group per work item) -- the launch shape the autotuner chooses. */
 mrhweno_status mrhweno_set_launch(mrhweno_ctx* ctx, int rows_2d, int grid_2d);
 
+/* Autotuner: time the 2D stage kernel (in its residual-only mode, which
+ * leaves the state untouched) on the instances' current states for every
+ * candidate launch shape -- rows per work item in rows_cand (n_rows
+ * entries, each in [8, 4096]) and grid sizes in grid_cand (n_grid entries,
+ * 0 = one work group per work item) -- with `reps` timed launches each, and
+ * apply the fastest.  best_rows/best_grid/best_ms (host, may be NULL)
+ * receive the choice and its mean launch time.  Synchronises. */
+mrhweno_status mrhweno_autotune(mrhweno_ctx* ctx, const int* rows_cand, int n_rows,
+                                const int* grid_cand, int n_grid, int reps,
+                                int* best_rows, int* best_grid, float* best_ms);
+
 /* Run nsteps steps launched one kernel at a time (no graph) with HIP events
  * recorded on the context's stream between kernel classes, then
  * synchronise.  ms_out (host, 4 floats) receives the summed device time of

@@ -228,6 +228,8 @@ static mrhweno_status upload_lists(mrhweno_ctx* c) {
   return MRHWENO_OK;
 }
 
+static mrhweno_status pull(mrhweno_ctx* c);
+
 /* Event hooks of the profiling mode: called between kernel classes. */
 struct mr_prof {
   hipEvent_t ev[64];
@@ -367,6 +369,14 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
   }
   build_lists(c);
   mrhweno_status st;
+  /* flag planes start cleared (read before the first step by the probes and
+     the autotuner) */
+  for (int q = 0; q < n; ++q)
+    for (int f = 0; f < 2; ++f)
+      if (hipMemset(c->h[q].flags[f], 0, (size_t)c->h[q].fex * c->h[q].fey) != hipSuccess) {
+        delete c;
+        return fail(nullptr, MRHWENO_ERR_DEVICE, "flag plane clear failed");
+      }
   if (hipMemcpy(c->d, c->h.data(), sizeof(mr_inst) * (n + 1), hipMemcpyHostToDevice) != hipSuccess) {
     delete c;
     return fail(nullptr, MRHWENO_ERR_DEVICE, "descriptor upload failed");
@@ -401,6 +411,85 @@ mrhweno_status mrhweno_step(mrhweno_ctx* c, int nsteps) {
     else MR_CHECK(c, enqueue_step(c));
   }
   return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_autotune(mrhweno_ctx* c, const int* rows_cand, int n_rows, const int* grid_cand, int n_grid,
+                                int reps, int* best_rows, int* best_grid, float* best_ms) {
+  if (!c || !rows_cand || n_rows <= 0 || reps <= 0 || (n_grid > 0 && !grid_cand))
+    return fail(c, MRHWENO_ERR_INVALID_ARG, "bad autotune arguments");
+  for (int a = 0; a < n_rows; ++a)
+    if (rows_cand[a] < kMinRows || rows_cand[a] > 4096) return fail(c, MRHWENO_ERR_INVALID_ARG, "rows candidate out of range");
+  mrhweno_status st = pull(c);
+  if (st != MRHWENO_OK) return st;
+  bool any2d = false;
+  for (auto& g : c->groups) any2d |= g.dim == 2;
+  if (!any2d) {
+    if (best_rows) *best_rows = c->rows2;
+    if (best_grid) *best_grid = c->grid2;
+    if (best_ms) *best_ms = 0.0f;
+    return MRHWENO_OK;
+  }
+  /* residual-only descriptors: input = current state, output = a free
+     rotation buffer; the real descriptors are restored afterwards */
+  std::vector<mr_inst> saved = c->h;
+  std::vector<mr_inst> tmp = c->h;
+  for (int q = 0; q < c->n; ++q) {
+    mr_inst& I = tmp[q];
+    const int cur = I.cur;
+    I.p_in[0] = I.buf[cur];
+    I.p_un = I.buf[cur];
+    I.p_out[0] = I.buf[(cur + 1) % 3];
+    I.lfa[0] = I.lfa[0] ? I.lfa[0] : 0x3ff0000000000000ull;   /* any alpha: only the time matters */
+  }
+  MR_CHECK(c, hipMemcpy(c->d, tmp.data(), sizeof(mr_inst) * c->n, hipMemcpyHostToDevice));
+  hipEvent_t e0, e1;
+  MR_CHECK(c, hipEventCreate(&e0));
+  MR_CHECK(c, hipEventCreate(&e1));
+  const int saved_rows = c->rows2, saved_grid = c->grid2;
+  float best = 1e30f;
+  int br = saved_rows, bg = saved_grid;
+  const int ng = n_grid > 0 ? n_grid : 1;
+  for (int a = 0; a < n_rows && st == MRHWENO_OK; ++a)
+    for (int b = 0; b < ng && st == MRHWENO_OK; ++b) {
+      c->rows2 = rows_cand[a];
+      c->grid2 = n_grid > 0 ? grid_cand[b] : 0;
+      build_lists(c);
+      if ((st = upload_lists(c)) != MRHWENO_OK) break;
+      auto launch = [&]() -> hipError_t {
+        for (auto& g : c->groups)
+          if (g.dim == 2) {
+            hipError_t e = mr_launch_stage2(c->stream, g.nc, g.bp, c->d, c->t2 + g.t_st2, g.n_st2, 3, c->grid2);
+            if (e != hipSuccess) return e;
+          }
+        return hipSuccess;
+      };
+      if (launch() != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, "autotune launch"); break; }
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < reps; ++r)
+        if (launch() != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, "autotune launch"); break; }
+      (void)hipEventRecord(e1, c->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, "autotune sync"); break; }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= reps;
+      if (ms < best) { best = ms; br = c->rows2; bg = c->grid2; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  /* restore the descriptors and apply the choice */
+  c->h = saved;
+  if (hipMemcpy(c->d, c->h.data(), sizeof(mr_inst) * c->n, hipMemcpyHostToDevice) != hipSuccess && st == MRHWENO_OK)
+    st = fail(c, MRHWENO_ERR_DEVICE, "descriptor restore");
+  c->rows2 = st == MRHWENO_OK ? br : saved_rows;
+  c->grid2 = st == MRHWENO_OK ? bg : saved_grid;
+  build_lists(c);
+  mrhweno_status s2 = upload_lists(c);
+  if (st == MRHWENO_OK) st = s2;
+  if (st == MRHWENO_OK) st = rebuild_graph(c);
+  if (best_rows) *best_rows = c->rows2;
+  if (best_grid) *best_grid = c->grid2;
+  if (best_ms) *best_ms = best;
+  return st;
 }
 
 mrhweno_status mrhweno_profile(mrhweno_ctx* c, int nsteps, float* ms_out, int* launches_out) {

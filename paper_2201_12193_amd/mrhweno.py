@@ -25,8 +25,8 @@ ERR_NONPHYSICAL = -4
 
 EXPORTS = ["mrhweno_workspace_bytes", "mrhweno_create", "mrhweno_step", "mrhweno_sync",
            "mrhweno_set_time", "mrhweno_last_dt", "mrhweno_reconstruct", "mrhweno_flag",
-           "mrhweno_residual", "mrhweno_set_launch", "mrhweno_profile", "mrhweno_last_error",
-           "mrhweno_destroy"]
+           "mrhweno_residual", "mrhweno_set_launch", "mrhweno_autotune", "mrhweno_profile",
+           "mrhweno_last_error", "mrhweno_destroy"]
 
 
 class MrProblem(C.Structure):
@@ -80,6 +80,8 @@ def lib():
         L.mrhweno_residual.argtypes = [vp, C.c_int, vp, vp, vp]
         L.mrhweno_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.mrhweno_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int)]
+        IP = C.POINTER(C.c_int)
+        L.mrhweno_autotune.argtypes = [vp, IP, C.c_int, IP, C.c_int, C.c_int, IP, IP, C.POINTER(C.c_float)]
         L.mrhweno_last_error.argtypes = [vp]
         L.mrhweno_last_error.restype = C.c_char_p
         L.mrhweno_destroy.argtypes = [vp]
@@ -155,6 +157,16 @@ class Solver:
 
     def set_launch(self, rows_2d: int, grid_2d: int = 0) -> None:
         _check(self.ctx, lib().mrhweno_set_launch(self.ctx, int(rows_2d), int(grid_2d)))
+
+    def autotune(self, rows=(8, 16, 32, 64, 128), grids=(0,), reps: int = 3):
+        """Time the candidate 2D launch shapes (state untouched) and apply the
+        fastest; returns (rows, grid, ms)."""
+        r = (C.c_int * len(rows))(*rows)
+        g = (C.c_int * len(grids))(*grids)
+        br, bg, bm = C.c_int(), C.c_int(), C.c_float()
+        _check(self.ctx, lib().mrhweno_autotune(self.ctx, r, len(rows), g, len(grids), int(reps),
+                                                C.byref(br), C.byref(bg), C.byref(bm)))
+        return br.value, bg.value, bm.value
 
     def profile(self, nsteps: int):
         """Advance nsteps with per-kernel-class HIP event timing.  Returns
