@@ -55,14 +55,18 @@ typedef enum {
   MRHWENO_ERR_INVALID_ARG = -1,
   MRHWENO_ERR_UNSUPPORTED = -2,
   MRHWENO_ERR_DEVICE = -3,
-  MRHWENO_ERR_NONPHYSICAL = -4
+  MRHWENO_ERR_NONPHYSICAL = -4,
+  MRHWENO_ERR_NOT_READY = -5    /* learned indicator used before its weights are set */
 } mrhweno_status;
 
 typedef enum { MRHWENO_BURGERS_LF = 0, MRHWENO_EULER_HLLC = 1 } mrhweno_flux;
 typedef enum { MRHWENO_BC_PERIODIC = 0, MRHWENO_BC_TRANSMISSIVE = 1 } mrhweno_bc;
 /* Step 2 variants named as in the paper's Sec. 3: HWENO6 (no
  * modification), HWENO6-M5-I (KXRCF-flagged cells), HWENO6-M5-NI (every
- * cell); LEARNED uses the learned indicator with a KXRCF fallback band. */
+ * cell).  LEARNED (2D Euler only; not part of the paper) takes the
+ * troubled-cell decision of Step 2.1 from a small network trained on KXRCF
+ * flags (mrhweno_set_indicator) and falls back to KXRCF for cells whose
+ * score lies in an uncertainty band. */
 typedef enum {
   MRHWENO_TC_NONE = 0,
   MRHWENO_TC_KXRCF = 1,
@@ -166,11 +170,91 @@ mrhweno_status mrhweno_autotune(mrhweno_ctx* ctx, const int* rows_cand, int n_ro
 /* Run nsteps steps launched one kernel at a time (no graph) with HIP events
  * recorded on the context's stream between kernel classes, then
  * synchronise.  ms_out (host, 4 floats) receives the summed device time of
- * [0] wave-speed reductions and dt, [1] KXRCF face summaries, [2] flags,
+ * [0] wave-speed reductions and dt, [1] KXRCF face summaries and
+ * learned-indicator inference, [2] KXRCF flags and the band fallback,
  * [3] stage kernels (reconstruction, fluxes, residual, RK combination);
  * launches_out (host, 4 ints, or NULL) the number of launches of each.
  * The state advances exactly as with mrhweno_step. */
 mrhweno_status mrhweno_profile(mrhweno_ctx* ctx, int nsteps, float* ms_out, int* launches_out);
+
+/* ------------------------------------------------------------------------
+ * Learned troubled-cell indicator (2D Euler; an addition to the paper's
+ * method, which uses KXRCF, eq. (KXRCF_), in Step 2.1).
+ *
+ * Features of a cell (MRHWENO_MLP_FEATURES = 320 BF16 values): the cell
+ * average and first moments of rho, rho u, rho v, E on the 5 x 5 window of
+ * cells around it, each minus (averages only) the cell's own average and
+ * divided by the cell's rho, rho c (momenta; c = sound speed of the cell
+ * average) or E; then log2(h)/16; then zeros.  Index f = 32 kb + 8 g + j
+ * with slot s = 8 kb + j: s < 60 -> component s/15, moment (s/5)%3, window
+ * offset (s%5 - 2, g - 2); 60 <= s < 75 -> component g, moment (s-60)/5,
+ * offset ((s-60)%5 - 2, 2); s = 75 with g = 0 -> log2(h)/16.
+ *
+ * Network: z = W3 . relu(W2 relu(W1 x + b1) + b2) + b3, score sigmoid(z);
+ * BF16 weights and activations, FP32 accumulation.  Parameter vector of
+ * MRHWENO_MLP_PARAMS entries: W1 [64][320], b1 [64], W2 [64][64], b2 [64],
+ * W3 [64], b3, 7 zeros (BF16 for inference, FP32 for the master copy and
+ * the gradients).  The troubled-cell decision: score > band_hi flagged,
+ * score < band_lo not flagged, otherwise KXRCF.
+ * ------------------------------------------------------------------------ */
+#define MRHWENO_MLP_FEATURES 320
+#define MRHWENO_MLP_PARAMS 24776
+
+/* Set the network of every LEARNED instance: params_dev is a device BF16
+ * parameter vector (read before the call returns; the library keeps its own
+ * copy), 0 <= band_lo <= band_hi <= 1 (0.2 and 0.8 by default).
+ * Synchronises.  Steps and probes of LEARNED instances return
+ * MRHWENO_ERR_NOT_READY until this has been called. */
+mrhweno_status mrhweno_set_indicator(mrhweno_ctx* ctx, const void* params_dev,
+                                     double band_lo, double band_hi);
+
+/* The learned indicator once on a given state of a LEARNED instance:
+ *   decision_dev  device uint8 [ny][nx]: 1 flagged, 0 not flagged, 2 left to
+ *                 KXRCF (band), or NULL;
+ *   flags_dev     device uint8 [ny][nx]: the final troubled-cell map, or NULL.
+ * Synchronises. */
+mrhweno_status mrhweno_indicator(mrhweno_ctx* ctx, int instance, const void* moments_dev,
+                                 void* decision_dev, void* flags_dev);
+
+/* Features of n cells of a 2D Euler instance from a given state:
+ *   cells_dev  device int32 [n], interior cell indices j*nx + i;
+ *   out_dev    device BF16 [n][MRHWENO_MLP_FEATURES].  Synchronises. */
+mrhweno_status mrhweno_features(mrhweno_ctx* ctx, int instance, const void* moments_dev,
+                                const int* cells_dev, int n, void* out_dev);
+
+/* Training kernels (no context; asynchronous on the given hipStream_t).
+ * All buffers are device memory owned by the caller. */
+int mrhweno_mlp_param_count(void);     /* MRHWENO_MLP_PARAMS   */
+int mrhweno_mlp_feature_count(void);   /* MRHWENO_MLP_FEATURES */
+/* bytes of the activation cache of a batch of `batch` samples */
+size_t mrhweno_mlp_cache_bytes(int batch);
+
+/* C[m][n] = sum_k A[m][k] B[k][n] (M x N x K), BF16 A and B, FP32 C, each
+ * addressed through its own row and column strides (in elements), on the
+ * matrix cores with FP32 accumulation. */
+mrhweno_status mrhweno_mlp_gemm(void* hip_stream, int M, int N, int K,
+                                const void* A, long long sAm, long long sAk,
+                                const void* B, long long sBk, long long sBn,
+                                void* C, long long sCm, long long sCn);
+
+/* Forward pass of a batch: x BF16 [batch][320], params BF16, cache of
+ * mrhweno_mlp_cache_bytes(batch) bytes (holds the activations for the
+ * backward pass), z FP32 [batch] logits. */
+mrhweno_status mrhweno_mlp_forward(void* hip_stream, const void* x, const void* params,
+                                   void* cache, void* z, int batch);
+
+/* Backward pass of the mean binary cross-entropy of the logits of the last
+ * forward pass on the same cache: labels FP32 [batch] in {0, 1}; grads FP32
+ * [MRHWENO_MLP_PARAMS] (overwritten); loss FP32 [batch] per-sample loss. */
+mrhweno_status mrhweno_mlp_backward(void* hip_stream, const void* x, const void* params,
+                                    void* cache, const void* labels, void* grads,
+                                    void* loss, int batch);
+
+/* One Adam step (step >= 1) on the FP32 master parameters, m and v
+ * moments (FP32), refreshing the BF16 copy params. */
+mrhweno_status mrhweno_mlp_adam(void* hip_stream, void* master, void* params, const void* grads,
+                                void* m, void* v, int step, float lr, float beta1,
+                                float beta2, float eps);
 
 /* Most recent error message (thread-local when ctx is NULL). */
 const char* mrhweno_last_error(const mrhweno_ctx* ctx);

@@ -70,6 +70,7 @@ def lib():
         L.orc_monomials_2d.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_hllc.argtypes = [D, D, C.c_int, C.c_int, C.c_double, D]
         L.orc_residual.argtypes = [P, D, D, B]
+        L.orc_residual_given.argtypes = [P, D, B, D]
         L.orc_reconstruct.argtypes = [P, D, D, B, D, D]
         L.orc_wave_speeds.argtypes = [P, D, D]
         L.orc_dt.argtypes = [P, D, C.c_double]
@@ -180,6 +181,19 @@ def residual(prob, U) -> Tuple[np.ndarray, np.ndarray]:
     flags = np.zeros(prob.ncell, dtype=np.uint8)
     lib().orc_residual(C.byref(cprob(prob)), _dp(U), _dp(L), _bp(flags))
     return L, flags.reshape(prob.shape()[2:])
+
+
+def residual_given(prob, U, flags_ext) -> np.ndarray:
+    """2D L(U) with the troubled-cell map of cells [-2, n+2)^2 supplied as a
+    (ny+4, nx+4) uint8 array instead of Step 2.1."""
+    U = _arr(U).reshape(prob.shape())
+    fe = np.ascontiguousarray(flags_ext, dtype=np.uint8)
+    if prob.dim != 2 or fe.shape != (prob.ny + 4, prob.nx + 4):
+        raise ValueError("2D problem and a (ny+4, nx+4) flag map required")
+    L = np.zeros_like(U)
+    if lib().orc_residual_given(C.byref(cprob(prob)), _dp(U), _bp(fe), _dp(L)) != 0:
+        raise RuntimeError("orc_residual_given failed")
+    return L
 
 
 def reconstruct(prob, U):

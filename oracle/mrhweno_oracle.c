@@ -891,7 +891,9 @@ static void kxrcf_2d(const orc_problem* P, const work2_t* W, int i, int j,
   *den_out = den;
 }
 
-static void op2d_values(const orc_problem* P, const double* U, work2_t* W) {
+/* given: optional troubled-cell map of cells [-2, n+2)^2 supplied by the
+   caller ((nx+4) x (ny+4), x fastest) in place of Step 2.1 */
+static void op2d_values(const orc_problem* P, const double* U, work2_t* W, const unsigned char* given) {
   init_1d();
   init_2d();
   grid_t G = {P, U, ncomp_of(P), 3};
@@ -909,6 +911,7 @@ static void op2d_values(const orc_problem* P, const double* U, work2_t* W) {
   for (int j = -2; j < P->ny + 2; ++j)
     for (int i = -2; i < P->nx + 2; ++i) {
       size_t k = w2idx(W, i, j);
+      if (given) { W->fl[k] = given[(size_t)(j + 2) * (P->nx + 4) + (i + 2)] != 0; continue; }
       if (P->tc_mode == 0) { W->fl[k] = 0; continue; }
       if (P->tc_mode == 2) { W->fl[k] = 1; continue; }
       kxrcf_2d(P, W, i, j, &W->fl[k], &W->anum[k], &W->aden[k]);
@@ -954,10 +957,11 @@ static void num_flux(const orc_problem* P, const double* uL, const double* uR, i
 
 /* L(U) of eq. (2D-equ-int-approximation) with the quadratures of eqs.
    (integral1)-(integral3). */
-static void residual_2d(const orc_problem* P, const double* U, double* L, unsigned char* flags) {
+static void residual_2d(const orc_problem* P, const double* U, double* L, unsigned char* flags,
+                        const unsigned char* given) {
   work2_t W;
   work2_alloc(P, &W);
-  op2d_values(P, U, &W);
+  op2d_values(P, U, &W, given);
   int nx = P->nx, ny = P->ny, nc = W.nc;
   double alpha = P->system == 0 ? lf_alpha(P, U) : 0.0;
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1027,7 +1031,15 @@ int orc_ncomp(const orc_problem* P) { return ncomp_of(P); }
 /* L(U); flags (optional) receive the troubled-cell map of the interior. */
 int orc_residual(const orc_problem* P, const double* U, double* L, unsigned char* flags) {
   if (P->dim == 1) residual_1d(P, U, L, flags);
-  else residual_2d(P, U, L, flags);
+  else residual_2d(P, U, L, flags, NULL);
+  return 0;
+}
+
+/* 2D L(U) with the troubled-cell map of cells [-2, n+2)^2 given by the
+   caller (Steps 2.2 and 2.3 then act on those cells). */
+int orc_residual_given(const orc_problem* P, const double* U, const unsigned char* given, double* L) {
+  if (P->dim != 2 || !given) return -1;
+  residual_2d(P, U, L, NULL, given);
   return 0;
 }
 
@@ -1054,7 +1066,7 @@ int orc_reconstruct(const orc_problem* P, const double* U, double* gl, unsigned 
   } else {
     work2_t W;
     work2_alloc(P, &W);
-    op2d_values(P, U, &W);
+    op2d_values(P, U, &W, NULL);
     size_t plane = (size_t)P->nx * P->ny;
     for (int j = 0; j < P->ny; ++j)
       for (int i = 0; i < P->nx; ++i) {

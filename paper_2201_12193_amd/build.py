@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmrhweno.so")
-SOURCES = ["mr_kernels.hip", "mr_stage2d.hip", "mr_api.hip"]
+SOURCES = ["mr_kernels.hip", "mr_stage2d.hip", "mr_mlp.hip", "mr_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions stay off (they are not needed for FP64 code)

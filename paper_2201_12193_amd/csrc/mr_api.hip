@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/mrhweno.h"
+#include "mr_mlp.h"
 #include "mr_types.h"
 
 extern "C" {
@@ -22,6 +23,17 @@ hipError_t mr_launch_flags(hipStream_t, int, mr_inst*, const mr_tile1*, int, int
 hipError_t mr_launch_stage1(hipStream_t, int, int, mr_inst*, const mr_tile1*, int, int, int);
 hipError_t mr_launch_stage2(hipStream_t, int, int, mr_inst*, const mr_tile2*, int, int, int);
 hipError_t mr_launch_values(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, double*);
+hipError_t mr_launch_zero(hipStream_t, int*, int);
+hipError_t mr_launch_pack(hipStream_t, const void*, mr_learn_w*);
+hipError_t mr_launch_learned(hipStream_t, mr_inst*, const mr_tile2*, int, int, const mr_learn_w*, mr_band*, int*, int);
+hipError_t mr_launch_fallback(hipStream_t, mr_inst*, const mr_band*, const int*, int, int);
+hipError_t mr_launch_features(hipStream_t, const mr_inst*, int, const int*, int, void*);
+size_t mr_mlp_cache_bytes(int);
+hipError_t mr_mlp_gemm(hipStream_t, int, int, int, const void*, long long, long long, const void*, long long,
+                       long long, void*, long long, long long);
+hipError_t mr_mlp_forward(hipStream_t, const void*, const void*, void*, void*, int);
+hipError_t mr_mlp_backward(hipStream_t, const void*, const void*, void*, const void*, void*, void*, int);
+hipError_t mr_mlp_adam(hipStream_t, void*, void*, const void*, void*, void*, int, float, float, float, float);
 }
 
 namespace {
@@ -30,6 +42,8 @@ constexpr int kBlock = 256;
 constexpr int kFHalo = 2;   /* flags: final values of cells -1..n need flags -2..n+1 */
 constexpr int kSHalo = 3;   /* summaries: flags of cells -2..n+1 need summaries -3..n+2 */
 constexpr int kMinRows = 8; /* smallest 2D strip height the work lists are sized for */
+constexpr int kLearnW = 64;     /* learned-indicator work item: 64 columns ...       */
+constexpr int kLearnRows = 32;  /* ... x 32 rows of the extended flag range          */
 
 thread_local std::string g_err;
 
@@ -39,12 +53,18 @@ int ncomp_of(const mrhweno_problem& p) { return p.flux == MRHWENO_BURGERS_LF ? 1
 long long plane_of(const mrhweno_problem& p) { return (long long)p.nx * (p.dim == 2 ? p.ny : 1); }
 size_t state_bytes(const mrhweno_problem& p) { return sizeof(double) * ncomp_of(p) * (p.dim + 1) * plane_of(p); }
 int ext(int n, int h) { return n + 2 * h; }
+int ceil_div_i(int a, int b) { return (a + b - 1) / b; }
 int fex(const mrhweno_problem& p) { return ext(p.nx, kFHalo); }
 int fey(const mrhweno_problem& p) { return p.dim == 2 ? ext(p.ny, kFHalo) : 1; }
 int sex(const mrhweno_problem& p) { return ext(p.nx, kSHalo); }
 int sey(const mrhweno_problem& p) { return p.dim == 2 ? ext(p.ny, kSHalo) : 1; }
 int nsumm(const mrhweno_problem& p) { return p.dim == 1 ? 5 : 9; }
-bool needs_summ(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_KXRCF || p.tc_mode == MRHWENO_TC_LEARNED; }
+bool needs_summ(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_KXRCF; }
+bool learned(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_LEARNED; }
+/* work items of the learned indicator: strips over [-2, n+2)^2 */
+int learn_tiles(const mrhweno_problem& p) {
+  return learned(p) ? ceil_div_i(ext(p.nx, kFHalo), kLearnW) * ceil_div_i(ext(p.ny, kFHalo), kLearnRows) : 0;
+}
 int strip_cells(const mrhweno_problem& p) { return kBlock / ncomp_of(p); }   /* 2D strip width incl. ring */
 
 std::string validate(const mrhweno_problem& p) {
@@ -60,6 +80,8 @@ std::string validate(const mrhweno_problem& p) {
   if (!(p.eps > 0.0)) return "eps must be positive";
   if (p.tc_mode < 0 || p.tc_mode > 3) return "unknown troubled-cell mode";
   if (p.beta_on != 0 && p.beta_on != 1) return "unknown beta_on";
+  if (p.tc_mode == MRHWENO_TC_LEARNED && (p.dim != 2 || p.flux != MRHWENO_EULER_HLLC))
+    return "the learned indicator is for 2D Euler";
   if (p.dim == 2) {
     const double dx = (p.x1 - p.x0) / p.nx, dy = (p.y1 - p.y0) / p.ny;
     if (std::fabs(dx - dy) > 1e-12 * std::max(dx, dy)) return "2D cells must be square (dx == dy)";
@@ -71,8 +93,9 @@ std::string validate(const mrhweno_problem& p) {
 /* workspace layout, computed identically for sizing and for creation */
 struct Layout {
   size_t insts = 0, tiles1 = 0, tiles2 = 0, probe_tiles = 0, probe_aleph = 0, total = 0;
+  size_t lw = 0, cnt = 0, band = 0, tilesl = 0;   /* learned indicator */
   std::vector<size_t> buf1, buf2, fl0, fl1, summ;
-  size_t n_tiles1 = 0, n_tiles2 = 0, n_probe_tiles = 0;
+  size_t n_tiles1 = 0, n_tiles2 = 0, n_probe_tiles = 0, n_tilesl = 0, n_band = 0;
 };
 
 int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -92,7 +115,10 @@ Layout layout(const mrhweno_problem* P, int n) {
     if (p.dim == 1) a += ceil_div(p.nx, kBlock - 2);
     else t2 += (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows);
     t1 += a;
-    tmax = std::max(tmax, a + (p.dim == 2 ? (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) : 0));
+    tmax = std::max(tmax, a + learn_tiles(p) +
+                              (p.dim == 2 ? (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) : 0));
+    L.n_tilesl += learn_tiles(p);
+    if (learned(p)) L.n_band += (size_t)fex(p) * fey(p);
   }
   L.n_tiles1 = t1;
   L.n_tiles2 = t2;
@@ -102,7 +128,13 @@ Layout layout(const mrhweno_problem* P, int n) {
   L.tiles2 = off;
   off += al(sizeof(mr_tile2) * std::max<size_t>(t2, 1));
   L.probe_tiles = off;
-  off += al(sizeof(mr_tile2) * (tmax + 32));
+  off += al(sizeof(mr_tile2) * (tmax + 64));
+  if (L.n_tilesl) {
+    L.lw = off; off += al(sizeof(mr_learn_w));
+    L.cnt = off; off += al(4 * sizeof(int));
+    L.band = off; off += al(sizeof(mr_band) * L.n_band);
+    L.tilesl = off; off += al(sizeof(mr_tile2) * L.n_tilesl);
+  }
   long long maxplane = 1;
   for (int q = 0; q < n; ++q) maxplane = std::max(maxplane, plane_of(P[q]));
   L.probe_aleph = off;
@@ -129,6 +161,13 @@ struct Group {
   int t_st2 = 0, n_st2 = 0;
 };
 
+/* learned-indicator work items of one instance (instance id `slot`) */
+void add_learn_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p) {
+  for (int y0 = -kFHalo; y0 < p.ny + kFHalo; y0 += kLearnRows)
+    for (int x0 = -kFHalo; x0 < p.nx + kFHalo; x0 += kLearnW)
+      v.push_back(mr_tile2{slot, x0, y0, std::min(kLearnRows, p.ny + kFHalo - y0)});
+}
+
 }  // namespace
 
 struct mrhweno_ctx {
@@ -146,6 +185,13 @@ struct mrhweno_ctx {
   std::vector<mr_tile1> h_t1;
   std::vector<mr_tile2> h_t2;
   int rows2 = 32, grid2 = 0;
+  /* learned indicator */
+  bool any_learned = false, weights_set = false;
+  mr_learn_w* lw = nullptr;
+  int* cnt = nullptr;
+  mr_band* band = nullptr;
+  mr_tile2* tl = nullptr;
+  int n_tl = 0, grid_l = 512, grid_fb = 1024;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool any_lf = false;
@@ -194,7 +240,8 @@ static void build_lists(mrhweno_ctx* c) {
       if (needs_summ(c->probs[q])) add_cells(c->h_t1, q, (long long)sex(c->probs[q]) * sey(c->probs[q]));
     g.n_summ = (int)c->h_t1.size() - g.t_summ;
     g.t_flag = (int)c->h_t1.size();
-    for (int q : g.insts) add_cells(c->h_t1, q, (long long)fex(c->probs[q]) * fey(c->probs[q]));
+    for (int q : g.insts)
+      if (!learned(c->probs[q])) add_cells(c->h_t1, q, (long long)fex(c->probs[q]) * fey(c->probs[q]));
     g.n_flag = (int)c->h_t1.size() - g.t_flag;
     g.t_st1 = (int)c->h_t1.size();
     if (g.dim == 1)
@@ -253,6 +300,7 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
   if ((e = mark(c, P, -1)) != hipSuccess) return e;
   if ((e = mr_launch_reduce(s, c->d, c->t1 + c->t_reduce, c->n_reduce, 0)) != hipSuccess) return e;
   if ((e = mr_launch_finalize(s, c->d, c->n, 0)) != hipSuccess) return e;
+  if (c->any_learned && (e = mr_launch_zero(s, c->cnt, 3)) != hipSuccess) return e;
   if ((e = mark(c, P, 0)) != hipSuccess) return e;
   for (int st = 0; st < 3; ++st) {
     if (st > 0 && c->any_lf) {
@@ -265,9 +313,15 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
         any = true;
         if ((e = mr_launch_summary(s, g.dim, g.bp, c->d, c->t1 + g.t_summ, g.n_summ, st)) != hipSuccess) return e;
       }
+    if (c->any_learned) {
+      any = true;
+      if ((e = mr_launch_learned(s, c->d, c->tl, c->n_tl, st, c->lw, c->band, c->cnt, c->grid_l)) != hipSuccess)
+        return e;
+    }
     if (any && (e = mark(c, P, 1)) != hipSuccess) return e;
     for (auto& g : c->groups)
-      if ((e = mr_launch_flags(s, g.dim, c->d, c->t1 + g.t_flag, g.n_flag, st)) != hipSuccess) return e;
+      if (g.n_flag > 0 && (e = mr_launch_flags(s, g.dim, c->d, c->t1 + g.t_flag, g.n_flag, st)) != hipSuccess) return e;
+    if (c->any_learned && (e = mr_launch_fallback(s, c->d, c->band, c->cnt, st, c->grid_fb)) != hipSuccess) return e;
     if ((e = mark(c, P, 2)) != hipSuccess) return e;
     for (auto& g : c->groups) {
       if (g.dim == 1) e = mr_launch_stage1(s, g.nc, g.bp, c->d, c->t1 + g.t_st1, g.n_st1, st, 0);
@@ -283,6 +337,7 @@ static mrhweno_status rebuild_graph(mrhweno_ctx* c) {
   if (c->exec) { (void)hipGraphExecDestroy(c->exec); c->exec = nullptr; }
   if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
   if (!c->stream) return MRHWENO_OK;   /* the legacy default stream cannot be captured */
+  if (c->any_learned && !c->weights_set) return MRHWENO_OK;   /* captured once weights are set */
   MR_CHECK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   hipError_t e = enqueue_step(c);
   hipGraph_t g = nullptr;
@@ -356,6 +411,29 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     if (p.flux == MRHWENO_BURGERS_LF) c->any_lf = true;
   }
   std::memset(&c->h[n], 0, sizeof(mr_inst));
+  /* learned indicator: work items, band list, counters */
+  if (c->L.n_tilesl) {
+    c->any_learned = true;
+    c->lw = (mr_learn_w*)(c->ws + c->L.lw);
+    c->cnt = (int*)(c->ws + c->L.cnt);
+    c->band = (mr_band*)(c->ws + c->L.band);
+    c->tl = (mr_tile2*)(c->ws + c->L.tilesl);
+    std::vector<mr_tile2> tl;
+    for (int q = 0; q < n; ++q)
+      if (learned(probs[q])) add_learn_tiles(tl, q, probs[q]);
+    c->n_tl = (int)tl.size();
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+      c->grid_l = 2 * cus;    /* two work groups of the fused kernel per CU */
+      c->grid_fb = 4 * cus;
+    }
+    if (hipMemcpy(c->tl, tl.data(), sizeof(mr_tile2) * tl.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(c->cnt, 0, 4 * sizeof(int)) != hipSuccess) {
+      delete c;
+      return fail(nullptr, MRHWENO_ERR_DEVICE, "learned-indicator set-up failed");
+    }
+  }
   /* launch groups */
   for (int q = 0; q < n; ++q) {
     const auto& p = probs[q];
@@ -406,6 +484,8 @@ mrhweno_status mrhweno_set_launch(mrhweno_ctx* c, int rows_2d, int grid_2d) {
 mrhweno_status mrhweno_step(mrhweno_ctx* c, int nsteps) {
   if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
   if (nsteps < 0) return fail(c, MRHWENO_ERR_INVALID_ARG, "nsteps < 0");
+  if (c->any_learned && !c->weights_set)
+    return fail(c, MRHWENO_ERR_NOT_READY, "learned indicator has no weights (mrhweno_set_indicator)");
   for (int k = 0; k < nsteps; ++k) {
     if (c->exec) MR_CHECK(c, hipGraphLaunch(c->exec, c->stream));
     else MR_CHECK(c, enqueue_step(c));
@@ -494,6 +574,8 @@ mrhweno_status mrhweno_autotune(mrhweno_ctx* c, const int* rows_cand, int n_rows
 
 mrhweno_status mrhweno_profile(mrhweno_ctx* c, int nsteps, float* ms_out, int* launches_out) {
   if (!c || !ms_out || nsteps < 0) return fail(c, MRHWENO_ERR_INVALID_ARG, "bad argument");
+  if (c->any_learned && !c->weights_set)
+    return fail(c, MRHWENO_ERR_NOT_READY, "learned indicator has no weights (mrhweno_set_indicator)");
   for (int k = 0; k < 4; ++k) { ms_out[k] = 0.0f; if (launches_out) launches_out[k] = 0; }
   mr_prof P;
   for (int k = 0; k < 64; ++k) MR_CHECK(c, hipEventCreate(&P.ev[k]));
@@ -562,14 +644,20 @@ mrhweno_status mrhweno_last_dt(mrhweno_ctx* c, double* dt_out) {
   return MRHWENO_OK;
 }
 
-/* kind: 0 = reconstruct, 1 = flag, 2 = residual */
+/* kind: 0 = reconstruct, 1 = flag, 2 = residual, 3 = learned-indicator
+   decisions (out = decision plane, may be NULL) */
 static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, void* flags, void* aleph, int kind) {
   if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
   if (q < 0 || q >= c->n || !U) return fail(c, MRHWENO_ERR_INVALID_ARG, "bad instance or NULL state");
-  if (kind != 1 && !out) return fail(c, MRHWENO_ERR_INVALID_ARG, "NULL output");
+  if ((kind == 0 || kind == 2) && !out) return fail(c, MRHWENO_ERR_INVALID_ARG, "NULL output");
+  const auto& p = c->probs[q];
+  const bool lrn = learned(p);
+  if (lrn && !c->weights_set)
+    return fail(c, MRHWENO_ERR_NOT_READY, "learned indicator has no weights (mrhweno_set_indicator)");
+  if (kind == 3 && !lrn) return fail(c, MRHWENO_ERR_INVALID_ARG, "instance does not use the learned indicator");
+  if (lrn && aleph) return fail(c, MRHWENO_ERR_UNSUPPORTED, "KXRCF ratios are not formed for learned-indicator instances");
   mrhweno_status st = pull(c);   /* the probe reuses the instance's scratch planes */
   if (st != MRHWENO_OK) return st;
-  const auto& p = c->probs[q];
   mr_inst I = c->h[q];
   I.buf[0] = (double*)U;
   I.cur = 0;
@@ -582,7 +670,6 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   I.dt = 0.0;
   double* al_buf = (double*)(c->ws + c->L.probe_aleph);
   I.aleph = aleph ? al_buf : nullptr;
-  /* probe with tc = LEARNED falls back to KXRCF for the flags */
   const int slot = c->n;
   std::vector<mr_tile1> t1;
   add_cells(t1, slot, plane_of(p));
@@ -591,13 +678,13 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   if (needs_summ(p)) add_cells(t1, slot, (long long)sex(p) * sey(p));
   const int n_sum = (int)t1.size() - t_sum;
   const int t_flg = (int)t1.size();
-  add_cells(t1, slot, (long long)fex(p) * fey(p));
+  if (!lrn) add_cells(t1, slot, (long long)fex(p) * fey(p));
   const int n_flg = (int)t1.size() - t_flg;
   const int t_val = (int)t1.size();
   add_cells(t1, slot, plane_of(p));
   const int n_val = (int)t1.size() - t_val;
   const int t_st = (int)t1.size();
-  std::vector<mr_tile2> t2;
+  std::vector<mr_tile2> t2, tl;
   if (p.dim == 1) {
     for (int s = 0; s < p.nx; s += kBlock - 2) t1.push_back(mr_tile1{slot, s, std::min(kBlock - 2, p.nx - s), 0});
   } else {
@@ -606,18 +693,34 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
       for (int x0 = 0; x0 < p.nx; x0 += w) t2.push_back(mr_tile2{slot, x0, y0, std::min(32, p.ny - y0)});
   }
   const int n_st = (int)t1.size() - t_st;
-  mr_tile1* d1 = (mr_tile1*)(c->ws + c->L.probe_tiles);
-  if (t1.size() + t2.size() + 16 > c->L.n_probe_tiles + 32) return fail(c, MRHWENO_ERR_DEVICE, "probe list overflow");
-  /* the probe area holds the 1D list followed by the 2D list */
+  if (lrn) add_learn_tiles(tl, slot, p);
+  /* the probe area holds the 1D list, the 2D list and the learned list */
+  char* area = c->ws + c->L.probe_tiles;
+  const size_t o2 = al(sizeof(mr_tile1) * t1.size());
+  const size_t o3 = o2 + al(sizeof(mr_tile2) * std::max<size_t>(t2.size(), 1));
+  if (o3 + sizeof(mr_tile2) * tl.size() > sizeof(mr_tile2) * (c->L.n_probe_tiles + 64))
+    return fail(c, MRHWENO_ERR_DEVICE, "probe list overflow");
+  mr_tile1* d1 = (mr_tile1*)area;
+  mr_tile2* d2 = (mr_tile2*)(area + o2);
+  mr_tile2* d3 = (mr_tile2*)(area + o3);
   MR_CHECK(c, hipMemcpy(&c->d[slot], &I, sizeof(mr_inst), hipMemcpyHostToDevice));
   MR_CHECK(c, hipMemcpy(d1, t1.data(), sizeof(mr_tile1) * t1.size(), hipMemcpyHostToDevice));
-  mr_tile2* d2 = (mr_tile2*)((char*)d1 + al(sizeof(mr_tile1) * t1.size()));
   if (!t2.empty()) MR_CHECK(c, hipMemcpy(d2, t2.data(), sizeof(mr_tile2) * t2.size(), hipMemcpyHostToDevice));
+  if (!tl.empty()) MR_CHECK(c, hipMemcpy(d3, tl.data(), sizeof(mr_tile2) * tl.size(), hipMemcpyHostToDevice));
   hipStream_t s = c->stream;
+  const size_t frow = (size_t)(p.dim == 2 ? kFHalo : 0) * I.fex + kFHalo;   /* first interior flag */
   MR_CHECK(c, mr_launch_reduce(s, c->d, d1, n_red, 0));
   MR_CHECK(c, mr_launch_finalize(s, c->d + slot, 1, 1));
-  MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, c->d, d1 + t_sum, n_sum, 3));
-  MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));
+  if (lrn) {
+    MR_CHECK(c, mr_launch_zero(s, c->cnt + 3, 1));
+    MR_CHECK(c, mr_launch_learned(s, c->d, d3, (int)tl.size(), 3, c->lw, c->band, c->cnt, c->grid_l));
+    if (kind == 3 && out)
+      MR_CHECK(c, hipMemcpy2DAsync(out, p.nx, I.flags[0] + frow, I.fex, p.nx, p.ny, hipMemcpyDeviceToDevice, s));
+    MR_CHECK(c, mr_launch_fallback(s, c->d, c->band, c->cnt, 3, c->grid_fb));
+  } else {
+    MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, c->d, d1 + t_sum, n_sum, 3));
+    MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));
+  }
   const int nc = ncomp_of(p);
   if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + t_val, n_val, (double*)out));
   if (kind == 2) {
@@ -625,8 +728,8 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
     else MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, c->d, d2, (int)t2.size(), 3, 0));
   }
   if (flags)
-    MR_CHECK(c, hipMemcpy2DAsync(flags, p.nx, I.flags[0] + (size_t)(p.dim == 2 ? kFHalo : 0) * I.fex + kFHalo, I.fex,
-                                 p.nx, p.dim == 2 ? p.ny : 1, hipMemcpyDeviceToDevice, s));
+    MR_CHECK(c, hipMemcpy2DAsync(flags, p.nx, I.flags[0] + frow, I.fex, p.nx, p.dim == 2 ? p.ny : 1,
+                                 hipMemcpyDeviceToDevice, s));
   if (aleph)
     MR_CHECK(c, hipMemcpyAsync(aleph, al_buf, sizeof(double) * 2 * plane_of(p), hipMemcpyDeviceToDevice, s));
   MR_CHECK(c, hipStreamSynchronize(s));
@@ -642,6 +745,84 @@ mrhweno_status mrhweno_flag(mrhweno_ctx* c, int q, const void* U, void* flags, v
 }
 mrhweno_status mrhweno_residual(mrhweno_ctx* c, int q, const void* U, void* R, void* flags) {
   return probe(c, q, U, R, flags, nullptr, 2);
+}
+
+mrhweno_status mrhweno_indicator(mrhweno_ctx* c, int q, const void* U, void* decision, void* flags) {
+  return probe(c, q, U, decision, flags, nullptr, 3);
+}
+
+mrhweno_status mrhweno_set_indicator(mrhweno_ctx* c, const void* params, double band_lo, double band_hi) {
+  if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
+  if (!params) return fail(c, MRHWENO_ERR_INVALID_ARG, "NULL parameters");
+  if (!(band_lo >= 0.0) || !(band_hi <= 1.0) || !(band_lo <= band_hi))
+    return fail(c, MRHWENO_ERR_INVALID_ARG, "band must satisfy 0 <= band_lo <= band_hi <= 1");
+  if (!c->any_learned) return fail(c, MRHWENO_ERR_INVALID_ARG, "no instance uses the learned indicator");
+  mrhweno_status st = pull(c);
+  if (st != MRHWENO_OK) return st;
+  MR_CHECK(c, mr_launch_pack(c->stream, params, c->lw));
+  for (int q = 0; q < c->n; ++q) {
+    c->h[q].band_lo = band_lo;
+    c->h[q].band_hi = band_hi;
+  }
+  MR_CHECK(c, hipStreamSynchronize(c->stream));
+  MR_CHECK(c, hipMemcpy(c->d, c->h.data(), sizeof(mr_inst) * c->n, hipMemcpyHostToDevice));
+  c->weights_set = true;
+  return rebuild_graph(c);
+}
+
+mrhweno_status mrhweno_features(mrhweno_ctx* c, int q, const void* U, const int* cells, int n, void* out) {
+  if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
+  if (q < 0 || q >= c->n || !U || !cells || !out || n < 0)
+    return fail(c, MRHWENO_ERR_INVALID_ARG, "bad instance, count or NULL pointer");
+  const auto& p = c->probs[q];
+  if (p.dim != 2 || p.flux != MRHWENO_EULER_HLLC) return fail(c, MRHWENO_ERR_INVALID_ARG, "features are for 2D Euler");
+  if (n == 0) return MRHWENO_OK;
+  mrhweno_status st = pull(c);
+  if (st != MRHWENO_OK) return st;
+  mr_inst I = c->h[q];
+  I.p_in[0] = (const double*)U;
+  const int slot = c->n;
+  MR_CHECK(c, hipMemcpy(&c->d[slot], &I, sizeof(mr_inst), hipMemcpyHostToDevice));
+  MR_CHECK(c, mr_launch_features(c->stream, c->d, slot, cells, n, out));
+  MR_CHECK(c, hipStreamSynchronize(c->stream));
+  return MRHWENO_OK;
+}
+
+/* ---- network training (stateless; on the caller's stream) ---- */
+int mrhweno_mlp_param_count(void) { return MR_NPARAM; }
+int mrhweno_mlp_feature_count(void) { return MR_KP; }
+size_t mrhweno_mlp_cache_bytes(int batch) { return mr_mlp_cache_bytes(batch); }
+
+#define MR_MLP_CHECK(expr)                                                                     do {                                                                                           hipError_t e_ = (expr);                                                                      if (e_ != hipSuccess) return fail(nullptr, MRHWENO_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   } while (0)
+
+mrhweno_status mrhweno_mlp_gemm(void* stream, int M, int N, int K, const void* A, long long sAm, long long sAk,
+                                const void* B, long long sBk, long long sBn, void* Cm, long long sCm, long long sCn) {
+  if (M <= 0 || N <= 0 || K <= 0 || !A || !B || !Cm) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "bad GEMM arguments");
+  MR_MLP_CHECK(mr_mlp_gemm((hipStream_t)stream, M, N, K, A, sAm, sAk, B, sBk, sBn, Cm, sCm, sCn));
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_mlp_forward(void* stream, const void* x, const void* params, void* cache, void* z, int batch) {
+  if (!x || !params || !cache || !z || batch <= 0) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "bad forward arguments");
+  MR_MLP_CHECK(mr_mlp_forward((hipStream_t)stream, x, params, cache, z, batch));
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_mlp_backward(void* stream, const void* x, const void* params, void* cache, const void* labels,
+                                    void* grads, void* loss, int batch) {
+  if (!x || !params || !cache || !labels || !grads || !loss || batch <= 0)
+    return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "bad backward arguments");
+  MR_MLP_CHECK(mr_mlp_backward((hipStream_t)stream, x, params, cache, labels, grads, loss, batch));
+  return MRHWENO_OK;
+}
+
+mrhweno_status mrhweno_mlp_adam(void* stream, void* master, void* params, const void* grads, void* m, void* v,
+                                int step, float lr, float beta1, float beta2, float eps) {
+  if (!master || !params || !grads || !m || !v || step < 1 || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+      !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "bad Adam arguments");
+  MR_MLP_CHECK(mr_mlp_adam((hipStream_t)stream, master, params, grads, m, v, step, lr, beta1, beta2, eps));
+  return MRHWENO_OK;
 }
 
 const char* mrhweno_last_error(const mrhweno_ctx* c) {

@@ -81,6 +81,59 @@ MR_INL void mr2_cell_values(const mr_grid& g, const mr_inst& I, const unsigned c
   mr_recon2d<BP>(u, v, w, I.W, out);
 }
 
+/* KXRCF face data of cell (i, j) from its Step-1 values, eqs. (KXRCF_),
+ * (line-integral-average_): f[0..3] Gauss-Lobatto means of the indicator
+ * variable (density; u for Burgers) on the left, right, bottom, top face,
+ * f[4..7] the same for the normal velocity, f[8] the max |u| over the 16
+ * points. */
+template <bool BP>
+MR_INL void mr2_face_summary(const mr_grid& g, const mr_inst& I, int i, int j, double f[9]) {
+  double rho[16];
+  double sl = 0.0, sr = 0.0, sb = 0.0, st = 0.0, nrm = 0.0;
+  double vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
+  const int ncomp = I.flux == 1 ? 3 : 1;
+#pragma unroll 1
+  for (int c = 0; c < ncomp; ++c) {
+    double u[9], v[9], w[9], r[16];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const int dx = l % 3 - 1, dy = l / 3 - 1;
+      u[l] = mr_ld(g, c, 0, i + dx, j + dy);
+      v[l] = mr_ld(g, c, 1, i + dx, j + dy);
+      w[l] = mr_ld(g, c, 2, i + dx, j + dy);
+    }
+    mr_recon2d<BP>(u, v, w, I.W, r);
+    if (c == 0) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        sl += glw(m) * r[0 + 4 * m];
+        sr += glw(m) * r[3 + 4 * m];
+        sb += glw(m) * r[m];
+        st += glw(m) * r[12 + m];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) { nrm = fmax(nrm, fabs(r[k])); rho[k] = r[k]; }
+      vl = sl; vr = sr; vb = sb; vt = st;   /* Burgers: f'(u) = u */
+      if (ncomp > 1) { vl = vr = vb = vt = 0.0; }
+    } else if (c == 1) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        vl += glw(m) * (r[0 + 4 * m] / rho[0 + 4 * m]);
+        vr += glw(m) * (r[3 + 4 * m] / rho[3 + 4 * m]);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        vb += glw(m) * (r[m] / rho[m]);
+        vt += glw(m) * (r[12 + m] / rho[12 + m]);
+      }
+    }
+  }
+  f[0] = sl; f[1] = sr; f[2] = sb; f[3] = st;
+  f[4] = vl; f[5] = vr; f[6] = vb; f[7] = vt;
+  f[8] = nrm;
+}
+
 /* U^n with the stage-1 modification applied at cell (x, y), component c */
 MR_INL void mr2_un_mod(const mr_grid& g, const unsigned char* fl1, const mr_inst& I,
                        int c, int x, int y, double* u, double* v, double* w) {

@@ -353,10 +353,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, con
 }
 
 /* ================================================================ 2D passes */
-/* KXRCF face data per cell over the extended range [-3, n+3)^2, planes:
- * 0..3 Gauss-Lobatto-weighted mean of the indicator variable on the left,
- * right, bottom, top face; 4..7 the same for the normal velocity; 8 max |u|
- * over the 16 points. */
+/* KXRCF face data (mr2_face_summary) per cell over the extended range
+ * [-3, n+3)^2, one plane per entry. */
 template <bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_summary(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
   mr_kt_fill();
@@ -364,60 +362,17 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_summary(mr_inst* insts, co
     const mr_tile1 tl = tiles[t];
     const mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
-    if (I.tc != 1 && I.tc != 3) continue;
+    if (I.tc != 1) continue;
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
     const int i = e % I.sex - I.shalo, j = e / I.sex - I.shalo;
     const mr_grid g{stage < 3 ? I.p_in[stage] : I.buf[0], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    const mr_wconst W = I.W;
-    /* component 0 gives the indicator variable; for Euler, components 1
-       and 2 give the velocities on the x and y faces */
-    double rho[16];
-    double sl = 0.0, sr = 0.0, sb = 0.0, st = 0.0, nrm = 0.0;
-    double vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
-    const int ncomp = I.flux == 1 ? 3 : 1;
-#pragma unroll 1
-    for (int c = 0; c < ncomp; ++c) {
-      double u[9], v[9], w[9], r[16];
-#pragma unroll
-      for (int l = 0; l < 9; ++l) {
-        const int dx = l % 3 - 1, dy = l / 3 - 1;
-        u[l] = mr_ld(g, c, 0, i + dx, j + dy);
-        v[l] = mr_ld(g, c, 1, i + dx, j + dy);
-        w[l] = mr_ld(g, c, 2, i + dx, j + dy);
-      }
-      mr_recon2d<BP>(u, v, w, W, r);
-      if (c == 0) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          sl += glw(m) * r[0 + 4 * m];
-          sr += glw(m) * r[3 + 4 * m];
-          sb += glw(m) * r[m];
-          st += glw(m) * r[12 + m];
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) { nrm = fmax(nrm, fabs(r[k])); rho[k] = r[k]; }
-        vl = sl; vr = sr; vb = sb; vt = st;   /* Burgers: f'(u) = u */
-        if (ncomp > 1) { vl = vr = vb = vt = 0.0; }
-      } else if (c == 1) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          vl += glw(m) * (r[0 + 4 * m] / rho[0 + 4 * m]);
-          vr += glw(m) * (r[3 + 4 * m] / rho[3 + 4 * m]);
-        }
-      } else {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          vb += glw(m) * (r[m] / rho[m]);
-          vt += glw(m) * (r[12 + m] / rho[12 + m]);
-        }
-      }
-    }
+    double f[9];
+    mr2_face_summary<BP>(g, I, i, j, f);
     const long long SE = (long long)I.sex * I.sey;
     double* S = I.summ;
-    S[0 * SE + e] = sl; S[1 * SE + e] = sr; S[2 * SE + e] = sb; S[3 * SE + e] = st;
-    S[4 * SE + e] = vl; S[5 * SE + e] = vr; S[6 * SE + e] = vb; S[7 * SE + e] = vt;
-    S[8 * SE + e] = nrm;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S[k * SE + e] = f[k];
   }
 }
 
@@ -432,6 +387,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k2_flags(mr_inst* insts, const mr_ti
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
     unsigned char* fl = I.flags[(stage == 0 || stage == 3) ? 0 : 1];
+    if (I.tc == 3) continue;   /* written by the learned indicator */
     if (I.tc == 0 || I.tc == 2) { fl[e] = (unsigned char)(I.tc == 2); continue; }
     const int i = e % I.fex - I.fhalo, j = e / I.fex - I.fhalo;
     const int sx = I.sex, d = I.shalo;

@@ -1,0 +1,213 @@
+"""Learned troubled-cell indicator: training data from the solver's own
+KXRCF runs, training on the GPU with the library's MFMA forward/backward
+kernels and Adam, and loading of the trained weights.
+
+Data: 2D Euler quadrant problems (four constant states plus a smooth
+Fourier field, periodic) at several resolutions are advanced with the KXRCF
+indicator; every few steps the KXRCF flags of the current state are the
+labels.  All flagged cells are kept, together with the unflagged cells next
+to them (the hard negatives) and a random sample of the remaining cells.
+
+Run `python -m paper_2201_12193_amd.indicator --out DIR` to train; it
+writes DIR/indicator_weights.npy (FP32 parameter vector) and
+DIR/indicator_train.json (data and training summary).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import inputs as I
+from .mrhweno import MLP_FEATURES, MLP_PARAMS, Solver, mlp_adam, mlp_backward, mlp_cache_bytes, mlp_forward
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+WEIGHTS = os.path.join(HERE, "indicator_weights.npy")
+
+NH = 64
+OFF_W1, OFF_B1 = 0, NH * MLP_FEATURES
+OFF_W2 = OFF_B1 + NH
+OFF_B2 = OFF_W2 + NH * NH
+OFF_W3 = OFF_B2 + NH
+OFF_B3 = OFF_W3 + NH
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases, zero padding columns (FP32)."""
+    rng = np.random.default_rng(seed)
+    P = np.zeros(MLP_PARAMS, dtype=np.float32)
+    nf = 301
+    W1 = np.zeros((NH, MLP_FEATURES), dtype=np.float32)
+    W1[:, :nf] = rng.standard_normal((NH, nf)) * math.sqrt(2.0 / nf)
+    P[OFF_W1:OFF_B1] = W1.ravel()
+    P[OFF_W2:OFF_B2] = (rng.standard_normal((NH, NH)) * math.sqrt(2.0 / NH)).ravel()
+    P[OFF_W3:OFF_B3] = rng.standard_normal(NH) * math.sqrt(1.0 / NH)
+    return P
+
+
+def load_weights(path: Optional[str] = None, device="cuda"):
+    """BF16 CUDA parameter tensor of the trained indicator."""
+    import torch
+    P = np.load(path or WEIGHTS)
+    if P.shape != (MLP_PARAMS,):
+        raise ValueError("indicator weights have the wrong size")
+    return torch.from_numpy(P.astype(np.float32)).to(device).to(torch.bfloat16)
+
+
+def _neighbours(mask: np.ndarray, r: int) -> np.ndarray:
+    """Cells within Chebyshev distance r of a set cell (periodic)."""
+    out = mask.copy()
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            out |= np.roll(np.roll(mask, dy, axis=0), dx, axis=1)
+    return out
+
+
+def collect(runs: Sequence[Tuple[int, int, int, int]], neg_ratio: float = 1.0, seed: int = 0,
+            log=print) -> Tuple["object", "object", Dict]:
+    """Features and KXRCF labels from the runs (seed, n, steps, every).
+    Returns (X bf16 [N][320] CUDA, y f32 [N] CUDA, summary)."""
+    import torch
+    rng = np.random.default_rng(seed)
+    Xs, ys = [], []
+    stats = {"runs": [], "cells_labelled": 0, "positives": 0, "samples": 0}
+    for (s, n, steps, every) in runs:
+        prob, U0, _ = I.euler_quadrants_2d(seed=s, n=n, nq=2)
+        prob = prob.replace(t_final=float("inf"))
+        U = torch.from_numpy(U0).cuda()
+        solver = Solver([prob], [U])
+        pos_run = 0
+        for k in range(0, steps + 1, every):
+            if k > 0:
+                solver.step(every)
+                solver.sync()
+            fl, _ = solver.flag(0, U)
+            lab = fl.cpu().numpy().astype(bool)
+            near = _neighbours(lab, 2) & ~lab
+            far = ~(lab | near)
+            pos = np.flatnonzero(lab)
+            hard = np.flatnonzero(near)
+            nfar = min(int(neg_ratio * max(pos.size, 1)), int(far.sum()))
+            rnd = rng.choice(np.flatnonzero(far), nfar, replace=False)
+            cells = np.concatenate([pos, hard, rnd]).astype(np.int32)
+            y = np.concatenate([np.ones(pos.size), np.zeros(hard.size + rnd.size)]).astype(np.float32)
+            X = solver.features(0, U, torch.from_numpy(cells).cuda())
+            Xs.append(X)
+            ys.append(torch.from_numpy(y).cuda())
+            stats["cells_labelled"] += lab.size
+            stats["positives"] += int(pos.size)
+            pos_run += int(pos.size)
+        solver.close()
+        stats["runs"].append({"seed": s, "n": n, "steps": steps, "every": every, "positives": pos_run})
+        log(f"collect: seed {s} n {n} steps {steps}: {pos_run} flagged cells", flush=True)
+    X = torch.cat(Xs)
+    y = torch.cat(ys)
+    stats["samples"] = int(y.numel())
+    return X, y, stats
+
+
+def train(X, y, steps: int = 4000, batch: int = 4096, lr: float = 2e-3, seed: int = 0, pos_weight: float = 1.0,
+          log=print, log_every: int = 500):
+    """Adam on the mean binary cross-entropy, with the library's kernels.
+    Returns (FP32 master parameters as numpy, loss history)."""
+    import torch
+    dev = X.device
+    master = torch.from_numpy(init_params(seed)).to(dev)
+    params = master.to(torch.bfloat16)
+    m = torch.zeros_like(master)
+    v = torch.zeros_like(master)
+    grads = torch.zeros_like(master)
+    cache = torch.empty(mlp_cache_bytes(batch) + 256, dtype=torch.uint8, device=dev)
+    z = torch.empty(batch, dtype=torch.float32, device=dev)
+    loss = torch.empty(batch, dtype=torch.float32, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    N = y.numel()
+    # class-balanced sampling: half positives, half negatives
+    pos = torch.nonzero(y > 0.5).squeeze(1)
+    neg = torch.nonzero(y <= 0.5).squeeze(1)
+    hist = []
+    stream = torch.cuda.current_stream()
+    for it in range(1, steps + 1):
+        ip = pos[torch.randint(pos.numel(), (batch // 2,), device=dev, generator=gen)]
+        ineg = neg[torch.randint(neg.numel(), (batch - batch // 2,), device=dev, generator=gen)]
+        idx = torch.cat([ip, ineg])
+        xb = X[idx].contiguous()
+        yb = y[idx].contiguous()
+        mlp_forward(xb, params, cache, z, stream)
+        mlp_backward(xb, params, cache, yb, grads, loss, stream)
+        mlp_adam(master, params, grads, m, v, it, lr * (0.5 * (1 + math.cos(math.pi * it / steps)) * 0.9 + 0.1),
+                 stream=stream)
+        if it == 1 or it % log_every == 0 or it == steps:
+            lv = float(loss.mean())
+            hist.append((it, lv))
+            log(f"train: step {it} loss {lv:.5f}", flush=True)
+    torch.cuda.synchronize()
+    return master.cpu().numpy(), hist
+
+
+def evaluate(P: np.ndarray, X, y, lo: float = 0.2, hi: float = 0.8, batch: int = 65536) -> Dict:
+    """Decision statistics of the trained network on labelled samples."""
+    import torch
+    dev = X.device
+    params = torch.from_numpy(P).to(dev).to(torch.bfloat16)
+    cache = torch.empty(mlp_cache_bytes(batch) + 256, dtype=torch.uint8, device=dev)
+    zs = []
+    for s in range(0, y.numel(), batch):
+        xb = X[s:s + batch].contiguous()
+        nb = xb.shape[0]
+        if nb % 16:
+            xb = torch.cat([xb, torch.zeros((16 - nb % 16, MLP_FEATURES), dtype=xb.dtype, device=dev)])
+        z = torch.empty(xb.shape[0], dtype=torch.float32, device=dev)
+        mlp_forward(xb, params, cache, z)
+        zs.append(z[:nb])
+    sg = torch.sigmoid(torch.cat(zs))
+    lab = y > 0.5
+    dec1, dec0 = sg > hi, sg < lo
+    band = ~(dec1 | dec0)
+    return {"samples": int(y.numel()), "positives": int(lab.sum()),
+            "false_negative_rate": float((dec0 & lab).sum()) / max(int(lab.sum()), 1),
+            "false_positive_rate": float((dec1 & ~lab).sum()) / max(int((~lab).sum()), 1),
+            "band_fraction": float(band.float().mean()),
+            "accuracy_confident": float(((dec1 & lab) | (dec0 & ~lab)).sum()) / max(int((~band).sum()), 1)}
+
+
+TRAIN_RUNS = [(101, 256, 400, 40), (102, 256, 400, 40), (103, 512, 400, 40), (104, 512, 300, 30),
+              (105, 1024, 300, 30), (106, 1024, 200, 40), (107, 2048, 200, 50)]
+VALID_RUNS = [(201, 512, 300, 60), (202, 1024, 200, 50)]
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--quick", action="store_true", help="small data set (smoke run)")
+    a = ap.parse_args(argv)
+    os.makedirs(a.out, exist_ok=True)
+    t0 = time.time()
+    runs = [(101, 128, 40, 20)] if a.quick else TRAIN_RUNS
+    vruns = [(201, 128, 40, 20)] if a.quick else VALID_RUNS
+    X, y, stats = collect(runs, seed=1)
+    Xv, yv, vstats = collect(vruns, seed=2)
+    t1 = time.time()
+    P, hist = train(X, y, steps=a.steps, batch=a.batch, lr=a.lr)
+    t2 = time.time()
+    summary = {"train_data": stats, "valid_data": vstats, "loss": hist,
+               "train_eval": evaluate(P, X, y), "valid_eval": evaluate(P, Xv, yv),
+               "seconds": {"collect": t1 - t0, "train": t2 - t1}, "steps": a.steps, "batch": a.batch,
+               "lr": a.lr}
+    np.save(os.path.join(a.out, "indicator_weights.npy"), P.astype(np.float32))
+    with open(os.path.join(a.out, "indicator_train.json"), "w") as f:
+        json.dump(summary, f, indent=1)
+    print(json.dumps({k: summary[k] for k in ("train_eval", "valid_eval", "seconds")}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -22,10 +22,16 @@ ERR_INVALID_ARG = -1
 ERR_UNSUPPORTED = -2
 ERR_DEVICE = -3
 ERR_NONPHYSICAL = -4
+ERR_NOT_READY = -5
+MLP_FEATURES = 320
+MLP_PARAMS = 24776
 
 EXPORTS = ["mrhweno_workspace_bytes", "mrhweno_create", "mrhweno_step", "mrhweno_sync",
            "mrhweno_set_time", "mrhweno_last_dt", "mrhweno_reconstruct", "mrhweno_flag",
            "mrhweno_residual", "mrhweno_set_launch", "mrhweno_autotune", "mrhweno_profile",
+           "mrhweno_set_indicator", "mrhweno_indicator", "mrhweno_features",
+           "mrhweno_mlp_param_count", "mrhweno_mlp_feature_count", "mrhweno_mlp_cache_bytes",
+           "mrhweno_mlp_gemm", "mrhweno_mlp_forward", "mrhweno_mlp_backward", "mrhweno_mlp_adam",
            "mrhweno_last_error", "mrhweno_destroy"]
 
 
@@ -82,6 +88,19 @@ def lib():
         L.mrhweno_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int)]
         IP = C.POINTER(C.c_int)
         L.mrhweno_autotune.argtypes = [vp, IP, C.c_int, IP, C.c_int, C.c_int, IP, IP, C.POINTER(C.c_float)]
+        L.mrhweno_set_indicator.argtypes = [vp, vp, C.c_double, C.c_double]
+        L.mrhweno_indicator.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.mrhweno_features.argtypes = [vp, C.c_int, vp, vp, C.c_int, vp]
+        L.mrhweno_mlp_param_count.argtypes = []
+        L.mrhweno_mlp_feature_count.argtypes = []
+        L.mrhweno_mlp_cache_bytes.argtypes = [C.c_int]
+        L.mrhweno_mlp_cache_bytes.restype = C.c_size_t
+        LL = C.c_longlong
+        L.mrhweno_mlp_gemm.argtypes = [vp, C.c_int, C.c_int, C.c_int, vp, LL, LL, vp, LL, LL, vp, LL, LL]
+        L.mrhweno_mlp_forward.argtypes = [vp, vp, vp, vp, vp, C.c_int]
+        L.mrhweno_mlp_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, C.c_int]
+        L.mrhweno_mlp_adam.argtypes = [vp, vp, vp, vp, vp, vp, C.c_int, C.c_float, C.c_float, C.c_float,
+                                       C.c_float]
         L.mrhweno_last_error.argtypes = [vp]
         L.mrhweno_last_error.restype = C.c_char_p
         L.mrhweno_destroy.argtypes = [vp]
@@ -208,6 +227,41 @@ class Solver:
                                                 C.c_void_p(R.data_ptr()), C.c_void_p(fl.data_ptr())))
         return R, fl
 
+    # ---------------------------------------------------- learned indicator
+    def set_indicator(self, params, band_lo: float = 0.2, band_hi: float = 0.8) -> None:
+        """params: BF16 CUDA tensor of MLP_PARAMS entries."""
+        import torch
+        if params.dtype != torch.bfloat16 or not params.is_cuda or params.numel() != MLP_PARAMS:
+            raise ValueError("params must be a bfloat16 CUDA tensor of MLP_PARAMS entries")
+        params = params.contiguous()
+        torch.cuda.synchronize()
+        _check(self.ctx, lib().mrhweno_set_indicator(self.ctx, C.c_void_p(params.data_ptr()),
+                                                     float(band_lo), float(band_hi)))
+
+    def indicator(self, instance: int, U):
+        """(decision, flags): network decision 0/1/2 (2 = left to KXRCF) and
+        the final troubled-cell map, both uint8 [ny][nx]."""
+        import torch
+        torch.cuda.synchronize()
+        p = self.problems[instance]
+        dec = torch.empty(p.shape()[2:], dtype=torch.uint8, device=U.device)
+        fl = torch.empty(p.shape()[2:], dtype=torch.uint8, device=U.device)
+        _check(self.ctx, lib().mrhweno_indicator(self.ctx, instance, C.c_void_p(U.data_ptr()),
+                                                 C.c_void_p(dec.data_ptr()), C.c_void_p(fl.data_ptr())))
+        return dec, fl
+
+    def features(self, instance: int, U, cells):
+        """BF16 [n][MLP_FEATURES] features of the interior cells `cells`
+        (int32 CUDA tensor of indices j*nx + i)."""
+        import torch
+        torch.cuda.synchronize()
+        cells = cells.to(torch.int32).contiguous()
+        out = torch.empty((cells.numel(), MLP_FEATURES), dtype=torch.bfloat16, device=U.device)
+        _check(self.ctx, lib().mrhweno_features(self.ctx, instance, C.c_void_p(U.data_ptr()),
+                                                C.c_void_p(cells.data_ptr()), int(cells.numel()),
+                                                C.c_void_p(out.data_ptr())))
+        return out
+
     def close(self) -> None:
         if getattr(self, "ctx", None):
             lib().mrhweno_destroy(self.ctx)
@@ -218,3 +272,51 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ training
+def _stream_ptr(stream) -> C.c_void_p:
+    import torch
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(st.cuda_stream)
+
+
+def mlp_cache_bytes(batch: int) -> int:
+    return int(lib().mrhweno_mlp_cache_bytes(int(batch)))
+
+
+def mlp_gemm(A, B, stream=None):
+    """C = A @ B for 2D bfloat16 CUDA tensors (any strides) on the library's
+    MFMA GEMM; returns a float32 tensor."""
+    import torch
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2 or A.dtype != torch.bfloat16 or B.dtype != torch.bfloat16:
+        raise ValueError("bf16 operands with matching inner dimension required")
+    Cm = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(None, lib().mrhweno_mlp_gemm(_stream_ptr(stream), M, N, K,
+                                        C.c_void_p(A.data_ptr()), A.stride(0), A.stride(1),
+                                        C.c_void_p(B.data_ptr()), B.stride(0), B.stride(1),
+                                        C.c_void_p(Cm.data_ptr()), Cm.stride(0), Cm.stride(1)))
+    return Cm
+
+
+def mlp_forward(x, params, cache, z, stream=None) -> None:
+    _check(None, lib().mrhweno_mlp_forward(_stream_ptr(stream), C.c_void_p(x.data_ptr()),
+                                           C.c_void_p(params.data_ptr()), C.c_void_p(cache.data_ptr()),
+                                           C.c_void_p(z.data_ptr()), int(x.shape[0])))
+
+
+def mlp_backward(x, params, cache, labels, grads, loss, stream=None) -> None:
+    _check(None, lib().mrhweno_mlp_backward(_stream_ptr(stream), C.c_void_p(x.data_ptr()),
+                                            C.c_void_p(params.data_ptr()), C.c_void_p(cache.data_ptr()),
+                                            C.c_void_p(labels.data_ptr()), C.c_void_p(grads.data_ptr()),
+                                            C.c_void_p(loss.data_ptr()), int(x.shape[0])))
+
+
+def mlp_adam(master, params, grads, m, v, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+             eps: float = 1e-8, stream=None) -> None:
+    _check(None, lib().mrhweno_mlp_adam(_stream_ptr(stream), C.c_void_p(master.data_ptr()),
+                                        C.c_void_p(params.data_ptr()), C.c_void_p(grads.data_ptr()),
+                                        C.c_void_p(m.data_ptr()), C.c_void_p(v.data_ptr()), int(step),
+                                        float(lr), float(beta1), float(beta2), float(eps)))
