@@ -1,24 +1,28 @@
 #!/usr/bin/env python3
-"""Benchmark: 2D Euler MR-HWENO cell-updates/s (FP64) on one MI355X.
+"""Benchmark: 2D Euler MR-HWENO cell-updates/s (FP64) on one MI355X, plain
+(KXRCF troubled cells) and with the learned troubled-cell indicator.
 
 Workload: 2D Euler (gamma 1.4), 2048 x 2048 periodic grid on [0, 1]^2, four
 seeded constant quadrant states overlaid with an 8-mode smooth Fourier
-field, HLLC flux, KXRCF troubled cells (HWENO6-M5-I), CFL 0.6.  One bench
-"step" is one SSP-RK3 step of the whole operator (dt reduction, KXRCF
-summaries and flags, reconstruction, fluxes, residual and stage combination
-for all three stages).  The default times 200 steps, the length of the
-configured run, after the state has been reset to t = 0.
+field, HLLC flux, HWENO6-M5-I (KXRCF troubled cells), CFL 0.6.  One bench
+"step" is one SSP-RK3 step of the whole operator (dt reduction, troubled-cell
+flags, reconstruction, fluxes, residual and stage combination for all three
+stages).  The default times 200 steps, the length of the configured run,
+after the state has been reset to t = 0.
 
 Prints one JSON line.  value = cells x RK stages / wall time of the timed
-region (inputs resident in HBM).  The timed steps are launched one kernel
-at a time with HIP events on the library's stream between kernel classes,
-which gives the per-kernel averages of the roofline entry.
+plain run (inputs resident in HBM).  The timed steps are launched one kernel
+class at a time with HIP events on the library's stream between classes,
+which gives the per-kernel averages of the roofline entry.  The learned
+path is then timed the same way and compared with the plain path at equal
+simulated time (relative L1 difference of the cell averages) and against
+KXRCF decisions on its own states (false-negative rate).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -27,11 +31,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E, vendor figure
-FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector, vendor figure
-# algorithmic HBM traffic of the stage kernel per cell and RK stage (FP64):
-# stage 1 reads U^n and writes U^(1) (2 x 96 B); stages 2 and 3 read the
-# stage input and U^n and write the output (3 x 96 B): mean 256 B
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+# algorithmic work of the stage kernel per cell and RK stage (2D Euler, FP64):
+# bytes: stage 1 reads U^n and writes U^(1) (2 x 96 B), stages 2 and 3 read
+# the stage input and U^n and write the output (3 x 96 B): mean 256 B;
+# FLOPs: Step 1 maps, smoothness indicators and weights, Gauss-Lobatto
+# evaluation, eight HLLC fluxes, volume quadratures, residual and RK update
+# at their minimal operation counts: 5.9 kFLOP
 STAGE_BYTES_PER_CELL = (2 * 96 + 3 * 96 + 3 * 96) / 3.0
+STAGE_FLOP_PER_CELL = 5900.0
+STAGE_KERNEL = "k2_stage<4,false>"
+COUNTERS = os.path.join(ROOT, "profiles", "k2_stage_euler2d_2048_counters.json")
+STAGE_SOURCES = ["mr_stage2d.hip", "mr_common.h", "mr_device.h", "mr_types.h", "recon_gen.h"]
 
 
 def parse():
@@ -41,11 +52,35 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=2048)
-    ap.add_argument("--rows", type=int, default=0, help="2D strip height (0: autotuned/default)")
+    ap.add_argument("--rows", type=int, default=0, help="2D strip height (0: default)")
+    ap.add_argument("--band", type=float, nargs=2, default=(0.1, 0.9),
+                    help="learned-indicator uncertainty band (KXRCF inside)")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     return ap.parse_args()
+
+
+def stage_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2201_12193_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(ncell: int):
+    """HBM bytes per launch of the stage kernel from the committed counter
+    profile, if it was taken on the current kernel source."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_hash") != stage_source_hash() or c.get("cells") != ncell:
+        return None
+    return c.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(prob, U0):
@@ -62,56 +97,101 @@ def cpu_baseline(prob, U0):
                       f"{dt:.1f} s on {threads} threads"}
 
 
+def timed_run(prob, U0, steps, warmup, rows=0, weights=None, band=None):
+    """Warm up, reset to t = 0, time `steps` steps with per-class events.
+    Returns (wall s, ms[4], launches[4], final time, final state)."""
+    import torch
+    from paper_2201_12193_amd.mrhweno import Solver
+    U_init = torch.from_numpy(U0).cuda()
+    Ut = U_init.clone()
+    s = Solver([prob], [Ut])
+    if weights is not None:
+        s.set_indicator(weights, *band)
+    if rows:
+        s.set_launch(rows, 0)
+    s.step(warmup)
+    s.sync()
+    Ut.copy_(U_init)
+    torch.cuda.synchronize()
+    s.set_time(0, 0.0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms, nl = s.profile(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t, _, _ = s.sync()
+    s.close()
+    return wall, ms, nl, t[0], Ut
+
+
+def learned_compare(prob, U0, Uk, T, weights, band, steps):
+    """The learned path run to the plain run's final time T (graph replay),
+    relative L1 difference of the cell averages per component, and the
+    KXRCF false-negative rate on snapshots of the learned run."""
+    import numpy as np
+    import torch
+    from paper_2201_12193_amd import inputs as I
+    from paper_2201_12193_amd.mrhweno import Solver
+    pl = prob.replace(tc_mode=I.TC_LEARNED, t_final=T)
+    U = torch.from_numpy(U0).cuda()
+    s = Solver([pl], [U])
+    s.set_indicator(weights, *band)
+    judge = Solver([prob], [torch.from_numpy(U0).cuda()])
+    fn = tp = fp = nband = ncell = 0
+    every = max(steps // 5, 1)
+    t = [0.0]
+    for k in range(6):
+        dec, fl = s.indicator(0, U)
+        fk, _ = judge.flag(0, U)
+        dec, fl, fk = dec.cpu().numpy(), fl.cpu().numpy().astype(bool), fk.cpu().numpy().astype(bool)
+        fn += int((fk & ~fl).sum())
+        tp += int((fk & fl).sum())
+        fp += int((~fk & fl).sum())
+        nband += int((dec == 2).sum())
+        ncell += dec.size
+        if k < 5:
+            s.step(every)
+    done = 5 * every
+    t, _, _ = s.sync()
+    while t[0] < T and done < 3 * steps:
+        s.step(10)         # steps past T do nothing
+        done += 10
+        t, _, _ = s.sync()
+    s.close()
+    judge.close()
+    a = U.cpu().numpy()
+    b = Uk.cpu().numpy()
+    l1 = [float(np.abs(a[c, 0] - b[c, 0]).sum() / np.abs(b[c, 0]).sum()) for c in range(prob.ncomp)]
+    return {"t": t[0], "rel_l1_diff": l1, "false_negative_rate": fn / max(fn + tp, 1),
+            "false_positives_per_kxrcf_flag": fp / max(fn + tp, 1), "kxrcf_flags_judged": fn + tp,
+            "band_fraction": nband / max(ncell, 1)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU decomposition is a design, not part of this build)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_2201_12193_amd import inputs as I
-    from paper_2201_12193_amd.mrhweno import Solver
 
     prob, U0, _ = I.euler_quadrants_2d(seed=args.seed, n=args.n, nq=2)
-    dev = torch.device("cuda:0")
-    U_init = torch.from_numpy(U0).to(dev)
-    Ut = U_init.clone()
-    s = Solver([prob], [Ut])
-    if args.rows:
-        s.set_launch(args.rows, 0)
-    # warm-up, then reset to t = 0 so the timed run is the configured run
-    s.step(args.warmup)
-    s.sync()
-    Ut.copy_(U_init)
-    torch.cuda.synchronize()
-    s.set_time(0, 0.0, 0)
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ms, nl = s.profile(args.steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    t, steps, _ = s.sync()
-    if args.calib_copy:
-        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
-        a.fill_(1.0)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        a.sum()                      # read-only pass over 1 GiB
-        torch.cuda.synchronize()
-        del a, b
+    wall, ms, nl, T, Uk = timed_run(prob, U0, args.steps, args.warmup, args.rows)
     ncell = prob.ncell
-    cell_updates = ncell * 3 * args.steps
-    value = cell_updates / wall
+    value = ncell * 3 * args.steps / wall
     stage_ms = ms[3] / max(nl[3], 1)
+    achieved_tflops = STAGE_FLOP_PER_CELL * ncell / (stage_ms * 1e-3) / 1e12
     achieved_gbs = STAGE_BYTES_PER_CELL * ncell / (stage_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "k2_stage<4,false>", "kernel_avg_ms": stage_ms,
-                "kernel_share": ms[3] / max(sum(ms), 1e-9)}
+    traffic = measured_traffic(ncell)
+    roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": traffic,
+                "kernel": STAGE_KERNEL, "kernel_avg_ms": stage_ms,
+                "kernel_share": ms[3] / max(sum(ms), 1e-9),
+                "algorithmic_flop_per_cell": STAGE_FLOP_PER_CELL,
+                "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved_gbs / HBM_PEAK_GBS,
+                        "algorithmic_bytes_per_cell": STAGE_BYTES_PER_CELL}}
     out = {
         "metric": "2D Euler MR-HWENO cell-updates/s (FP64), plain vs learned-indicator at equal L1",
         "value": value,
@@ -127,15 +207,38 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D Euler quadrants+Fourier {prob.nx}x{prob.ny} periodic, HLLC, KXRCF (M5-I), "
                                f"CFL 0.6, {args.steps} SSP-RK3 steps",
-                   "cells": ncell, "rk_stages_per_step": 3, "seed": args.seed,
-                   "sim_time": t[0]},
+                   "cells": ncell, "rk_stages_per_step": 3, "seed": args.seed, "sim_time": T},
         "kernels_ms": {"reduce_dt": ms[0], "kxrcf_summary": ms[1], "flags": ms[2], "stage": ms[3],
                        "launches": nl},
         "roofline": roofline,
     }
+    if not args.no_learned:
+        from paper_2201_12193_amd.indicator import load_weights
+        W = load_weights()
+        pl = prob.replace(tc_mode=I.TC_LEARNED)
+        lw, lms, lnl, lT, _ = timed_run(pl, U0, args.steps, args.warmup, args.rows, W, args.band)
+        lv = ncell * 3 * args.steps / lw
+        cmp = learned_compare(prob, U0, Uk, T, W, args.band, args.steps)
+        out["learned"] = {"value": lv, "speedup_vs_plain": lv / value, "band": list(args.band),
+                          "ms_per_step": lw / args.steps * 1e3,
+                          "kernels_ms": {"reduce_dt": lms[0], "inference": lms[1], "band_fallback": lms[2],
+                                         "stage": lms[3], "launches": lnl},
+                          "inference_avg_ms": lms[1] / max(lnl[1], 1),
+                          "at_equal_time": cmp}
+    del Uk
+    torch.cuda.empty_cache()
+    if args.calib_copy:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        a.sum()                      # read-only pass over 1 GiB
+        torch.cuda.synchronize()
+        del a, b
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, U0)
-    s.close()
     print(json.dumps(out), flush=True)
 
 

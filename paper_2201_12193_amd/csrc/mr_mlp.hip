@@ -33,16 +33,18 @@ MR_INL f32x4 mr_mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 /* ------------------------------------------------------------ features */
 /* normalisation of a cell from its FP32 averages: scale sc[4], centre cs[4] */
 MR_INL void mr_feat_norm(float rho, float mx, float my, float E, float gam, float* sc, float* cs) {
+  /* hardware reciprocal and square root (1 ulp): the features are rounded
+     to BF16 afterwards */
   const float r = rho > 1e-30f ? rho : 1e-30f;
-  const float ir = 1.0f / r;
+  const float ir = __builtin_amdgcn_rcpf(r);
   const float p = (gam - 1.0f) * (E - 0.5f * (mx * mx + my * my) * ir);
   float c2 = gam * p * ir;
   c2 = c2 > 1e-30f ? c2 : 1e-30f;
-  const float rc = 1.0f / (r * sqrtf(c2));
+  const float rc = __builtin_amdgcn_rcpf(r * __builtin_amdgcn_sqrtf(c2));
   sc[0] = ir;
   sc[1] = rc;
   sc[2] = rc;
-  sc[3] = 1.0f / (E > 1e-30f ? E : 1e-30f);
+  sc[3] = __builtin_amdgcn_rcpf(E > 1e-30f ? E : 1e-30f);
   cs[0] = rho;
   cs[1] = mx;
   cs[2] = my;
@@ -126,6 +128,10 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
   }
   const bf16x8* W1 = reinterpret_cast<const bf16x8*>(sh.w.w1);
   const bf16x8* W2 = reinterpret_cast<const bf16x8*>(sh.w.w2);
+  /* staging: thread (column scol, moment sm) of the first 3 x 68 threads
+     loads that column and moment of every component and row */
+  const int scol = tid % MR_LCOLS, sm = tid / MR_LCOLS;
+  const bool stager = tid < 3 * MR_LCOLS;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile2 tl = tiles[t];
     mr_inst& I = insts[tl.inst];
@@ -138,20 +144,47 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
     const int xend = I.nx + fh;
     const float gam = (float)I.gam, lh = (float)(log2(I.dx) * (1.0 / 16.0));
     const float blo = (float)I.band_lo, bhi = (float)I.band_hi;
-    /* rows ylo-2 .. ylo+1 into ring slots 0..3 */
-    __syncthreads();
-    for (int e = tid; e < 4 * 12 * MR_LCOLS; e += MR_BLOCK) {
-      const int rr = e / (12 * MR_LCOLS), q = (e / MR_LCOLS) % 12, col = e % MR_LCOLS;
-      sh.mom[q * MR_LPL + rr * MR_LRS + col] = (float)mr_ld(gr, q / 3, q % 3, xs + col, ylo - 2 + rr);
-    }
-    for (int y = ylo; y < yhi; y += 4) {
-      /* rows y+2 .. y+5 into their slots */
-      for (int e = tid; e < 4 * 12 * MR_LCOLS; e += MR_BLOCK) {
-        const int rr = e / (12 * MR_LCOLS), q = (e / MR_LCOLS) % 12, col = e % MR_LCOLS;
-        const int row = y + 2 + rr;
-        sh.mom[q * MR_LPL + ((row - ylo + 2) & 7) * MR_LRS + col] =
-            (float)mr_ld(gr, q / 3, q % 3, xs + col, row);
+    /* staging of four rows: every thread issues its loads together (into
+       registers) so that their latencies overlap, then converts and stores;
+       first moments of transmissive ghosts read as zero */
+    const int xi = xs + scol;
+    const bool zx = sm != 0 && (xi < 0 || xi >= I.nx) && I.bcx != 0;
+    int ii = I.bcx == 0 ? (xi < 0 ? xi + I.nx : (xi >= I.nx ? xi - I.nx : xi)) : xi;
+    ii = min(max(ii, 0), I.nx - 1);
+    const double* ub = gr.U + (long long)sm * I.plane + ii;
+    double pf[16];
+    auto fetch = [&](int row0) {
+      if (!stager) return;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int j = row0 + rr;
+        const bool oy = j < 0 || j >= I.ny;
+        int jj = I.bcy == 0 ? (j < 0 ? j + I.ny : (j >= I.ny ? j - I.ny : j)) : j;
+        jj = min(max(jj, 0), I.ny - 1);
+        const bool zero = zx || (sm != 0 && oy && I.bcy != 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double v = ub[(3 * c) * I.plane + (long long)jj * I.nx];
+          pf[4 * rr + c] = zero ? 0.0 : v;
+        }
       }
+    };
+    auto store = [&](int row0) {
+      if (!stager) return;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int slot = (row0 + rr - ylo + 2) & 7;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          sh.mom[(3 * c + sm) * MR_LPL + slot * MR_LRS + scol] = (float)pf[4 * rr + c];
+      }
+    };
+    __syncthreads();
+    fetch(ylo - 2);
+    store(ylo - 2);   /* rows ylo-2 .. ylo+1 */
+    for (int y = ylo; y < yhi; y += 4) {
+      fetch(y + 2);
+      store(y + 2);   /* rows y+2 .. y+5 */
       __syncthreads();
       const int Y = y + wv;
       /* LDS bases: centre row, the lane group's window row (wy = g - 2),
@@ -200,18 +233,12 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
         }
       }
       /* layer 2 and 3; this lane holds hidden units 16m + 4g + j */
-      float b1v[16], b2v[16], w3v[16];
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          b1v[4 * m + j] = sh.w.b1[16 * m + 4 * g + j];
-          b2v[4 * m + j] = sh.w.b2[16 * m + 4 * g + j];
-          w3v[4 * m + j] = sh.w.w3[16 * m + 4 * g + j];
-        }
       float z[4];
 #pragma unroll
       for (int gi = 0; gi < 4; ++gi) {
+        const float4* b1v4 = reinterpret_cast<const float4*>(sh.w.b1);
+        const float4* b2v4 = reinterpret_cast<const float4*>(sh.w.b2);
+        const float4* w3v4 = reinterpret_cast<const float4*>(sh.w.w3);
         f32x4 o[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) o[m] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -220,8 +247,9 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
           bf16x8 b;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float lo = h[gi][2 * kb2][j] + b1v[4 * (2 * kb2) + j];
-            const float hi = h[gi][2 * kb2 + 1][j] + b1v[4 * (2 * kb2 + 1) + j];
+            const float4 blo4 = b1v4[4 * (2 * kb2) + g], bhi4 = b1v4[4 * (2 * kb2 + 1) + g];
+            const float lo = h[gi][2 * kb2][j] + (&blo4.x)[j];
+            const float hi = h[gi][2 * kb2 + 1][j] + (&bhi4.x)[j];
             b[j] = (__bf16)(lo > 0.f ? lo : 0.f);
             b[4 + j] = (__bf16)(hi > 0.f ? hi : 0.f);
           }
@@ -230,19 +258,21 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
         }
         float zp = 0.f;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m) {
+          const float4 bb = b2v4[4 * m + g], ww = w3v4[4 * m + g];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float v = o[m][j] + b2v[4 * m + j];
-            zp += (v > 0.f ? v : 0.f) * w3v[4 * m + j];
+            const float v = o[m][j] + (&bb.x)[j];
+            zp += (v > 0.f ? v : 0.f) * (&ww.x)[j];
           }
+        }
         zp += __shfl_xor(zp, 16);
         zp += __shfl_xor(zp, 32);
         z[gi] = zp + sh.w.b3;
       }
       /* lane L decides cell x0 + L of row Y */
       const float zz = g == 0 ? z[0] : (g == 1 ? z[1] : (g == 2 ? z[2] : z[3]));
-      const float sg = 1.0f / (1.0f + expf(-zz));
+      const float sg = __builtin_amdgcn_rcpf(1.0f + __expf(-zz));
       const int x = tl.x0 + lane;
       const bool valid = Y < yhi && x < xend;
       const unsigned char f = sg > bhi ? 1 : (sg < blo ? 0 : 2);
@@ -263,37 +293,62 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
   }
 }
 
-/* KXRCF (eq. (KXRCF_), as the flag kernel evaluates it) for the cells the
- * network left undecided; the face data of the cell and of its four
- * neighbours are recomputed here. */
-template <bool BP>
-MR_INL void mr2_fallback_cell(const mr_inst& I, const mr_grid& g, int i, int j, unsigned char* out) {
-  double o[9];
-  mr2_face_summary<BP>(g, I, i, j, o);
-  double J = 0.0, len = 0.0;
-#pragma unroll 1
-  for (int k = 0; k < 4; ++k) {
-    double nb[9];
-    mr2_face_summary<BP>(g, I, i + (k == 0 ? -1 : (k == 1 ? 1 : 0)), j + (k == 2 ? -1 : (k == 3 ? 1 : 0)), nb);
-    if (k == 0) {
-      const double vl = 0.5 * (o[4] + nb[5]);
-      if (vl > 0.0) { J += I.dy * (o[0] - nb[1]); len += I.dy; }
-    } else if (k == 1) {
-      const double vr = 0.5 * (o[5] + nb[4]);
-      if (-vr > 0.0) { J += I.dy * (o[1] - nb[0]); len += I.dy; }
-    } else if (k == 2) {
-      const double vb = 0.5 * (o[6] + nb[7]);
-      if (vb > 0.0) { J += I.dx * (o[2] - nb[3]); len += I.dx; }
-    } else {
-      const double vt = 0.5 * (o[7] + nb[6]);
-      if (-vt > 0.0) { J += I.dx * (o[3] - nb[2]); len += I.dx; }
+/* KXRCF for the cells the network left undecided (band list, count
+ * cnt[stage]), in three passes that share the face data of neighbouring band
+ * cells:
+ *   k_fb_mark:    every band cell claims itself and its four neighbours in
+ *                 the instance's mark plane (an atomic exchange with this
+ *                 pass's epoch); the first claimant appends the cell to the
+ *                 summary list (count cnt[4 + stage]);
+ *   k_fb_summary: KXRCF face data (mr2_face_summary) of the listed cells;
+ *   k_fb_flags:   eq. (KXRCF_) for the band cells, as the flag kernel
+ *                 evaluates it.
+ * The epoch of a pass is cnt[8] + stage + 1; cnt[8] advances by 4 before
+ * every step and every probe, so marks never need clearing. */
+__global__ __launch_bounds__(MR_BLOCK) void k_fb_mark(mr_inst* insts, const mr_band* band, mr_band* list, int* cnt,
+                                                     int stage) {
+  const int n = cnt[stage];
+  const int epoch = cnt[8] + stage + 1;
+  for (int k = blockIdx.x * MR_BLOCK + threadIdx.x; k < n; k += gridDim.x * MR_BLOCK) {
+    const mr_band b = band[k];
+    const mr_inst& I = insts[b.inst];
+    const int i = b.e % I.fex - I.fhalo, j = b.e / I.fex - I.fhalo;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+      const int di = d == 1 ? -1 : (d == 2 ? 1 : 0), dj = d == 3 ? -1 : (d == 4 ? 1 : 0);
+      const int es = (j + dj + I.shalo) * I.sex + (i + di + I.shalo);
+      if (atomicExch(&I.mark[es], epoch) != epoch) {
+        const int at = atomicAdd(&cnt[4 + stage], 1);
+        list[at] = mr_band{b.inst, es};
+      }
     }
   }
-  *out = (unsigned char)(fabs(J) > I.dx * I.dx * len * o[8]);
 }
 
-__global__ __launch_bounds__(MR_BLOCK) void k2_fallback(mr_inst* insts, const mr_band* band, const int* cnt,
-                                                       int stage) {
+template <bool BP>
+MR_INL void mr_fb_summary_cell(mr_inst& I, const mr_grid& g, int es) {
+  double f[9];
+  mr2_face_summary<BP>(g, I, es % I.sex - I.shalo, es / I.sex - I.shalo, f);
+  const long long SE = (long long)I.sex * I.sey;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) I.summ[k * SE + es] = f[k];
+}
+
+/* one launch per smoothness-indicator variant; each skips the other's cells */
+template <bool BP>
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k_fb_summary(mr_inst* insts, const mr_band* list, const int* cnt,
+                                                               int stage) {
+  const int n = cnt[4 + stage];
+  for (int k = blockIdx.x * MR_BLOCK + threadIdx.x; k < n; k += gridDim.x * MR_BLOCK) {
+    const mr_band b = list[k];
+    mr_inst& I = insts[b.inst];
+    if ((I.beta_on != 0) != BP) continue;
+    const mr_grid g{stage < 3 ? I.p_in[stage] : I.buf[0], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    mr_fb_summary_cell<BP>(I, g, b.e);
+  }
+}
+
+__global__ __launch_bounds__(MR_BLOCK) void k_fb_flags(mr_inst* insts, const mr_band* band, const int* cnt, int stage) {
 #pragma clang fp contract(off)
   const int n = cnt[stage];
   for (int k = blockIdx.x * MR_BLOCK + threadIdx.x; k < n; k += gridDim.x * MR_BLOCK) {
@@ -301,15 +356,35 @@ __global__ __launch_bounds__(MR_BLOCK) void k2_fallback(mr_inst* insts, const mr
     const mr_inst& I = insts[b.inst];
     unsigned char* fl = I.flags[(stage == 0 || stage == 3) ? 0 : 1];
     const int i = b.e % I.fex - I.fhalo, j = b.e / I.fex - I.fhalo;
-    const mr_grid g{stage < 3 ? I.p_in[stage] : I.buf[0], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    if (I.beta_on) mr2_fallback_cell<true>(I, g, i, j, &fl[b.e]);
-    else mr2_fallback_cell<false>(I, g, i, j, &fl[b.e]);
+    const int sx = I.sex;
+    const long long SE = (long long)sx * I.sey;
+    const double* S = I.summ;
+    const long long o = (long long)(j + I.shalo) * sx + (i + I.shalo);
+    double J = 0.0, len = 0.0;
+    const double vl = 0.5 * (S[4 * SE + o] + S[5 * SE + o - 1]);
+    if (vl > 0.0) { J += I.dy * (S[0 * SE + o] - S[1 * SE + o - 1]); len += I.dy; }
+    const double vr = 0.5 * (S[5 * SE + o] + S[4 * SE + o + 1]);
+    if (-vr > 0.0) { J += I.dy * (S[1 * SE + o] - S[0 * SE + o + 1]); len += I.dy; }
+    const double vb = 0.5 * (S[6 * SE + o] + S[7 * SE + o - sx]);
+    if (vb > 0.0) { J += I.dx * (S[2 * SE + o] - S[3 * SE + o - sx]); len += I.dx; }
+    const double vt = 0.5 * (S[7 * SE + o] + S[6 * SE + o + sx]);
+    if (-vt > 0.0) { J += I.dx * (S[3 * SE + o] - S[2 * SE + o + sx]); len += I.dx; }
+    fl[b.e] = (unsigned char)(fabs(J) > I.dx * I.dx * len * S[8 * SE + o]);
   }
 }
 
-__global__ void k_zero_ints(int* p, int n) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < n) p[e] = 0;
+/* before a step (stages 0..2) or a probe (stage 3): clear the band and
+ * summary-list counts of those stages and advance the epoch */
+__global__ void k_fb_reset(int* cnt, int probe) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (probe) {
+    cnt[3] = 0;
+    cnt[7] = 0;
+  } else {
+    cnt[0] = cnt[1] = cnt[2] = 0;
+    cnt[4] = cnt[5] = cnt[6] = 0;
+  }
+  cnt[8] += 4;
 }
 
 /* BF16 parameter vector -> operand-ordered weights of the fused kernel */
@@ -498,8 +573,8 @@ static mr_mlp_cache mr_mlp_cache_at(void* base, int Bn) {
 /* ------------------------------------------------------------ launchers */
 extern "C" {
 
-hipError_t mr_launch_zero(hipStream_t s, int* p, int n) {
-  hipLaunchKernelGGL(k_zero_ints, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+hipError_t mr_launch_fb_reset(hipStream_t s, int* cnt, int probe) {
+  hipLaunchKernelGGL(k_fb_reset, dim3(1), dim3(64), 0, s, cnt, probe);
   return hipGetLastError();
 }
 
@@ -517,8 +592,12 @@ hipError_t mr_launch_learned(hipStream_t s, mr_inst* d, const mr_tile2* t, int n
   return hipGetLastError();
 }
 
-hipError_t mr_launch_fallback(hipStream_t s, mr_inst* d, const mr_band* band, const int* cnt, int stage, int grid) {
-  hipLaunchKernelGGL(k2_fallback, dim3(grid), dim3(MR_BLOCK), 0, s, d, band, cnt, stage);
+hipError_t mr_launch_fallback(hipStream_t s, mr_inst* d, const mr_band* band, mr_band* list, int* cnt, int stage,
+                              int grid, int any_bp) {
+  hipLaunchKernelGGL(k_fb_mark, dim3(grid), dim3(MR_BLOCK), 0, s, d, band, list, cnt, stage);
+  hipLaunchKernelGGL(k_fb_summary<false>, dim3(grid), dim3(MR_BLOCK), 0, s, d, list, cnt, stage);
+  if (any_bp) hipLaunchKernelGGL(k_fb_summary<true>, dim3(grid), dim3(MR_BLOCK), 0, s, d, list, cnt, stage);
+  hipLaunchKernelGGL(k_fb_flags, dim3(grid), dim3(MR_BLOCK), 0, s, d, band, cnt, stage);
   return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ struct mr_inst {
   unsigned char* flags[2];    /* [0] stage-1 flags, [1] stage-2/3 flags        */
   double* summ;               /* KXRCF face summaries (extended planes)        */
   double* aleph;              /* optional KXRCF numerator/denominator output   */
+  int* mark;                  /* learned indicator: summary-plane epoch marks  */
   /* ---- dynamic (device) ---- */
   double t, dt, t_prev;
   long long steps;

@@ -4,9 +4,12 @@ kernels and Adam, and loading of the trained weights.
 
 Data: 2D Euler quadrant problems (four constant states plus a smooth
 Fourier field, periodic) at several resolutions are advanced with the KXRCF
-indicator; every few steps the KXRCF flags of the current state are the
+indicator; every few steps the KXRCF test of the current state supplies the
 labels.  All flagged cells are kept, together with the unflagged cells next
 to them (the hard negatives) and a random sample of the remaining cells.
+The training target of a cell is its KXRCF flag, or optionally the soft
+label sigmoid(k log(|J| / d)), with |J| > d the KXRCF test, which asks the
+network for the logarithm of the KXRCF ratio (scaled by k).
 
 Run `python -m paper_2201_12193_amd.indicator --out DIR` to train; it
 writes DIR/indicator_weights.npy (FP32 parameter vector) and
@@ -69,9 +72,10 @@ def _neighbours(mask: np.ndarray, r: int) -> np.ndarray:
 
 
 def collect(runs: Sequence[Tuple[int, int, int, int]], neg_ratio: float = 1.0, seed: int = 0,
-            log=print) -> Tuple["object", "object", Dict]:
+            log=print, soft_k: Optional[float] = None) -> Tuple["object", "object", Dict]:
     """Features and KXRCF labels from the runs (seed, n, steps, every).
-    Returns (X bf16 [N][320] CUDA, y f32 [N] CUDA, summary)."""
+    Returns (X bf16 [N][320] CUDA, labels f32 [N][2] CUDA: column 0 the
+    KXRCF flag, column 1 the training target, summary)."""
     import torch
     rng = np.random.default_rng(seed)
     Xs, ys = [], []
@@ -82,12 +86,19 @@ def collect(runs: Sequence[Tuple[int, int, int, int]], neg_ratio: float = 1.0, s
         U = torch.from_numpy(U0).cuda()
         solver = Solver([prob], [U])
         pos_run = 0
+        stopped = None
         for k in range(0, steps + 1, every):
             if k > 0:
                 solver.step(every)
-                solver.sync()
-            fl, _ = solver.flag(0, U)
+                if solver.sync(raise_on_error=False)[2] != 0:
+                    stopped = k       # the scheme met a non-physical state: keep what came before
+                    break
+            fl, al = solver.flag(0, U)
             lab = fl.cpu().numpy().astype(bool)
+            al = al.cpu().numpy()
+            with np.errstate(divide="ignore", invalid="ignore"):
+                lr = np.log(al[..., 0]) - np.log(al[..., 1])
+            lr = np.clip(np.nan_to_num(lr, nan=-20.0, posinf=20.0, neginf=-20.0), -20.0, 20.0)
             near = _neighbours(lab, 2) & ~lab
             far = ~(lab | near)
             pos = np.flatnonzero(lab)
@@ -95,7 +106,9 @@ def collect(runs: Sequence[Tuple[int, int, int, int]], neg_ratio: float = 1.0, s
             nfar = min(int(neg_ratio * max(pos.size, 1)), int(far.sum()))
             rnd = rng.choice(np.flatnonzero(far), nfar, replace=False)
             cells = np.concatenate([pos, hard, rnd]).astype(np.int32)
-            y = np.concatenate([np.ones(pos.size), np.zeros(hard.size + rnd.size)]).astype(np.float32)
+            y = np.zeros((cells.size, 2), dtype=np.float32)
+            y[:, 0] = lab.ravel()[cells]
+            y[:, 1] = y[:, 0] if soft_k is None else 1.0 / (1.0 + np.exp(-soft_k * lr.ravel()[cells]))
             X = solver.features(0, U, torch.from_numpy(cells).cuda())
             Xs.append(X)
             ys.append(torch.from_numpy(y).cuda())
@@ -103,18 +116,21 @@ def collect(runs: Sequence[Tuple[int, int, int, int]], neg_ratio: float = 1.0, s
             stats["positives"] += int(pos.size)
             pos_run += int(pos.size)
         solver.close()
-        stats["runs"].append({"seed": s, "n": n, "steps": steps, "every": every, "positives": pos_run})
+        stats["runs"].append({"seed": s, "n": n, "steps": steps, "every": every, "positives": pos_run,
+                              "stopped_at": stopped})
         log(f"collect: seed {s} n {n} steps {steps}: {pos_run} flagged cells", flush=True)
     X = torch.cat(Xs)
     y = torch.cat(ys)
-    stats["samples"] = int(y.numel())
+    stats["samples"] = int(y.shape[0])
     return X, y, stats
 
 
-def train(X, y, steps: int = 4000, batch: int = 4096, lr: float = 2e-3, seed: int = 0, pos_weight: float = 1.0,
-          log=print, log_every: int = 500):
-    """Adam on the mean binary cross-entropy, with the library's kernels.
-    Returns (FP32 master parameters as numpy, loss history)."""
+def train(X, y, steps: int = 4000, batch: int = 4096, lr: float = 2e-3, seed: int = 0, log=print,
+          log_every: int = 500):
+    """Adam on the mean binary cross-entropy against the targets (y[:, 1]),
+    with the library's kernels; batches draw flagged and
+    unflagged cells (y[:, 0]) in equal numbers.  Returns (FP32 master
+    parameters as numpy, loss history)."""
     import torch
     dev = X.device
     master = torch.from_numpy(init_params(seed)).to(dev)
@@ -127,10 +143,9 @@ def train(X, y, steps: int = 4000, batch: int = 4096, lr: float = 2e-3, seed: in
     loss = torch.empty(batch, dtype=torch.float32, device=dev)
     gen = torch.Generator(device=dev)
     gen.manual_seed(seed)
-    N = y.numel()
-    # class-balanced sampling: half positives, half negatives
-    pos = torch.nonzero(y > 0.5).squeeze(1)
-    neg = torch.nonzero(y <= 0.5).squeeze(1)
+    pos = torch.nonzero(y[:, 0] > 0.5).squeeze(1)
+    neg = torch.nonzero(y[:, 0] <= 0.5).squeeze(1)
+    ysoft = y[:, 1].contiguous()
     hist = []
     stream = torch.cuda.current_stream()
     for it in range(1, steps + 1):
@@ -138,7 +153,7 @@ def train(X, y, steps: int = 4000, batch: int = 4096, lr: float = 2e-3, seed: in
         ineg = neg[torch.randint(neg.numel(), (batch - batch // 2,), device=dev, generator=gen)]
         idx = torch.cat([ip, ineg])
         xb = X[idx].contiguous()
-        yb = y[idx].contiguous()
+        yb = ysoft[idx].contiguous()
         mlp_forward(xb, params, cache, z, stream)
         mlp_backward(xb, params, cache, yb, grads, loss, stream)
         mlp_adam(master, params, grads, m, v, it, lr * (0.5 * (1 + math.cos(math.pi * it / steps)) * 0.9 + 0.1),
@@ -152,13 +167,14 @@ def train(X, y, steps: int = 4000, batch: int = 4096, lr: float = 2e-3, seed: in
 
 
 def evaluate(P: np.ndarray, X, y, lo: float = 0.2, hi: float = 0.8, batch: int = 65536) -> Dict:
-    """Decision statistics of the trained network on labelled samples."""
+    """Decision statistics of the trained network against the KXRCF flags
+    (y[:, 0]) of labelled samples."""
     import torch
     dev = X.device
     params = torch.from_numpy(P).to(dev).to(torch.bfloat16)
     cache = torch.empty(mlp_cache_bytes(batch) + 256, dtype=torch.uint8, device=dev)
     zs = []
-    for s in range(0, y.numel(), batch):
+    for s in range(0, y.shape[0], batch):
         xb = X[s:s + batch].contiguous()
         nb = xb.shape[0]
         if nb % 16:
@@ -167,10 +183,10 @@ def evaluate(P: np.ndarray, X, y, lo: float = 0.2, hi: float = 0.8, batch: int =
         mlp_forward(xb, params, cache, z)
         zs.append(z[:nb])
     sg = torch.sigmoid(torch.cat(zs))
-    lab = y > 0.5
+    lab = y[:, 0] > 0.5
     dec1, dec0 = sg > hi, sg < lo
     band = ~(dec1 | dec0)
-    return {"samples": int(y.numel()), "positives": int(lab.sum()),
+    return {"samples": int(y.shape[0]), "positives": int(lab.sum()),
             "false_negative_rate": float((dec0 & lab).sum()) / max(int(lab.sum()), 1),
             "false_positive_rate": float((dec1 & ~lab).sum()) / max(int((~lab).sum()), 1),
             "band_fraction": float(band.float().mean()),
@@ -185,7 +201,7 @@ VALID_RUNS = [(201, 512, 300, 60), (202, 1024, 200, 50)]
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--steps", type=int, default=6000)
+    ap.add_argument("--steps", type=int, default=20000)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--quick", action="store_true", help="small data set (smoke run)")
