@@ -18,8 +18,12 @@
  *   R2  Euler systems are reconstructed component by component on the
  *       conserved variables.
  *   R3  the first-moment modification (Step 2.2) is Jacobi: modified moments
- *       use the original neighbour moments; the modified moments are
- *       internal to the spatial operator and never written back to U.
+ *       use the original neighbour moments.  The modified first moments
+ *       replace those of the stage input in the Runge-Kutta combination,
+ *       U^n included (orc_rk3_step, persist = 1): with that reading the
+ *       modified-everywhere variant (M5-NI) is stable and Tables 1 and 3 are
+ *       reproduced; persist = 0 keeps the modification internal to L(U),
+ *       persist = 2 replaces the stage inputs but not U^n.
  *   R4  a troubled cell has the first moments of all components modified.
  *   R5  sf(z) = 1 if z > 0 else 0; the interface velocity is the mean of the
  *       velocities of the two reconstructed face states (in 2D, the
