@@ -97,7 +97,7 @@ std::string validate(const mrhweno_problem& p) {
 struct Layout {
   size_t insts = 0, tiles1 = 0, tiles2 = 0, probe_tiles = 0, probe_aleph = 0, total = 0;
   size_t lw = 0, cnt = 0, band = 0, slist = 0, tilesl = 0;   /* learned indicator */
-  std::vector<size_t> buf1, buf2, fl0, fl1, summ, mark;
+  std::vector<size_t> buf1, buf2, unm, fl0, fl1, summ, mark;
   size_t n_tiles1 = 0, n_tiles2 = 0, n_probe_tiles = 0, n_tilesl = 0, n_band = 0, n_slist = 0;
 };
 
@@ -150,6 +150,8 @@ Layout layout(const mrhweno_problem* P, int n) {
     const auto& p = P[q];
     L.buf1.push_back(off); off += al(state_bytes(p));
     L.buf2.push_back(off); off += al(state_bytes(p));
+    L.unm.push_back(off);
+    if (p.dim == 2) off += al(sizeof(double) * ncomp_of(p) * 2 * (size_t)plane_of(p));
     L.fl0.push_back(off); off += al((size_t)fex(p) * fey(p));
     L.fl1.push_back(off); off += al((size_t)fex(p) * fey(p));
     L.summ.push_back(off);
@@ -416,6 +418,7 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     I.buf[0] = (double*)moments_dev[q];
     I.buf[1] = (double*)(c->ws + c->L.buf1[q]);
     I.buf[2] = (double*)(c->ws + c->L.buf2[q]);
+    I.unm = p.dim == 2 ? (double*)(c->ws + c->L.unm[q]) : nullptr;
     I.flags[0] = (unsigned char*)(c->ws + c->L.fl0[q]);
     I.flags[1] = (unsigned char*)(c->ws + c->L.fl1[q]);
     I.summ = has_summ(p) ? (double*)(c->ws + c->L.summ[q]) : nullptr;

@@ -7,11 +7,16 @@
  * cells in x (two of them ring cells) and sweeps it upward over `rows` rows
  * plus one ring row below and one above.
  *
- * Moments: the rows y-2..y+2 of the strip (plus two columns each side) sit
- * in an LDS ring of five rows; each value is loaded from HBM once per work
+ * Moments (the strip plus two columns each side) sit in LDS rings: the cell
+ * averages and y moments of rows y-2..y+2 (five rows: the modification of
+ * the stencil's upper and lower cells reads rows y +- 2), the x moments of
+ * rows y-1..y+1 (three rows); each value is loaded from HBM once per work
  * group, with the boundary condition applied when it is loaded, and the
- * row needed next is fetched into registers while the current row is
+ * rows needed next are fetched into registers while the current row is
  * computed.  Flags of rows y-1..y+1 sit in a three-row LDS ring.
+ *
+ * Stage 1 also writes the first moments of U^n after Step 2.2 (I.unm), which
+ * the combination of stages 2 and 3 uses.
  *
  * With NC = 4 the four lanes of a cell each reconstruct one conserved
  * component, then each lane takes one row eta_r of the cell's 4x4
@@ -23,26 +28,32 @@ template <int NC>
 struct mr2_lds {
   static constexpr int CW = MR_BLOCK / NC;   /* strip cells incl. ring */
   static constexpr int XW = CW + 4;          /* staged columns */
-  static constexpr int NP = 3 * NC;          /* staged planes */
+  static constexpr int NP = 3 * NC;          /* staged planes per row step */
   /* point-major layouts with padded strides: the lanes of one access
      (cells cs, roles/components k) fall on distinct LDS banks */
   static constexpr int CS = CW + 4;          /* component stride */
   static constexpr int VS = NC * CS + 1;     /* point stride of val */
   static constexpr int TS = NC * CS + 4;     /* point stride of top */
   static constexpr int FS = NC * CS;         /* stride of fs */
-  double mom[3][NP][XW];
+  double mA[5][2 * NC][XW];   /* planes (c, m = 0) and (c, m = 2): index 2c, 2c+1 */
+  double mB[3][NC][XW];       /* planes (c, m = 1)                               */
   unsigned char flg[3][XW];
   double val[16 * VS];
   double top[4 * TS];
   double fs[2 * FS];
 };
 
-/* one staged element: plane q (= 3 c + m) of row y, column col of the strip */
-MR_INL double mr2_stage_ld(const mr_grid& g, int q, int x, int y) {
-  return mr_ld(g, q / 3, q % 3, x, y);
-}
-
 MR_INL int mr_mod3(int y) { return ((y % 3) + 3) % 3; }
+MR_INL int mr_mod5(int y) { return ((y % 5) + 5) % 5; }
+
+/* staged element e of a row step at row y (A planes at row y+1, B planes
+   at row y): plane pl < 2 NC is A plane pl, else B plane pl - 2 NC */
+template <int NC, int XW>
+MR_INL double mr2_stage_ld(const mr_grid& g, int e, int xs0, int y) {
+  const int pl = e / XW, col = e % XW;
+  if (pl < 2 * NC) return mr_ld(g, pl / 2, (pl % 2) * 2, xs0 + col, y + 1);
+  return mr_ld(g, pl - 2 * NC, 1, xs0 + col, y);
+}
 
 template <int NC, bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, const mr_tile2* tiles, int ntiles, int mode) {
@@ -72,31 +83,38 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
     const int xs0 = tl.x0 - 3;                 /* strip column 0 */
     const int x = tl.x0 - 1 + cs;
     const bool outx = cs >= 1 && cs <= CW - 2 && x < I.nx;
-    /* ---- prologue: moment and flag rows y0-2 .. y0 ---- */
+    /* ---- prologue: A rows y0-3 .. y0+1, B and flag rows y0-2 .. y0 ---- */
+    for (int r = tl.y0 - 3; r <= tl.y0 - 2; ++r)
+      for (int e = tid; e < 2 * NC * XW; e += MR_BLOCK)
+        sh.mA[mr_mod5(r)][e / XW][e % XW] = mr_ld(g, (e / XW) / 2, ((e / XW) % 2) * 2, xs0 + e % XW, r);
     for (int r = tl.y0 - 2; r <= tl.y0; ++r) {
-      const int sl = mr_mod3(r);
-      for (int e = tid; e < NP * XW; e += MR_BLOCK)
-        sh.mom[sl][e / XW][e % XW] = mr2_stage_ld(g, e / XW, xs0 + e % XW, r);
+      for (int e = tid; e < NP * XW; e += MR_BLOCK) {
+        const double v = mr2_stage_ld<NC, XW>(g, e, xs0, r);
+        if (e / XW < 2 * NC) sh.mA[mr_mod5(r + 1)][e / XW][e % XW] = v;
+        else sh.mB[mr_mod3(r)][e / XW - 2 * NC][e % XW] = v;
+      }
       for (int e = tid; e < XW; e += MR_BLOCK)
-        sh.flg[sl][e] = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + e, r);
+        sh.flg[mr_mod3(r)][e] = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + e, r);
     }
     __syncthreads();
     double pAu = 0.0, pAv = 0.0, pAw = 0.0, pB0 = 0.0, pB1 = 0.0, pU = 0.0, pV = 0.0, pW = 0.0;
     for (int jr = -1; jr <= tl.rows; ++jr) {
       const int y = tl.y0 + jr;
-      /* prefetch moment and flag row y+2 (stored once row y-1 is consumed) */
+      /* prefetch A row y+3, B and flag row y+2 (stored once rows y-2 and
+         y-1 are consumed) */
       double pre[NE];
       unsigned char pref = 0;
 #pragma unroll
       for (int q = 0; q < NE; ++q) {
         const int e = tid + q * MR_BLOCK;
-        pre[q] = (e < NP * XW) ? mr2_stage_ld(g, e / XW, xs0 + e % XW, y + 2) : 0.0;
+        pre[q] = (e < NP * XW) ? mr2_stage_ld<NC, XW>(g, e, xs0, y + 2) : 0.0;
       }
       if (tid < XW) pref = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + tid, y + 2);
       /* ---- Steps 1, 2.2, 2.3 for component `comp` of cell (x, y) ---- */
       double cu, cv, cw;
       {
-        const int rr[3] = {mr_mod3(y - 1), mr_mod3(y), mr_mod3(y + 1)};
+        const int ra[5] = {mr_mod5(y - 2), mr_mod5(y - 1), mr_mod5(y), mr_mod5(y + 1), mr_mod5(y + 2)};
+        const int rb[3] = {mr_mod3(y - 1), mr_mod3(y), mr_mod3(y + 1)};
         const int c0 = cs + 2;                    /* staged column of cell x */
         double u[9], v[9], w[9];
         int fs[9];
@@ -105,15 +123,14 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
 #pragma unroll
           for (int dx = 0; dx < 3; ++dx) {
             const int l = dx + 3 * dy;
-            u[l] = sh.mom[rr[dy]][3 * comp + 0][c0 + dx - 1];
-            v[l] = sh.mom[rr[dy]][3 * comp + 1][c0 + dx - 1];
-            w[l] = sh.mom[rr[dy]][3 * comp + 2][c0 + dx - 1];
-            fs[l] = sh.flg[rr[dy]][c0 + dx - 1];
+            u[l] = sh.mA[ra[dy + 1]][2 * comp][c0 + dx - 1];
+            v[l] = sh.mB[rb[dy]][comp][c0 + dx - 1];
+            w[l] = sh.mA[ra[dy + 1]][2 * comp + 1][c0 + dx - 1];
+            fs[l] = sh.flg[rb[dy]][c0 + dx - 1];
           }
         if (fs[4]) {
           /* troubled cell: first moments of the troubled cells of the
-             stencil modified from the unmodified input (Jacobi); rows
-             y +- 2 come from global memory (rare path) */
+             stencil modified from the unmodified input (Jacobi) */
 #pragma unroll
           for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
@@ -121,14 +138,10 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
               const int l = dx + 3 * dy;
               if (!fs[l]) continue;
               const int cc = c0 + dx - 1;
-              const int rw = rr[dy];
-              v[l] = mr_modified_moment(sh.mom[rw][3 * comp][cc - 1], sh.mom[rw][3 * comp][cc + 1],
-                                        sh.mom[rw][3 * comp + 1][cc - 1], sh.mom[rw][3 * comp + 1][cc + 1]);
-              const double ub = dy == 0 ? mr_ld(g, comp, 0, x + dx - 1, y - 2) : sh.mom[rr[dy - 1]][3 * comp][cc];
-              const double wb = dy == 0 ? mr_ld(g, comp, 2, x + dx - 1, y - 2) : sh.mom[rr[dy - 1]][3 * comp + 2][cc];
-              const double ut = dy == 2 ? mr_ld(g, comp, 0, x + dx - 1, y + 2) : sh.mom[rr[dy + 1]][3 * comp][cc];
-              const double wt = dy == 2 ? mr_ld(g, comp, 2, x + dx - 1, y + 2) : sh.mom[rr[dy + 1]][3 * comp + 2][cc];
-              w[l] = mr_modified_moment(ub, ut, wb, wt);
+              v[l] = mr_modified_moment(sh.mA[ra[dy + 1]][2 * comp][cc - 1], sh.mA[ra[dy + 1]][2 * comp][cc + 1],
+                                        sh.mB[rb[dy]][comp][cc - 1], sh.mB[rb[dy]][comp][cc + 1]);
+              w[l] = mr_modified_moment(sh.mA[ra[dy]][2 * comp][cc], sh.mA[ra[dy + 2]][2 * comp][cc],
+                                        sh.mA[ra[dy]][2 * comp + 1][cc], sh.mA[ra[dy + 2]][2 * comp + 1][cc]);
             }
         }
         cu = u[4];
@@ -140,15 +153,19 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
         for (int q = 0; q < 16; ++q) VAL(q, comp, cs) = val[q];
       }
       __syncthreads();
-      /* the moment/flag slot of row y-1 is consumed: store row y+2 */
+      /* the slots of A row y-2 and of B/flag row y-1 are consumed: store
+         A row y+3 and B/flag row y+2 */
       {
-        const int sl = mr_mod3(y + 2);
+        const int sa = mr_mod5(y + 3), sb = mr_mod3(y + 2);
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
           const int e = tid + q * MR_BLOCK;
-          if (e < NP * XW) sh.mom[sl][e / XW][e % XW] = pre[q];
+          if (e < NP * XW) {
+            if (e / XW < 2 * NC) sh.mA[sa][e / XW][e % XW] = pre[q];
+            else sh.mB[sb][e / XW - 2 * NC][e % XW] = pre[q];
+          }
         }
-        if (tid < XW) sh.flg[sl][tid] = pref;
+        if (tid < XW) sh.flg[sb][tid] = pref;
       }
       /* ---- volume integrals and the fluxes this lane owns ---- */
       double F[NC], G[NC], XL0[NC], XL1[NC], YB0[NC], YB1[NC];
@@ -212,17 +229,22 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
         const double Lv = pAv - (yb1 - pB1) * rdy;
         const double Lw = pAw - (yb0 + pB0) * (0.5 * rdy);
         double r0, r1, r2;
+        const long long cell = (long long)yp * I.nx + x;
         if (mode == 3) { r0 = Lu; r1 = Lv; r2 = Lw; }
-        else if (mode == 0) { r0 = pU + dt * Lu; r1 = pV + dt * Lv; r2 = pW + dt * Lw; }
-        else {
+        else if (mode == 0) {
+          r0 = pU + dt * Lu; r1 = pV + dt * Lv; r2 = pW + dt * Lw;
+          /* U^n after Step 2.2 (its first moments) for stages 2 and 3 */
+          I.unm[(long long)(comp * 2 + 0) * P + cell] = pV;
+          I.unm[(long long)(comp * 2 + 1) * P + cell] = pW;
+        } else {
           const double a = mode == 1 ? 0.75 : 1.0 / 3.0, b = mode == 1 ? 0.25 : 2.0 / 3.0;
-          double un, vn, wn;
-          mr2_un_mod(gn, I.flags[0], I, comp, x, yp, &un, &vn, &wn);
+          const double un = gn.U[(long long)(comp * 3) * P + cell];
+          const double vn = I.unm[(long long)(comp * 2 + 0) * P + cell];
+          const double wn = I.unm[(long long)(comp * 2 + 1) * P + cell];
           r0 = a * un + b * pU + b * dt * Lu;
           r1 = a * vn + b * pV + b * dt * Lv;
           r2 = a * wn + b * pW + b * dt * Lw;
         }
-        const long long cell = (long long)yp * I.nx + x;
         O[(long long)(comp * 3 + 0) * P + cell] = r0;
         O[(long long)(comp * 3 + 1) * P + cell] = r1;
         O[(long long)(comp * 3 + 2) * P + cell] = r2;

@@ -40,6 +40,9 @@ struct mr_inst {
   double* summ;               /* KXRCF face summaries (extended planes)        */
   double* aleph;              /* optional KXRCF numerator/denominator output   */
   int* mark;                  /* learned indicator: summary-plane epoch marks  */
+  double* unm;                /* 2D: first moments of U^n after Step 2.2 of
+                                 stage 1, [comp][2][ny][nx] (written by stage 1,
+                                 read by the RK combination of stages 2, 3)   */
   /* ---- dynamic (device) ---- */
   double t, dt, t_prev;
   long long steps;
