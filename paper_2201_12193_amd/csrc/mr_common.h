@@ -161,6 +161,17 @@ MR_INL void mr_physflux(const double* u, double gam, double* f) {
   else mr_euler_flux<NC, D>(u, gam, f);
 }
 
+/* exchange with lane ^ 1 or lane ^ 2 inside a group of four lanes, through
+ * the DPP quad permutation (no LDS traffic) */
+template <int X>
+MR_INL double mr_quad_xor(double v) {
+  constexpr int ctrl = X == 1 ? 0xB1 : 0x4E;   /* quad_perm [1,0,3,2] / [2,3,0,1] */
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), ctrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), ctrl, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 /* reduce-scatter over the NC lanes of a cell: lane k receives sum_r a_r[k] */
 template <int NC>
 MR_INL double mr_rs(const double (&a)[NC], int k) {
@@ -168,11 +179,11 @@ MR_INL double mr_rs(const double (&a)[NC], int k) {
   const bool hi = (k & 2) != 0;
   const double s0 = hi ? a[0] : a[2], s1 = hi ? a[1] : a[3];
   const double k0 = hi ? a[2] : a[0], k1 = hi ? a[3] : a[1];
-  const double b0 = k0 + __shfl_xor(s0, 2);
-  const double b1 = k1 + __shfl_xor(s1, 2);
+  const double b0 = k0 + mr_quad_xor<2>(s0);
+  const double b1 = k1 + mr_quad_xor<2>(s1);
   const bool odd = (k & 1) != 0;
   const double s = odd ? b0 : b1, kk = odd ? b1 : b0;
-  return kk + __shfl_xor(s, 1);
+  return kk + mr_quad_xor<1>(s);
 }
 
 /* 2D final Gauss-Lobatto values of interior cells: gl[(c*16 + p)*plane + cell]. */
