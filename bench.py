@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=2048)
-    ap.add_argument("--rows", type=int, default=0, help="2D strip height (0: default)")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="2D strip height (0: chosen by the autotuner before the timed run)")
     ap.add_argument("--band", type=float, nargs=2, default=(0.1, 0.9),
                     help="learned-indicator uncertainty band (KXRCF inside)")
     ap.add_argument("--no-learned", action="store_true")
@@ -97,18 +98,26 @@ def cpu_baseline(prob, U0):
                       f"{dt:.1f} s on {threads} threads"}
 
 
-def timed_run(prob, U0, steps, warmup, rows=0, weights=None, band=None):
-    """Warm up, reset to t = 0, time `steps` steps with per-class events.
-    Returns (wall s, ms[4], launches[4], final time, final state)."""
+def timed_run(prob, U0, steps, warmup, rows=0, weights=None, band=None, shape=None):
+    """Autotune the launch shape (unless given), warm up, reset to t = 0,
+    time `steps` steps with per-class events.  Returns (wall s, ms[4],
+    launches[4], final time, final state, (rows, grid))."""
     import torch
     from paper_2201_12193_amd.mrhweno import Solver
+    from paper_2201_12193_amd import autotune
     U_init = torch.from_numpy(U0).cuda()
     Ut = U_init.clone()
     s = Solver([prob], [Ut])
     if weights is not None:
         s.set_indicator(weights, *band)
-    if rows:
+    if shape is not None:
+        s.set_launch(*shape)
+    elif rows:
         s.set_launch(rows, 0)
+        shape = (rows, 0)
+    else:
+        r, g, _ = autotune.tune(s, use_cache=False, reps=5)
+        shape = (r, g)
     s.step(warmup)
     s.sync()
     Ut.copy_(U_init)
@@ -121,7 +130,7 @@ def timed_run(prob, U0, steps, warmup, rows=0, weights=None, band=None):
     wall = time.perf_counter() - t0
     t, _, _ = s.sync()
     s.close()
-    return wall, ms, nl, t[0], Ut
+    return wall, ms, nl, t[0], Ut, shape
 
 
 def learned_compare(prob, U0, Uk, T, weights, band, steps):
@@ -177,7 +186,7 @@ def main():
     from paper_2201_12193_amd import inputs as I
 
     prob, U0, _ = I.euler_quadrants_2d(seed=args.seed, n=args.n, nq=2)
-    wall, ms, nl, T, Uk = timed_run(prob, U0, args.steps, args.warmup, args.rows)
+    wall, ms, nl, T, Uk, shape = timed_run(prob, U0, args.steps, args.warmup, args.rows)
     ncell = prob.ncell
     value = ncell * 3 * args.steps / wall
     stage_ms = ms[3] / max(nl[3], 1)
@@ -207,7 +216,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D Euler quadrants+Fourier {prob.nx}x{prob.ny} periodic, HLLC, KXRCF (M5-I), "
                                f"CFL 0.6, {args.steps} SSP-RK3 steps",
-                   "cells": ncell, "rk_stages_per_step": 3, "seed": args.seed, "sim_time": T},
+                   "cells": ncell, "rk_stages_per_step": 3, "seed": args.seed, "sim_time": T,
+                   "launch": {"rows_per_strip": shape[0], "grid": shape[1],
+                              "chosen_by": "given" if args.rows else "autotuner"}},
         "kernels_ms": {"reduce_dt": ms[0], "kxrcf_summary": ms[1], "flags": ms[2], "stage": ms[3],
                        "launches": nl},
         "roofline": roofline,
@@ -216,7 +227,7 @@ def main():
         from paper_2201_12193_amd.indicator import load_weights
         W = load_weights()
         pl = prob.replace(tc_mode=I.TC_LEARNED)
-        lw, lms, lnl, lT, _ = timed_run(pl, U0, args.steps, args.warmup, args.rows, W, args.band)
+        lw, lms, lnl, lT, _, _ = timed_run(pl, U0, args.steps, args.warmup, args.rows, W, args.band, shape)
         lv = ncell * 3 * args.steps / lw
         cmp = learned_compare(prob, U0, Uk, T, W, args.band, args.steps)
         out["learned"] = {"value": lv, "speedup_vs_plain": lv / value, "band": list(args.band),

@@ -80,7 +80,8 @@ typedef enum { MRHWENO_BETA_ON_Q = 0, MRHWENO_BETA_ON_P = 1 } mrhweno_beta;
 /* A problem posed as the paper poses it (Secs. 2.1, 2.2, 3). */
 typedef struct {
   int dim;                 /* 1 or 2                                              */
-  int nx, ny;              /* cells (ny ignored in 1D); each >= 8                 */
+  int nx, ny;              /* cells (ny ignored in 1D); each >= 8; 2D: nx*ny
+                              below 2^30/13                                       */
   double x0, x1, y0, y1;   /* domain; 2D requires square cells (dx == dy)        */
   int bc_x, bc_y;          /* mrhweno_bc                                         */
   int flux;                /* mrhweno_flux; ncomp = 1 (Burgers), 3 (1D Euler),

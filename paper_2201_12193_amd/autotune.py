@@ -14,7 +14,7 @@ from typing import Optional, Tuple
 
 CACHE = os.path.join(os.path.expanduser(os.environ.get("MRHWENO_CACHE_DIR", "~/.cache/mrhweno")),
                      "autotune.json")
-ROWS = (8, 16, 32, 64, 128)
+ROWS = (16, 24, 32, 40, 48, 64, 96)
 
 
 def _arch() -> str:
@@ -40,10 +40,20 @@ def _load() -> dict:
         return {}
 
 
-def tune(solver, use_cache: bool = True, grids=(0,), reps: int = 3) -> Tuple[int, int, Optional[float]]:
+def resident_grid() -> int:
+    """Work groups of the 2D stage kernel that fit the GPU at once (two per
+    compute unit)."""
+    import torch
+    return 2 * torch.cuda.get_device_properties(0).multi_processor_count
+
+
+def tune(solver, use_cache: bool = True, grids=None, reps: int = 3) -> Tuple[int, int, Optional[float]]:
     """Apply the cached launch shape for this kind of problem, or time the
-    candidates, apply the fastest and cache it.  Returns (rows, grid, ms)
-    (ms is None for a cache hit)."""
+    candidates (strip heights ROWS; grids: one work group per work item and
+    a persistent grid of resident size, unless given), apply the fastest and
+    cache it.  Returns (rows, grid, ms) (ms is None for a cache hit)."""
+    if grids is None:
+        grids = (0, resident_grid())
     k = key(solver)
     db = _load()
     if use_cache and k in db:

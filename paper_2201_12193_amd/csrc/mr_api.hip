@@ -90,6 +90,8 @@ std::string validate(const mrhweno_problem& p) {
     if (std::fabs(dx - dy) > 1e-12 * std::max(dx, dy)) return "2D cells must be square (dx == dy)";
   }
   if (plane_of(p) > (1ll << 31) - 1) return "grid too large";
+  /* the 2D stage kernel addresses a moment plane and row as a 30-bit offset */
+  if (p.dim == 2 && 13ll * plane_of(p) >= (1ll << 30)) return "2D grid too large (at most 2^30/13 cells)";
   return "";
 }
 
