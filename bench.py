@@ -53,7 +53,8 @@ def parse():
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--seed", type=int, default=2048)
     ap.add_argument("--rows", type=int, default=0,
-                    help="2D strip height (0: chosen by the autotuner before the timed run)")
+                    help="2D strip height (0: launch shape chosen by the autotuner before the timed run)")
+    ap.add_argument("--grid", type=int, default=0, help="2D stage grid size with --rows (0: one group per strip)")
     ap.add_argument("--band", type=float, nargs=2, default=(0.1, 0.9),
                     help="learned-indicator uncertainty band (KXRCF inside)")
     ap.add_argument("--no-learned", action="store_true")
@@ -98,7 +99,7 @@ def cpu_baseline(prob, U0):
                       f"{dt:.1f} s on {threads} threads"}
 
 
-def timed_run(prob, U0, steps, warmup, rows=0, weights=None, band=None, shape=None):
+def timed_run(prob, U0, steps, warmup, rows=0, grid=0, weights=None, band=None, shape=None):
     """Autotune the launch shape (unless given), warm up, reset to t = 0,
     time `steps` steps with per-class events.  Returns (wall s, ms[4],
     launches[4], final time, final state, (rows, grid))."""
@@ -113,8 +114,8 @@ def timed_run(prob, U0, steps, warmup, rows=0, weights=None, band=None, shape=No
     if shape is not None:
         s.set_launch(*shape)
     elif rows:
-        s.set_launch(rows, 0)
-        shape = (rows, 0)
+        s.set_launch(rows, grid)
+        shape = (rows, grid)
     else:
         r, g, _ = autotune.tune(s, use_cache=False, reps=5)
         shape = (r, g)
@@ -186,7 +187,7 @@ def main():
     from paper_2201_12193_amd import inputs as I
 
     prob, U0, _ = I.euler_quadrants_2d(seed=args.seed, n=args.n, nq=2)
-    wall, ms, nl, T, Uk, shape = timed_run(prob, U0, args.steps, args.warmup, args.rows)
+    wall, ms, nl, T, Uk, shape = timed_run(prob, U0, args.steps, args.warmup, args.rows, args.grid)
     ncell = prob.ncell
     value = ncell * 3 * args.steps / wall
     stage_ms = ms[3] / max(nl[3], 1)
@@ -227,7 +228,7 @@ def main():
         from paper_2201_12193_amd.indicator import load_weights
         W = load_weights()
         pl = prob.replace(tc_mode=I.TC_LEARNED)
-        lw, lms, lnl, lT, _, _ = timed_run(pl, U0, args.steps, args.warmup, args.rows, W, args.band, shape)
+        lw, lms, lnl, lT, _, _ = timed_run(pl, U0, args.steps, args.warmup, args.rows, args.grid, W, args.band, shape)
         lv = ncell * 3 * args.steps / lw
         cmp = learned_compare(prob, U0, Uk, T, W, args.band, args.steps)
         out["learned"] = {"value": lv, "speedup_vs_plain": lv / value, "band": list(args.band),
