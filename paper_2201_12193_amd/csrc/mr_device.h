@@ -217,13 +217,28 @@ MR_HD void mr_euler_flux(const double* u, double gam, double* f) {
   f[NC - 1] = vn * (u[NC - 1] + p);
 }
 
-/* physical fluxes f (x) and g (y) of the 2D Euler equations at one point */
-MR_HD void mr_euler_fg(const double* u, double gam, double* f, double* g) {
-  const double r = 1.0 / u[0];
+/* physical fluxes f (x) and g (y) of the 2D Euler equations at one point,
+ * given r = 1/rho */
+MR_HD void mr_euler_fg_r(const double* u, double r, double gam, double* f, double* g) {
   const double vx = u[1] * r, vy = u[2] * r;
   const double p = (gam - 1.0) * (u[3] - 0.5 * (u[1] * u[1] + u[2] * u[2]) * r);
   f[0] = u[1]; f[1] = u[1] * vx + p; f[2] = u[2] * vx; f[3] = vx * (u[3] + p);
   g[0] = u[2]; g[1] = u[1] * vy; g[2] = u[2] * vy + p; g[3] = vy * (u[3] + p);
+}
+
+MR_HD void mr_euler_fg(const double* u, double gam, double* f, double* g) {
+  mr_euler_fg_r(u, 1.0 / u[0], gam, f, g);
+}
+
+/* 1/a, 1/b, 1/c, 1/d with one division (positive, moderate arguments) */
+MR_HD void mr_recip4(double a, double b, double c, double d, double* r) {
+  const double ab = a * b, cd = c * d;
+  const double inv = 1.0 / (ab * cd);
+  const double icd = ab * inv, iab = cd * inv;   /* 1/(cd), 1/(ab) */
+  r[0] = b * iab;
+  r[1] = a * iab;
+  r[2] = d * icd;
+  r[3] = c * icd;
 }
 
 /* HLLC flux of eqs. (f_HLLC), (COEF), (uLR_) with the printed PVRS star
@@ -235,7 +250,9 @@ MR_HD void mr_hllc(const double* uL, const double* uR, double gam, double* f) {
   constexpr int N = 1 + D;
   constexpr int T = (NC == 4) ? 2 - D : 1;
   const double rL = uL[0], rR = uR[0];
-  const double irL = 1.0 / rL, irR = 1.0 / rR;
+  /* 1/rho_L and 1/rho_R from one division */
+  const double irLR = 1.0 / (rL * rR);
+  const double irL = rR * irLR, irR = rL * irLR;
   const double muL = uL[N] * irL, muR = uR[N] * irR;
   double m2L = uL[1] * uL[1], m2R = uR[1] * uR[1];
   if (NC == 4) { m2L += uL[2] * uL[2]; m2R += uR[2] * uR[2]; }
@@ -245,11 +262,15 @@ MR_HD void mr_hllc(const double* uL, const double* uR, double gam, double* f) {
   const double cL = sqrt(gam * pL * irL), cR = sqrt(gam * pR * irR);
   const double rs = 0.5 * (rL + rR), cs = 0.5 * (cL + cR);
   const double crs = cs * rs;
+  /* 1/crs, 1/p_L, 1/p_R from one division */
+  const double pLR = pL * pR;
+  const double i3 = 1.0 / (crs * pLR);
+  const double icrs = pLR * i3, ipL = crs * pR * i3, ipR = crs * pL * i3;
   const double ps = 0.5 * (pL + pR + (muL - muR) * crs);
-  const double ss = 0.5 * (muL + muR + (pL - pR) / crs);   /* s* of the printed PVRS */
+  const double ss = 0.5 * (muL + muR + (pL - pR) * icrs);   /* s* of the printed PVRS */
   const double k1 = (gam + 1.0) / (2.0 * gam);
-  const double coefL = (ps <= pL) ? 1.0 : sqrt(1.0 + k1 * (ps / pL - 1.0));
-  const double coefR = (ps <= pR) ? 1.0 : sqrt(1.0 + k1 * (ps / pR - 1.0));
+  const double coefL = (ps <= pL) ? 1.0 : sqrt(1.0 + k1 * (ps * ipL - 1.0));
+  const double coefR = (ps <= pR) ? 1.0 : sqrt(1.0 + k1 * (ps * ipR - 1.0));
   const double sL = muL - cL * coefL, sR = muR + cR * coefR;
   /* ordered branch chain: 0 <= sL -> f_L; 0 <= s* -> f*_L; 0 <= sR -> f*_R; f_R */
   const int br = (0.0 <= sL) ? 0 : ((0.0 <= ss) ? 1 : ((0.0 <= sR) ? 2 : 3));

@@ -214,13 +214,17 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
         const int r = (NC == 1) ? rr : k;
         const double wr = glw(r), er = gln(r);
         if (body) {
+          double pts[4][NC], rr4[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) pts[q][c] = VAL(q + 4 * r, c, cs);
+          if (NC == 4) mr_recip4(pts[0][0], pts[1][0], pts[2][0], pts[3][0], rr4);
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            double pt[NC], f[NC], gg[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) pt[c] = VAL(q + 4 * r, c, cs);
-            if (NC == 4) mr_euler_fg(pt, gam, f, gg);
-            else { f[0] = 0.5 * pt[0] * pt[0]; gg[0] = f[0]; }
+            double f[NC], gg[NC];
+            if (NC == 4) mr_euler_fg_r(pts[q], rr4[q], gam, f, gg);
+            else { f[0] = 0.5 * pts[q][0] * pts[q][0]; gg[0] = f[0]; }
             const double wq = glw(q) * wr;
 #pragma unroll
             for (int c = 0; c < NC; ++c) { F[c] += wq * f[c]; G[c] += wq * gg[c]; }
