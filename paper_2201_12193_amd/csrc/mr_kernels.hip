@@ -39,7 +39,9 @@ MR_INL void mr_block_max2(double* ax, double* ay, double* sh) {
 
 /* Each work group takes a contiguous run of `chunk` work items, keeps a
  * running max per instance and publishes it with one atomic per instance
- * run (max is exact, so the result does not depend on the order). */
+ * run (max is exact, so the result does not depend on the order).  The
+ * loads of four work items are issued together so that their latencies
+ * overlap. */
 __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_tile1* tiles, int ntiles,
                                                      int stage, int chunk) {
 #pragma clang fp contract(off)
@@ -48,61 +50,80 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
   int cur = -1;
   double ax = 0.0, ay = 0.0;
   int bad = 0;
-  for (int t = t0; t <= t1; ++t) {
-    const int inst = (t < t1) ? tiles[t].inst : -2;
-    if (inst != cur && cur >= 0) {
-      /* flush the finished instance (uniform across the block) */
-      mr_inst& J = insts[cur];
-      const int anybad = __syncthreads_or(bad);
-      mr_block_max2(&ax, &ay, sh);
-      if (threadIdx.x == 0) {
-        if (stage == 0) {
-          atomicMax(&J.amax[0], mr_dbits(ax));
-          atomicMax(&J.amax[1], mr_dbits(ay));
-          if (anybad) atomicOr(&J.err, 1);
-        } else {
-          atomicMax(&J.lfa[stage], mr_dbits(ax));
-        }
+  auto flush = [&]() {
+    /* publish the finished instance (uniform across the block) */
+    mr_inst& J = insts[cur];
+    const int anybad = __syncthreads_or(bad);
+    mr_block_max2(&ax, &ay, sh);
+    if (threadIdx.x == 0) {
+      if (stage == 0) {
+        atomicMax(&J.amax[0], mr_dbits(ax));
+        atomicMax(&J.amax[1], mr_dbits(ay));
+        if (anybad) atomicOr(&J.err, 1);
+      } else {
+        atomicMax(&J.lfa[stage], mr_dbits(ax));
       }
-      ax = ay = 0.0;
-      bad = 0;
     }
-    cur = inst;
-    if (t >= t1) break;
-    const mr_tile1 tl = tiles[t];
-    mr_inst& I = insts[tl.inst];
-    const double* U;
-    if (stage == 0) {
-      if (I.err) continue;
-      U = I.buf[I.cur];
-    } else {
-      if (!I.active || I.flux != 0) continue;
-      U = I.p_out[stage - 1];
-    }
-    const int k = tl.start + (int)threadIdx.x;
-    if (k < tl.start + tl.count) {
+    ax = ay = 0.0;
+    bad = 0;
+  };
+  for (int g0 = t0; g0 < t1; g0 += 4) {
+    double u[4][4];
+    int inst[4], use[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int t = g0 + q;
+      inst[q] = -1;
+      use[q] = 0;
+      if (t >= t1) continue;
+      const mr_tile1 tl = tiles[t];
+      const mr_inst& I = insts[tl.inst];
+      inst[q] = tl.inst;
+      const double* U;
+      if (stage == 0) {
+        if (I.err) continue;
+        U = I.buf[I.cur];
+      } else {
+        if (!I.active || I.flux != 0) continue;
+        U = I.p_out[stage - 1];
+      }
+      const int k = tl.start + (int)threadIdx.x;
+      if (k >= tl.start + tl.count) continue;
+      use[q] = 1;
       const long long P = I.plane;
       const int nm = I.dim + 1;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) u[q][c] = c < I.nc ? U[(long long)c * nm * P + k] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (inst[q] < 0) break;
+      if (inst[q] != cur) {
+        if (cur >= 0) flush();
+        cur = inst[q];
+      }
+      if (!use[q]) continue;
+      const mr_inst& I = insts[inst[q]];
       if (I.flux == 0) {
-        const double a = fabs(U[k]);
+        const double a = fabs(u[q][0]);
         ax = fmax(ax, a);
         ay = fmax(ay, a);
         bad |= !(a <= 1.0e300);
       } else {
-        double u[4];
-        for (int c = 0; c < I.nc; ++c) u[c] = U[(long long)c * nm * P + k];
-        double ke = u[1] * u[1];
-        if (I.nc == 4) ke += u[2] * u[2];
-        const double p = (I.gam - 1.0) * (u[I.nc - 1] - 0.5 * ke / u[0]);
-        const double cs = sqrt(I.gam * p / u[0]);
-        const double sx = fabs(u[1] / u[0]) + cs;
-        const double sy = (I.nc == 4) ? fabs(u[2] / u[0]) + cs : 0.0;
-        const int b = !(u[0] > 0.0) || !(p > 0.0) || !(sx <= 1.0e300) || !(sy <= 1.0e300);
+        double ke = u[q][1] * u[q][1];
+        if (I.nc == 4) ke += u[q][2] * u[q][2];
+        const double E = I.nc == 4 ? u[q][3] : u[q][2];
+        const double p = (I.gam - 1.0) * (E - 0.5 * ke / u[q][0]);
+        const double cs = sqrt(I.gam * p / u[q][0]);
+        const double sx = fabs(u[q][1] / u[q][0]) + cs;
+        const double sy = (I.nc == 4) ? fabs(u[q][2] / u[q][0]) + cs : 0.0;
+        const int b = !(u[q][0] > 0.0) || !(p > 0.0) || !(sx <= 1.0e300) || !(sy <= 1.0e300);
         bad |= b;
         if (!b) { ax = fmax(ax, sx); ay = fmax(ay, sy); }
       }
     }
   }
+  if (cur >= 0) flush();
 }
 
 /* Time step of the current step and the state rotation, one thread per
@@ -437,7 +458,8 @@ extern "C" {
 
 hipError_t mr_launch_reduce(hipStream_t s, mr_inst* d, const mr_tile1* t, int nt, int stage) {
   if (nt <= 0) return hipSuccess;
-  const int chunk = nt > 2048 ? (nt + 2047) / 2048 : 1;
+  /* few enough work groups that the per-instance atomics do not contend */
+  const int chunk = nt > 512 ? (nt + 511) / 512 : 1;
   const int grid = (nt + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(MR_BLOCK), 0, s, d, t, nt, stage, chunk);
   return hipGetLastError();
