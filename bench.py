@@ -58,6 +58,12 @@ def parse():
     ap.add_argument("--band", type=float, nargs=2, default=(0.1, 0.9),
                     help="learned-indicator uncertainty band (KXRCF inside)")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--workload", default="quadrants2d",
+                    choices=("quadrants2d", "batched", "riemann1d", "burgers1d"),
+                    help="quadrants2d: the benchmark above; the others time the batched and 1D "
+                         "configurations (256 instances of uneven sizes in one launch per kernel "
+                         "class; 1D Euler N = 4096; 1D Burgers N = 200) with every instance kept "
+                         "advancing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
@@ -177,12 +183,64 @@ def learned_compare(prob, U0, Uk, T, weights, band, steps):
             "band_fraction": nband / max(ncell, 1)}
 
 
+def other_workload(args):
+    """Throughput of the batched and 1D configurations: graph replay of
+    `steps` steps of every instance (final times lifted so that all
+    instances advance), plus one profiled pass for the kernel classes."""
+    import torch
+    from paper_2201_12193_amd import inputs as I
+    from paper_2201_12193_amd.mrhweno import Solver
+    from paper_2201_12193_amd import autotune
+    if args.workload == "batched":
+        pairs = I.batched_instances(args.seed)
+        desc = "256 Euler instances (192 1D, N log-uniform 128..16384; 64 2D, side log-uniform 64..1024)"
+    elif args.workload == "riemann1d":
+        p, U, _ = I.euler_riemann_1d(args.seed, n=4096)
+        pairs = [(p, U)]
+        desc = "1D Euler Riemann data, N = 4096, transmissive, HLLC"
+    else:
+        p, U, _ = I.burgers_smooth_1d(args.seed, n=200)
+        pairs = [(p, U)]
+        desc = "1D Burgers, N = 200, periodic, Lax-Friedrichs"
+    probs = [p.replace(t_final=float("inf")) for p, _ in pairs]
+    Us = [torch.from_numpy(U).cuda() for _, U in pairs]
+    s = Solver(probs, Us)
+    shape = autotune.tune(s, use_cache=False, reps=3)[:2] if any(p.dim == 2 for p in probs) else None
+    s.step(args.warmup)
+    _, st0, _ = s.sync(raise_on_error=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    _, st1, status = s.sync(raise_on_error=False)
+    wall = time.perf_counter() - t0
+    ms, nl = s.profile(min(args.steps, 20))
+    s.close()
+    cells = sum(p.ncell for p in probs)
+    # an instance that meets a non-physical state stops advancing: count the
+    # steps each instance actually took
+    updates = sum(p.ncell * 3 * (b - a) for p, a, b in zip(probs, st0, st1))
+    stopped = sum(1 for a, b in zip(st0, st1) if b - a < args.steps)
+    out = {"metric": "MR-HWENO cell-updates/s (FP64)", "value": updates / wall,
+           "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": desc, "instances": len(probs), "cells": cells, "seed": args.seed,
+                      "instances_stopped_nonphysical": stopped,
+                      "launch": None if shape is None else {"rows_per_strip": shape[0], "grid": shape[1]}},
+           "kernels_ms_per_step": {"reduce_dt": ms[0] / max(nl[0], 1) * (nl[0] / max(1, min(args.steps, 20))),
+                                   "kxrcf": (ms[1] + ms[2]) / min(args.steps, 20),
+                                   "stage": ms[3] / min(args.steps, 20)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU decomposition is a design, not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "quadrants2d":
+        return other_workload(args)
     import torch
     from paper_2201_12193_amd import inputs as I
 
