@@ -10,7 +10,8 @@
  * Features of cell (x, y): moment m in {0, 1, 2} (cell average, x and y
  * first moments) of component c in {rho, rho u, rho v, E} at cell
  * (x + wx, y + wy), |wx|, |wy| <= 2, normalised by the cell's own averages:
- *   (raw - [m == 0] centre_c) * scale_c,
+ *   (raw - [m == 0] centre_c) * scale_c  (evaluated as one fma with the
+ *   scaled centre),
  *   scale_rho = 1/rho, scale_(rho u) = scale_(rho v) = 1/(rho c), scale_E = 1/E,
  * with c the sound speed of the cell average, plus log2(h)/16.  The values
  * are computed in FP32 and rounded to BF16.  Index of a feature: f =
@@ -31,7 +32,8 @@ MR_INL f32x4 mr_mfma(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 
 /* ------------------------------------------------------------ features */
-/* normalisation of a cell from its FP32 averages: scale sc[4], centre cs[4] */
+/* normalisation of a cell from its FP32 averages: scale sc[4] and the
+ * scaled centre cs[c] = centre_c * sc[c] (a feature is one fma) */
 MR_INL void mr_feat_norm(float rho, float mx, float my, float E, float gam, float* sc, float* cs) {
   /* hardware reciprocal and square root (1 ulp): the features are rounded
      to BF16 afterwards */
@@ -45,14 +47,14 @@ MR_INL void mr_feat_norm(float rho, float mx, float my, float E, float gam, floa
   sc[1] = rc;
   sc[2] = rc;
   sc[3] = __builtin_amdgcn_rcpf(E > 1e-30f ? E : 1e-30f);
-  cs[0] = rho;
-  cs[1] = mx;
-  cs[2] = my;
-  cs[3] = E;
+  cs[0] = rho * sc[0];
+  cs[1] = mx * sc[1];
+  cs[2] = my * sc[2];
+  cs[3] = E * sc[3];
 }
 
-MR_INL float mr_feat_val(float raw, int m, float centre, float scale) {
-  return (m == 0 ? raw - centre : raw) * scale;
+MR_INL float mr_feat_val(float raw, int m, float scentre, float scale) {
+  return m == 0 ? fmaf(raw, scale, -scentre) : raw * scale;
 }
 
 /* slot s of lane group g -> (component, moment, wx, wy); kind 0 moment,
@@ -200,56 +202,97 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
         scg[gi] = g == 0 ? sc[gi][0] : (g == 3 ? sc[gi][3] : sc[gi][1]);
         csg[gi] = g == 0 ? cs[gi][0] : (g == 1 ? cs[gi][1] : (g == 2 ? cs[gi][2] : cs[gi][3]));
       }
+      /* the accumulators start from the biases: lane (r, g) accumulates
+         hidden units 16m + 4g + j */
+      const float4* b1v4 = reinterpret_cast<const float4*>(sh.w.b1);
+      const float4* b2v4 = reinterpret_cast<const float4*>(sh.w.b2);
+      const float4* w3v4 = reinterpret_cast<const float4*>(sh.w.w3);
       f32x4 h[4][4];
 #pragma unroll
-      for (int gi = 0; gi < 4; ++gi)
+      for (int m = 0; m < 4; ++m) {
+        const float4 bb = b1v4[4 * m + g];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) h[gi][m] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int gi = 0; gi < 4; ++gi) h[gi][m] = f32x4{bb.x, bb.y, bb.z, bb.w};
+      }
+      /* raw moment of slot s for cell group gi (LDS), 0 for the other slots */
+      auto raw = [&](int s, int gi) -> float {
+        if (s < 60) {
+          const int c = s / 15, m = (s / 5) % 3, wx = s % 5 - 2;
+          return sh.mom[(3 * c + m) * MR_LPL + bo + 16 * gi + wx];
+        }
+        if (s < 75) {
+          const int m = (s - 60) / 5, wx = (s - 60) % 5 - 2;
+          return sh.mom[m * MR_LPL + b2 + 16 * gi + wx];
+        }
+        return 0.0f;
+      };
+      /* software pipeline over (contraction block, pair of cell groups): the
+         LDS reads of the next step are issued before the current step's
+         conversions and MFMAs, so their latency is hidden */
+      float nxt[2][8];
+#pragma unroll
+      for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) nxt[h2][j] = raw(j, h2);
 #pragma unroll
       for (int kb = 0; kb < MR_KP / 32; ++kb) {
         bf16x8 a[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) a[m] = W1[(kb * 4 + m) * 64 + lane];
 #pragma unroll
-        for (int gi = 0; gi < 4; ++gi) {
-          bf16x8 b;
+        for (int pr = 0; pr < 2; ++pr) {
+          float cur[2][8];
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int s = 8 * kb + j;
-            float v = 0.0f;
-            if (s < 60) {
-              const int c = s / 15, m = (s / 5) % 3, wx = s % 5 - 2;
-              v = mr_feat_val(sh.mom[(3 * c + m) * MR_LPL + bo + 16 * gi + wx], m, cs[gi][c], sc[gi][c]);
-            } else if (s < 75) {
-              const int m = (s - 60) / 5, wx = (s - 60) % 5 - 2;
-              v = mr_feat_val(sh.mom[m * MR_LPL + b2 + 16 * gi + wx], m, csg[gi], scg[gi]);
-            } else if (s == 75) {
-              v = g == 0 ? lh : 0.0f;
-            }
-            b[j] = (__bf16)v;
+          for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cur[h2][j] = nxt[h2][j];
+          const int nkb = pr == 1 ? kb + 1 : kb, npr = pr == 1 ? 0 : 1;
+          if (nkb < MR_KP / 32) {
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2)
+#pragma unroll
+              for (int j = 0; j < 8; ++j) nxt[h2][j] = raw(8 * nkb + j, 2 * npr + h2);
           }
 #pragma unroll
-          for (int m = 0; m < 4; ++m) h[gi][m] = mr_mfma(a[m], b, h[gi][m]);
+          for (int h2 = 0; h2 < 2; ++h2) {
+            const int gi = 2 * pr + h2;
+            bf16x8 b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int s = 8 * kb + j;
+              float v = 0.0f;
+              if (s < 60) {
+                const int c = s / 15, m = (s / 5) % 3;
+                v = mr_feat_val(cur[h2][j], m, cs[gi][c], sc[gi][c]);
+              } else if (s < 75) {
+                v = mr_feat_val(cur[h2][j], (s - 60) / 5, csg[gi], scg[gi]);
+              } else if (s == 75) {
+                v = g == 0 ? lh : 0.0f;
+              }
+              b[j] = (__bf16)v;
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) h[gi][m] = mr_mfma(a[m], b, h[gi][m]);
+          }
         }
       }
       /* layer 2 and 3; this lane holds hidden units 16m + 4g + j */
       float z[4];
 #pragma unroll
       for (int gi = 0; gi < 4; ++gi) {
-        const float4* b1v4 = reinterpret_cast<const float4*>(sh.w.b1);
-        const float4* b2v4 = reinterpret_cast<const float4*>(sh.w.b2);
-        const float4* w3v4 = reinterpret_cast<const float4*>(sh.w.w3);
         f32x4 o[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) o[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int m = 0; m < 4; ++m) {
+          const float4 bb = b2v4[4 * m + g];
+          o[m] = f32x4{bb.x, bb.y, bb.z, bb.w};
+        }
 #pragma unroll
         for (int kb2 = 0; kb2 < 2; ++kb2) {
           bf16x8 b;
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float4 blo4 = b1v4[4 * (2 * kb2) + g], bhi4 = b1v4[4 * (2 * kb2 + 1) + g];
-            const float lo = h[gi][2 * kb2][j] + (&blo4.x)[j];
-            const float hi = h[gi][2 * kb2 + 1][j] + (&bhi4.x)[j];
+            const float lo = h[gi][2 * kb2][j];
+            const float hi = h[gi][2 * kb2 + 1][j];
             b[j] = (__bf16)(lo > 0.f ? lo : 0.f);
             b[4 + j] = (__bf16)(hi > 0.f ? hi : 0.f);
           }
@@ -259,10 +302,10 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
         float zp = 0.f;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const float4 bb = b2v4[4 * m + g], ww = w3v4[4 * m + g];
+          const float4 ww = w3v4[4 * m + g];
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
-            const float v = o[m][j] + (&bb.x)[j];
+            const float v = o[m][j];
             zp += (v > 0.f ? v : 0.f) * (&ww.x)[j];
           }
         }
