@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--rows", type=int, default=0,
                     help="2D strip height (0: launch shape chosen by the autotuner before the timed run)")
     ap.add_argument("--grid", type=int, default=0, help="2D stage grid size with --rows (0: one group per strip)")
-    ap.add_argument("--band", type=float, nargs=2, default=(0.1, 0.9),
+    ap.add_argument("--band", type=float, nargs=2, default=(0.2, 0.8),
                     help="learned-indicator uncertainty band (KXRCF inside)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--workload", default="quadrants2d",
