@@ -93,3 +93,40 @@ def test_fullsize_conservation(developed):
     b = V[:, 0].sum(dim=(1, 2))
     scale = torch.from_numpy(U0).cuda()[:, 0].abs().sum(dim=(1, 2))
     assert float(((b - a).abs() / scale).max()) < 1e-13
+
+
+def test_fullsize_flags_and_learned_decisions(developed):
+    """At full size: the KXRCF flags of every cell equal the oracle's except
+    at near-ties; the learned indicator's band cells get the oracle's KXRCF
+    flag, and its confident decisions agree with the FP64 network on sampled
+    cells (up to BF16 rounding near the band edges)."""
+    import torch
+    from oracle import mlp
+    from paper_2201_12193_amd.mrhweno import Solver
+    from paper_2201_12193_amd.indicator import load_weights
+    from tests.parity_util import flag_mismatch
+    prob, _, Ut = developed
+    U = Ut.cpu().numpy()
+    _, fk_orc, num, den = oracle.reconstruct(prob, U)
+    s = Solver([prob], [Ut.clone()])
+    fk, _ = s.flag(0, Ut)
+    s.close()
+    bad, ties = flag_mismatch(fk.cpu().numpy(), fk_orc, num, den)
+    assert bad == 0 and ties <= 4, (bad, ties)
+    W = load_weights()
+    sl = Solver([prob.replace(tc_mode=I.TC_LEARNED)], [Ut.clone()])
+    sl.set_indicator(W, 0.2, 0.8)
+    dec, fl = sl.indicator(0, Ut)
+    sl.close()
+    dec, fl = dec.cpu().numpy().ravel(), fl.cpu().numpy().ravel()
+    band = dec == 2
+    assert np.array_equal(fl[~band], dec[~band])
+    bad, ties = flag_mismatch(fl[band], fk_orc.ravel()[band], num.ravel()[band], den.ravel()[band])
+    assert bad == 0 and ties <= 2, (bad, ties)
+    rng = np.random.default_rng(23)
+    cells = rng.choice(prob.ncell, 300, replace=False)
+    P = mlp.bf16_round(W.float().cpu().numpy().astype(np.float64))
+    sr = mlp.sigmoid(mlp.forward(mlp.features(prob, U, cells), P, bf16_hidden=True)[0])
+    want = np.where(sr > 0.8, 1, np.where(sr < 0.2, 0, 2))
+    near = (np.abs(sr - 0.2) < 0.03) | (np.abs(sr - 0.8) < 0.03)
+    assert np.all((dec[cells] == want) | near)
