@@ -22,6 +22,7 @@ hipError_t mr_launch_summary(hipStream_t, int, int, mr_inst*, const mr_tile1*, i
 hipError_t mr_launch_flags(hipStream_t, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_stage1(hipStream_t, int, int, mr_inst*, const mr_tile1*, int, int, int);
 hipError_t mr_launch_stage2(hipStream_t, int, int, mr_inst*, const mr_tile2*, int, int, int);
+hipError_t mr_launch_kxrcf2(hipStream_t, int, int, mr_inst*, const mr_tile2*, int, int);
 hipError_t mr_launch_values(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, double*);
 hipError_t mr_launch_fb_reset(hipStream_t, int*, int);
 hipError_t mr_launch_pack(hipStream_t, const void*, mr_learn_w*);
@@ -42,6 +43,8 @@ constexpr int kBlock = 256;
 constexpr int kFHalo = 2;   /* flags: final values of cells -1..n need flags -2..n+1 */
 constexpr int kSHalo = 3;   /* summaries: flags of cells -2..n+1 need summaries -3..n+2 */
 constexpr int kMinRows = 8; /* smallest 2D strip height the work lists are sized for */
+constexpr int kKxW = 62;    /* 2D KXRCF work item: 62 flag columns ...                */
+constexpr int kKxRows = 46; /* ... x 46 flag rows of the extended flag range          */
 constexpr int kLearnW = 64;     /* learned-indicator work item: 64 columns ...       */
 constexpr int kLearnRows = 32;  /* ... x 32 rows of the extended flag range          */
 
@@ -62,13 +65,19 @@ int nsumm(const mrhweno_problem& p) { return p.dim == 1 ? 5 : 9; }
 bool learned(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_LEARNED; }
 /* KXRCF face summaries over the whole extended plane (the learned
    indicator keeps a summary plane too, filled only around band cells) */
-bool needs_summ(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_KXRCF; }
+bool kxrcf(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_KXRCF; }
+/* 1D KXRCF keeps face summaries in a plane; 2D KXRCF computes them in LDS */
+bool needs_summ(const mrhweno_problem& p) { return kxrcf(p) && p.dim == 1; }
 bool has_summ(const mrhweno_problem& p) { return needs_summ(p) || learned(p); }
 /* work items of the learned indicator: strips over [-2, n+2)^2 */
 int learn_tiles(const mrhweno_problem& p) {
   return learned(p) ? ceil_div_i(ext(p.nx, kFHalo), kLearnW) * ceil_div_i(ext(p.ny, kFHalo), kLearnRows) : 0;
 }
 int strip_cells(const mrhweno_problem& p) { return kBlock / ncomp_of(p); }   /* 2D strip width incl. ring */
+/* 2D KXRCF work items: strips over [-2, n+2)^2 */
+int kx_tiles(const mrhweno_problem& p) {
+  return p.dim == 2 && kxrcf(p) ? ceil_div_i(ext(p.nx, kFHalo), kKxW) * ceil_div_i(ext(p.ny, kFHalo), kKxRows) : 0;
+}
 
 std::string validate(const mrhweno_problem& p) {
   if (p.dim != 1 && p.dim != 2) return "dim must be 1 or 2";
@@ -118,9 +127,9 @@ Layout layout(const mrhweno_problem* P, int n) {
     size_t a = ceil_div(plane_of(p), kBlock) + ceil_div((long long)sex(p) * sey(p), kBlock) +
                ceil_div((long long)fex(p) * fey(p), kBlock) + ceil_div(plane_of(p), kBlock);
     if (p.dim == 1) a += ceil_div(p.nx, kBlock - 2);
-    else t2 += (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows);
+    else t2 += (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) + kx_tiles(p);
     t1 += a;
-    tmax = std::max(tmax, a + learn_tiles(p) +
+    tmax = std::max(tmax, a + learn_tiles(p) + kx_tiles(p) +
                               (p.dim == 2 ? (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) : 0));
     L.n_tilesl += learn_tiles(p);
     if (learned(p)) {
@@ -171,10 +180,16 @@ struct Group {
   bool any_summ = false, any_lf = false;
   std::vector<int> insts;
   int t_summ = 0, n_summ = 0, t_flag = 0, n_flag = 0, t_st1 = 0, n_st1 = 0;
-  int t_st2 = 0, n_st2 = 0;
+  int t_st2 = 0, n_st2 = 0, t_kx = 0, n_kx = 0;
 };
 
 /* learned-indicator work items of one instance (instance id `slot`) */
+void add_kx_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p) {
+  for (int y0 = -kFHalo; y0 < p.ny + kFHalo; y0 += kKxRows)
+    for (int x0 = -kFHalo; x0 < p.nx + kFHalo; x0 += kKxW)
+      v.push_back(mr_tile2{slot, x0, y0, std::min(kKxRows, p.ny + kFHalo - y0)});
+}
+
 void add_learn_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p) {
   for (int y0 = -kFHalo; y0 < p.ny + kFHalo; y0 += kLearnRows)
     for (int x0 = -kFHalo; x0 < p.nx + kFHalo; x0 += kLearnW)
@@ -242,6 +257,10 @@ static void add_cells(std::vector<mr_tile1>& v, int inst, long long count) {
     v.push_back(mr_tile1{inst, (int)s, (int)std::min<long long>(kBlock, count - s), 0});
 }
 
+static void add_kx_tiles_if(std::vector<mr_tile2>& v, int q, const mrhweno_problem& p) {
+  if (kx_tiles(p) > 0) add_kx_tiles(v, q, p);
+}
+
 static void build_lists(mrhweno_ctx* c) {
   c->h_t1.clear();
   c->h_t2.clear();
@@ -255,8 +274,9 @@ static void build_lists(mrhweno_ctx* c) {
       if (needs_summ(c->probs[q])) add_cells(c->h_t1, q, (long long)sex(c->probs[q]) * sey(c->probs[q]));
     g.n_summ = (int)c->h_t1.size() - g.t_summ;
     g.t_flag = (int)c->h_t1.size();
-    for (int q : g.insts)
-      if (!learned(c->probs[q])) add_cells(c->h_t1, q, (long long)fex(c->probs[q]) * fey(c->probs[q]));
+    for (int q : g.insts)   /* 2D KXRCF flags come from the fused kernel */
+      if (!learned(c->probs[q]) && !(g.dim == 2 && kxrcf(c->probs[q])))
+        add_cells(c->h_t1, q, (long long)fex(c->probs[q]) * fey(c->probs[q]));
     g.n_flag = (int)c->h_t1.size() - g.t_flag;
     g.t_st1 = (int)c->h_t1.size();
     if (g.dim == 1)
@@ -280,6 +300,9 @@ static void build_lists(mrhweno_ctx* c) {
       }
     }
     g.n_st2 = (int)c->h_t2.size() - g.t_st2;
+    g.t_kx = (int)c->h_t2.size();
+    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q]);
+    g.n_kx = (int)c->h_t2.size() - g.t_kx;
   }
 }
 
@@ -327,6 +350,11 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
       if (g.any_summ) {
         any = true;
         if ((e = mr_launch_summary(s, g.dim, g.bp, c->d, c->t1 + g.t_summ, g.n_summ, st)) != hipSuccess) return e;
+      }
+    for (auto& g : c->groups)
+      if (g.n_kx > 0) {
+        any = true;
+        if ((e = mr_launch_kxrcf2(s, g.nc == 4 ? 3 : 1, g.bp, c->d, c->t2 + g.t_kx, g.n_kx, st)) != hipSuccess) return e;
       }
     if (c->any_learned) {
       any = true;
@@ -708,7 +736,8 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   if (needs_summ(p)) add_cells(t1, slot, (long long)sex(p) * sey(p));
   const int n_sum = (int)t1.size() - t_sum;
   const int t_flg = (int)t1.size();
-  if (!lrn) add_cells(t1, slot, (long long)fex(p) * fey(p));
+  const bool kx2 = kx_tiles(p) > 0;   /* 2D KXRCF: flags from the fused kernel */
+  if (!lrn && !kx2) add_cells(t1, slot, (long long)fex(p) * fey(p));
   const int n_flg = (int)t1.size() - t_flg;
   const int t_val = (int)t1.size();
   add_cells(t1, slot, plane_of(p));
@@ -724,7 +753,9 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   }
   const int n_st = (int)t1.size() - t_st;
   if (lrn) add_learn_tiles(tl, slot, p);
-  /* the probe area holds the 1D list, the 2D list and the learned list */
+  if (kx2) add_kx_tiles(tl, slot, p);
+  /* the probe area holds the 1D list, the 2D list and the learned or the
+     2D KXRCF list */
   char* area = c->ws + c->L.probe_tiles;
   const size_t o2 = al(sizeof(mr_tile1) * t1.size());
   const size_t o3 = o2 + al(sizeof(mr_tile2) * std::max<size_t>(t2.size(), 1));
@@ -750,6 +781,7 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   } else {
     MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, c->d, d1 + t_sum, n_sum, 3));
     MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));
+    if (kx2) MR_CHECK(c, mr_launch_kxrcf2(s, ncomp_of(p) == 4 ? 3 : 1, p.beta_on, c->d, d3, (int)tl.size(), 3));
   }
   const int nc = ncomp_of(p);
   if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + t_val, n_val, (double*)out));

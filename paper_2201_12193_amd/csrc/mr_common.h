@@ -11,8 +11,17 @@
 #define MR_OCC __attribute__((amdgpu_waves_per_eu(MR_WAVES)))
 
 /* =================================================================== helpers */
+/* Global-memory view of a pointer taken from an instance descriptor.  The
+ * compiler cannot infer the address space of a pointer loaded from memory
+ * and would access it with flat instructions, which also count against the
+ * LDS wait counter: every LDS wait would then wait for the HBM loads in
+ * flight as well. */
+#define MR_GLB __attribute__((address_space(1)))
+template <class T>
+MR_INL MR_GLB T* mr_gp(T* p) { return (MR_GLB T*)p; }
+
 struct mr_grid {
-  const double* U;  /* state base: comp c, moment m plane at U + (c*nm + m)*P */
+  const MR_GLB double* U;  /* state base: comp c, moment m plane at U + (c*nm + m)*P */
   long long P;
   int nx, ny, bcx, bcy, nm;
 };
@@ -27,7 +36,8 @@ MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
 }
 
 /* flag of cell (i, j) from an extended plane with halo h (clamped) */
-MR_INL int mr_flag(const unsigned char* fl, int ex, int ey, int h, int i, int j) {
+template <class P>
+MR_INL int mr_flag(P fl, int ex, int ey, int h, int i, int j) {
   int a = i + h, b = j + h;
   a = a < 0 ? 0 : (a >= ex ? ex - 1 : a);
   b = b < 0 ? 0 : (b >= ey ? ey - 1 : b);
@@ -60,7 +70,7 @@ MR_INL void mr2_modify_stencil(const mr_grid& g, int c, int x, int y, const int*
  * of the troubled cells of its stencil replaced (Steps 2.2, 2.3).
  * ue/ve/we receive the cell's own (possibly modified) moments. */
 template <bool BP>
-MR_INL void mr2_cell_values(const mr_grid& g, const mr_inst& I, const unsigned char* fl,
+MR_INL void mr2_cell_values(const mr_grid& g, const mr_inst& I, const MR_GLB unsigned char* fl,
                             int c, int x, int y, double out[16], double* ue, double* ve, double* we) {
   double u[9], v[9], w[9];
   int fs[9];
@@ -132,21 +142,6 @@ MR_INL void mr2_face_summary(const mr_grid& g, const mr_inst& I, int i, int j, d
   f[0] = sl; f[1] = sr; f[2] = sb; f[3] = st;
   f[4] = vl; f[5] = vr; f[6] = vb; f[7] = vt;
   f[8] = nrm;
-}
-
-/* U^n with the stage-1 modification applied at cell (x, y), component c */
-MR_INL void mr2_un_mod(const mr_grid& g, const unsigned char* fl1, const mr_inst& I,
-                       int c, int x, int y, double* u, double* v, double* w) {
-  *u = mr_ld(g, c, 0, x, y);
-  if (mr_flag(fl1, I.fex, I.fey, I.fhalo, x, y)) {
-    *v = mr_modified_moment(mr_ld(g, c, 0, x - 1, y), mr_ld(g, c, 0, x + 1, y),
-                            mr_ld(g, c, 1, x - 1, y), mr_ld(g, c, 1, x + 1, y));
-    *w = mr_modified_moment(mr_ld(g, c, 0, x, y - 1), mr_ld(g, c, 0, x, y + 1),
-                            mr_ld(g, c, 2, x, y - 1), mr_ld(g, c, 2, x, y + 1));
-  } else {
-    *v = mr_ld(g, c, 1, x, y);
-    *w = mr_ld(g, c, 2, x, y);
-  }
 }
 
 template <int NC, int D>

@@ -241,6 +241,27 @@ MR_HD void mr_recip4(double a, double b, double c, double d, double* r) {
   r[3] = c * icd;
 }
 
+/* Square root of a positive normal x >= 2^-767: Goldschmidt iteration from
+ * the hardware reciprocal-square-root estimate (two corrections), i.e. the
+ * usual FP64 sequence without its range scaling and special-case selects,
+ * which this range does not need.  Zero, negative or non-finite x give NaN
+ * (a state reaching them is non-physical and is caught as such). */
+MR_HD double mr_sqrtp(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const double r = __builtin_amdgcn_rsq(x);
+  double g = x * r, h = 0.5 * r;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+#else
+  return sqrt(x);
+#endif
+}
+
 /* HLLC flux of eqs. (f_HLLC), (COEF), (uLR_) with the printed PVRS star
  * estimates; in 2D the normal direction D plays the role of mu and the
  * tangential momentum is carried in the star state.  Branches in the order
@@ -259,7 +280,7 @@ MR_HD void mr_hllc(const double* uL, const double* uR, double gam, double* f) {
   const double EL = uL[NC - 1], ER = uR[NC - 1];
   const double pL = (gam - 1.0) * (EL - 0.5 * m2L * irL);
   const double pR = (gam - 1.0) * (ER - 0.5 * m2R * irR);
-  const double cL = sqrt(gam * pL * irL), cR = sqrt(gam * pR * irR);
+  const double cL = mr_sqrtp(gam * pL * irL), cR = mr_sqrtp(gam * pR * irR);
   const double rs = 0.5 * (rL + rR), cs = 0.5 * (cL + cR);
   const double crs = cs * rs;
   /* 1/crs, 1/p_L, 1/p_R from one division */
@@ -269,8 +290,8 @@ MR_HD void mr_hllc(const double* uL, const double* uR, double gam, double* f) {
   const double ps = 0.5 * (pL + pR + (muL - muR) * crs);
   const double ss = 0.5 * (muL + muR + (pL - pR) * icrs);   /* s* of the printed PVRS */
   const double k1 = (gam + 1.0) / (2.0 * gam);
-  const double coefL = (ps <= pL) ? 1.0 : sqrt(1.0 + k1 * (ps * ipL - 1.0));
-  const double coefR = (ps <= pR) ? 1.0 : sqrt(1.0 + k1 * (ps * ipR - 1.0));
+  const double coefL = (ps <= pL) ? 1.0 : mr_sqrtp(1.0 + k1 * (ps * ipL - 1.0));
+  const double coefR = (ps <= pR) ? 1.0 : mr_sqrtp(1.0 + k1 * (ps * ipR - 1.0));
   const double sL = muL - cL * coefL, sR = muR + cR * coefR;
   /* ordered branch chain: 0 <= sL -> f_L; 0 <= s* -> f*_L; 0 <= sR -> f*_R; f_R */
   const int br = (0.0 <= sL) ? 0 : ((0.0 <= ss) ? 1 : ((0.0 <= sR) ? 2 : 3));

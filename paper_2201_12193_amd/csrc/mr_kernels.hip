@@ -4,17 +4,19 @@
  *   k_reduce(0)  -> k_finalize                      (dt from U^n, CFL)
  *   per stage s = 0, 1, 2:
  *     [k_reduce(s) for Lax-Friedrichs alpha when s > 0]
- *     k{1,2}_summary -> k{1,2}_flags                (Step 2.1, KXRCF)
+ *     1D: k1_summary -> k1_flags, 2D: k2_kxrcf     (Step 2.1, KXRCF)
  *     k{1,2}_stage(s)                               (Steps 1, 2.2, 2.3, fluxes,
  *                                                    residual, RK combination)
  * Every kernel takes a work list spanning all instances, so one launch
- * serves a whole batch of problems of different sizes.
+ * serves a whole batch of problems of different sizes.  The 2D stage and
+ * KXRCF kernels live in mr_stage2d.hip.
  *
  * Modified first moments of troubled cells replace those of the stage input
  * (Step 2.2).  Within a stage they are computed from the unmodified input
  * (Jacobi); the RK combination uses the modified stage input, and the
- * modification of U^n made in the first stage is reapplied on the fly in
- * stages two and three from the stage-1 flags.
+ * modification of U^n made in the first stage is reapplied in stages two
+ * and three (1D: on the fly from the stage-1 flags; 2D: the first stage
+ * keeps the modified first moments of U^n).
  */
 #include "mr_common.h"
 
@@ -79,13 +81,13 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
       const mr_tile1 tl = tiles[t];
       const mr_inst& I = insts[tl.inst];
       inst[q] = tl.inst;
-      const double* U;
+      const MR_GLB double* U;
       if (stage == 0) {
         if (I.err) continue;
-        U = I.buf[I.cur];
+        U = mr_gp(I.buf[I.cur]);
       } else {
         if (!I.active || I.flux != 0) continue;
-        U = I.p_out[stage - 1];
+        U = mr_gp(I.p_out[stage - 1]);
       }
       const int k = tl.start + (int)threadIdx.x;
       if (k >= tl.start + tl.count) continue;
@@ -197,7 +199,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
     const int i = e - I.shalo;
-    mr_grid g{stage < 3 ? I.p_in[stage] : I.buf[0], I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+    mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
     double r[4];
     mr_recon1d<BP>(mr_ld(g, 0, 0, i - 1, 0), mr_ld(g, 0, 0, i, 0), mr_ld(g, 0, 0, i + 1, 0),
                    mr_ld(g, 0, 1, i - 1, 0), mr_ld(g, 0, 1, i, 0), mr_ld(g, 0, 1, i + 1, 0), I.W, r);
@@ -213,11 +215,12 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
 #pragma unroll
     for (int k = 0; k < 4; ++k) nrm = fmax(nrm, fabs(r[k]));
     const long long SE = I.sex;
-    I.summ[0 * SE + e] = r[0];
-    I.summ[1 * SE + e] = r[3];
-    I.summ[2 * SE + e] = vl;
-    I.summ[3 * SE + e] = vr;
-    I.summ[4 * SE + e] = nrm;
+    MR_GLB double* S = mr_gp(I.summ);
+    S[0 * SE + e] = r[0];
+    S[1 * SE + e] = r[3];
+    S[2 * SE + e] = vl;
+    S[3 * SE + e] = vr;
+    S[4 * SE + e] = nrm;
   }
 }
 
@@ -231,11 +234,11 @@ __global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_ti
     if (stage < 3 && !I.active) continue;
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
-    unsigned char* fl = I.flags[(stage == 0 || stage == 3) ? 0 : 1];
+    MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
     if (I.tc == 0 || I.tc == 2) { fl[e] = (unsigned char)(I.tc == 2); continue; }
     const int s = e + (I.shalo - I.fhalo);   /* same cell in the summary plane */
     const long long SE = I.sex;
-    const double* S = I.summ;
+    const MR_GLB double* S = mr_gp(I.summ);
     const double jl = S[0 * SE + s] - S[1 * SE + s - 1];
     const double vl = 0.5 * (S[2 * SE + s] + S[3 * SE + s - 1]);
     const double jr = S[1 * SE + s] - S[0 * SE + s + 1];
@@ -265,8 +268,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
     const mr_inst& I = insts[tl.inst];
     if (mode < 3 && !I.active) continue;
     const int st = mode == 3 ? 0 : mode;
-    const mr_grid g{I.p_in[st], I.plane, I.nx, 1, I.bcx, I.bcy, 2};
-    const unsigned char* fl = I.flags[(mode == 0 || mode == 3) ? 0 : 1];
+    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+    const MR_GLB unsigned char* fl = mr_gp(I.flags[(mode == 0 || mode == 3) ? 0 : 1]);
     const int x = tl.start - 1 + cs;
     const int fh = I.fhalo;
     const int f0 = mr_flag(fl, I.fex, 1, fh, x, 0);
@@ -314,11 +317,11 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
 #pragma unroll
         for (int c = 0; c < NC; ++c) F[c] += glw(q) * f[c];
       }
-      double* O = I.p_out[st];
+      MR_GLB double* O = mr_gp(I.p_out[st]);
       const long long P = I.plane;
       const double dt = I.dt;
-      const mr_grid gn{I.p_un, I.plane, I.nx, 1, I.bcx, I.bcy, 2};
-      const int f1 = (mode == 1 || mode == 2) ? mr_flag(I.flags[0], I.fex, 1, fh, x, 0) : 0;
+      const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+      const int f1 = (mode == 1 || mode == 2) ? mr_flag(mr_gp(I.flags[0]), I.fex, 1, fh, x, 0) : 0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double fm_ = s_fl[cs * NC + c], fp_ = s_fl[(cs + 1) * NC + c];
@@ -353,8 +356,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, con
     const mr_inst& I = insts[tl.inst];
     const int x = tl.start + (int)threadIdx.x;
     if (x >= tl.start + tl.count) continue;
-    const mr_grid g{I.p_in[0], I.plane, I.nx, 1, I.bcx, I.bcy, 2};
-    const unsigned char* fl = I.flags[0];
+    const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+    const MR_GLB unsigned char* fl = mr_gp(I.flags[0]);
     const int fh = I.fhalo;
     const int f0 = mr_flag(fl, I.fex, 1, fh, x, 0);
     const int fm = mr_flag(fl, I.fex, 1, fh, x - 1, 0), fp = mr_flag(fl, I.fex, 1, fh, x + 1, 0);
@@ -374,64 +377,18 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, con
 }
 
 /* ================================================================ 2D passes */
-/* KXRCF face data (mr2_face_summary) per cell over the extended range
- * [-3, n+3)^2, one plane per entry. */
-template <bool BP>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_summary(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
-  mr_kt_fill();
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const mr_tile1 tl = tiles[t];
-    const mr_inst& I = insts[tl.inst];
-    if (stage < 3 && !I.active) continue;
-    if (I.tc != 1) continue;
-    const int e = tl.start + (int)threadIdx.x;
-    if (e >= tl.start + tl.count) continue;
-    const int i = e % I.sex - I.shalo, j = e / I.sex - I.shalo;
-    const mr_grid g{stage < 3 ? I.p_in[stage] : I.buf[0], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    double f[9];
-    mr2_face_summary<BP>(g, I, i, j, f);
-    const long long SE = (long long)I.sex * I.sey;
-    double* S = I.summ;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) S[k * SE + e] = f[k];
-  }
-}
-
-/* Troubled-cell flags, eq. (KXRCF_) with eq. (line-integral-average_), over
- * [-2, n+2)^2, evaluated as |J| > h^2 |dI^-| ||u|| with h = dx. */
+/* Flags of the 2D instances without an indicator pass (no troubled cells,
+ * or all cells troubled) over [-2, n+2)^2; the KXRCF flags of 2D instances
+ * come from the fused kernel k2_kxrcf, the learned ones from k2_learned. */
 __global__ __launch_bounds__(MR_BLOCK) void k2_flags(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
-#pragma clang fp contract(off)
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
     mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
-    unsigned char* fl = I.flags[(stage == 0 || stage == 3) ? 0 : 1];
-    if (I.tc == 3) continue;   /* written by the learned indicator */
-    if (I.tc == 0 || I.tc == 2) { fl[e] = (unsigned char)(I.tc == 2); continue; }
-    const int i = e % I.fex - I.fhalo, j = e / I.fex - I.fhalo;
-    const int sx = I.sex, d = I.shalo;
-    const long long SE = (long long)sx * I.sey;
-    const double* S = I.summ;
-    const long long o = (long long)(j + d) * sx + (i + d);
-    double J = 0.0, len = 0.0;
-    const double vl = 0.5 * (S[4 * SE + o] + S[5 * SE + o - 1]);
-    if (vl > 0.0) { J += I.dy * (S[0 * SE + o] - S[1 * SE + o - 1]); len += I.dy; }
-    const double vr = 0.5 * (S[5 * SE + o] + S[4 * SE + o + 1]);
-    if (-vr > 0.0) { J += I.dy * (S[1 * SE + o] - S[0 * SE + o + 1]); len += I.dy; }
-    const double vb = 0.5 * (S[6 * SE + o] + S[7 * SE + o - sx]);
-    if (vb > 0.0) { J += I.dx * (S[2 * SE + o] - S[3 * SE + o - sx]); len += I.dx; }
-    const double vt = 0.5 * (S[7 * SE + o] + S[6 * SE + o + sx]);
-    if (-vt > 0.0) { J += I.dx * (S[3 * SE + o] - S[2 * SE + o + sx]); len += I.dx; }
-    const double num = fabs(J);
-    const double den = I.dx * I.dx * len * S[8 * SE + o];
-    fl[e] = (unsigned char)(num > den);
-    if (I.aleph && i >= 0 && i < I.nx && j >= 0 && j < I.ny) {
-      const long long cell = (long long)j * I.nx + i;
-      I.aleph[2 * cell] = num;
-      I.aleph[2 * cell + 1] = den;
-    }
+    MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
+    if (I.tc == 0 || I.tc == 2) fl[e] = (unsigned char)(I.tc == 2);
   }
 }
 
@@ -444,10 +401,10 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_values(mr_inst* insts, con
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
     const int x = e % I.nx, y = e / I.nx;
-    const mr_grid g{I.p_in[0], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
     for (int c = 0; c < NC; ++c) {
       double val[16], a, b, d;
-      mr2_cell_values<BP>(g, I, I.flags[0], c, x, y, val, &a, &b, &d);
+      mr2_cell_values<BP>(g, I, mr_gp(I.flags[0]), c, x, y, val, &a, &b, &d);
       for (int p = 0; p < 16; ++p) gl[(long long)(c * 16 + p) * I.plane + e] = val[p];
     }
   }
@@ -472,13 +429,9 @@ hipError_t mr_launch_finalize(hipStream_t s, mr_inst* d, int n, int probe) {
 
 hipError_t mr_launch_summary(hipStream_t s, int dim, int bp, mr_inst* d, const mr_tile1* t, int nt, int stage) {
   if (nt <= 0) return hipSuccess;
-  if (dim == 1) {
-    if (bp) hipLaunchKernelGGL(k1_summary<true>, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
-    else hipLaunchKernelGGL(k1_summary<false>, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
-  } else {
-    if (bp) hipLaunchKernelGGL(k2_summary<true>, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
-    else hipLaunchKernelGGL(k2_summary<false>, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
-  }
+  if (dim != 1) return hipErrorInvalidValue;   /* 2D: k2_kxrcf */
+  if (bp) hipLaunchKernelGGL(k1_summary<true>, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
+  else hipLaunchKernelGGL(k1_summary<false>, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
   return hipGetLastError();
 }
 

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k_features(const mr_inst* insts, int
   if (e >= (long long)n * MR_KP) return;
   const int smp = (int)(e / MR_KP), f = (int)(e % MR_KP);
   const mr_inst& I = insts[inst];
-  const mr_grid g{I.p_in[0], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+  const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
   const int cell = cells[smp];
   if (cell < 0 || (long long)cell >= I.plane) {   /* not an interior cell */
     out[e] = (__bf16)0.0f;
@@ -139,8 +139,8 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
     mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
     if (I.tc != 3) continue;
-    const mr_grid gr{stage < 3 ? I.p_in[stage] : I.buf[0], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    unsigned char* fl = I.flags[(stage == 0 || stage == 3) ? 0 : 1];
+    const mr_grid gr{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
     const int fh = I.fhalo, fex = I.fex;
     const int xs = tl.x0 - 2, ylo = tl.y0, yhi = tl.y0 + tl.rows;
     const int xend = I.nx + fh;
@@ -153,7 +153,7 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
     const bool zx = sm != 0 && (xi < 0 || xi >= I.nx) && I.bcx != 0;
     int ii = I.bcx == 0 ? (xi < 0 ? xi + I.nx : (xi >= I.nx ? xi - I.nx : xi)) : xi;
     ii = min(max(ii, 0), I.nx - 1);
-    const double* ub = gr.U + (long long)sm * I.plane + ii;
+    const MR_GLB double* ub = gr.U + (long long)sm * I.plane + ii;
     double pf[16];
     auto fetch = [&](int row0) {
       if (!stager) return;
@@ -373,8 +373,9 @@ MR_INL void mr_fb_summary_cell(mr_inst& I, const mr_grid& g, int es) {
   double f[9];
   mr2_face_summary<BP>(g, I, es % I.sex - I.shalo, es / I.sex - I.shalo, f);
   const long long SE = (long long)I.sex * I.sey;
+  MR_GLB double* S = mr_gp(I.summ);
 #pragma unroll
-  for (int k = 0; k < 9; ++k) I.summ[k * SE + es] = f[k];
+  for (int k = 0; k < 9; ++k) S[k * SE + es] = f[k];
 }
 
 /* one launch per smoothness-indicator variant; each skips the other's cells */
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k_fb_summary(mr_inst* insts, 
     const mr_band b = list[k];
     mr_inst& I = insts[b.inst];
     if ((I.beta_on != 0) != BP) continue;
-    const mr_grid g{stage < 3 ? I.p_in[stage] : I.buf[0], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
     mr_fb_summary_cell<BP>(I, g, b.e);
   }
 }
@@ -397,11 +398,11 @@ __global__ __launch_bounds__(MR_BLOCK) void k_fb_flags(mr_inst* insts, const mr_
   for (int k = blockIdx.x * MR_BLOCK + threadIdx.x; k < n; k += gridDim.x * MR_BLOCK) {
     const mr_band b = band[k];
     const mr_inst& I = insts[b.inst];
-    unsigned char* fl = I.flags[(stage == 0 || stage == 3) ? 0 : 1];
+    MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
     const int i = b.e % I.fex - I.fhalo, j = b.e / I.fex - I.fhalo;
     const int sx = I.sex;
     const long long SE = (long long)sx * I.sey;
-    const double* S = I.summ;
+    const MR_GLB double* S = mr_gp(I.summ);
     const long long o = (long long)(j + I.shalo) * sx + (i + I.shalo);
     double J = 0.0, len = 0.0;
     const double vl = 0.5 * (S[4 * SE + o] + S[5 * SE + o - 1]);

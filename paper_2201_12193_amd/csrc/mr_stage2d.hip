@@ -35,8 +35,11 @@ struct mr2_lds {
   static constexpr int VS = NC * CS + 1;     /* point stride of val */
   static constexpr int TS = NC * CS + 4;     /* point stride of top */
   static constexpr int FS = NC * CS;         /* stride of fs */
-  double mA[5][2 * NC][XW];   /* planes (c, m = 0) and (c, m = 2): index 2c, 2c+1 */
-  double mB[3][NC][XW];       /* planes (c, m = 1)                               */
+  /* padded plane stride: planes 2 apart start 280 dwords apart, so the
+     lanes of one access (four components, four cells) hit distinct banks */
+  static constexpr int XP = XW + 2;
+  double mA[5][2 * NC][XP];   /* planes (c, m = 0) and (c, m = 2): index 2c, 2c+1 */
+  double mB[3][NC][XP];       /* planes (c, m = 1)                               */
   unsigned char flg[3][XW];
   double val[16 * VS];
   double top[4 * TS];
@@ -73,12 +76,13 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
     const mr_inst& I = insts[tl.inst];
     if (mode < 3 && !I.active) continue;
     const int st = mode == 3 ? 0 : mode;
-    const mr_grid g{I.p_in[st], I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    const mr_grid gn{I.p_un, I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    const unsigned char* fl = I.flags[(mode == 0 || mode == 3) ? 0 : 1];
+    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const MR_GLB unsigned char* fl = mr_gp(I.flags[(mode == 0 || mode == 3) ? 0 : 1]);
+    MR_GLB double* unm = mr_gp(I.unm);
     const double rdx = I.rdx, rdy = I.rdy, dt = I.dt, gam = I.gam;
     const double alpha = (NC == 1) ? mr_bitsd(I.lfa[st]) : 0.0;
-    double* O = I.p_out[st];
+    MR_GLB double* O = mr_gp(I.p_out[st]);
     const long long P = I.plane;
     const int xs0 = tl.x0 - 3;                 /* strip column 0 */
     const int x = tl.x0 - 1 + cs;
@@ -275,13 +279,13 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
         else if (mode == 0) {
           r0 = pU + dt * Lu; r1 = pV + dt * Lv; r2 = pW + dt * Lw;
           /* U^n after Step 2.2 (its first moments) for stages 2 and 3 */
-          I.unm[(long long)(comp * 2 + 0) * P + cell] = pV;
-          I.unm[(long long)(comp * 2 + 1) * P + cell] = pW;
+          unm[(long long)(comp * 2 + 0) * P + cell] = pV;
+          unm[(long long)(comp * 2 + 1) * P + cell] = pW;
         } else {
           const double a = mode == 1 ? 0.75 : 1.0 / 3.0, b = mode == 1 ? 0.25 : 2.0 / 3.0;
           const double un = gn.U[(long long)(comp * 3) * P + cell];
-          const double vn = I.unm[(long long)(comp * 2 + 0) * P + cell];
-          const double wn = I.unm[(long long)(comp * 2 + 1) * P + cell];
+          const double vn = unm[(long long)(comp * 2 + 0) * P + cell];
+          const double wn = unm[(long long)(comp * 2 + 1) * P + cell];
           r0 = a * un + b * pU + b * dt * Lu;
           r1 = a * vn + b * pV + b * dt * Lv;
           r2 = a * wn + b * pW + b * dt * Lw;
@@ -322,3 +326,200 @@ extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, mr_inst* d
   return hipGetLastError();
 }
 
+
+/* ================================================= fused KXRCF (2D, tc = 1) */
+/* Troubled-cell flags of eq. (KXRCF_) with the face averages of eq.
+ * (line-integral-average_), in one pass: a work group owns a strip of 62
+ * flag columns and sweeps it upward four rows at a time.  Each thread
+ * reconstructs one cell (Step 1 on the unmodified stage input) of the
+ * strip plus one ring column each side and keeps its face data in LDS; once
+ * the rows above and below are there, the flags of the strip's cells follow
+ * from the face data of the cell and its four neighbours.
+ *
+ * Moments of the strip (64 + 2 columns, the planes the indicator reads) sit
+ * in a ten-row LDS ring, each loaded from HBM once per work group with the
+ * boundary condition applied: a step reads six rows and writes the four
+ * that the next step adds.  The face data sit in a six-row ring. */
+#define KX_W 64                       /* reconstructed columns of a strip */
+#define KX_XW (KX_W + 2)              /* staged columns                   */
+#define KX_MR 10                      /* moment ring rows                 */
+#define KX_FR 6                       /* face data ring rows              */
+
+/* ring slot of row y >= -12 */
+MR_INL int kx_slot(int y, int n) { return (y + 12 * n) % n; }
+
+/* face data of the cell at staged column col whose rows y-1, y, y+1 sit in
+   ring slots s0, s1, s2 (f as mr2_face_summary) */
+template <int NK, bool BP>
+MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, int s2, int col,
+                         const mr_wconst& W, double f[9]) {
+  double rho[16];
+  double sl = 0.0, sr = 0.0, sb = 0.0, st = 0.0, nrm = 0.0;
+  double vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
+#pragma unroll 1
+  for (int c = 0; c < NK; ++c) {
+    /* the constant table stays in LDS: no loads of it are hoisted out of
+       the component loop (they would hold its entries in registers) */
+    __asm__ volatile("" ::: "memory");
+    double u[9], v[9], w[9], q[16];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const int dx = l % 3 - 1, slot = l < 3 ? s0 : (l < 6 ? s1 : s2);
+      u[l] = mom[slot][(3 * c + 0) * KX_XW + col + dx];
+      v[l] = mom[slot][(3 * c + 1) * KX_XW + col + dx];
+      w[l] = mom[slot][(3 * c + 2) * KX_XW + col + dx];
+    }
+    mr_recon2d<BP>(u, v, w, W, q);
+    if (c == 0) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        sl += glw(m) * q[0 + 4 * m];
+        sr += glw(m) * q[3 + 4 * m];
+        sb += glw(m) * q[m];
+        st += glw(m) * q[12 + m];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) { nrm = fmax(nrm, fabs(q[k])); rho[k] = q[k]; }
+      if (NK == 1) { vl = sl; vr = sr; vb = sb; vt = st; }   /* Burgers: f'(u) = u */
+    } else if (c == 1) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        vl += glw(m) * (q[0 + 4 * m] / rho[0 + 4 * m]);
+        vr += glw(m) * (q[3 + 4 * m] / rho[3 + 4 * m]);
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        vb += glw(m) * (q[m] / rho[m]);
+        vt += glw(m) * (q[12 + m] / rho[12 + m]);
+      }
+    }
+  }
+  f[0] = sl; f[1] = sr; f[2] = sb; f[3] = st;
+  f[4] = vl; f[5] = vr; f[6] = vb; f[7] = vt;
+  f[8] = nrm;
+}
+
+/* NK: components the indicator reads (1 Burgers, 3 Euler: rho and the
+   momenta).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
+   of the extended flag range [-2, n+2)^2 (y0 >= -2). */
+template <int NK, bool BP>
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, const mr_tile2* tiles, int ntiles, int stage) {
+  mr_kt_fill();
+  constexpr int NPL = 3 * NK;
+  constexpr int NROW = NPL * KX_XW;                       /* staged values per row */
+  constexpr int NQ = (NROW + MR_BLOCK - 1) / MR_BLOCK;    /* ... per thread        */
+  __shared__ double mom[KX_MR][NROW];                     /* [row][plane][column]  */
+  __shared__ double fd[KX_FR][9][KX_W];
+  const int tid = threadIdx.x, cx = tid % KX_W, ry = tid / KX_W;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const mr_tile2 tl = tiles[t];
+    const mr_inst& I = insts[tl.inst];
+    if (stage < 3 && !I.active) continue;
+    const MR_GLB double* U = mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]);
+    MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
+    MR_GLB double* aleph = mr_gp(I.aleph);
+    const int xs = tl.x0 - 2;              /* staged column 0 */
+    const int ylast = tl.y0 + tl.rows;     /* last reconstructed row */
+    /* staged element q of this thread in every row: plane offset plus folded
+       column, and whether it is a first moment (of a transmissive x ghost) */
+    int soff[NQ];
+    unsigned szero = 0u, sfm = 0u;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int e = min(tid + q * MR_BLOCK, NROW - 1);
+      const int pl = e / KX_XW, i = xs + e % KX_XW;
+      const bool ox = i < 0 || i >= I.nx;
+      int ii = I.bcx == 0 ? (i < 0 ? i + I.nx : (i >= I.nx ? i - I.nx : i)) : i;
+      ii = min(max(ii, 0), I.nx - 1);
+      soff[q] = (pl / 3 * 3 + pl % 3) * (int)I.plane + ii;
+      if (pl % 3 != 0) sfm |= 1u << q;
+      if (pl % 3 != 0 && ox && I.bcx != 0) szero |= 1u << q;
+    }
+    /* fetch moment row y into v; the elements that read as zero (first
+       moments of transmissive ghosts) are marked in *z and cleared when
+       stored.  The fold of y is uniform over the work group. */
+    auto fetch = [&](int y, double* v, unsigned* z) {
+      const bool oy = y < 0 || y >= I.ny;
+      int jj = I.bcy == 0 ? (y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y)) : y;
+      jj = min(max(jj, 0), I.ny - 1) * I.nx;
+      *z = szero | ((oy && I.bcy != 0) ? sfm : 0u);
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) v[q] = U[soff[q] + jj];
+    };
+    auto store = [&](int y, const double* v, unsigned z) {
+      double* d = mom[kx_slot(y, KX_MR)];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        if (tid + q * MR_BLOCK < NROW) d[tid + q * MR_BLOCK] = ((z >> q) & 1u) ? 0.0 : v[q];
+    };
+    /* prologue: moment rows y0-2 .. y0+3 */
+#pragma unroll 1
+    for (int y = tl.y0 - 2; y <= tl.y0 + 3; y += 2) {
+      double a[NQ], b[NQ];
+      unsigned za, zb;
+      fetch(y, a, &za);
+      fetch(y + 1, b, &zb);
+      store(y, a, za);
+      store(y + 1, b, zb);
+    }
+    __syncthreads();
+    for (int s = 0; 4 * s <= tl.rows + 1; ++s) {
+      const int r0 = tl.y0 - 1 + 4 * s;    /* rows r0 .. r0+3 are reconstructed */
+      const int r = r0 + ry;
+      if (r <= ylast) {
+        double f[9];
+        kx_face_data<NK, BP>(mom, kx_slot(r - 1, KX_MR), kx_slot(r, KX_MR), kx_slot(r + 1, KX_MR), cx + 1, I.W, f);
+        const int sf = kx_slot(r, KX_FR);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) fd[sf][k][cx] = f[k];
+      }
+      /* moment rows r0+5 .. r0+8 (up to ylast+1) for the next step: fetched
+         now, stored (into the slots of rows r0-5 .. r0-2, which this step
+         does not read) once the flags below are formed */
+      double v[4][NQ];
+      unsigned z[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) fetch(r0 + 5 + k, v[k], &z[k]);   /* rows past ylast+1: clamped, unused */
+      __syncthreads();
+      /* flags of row r0-1+ry from the face data of rows rf-1 .. rf+1 */
+      const int rf = r0 - 1 + ry, x = xs + 1 + cx;
+      if (rf >= tl.y0 && rf < tl.y0 + tl.rows && cx >= 1 && cx <= KX_W - 2 && x < I.nx + I.fhalo) {
+#pragma clang fp contract(off)
+        const int a = kx_slot(rf, KX_FR), b = kx_slot(rf - 1, KX_FR), u = kx_slot(rf + 1, KX_FR);
+        double J = 0.0, len = 0.0;
+        const double vl = 0.5 * (fd[a][4][cx] + fd[a][5][cx - 1]);
+        if (vl > 0.0) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
+        const double vr = 0.5 * (fd[a][5][cx] + fd[a][4][cx + 1]);
+        if (-vr > 0.0) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
+        const double vb = 0.5 * (fd[a][6][cx] + fd[b][7][cx]);
+        if (vb > 0.0) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
+        const double vt = 0.5 * (fd[a][7][cx] + fd[u][6][cx]);
+        if (-vt > 0.0) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
+        const double num = fabs(J);
+        const double den = I.dx * I.dx * len * fd[a][8][cx];
+        fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(num > den);
+        if (aleph && x >= 0 && x < I.nx && rf >= 0 && rf < I.ny) {
+          const long long cell = (long long)rf * I.nx + x;
+          aleph[2 * cell] = num;
+          aleph[2 * cell + 1] = den;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (r0 + 5 + k <= ylast + 1) store(r0 + 5 + k, v[k], z[k]);
+      __syncthreads();
+    }
+  }
+}
+
+extern "C" hipError_t mr_launch_kxrcf2(hipStream_t s, int nk, int bp, mr_inst* d, const mr_tile2* t, int nt, int stage) {
+  if (nt <= 0) return hipSuccess;
+  const dim3 G(nt), B(MR_BLOCK);
+#define MR_LK(NK_, BP_) hipLaunchKernelGGL((k2_kxrcf<NK_, BP_>), G, B, 0, s, d, t, nt, stage)
+  if (nk == 1) { if (bp) MR_LK(1, true); else MR_LK(1, false); }
+  else if (nk == 3) { if (bp) MR_LK(3, true); else MR_LK(3, false); }
+  else return hipErrorInvalidValue;
+#undef MR_LK
+  return hipGetLastError();
+}
