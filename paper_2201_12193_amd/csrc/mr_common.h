@@ -98,7 +98,7 @@ MR_INL void mr2_cell_values(const mr_grid& g, const mr_inst& I, const MR_GLB uns
  * points. */
 template <bool BP>
 MR_INL void mr2_face_summary(const mr_grid& g, const mr_inst& I, int i, int j, double f[9]) {
-  double rho[16];
+  double irl[4], irr[4], irm[4];   /* 1/rho at points 0,4,8,12 | 3,7,11,15 | 1,2,13,14 */
   double sl = 0.0, sr = 0.0, sb = 0.0, st = 0.0, nrm = 0.0;
   double vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
   const int ncomp = I.flux == 1 ? 3 : 1;
@@ -122,21 +122,22 @@ MR_INL void mr2_face_summary(const mr_grid& g, const mr_inst& I, int i, int j, d
         st += glw(m) * r[12 + m];
       }
 #pragma unroll
-      for (int k = 0; k < 16; ++k) { nrm = fmax(nrm, fabs(r[k])); rho[k] = r[k]; }
-      vl = sl; vr = sr; vb = sb; vt = st;   /* Burgers: f'(u) = u */
-      if (ncomp > 1) { vl = vr = vb = vt = 0.0; }
+      for (int k = 0; k < 16; ++k) nrm = fmax(nrm, fabs(r[k]));
+      if (ncomp == 1) { vl = sl; vr = sr; vb = sb; vt = st; }   /* Burgers: f'(u) = u */
+      else {
+        mr_recip4(r[0], r[4], r[8], r[12], irl);
+        mr_recip4(r[3], r[7], r[11], r[15], irr);
+        mr_recip4(r[1], r[2], r[13], r[14], irm);
+      }
     } else if (c == 1) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        vl += glw(m) * (r[0 + 4 * m] / rho[0 + 4 * m]);
-        vr += glw(m) * (r[3 + 4 * m] / rho[3 + 4 * m]);
+        vl += glw(m) * (r[0 + 4 * m] * irl[m]);
+        vr += glw(m) * (r[3 + 4 * m] * irr[m]);
       }
     } else {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        vb += glw(m) * (r[m] / rho[m]);
-        vt += glw(m) * (r[12 + m] / rho[12 + m]);
-      }
+      vb = glw(0) * (r[0] * irl[0]) + glw(1) * (r[1] * irm[0]) + glw(2) * (r[2] * irm[1]) + glw(3) * (r[3] * irr[0]);
+      vt = glw(0) * (r[12] * irl[3]) + glw(1) * (r[13] * irm[2]) + glw(2) * (r[14] * irm[3]) + glw(3) * (r[15] * irr[3]);
     }
   }
   f[0] = sl; f[1] = sr; f[2] = sb; f[3] = st;

@@ -349,11 +349,12 @@ extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, mr_inst* d
 MR_INL int kx_slot(int y, int n) { return (y + 12 * n) % n; }
 
 /* face data of the cell at staged column col whose rows y-1, y, y+1 sit in
-   ring slots s0, s1, s2 (f as mr2_face_summary) */
+   ring slots s0, s1, s2 (f as mr2_face_summary; the velocities use shared
+   reciprocals of the density at the twelve face points) */
 template <int NK, bool BP>
 MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, int s2, int col,
                          const mr_wconst& W, double f[9]) {
-  double rho[16];
+  double irl[4], irr[4], irm[4];   /* 1/rho at points 0,4,8,12 | 3,7,11,15 | 1,2,13,14 */
   double sl = 0.0, sr = 0.0, sb = 0.0, st = 0.0, nrm = 0.0;
   double vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
 #pragma unroll 1
@@ -379,20 +380,22 @@ MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, in
         st += glw(m) * q[12 + m];
       }
 #pragma unroll
-      for (int k = 0; k < 16; ++k) { nrm = fmax(nrm, fabs(q[k])); rho[k] = q[k]; }
+      for (int k = 0; k < 16; ++k) nrm = fmax(nrm, fabs(q[k]));
       if (NK == 1) { vl = sl; vr = sr; vb = sb; vt = st; }   /* Burgers: f'(u) = u */
+      else {
+        mr_recip4(q[0], q[4], q[8], q[12], irl);
+        mr_recip4(q[3], q[7], q[11], q[15], irr);
+        mr_recip4(q[1], q[2], q[13], q[14], irm);
+      }
     } else if (c == 1) {
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        vl += glw(m) * (q[0 + 4 * m] / rho[0 + 4 * m]);
-        vr += glw(m) * (q[3 + 4 * m] / rho[3 + 4 * m]);
+        vl += glw(m) * (q[0 + 4 * m] * irl[m]);
+        vr += glw(m) * (q[3 + 4 * m] * irr[m]);
       }
     } else {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        vb += glw(m) * (q[m] / rho[m]);
-        vt += glw(m) * (q[12 + m] / rho[12 + m]);
-      }
+      vb = glw(0) * (q[0] * irl[0]) + glw(1) * (q[1] * irm[0]) + glw(2) * (q[2] * irm[1]) + glw(3) * (q[3] * irr[0]);
+      vt = glw(0) * (q[12] * irl[3]) + glw(1) * (q[13] * irm[2]) + glw(2) * (q[14] * irm[3]) + glw(3) * (q[15] * irr[3]);
     }
   }
   f[0] = sl; f[1] = sr; f[2] = sb; f[3] = st;
