@@ -26,6 +26,9 @@
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 MR_INL f32x4 mr_mfma(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -288,14 +291,16 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
         }
 #pragma unroll
         for (int kb2 = 0; kb2 < 2; ++kb2) {
-          bf16x8 b;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const float lo = h[gi][2 * kb2][j];
-            const float hi = h[gi][2 * kb2 + 1][j];
-            b[j] = (__bf16)(lo > 0.f ? lo : 0.f);
-            b[4 + j] = (__bf16)(hi > 0.f ? hi : 0.f);
-          }
+          const f32x4 x = h[gi][2 * kb2], y = h[gi][2 * kb2 + 1];
+          const bf16x2 p0 = __builtin_convertvector(f32x2{x[0], x[1]}, bf16x2);
+          const bf16x2 p1 = __builtin_convertvector(f32x2{x[2], x[3]}, bf16x2);
+          const bf16x2 p2 = __builtin_convertvector(f32x2{y[0], y[1]}, bf16x2);
+          const bf16x2 p3 = __builtin_convertvector(f32x2{y[2], y[3]}, bf16x2);
+          bf16x8 b = {p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+          /* ReLU after the rounding (rounding keeps the sign): a negative
+             BF16 is a negative int16, so a packed integer max with 0 clears
+             it, two values per instruction */
+          b = __builtin_bit_cast(bf16x8, __builtin_elementwise_max(__builtin_bit_cast(i16x8, b), i16x8{}));
 #pragma unroll
           for (int m = 0; m < 4; ++m) o[m] = mr_mfma(W2[(kb2 * 4 + m) * 64 + lane], b, o[m]);
         }
@@ -306,7 +311,8 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const float v = o[m][j];
-            zp += (v > 0.f ? v : 0.f) * (&ww.x)[j];
+            /* ReLU on the bit pattern: a negative float is a negative int32 */
+            zp += __builtin_bit_cast(float, max(__builtin_bit_cast(int, v), 0)) * (&ww.x)[j];
           }
         }
         zp += __shfl_xor(zp, 16);
@@ -352,17 +358,26 @@ __global__ __launch_bounds__(MR_BLOCK) void k_fb_mark(mr_inst* insts, const mr_b
                                                      int stage) {
   const int n = cnt[stage];
   const int epoch = cnt[8] + stage + 1;
-  for (int k = blockIdx.x * MR_BLOCK + threadIdx.x; k < n; k += gridDim.x * MR_BLOCK) {
-    const mr_band b = band[k];
+  const int lane = threadIdx.x % 64;
+  /* wave-uniform trip count: the appends of a wave take one atomic */
+  for (int k0 = blockIdx.x * MR_BLOCK + (int)threadIdx.x - lane; k0 < n; k0 += gridDim.x * MR_BLOCK) {
+    const int k = k0 + lane;
+    const bool act = k < n;
+    const mr_band b = act ? band[k] : mr_band{0, 0};
     const mr_inst& I = insts[b.inst];
     const int i = b.e % I.fex - I.fhalo, j = b.e / I.fex - I.fhalo;
+    MR_GLB int* mark = mr_gp(I.mark);
 #pragma unroll
     for (int d = 0; d < 5; ++d) {
       const int di = d == 1 ? -1 : (d == 2 ? 1 : 0), dj = d == 3 ? -1 : (d == 4 ? 1 : 0);
       const int es = (j + dj + I.shalo) * I.sex + (i + di + I.shalo);
-      if (atomicExch(&I.mark[es], epoch) != epoch) {
-        const int at = atomicAdd(&cnt[4 + stage], 1);
-        list[at] = mr_band{b.inst, es};
+      const bool mine = act && __hip_atomic_exchange(&mark[es], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch;
+      const unsigned long long bm = __ballot(mine);
+      if (bm) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&cnt[4 + stage], __popcll(bm));
+        base = __shfl(base, 0);
+        if (mine) list[base + __popcll(bm & ((1ull << lane) - 1ull))] = mr_band{b.inst, es};
       }
     }
   }

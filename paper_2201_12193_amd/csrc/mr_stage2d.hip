@@ -35,11 +35,10 @@ struct mr2_lds {
   static constexpr int VS = NC * CS + 1;     /* point stride of val */
   static constexpr int TS = NC * CS + 4;     /* point stride of top */
   static constexpr int FS = NC * CS;         /* stride of fs */
-  /* padded plane stride: planes 2 apart start 280 dwords apart, so the
-     lanes of one access (four components, four cells) hit distinct banks */
+  /* plane strides chosen by measured LDS bank conflicts (mA padded by 2) */
   static constexpr int XP = XW + 2;
   double mA[5][2 * NC][XP];   /* planes (c, m = 0) and (c, m = 2): index 2c, 2c+1 */
-  double mB[3][NC][XP];       /* planes (c, m = 1)                               */
+  double mB[3][NC][XW];       /* planes (c, m = 1)                               */
   unsigned char flg[3][XW];
   double val[16 * VS];
   double top[4 * TS];
