@@ -14,13 +14,16 @@
  * that an instruction cannot encode).  A translation unit that defines
  * MR_KT_IN_LDS copies it into LDS once per work group (mr_kt_fill) and reads
  * it from there, which keeps the constants out of the scalar registers of
- * its large kernels; elsewhere the entries fold into literals. */
+ * its large kernels; elsewhere the entries fold into literals.  The table's
+ * 256-byte alignment makes the compiler place it before the kernels' own
+ * LDS blocks, at offsets that fit the immediate offset field of an LDS
+ * read (above 64 KiB every constant load needed its address in a VGPR). */
 #define MR_KT_MAX 128
 #if defined(__HIP_DEVICE_COMPILE__) && defined(MR_KT_IN_LDS)
 #define MR_KT(i) (mr_kt_lds[i])
 #define MR_KT_DECLARE                                            \
   __constant__ double mr_kt_dev[MR_NKT + 1] = {MR_KT_VALUES};    \
-  __shared__ double mr_kt_lds[MR_KT_MAX];
+  __shared__ __attribute__((aligned(256))) double mr_kt_lds[MR_KT_MAX];
 #else
 #define MR_KT(i) (mr_kt_lit[i])
 #define MR_KT_DECLARE static constexpr double mr_kt_lit[MR_NKT + 1] = {MR_KT_VALUES};
