@@ -76,6 +76,14 @@ typedef enum {
 /* Smoothness indicators of eq. (beta)/(2D-beta) taken on q_l (default; the
  * reading under which Remark 1's expansion holds) or on p_l as printed. */
 typedef enum { MRHWENO_BETA_ON_Q = 0, MRHWENO_BETA_ON_P = 1 } mrhweno_beta;
+/* Where the modified first moments of Step 2.2 go besides the troubled
+ * cells' re-reconstruction (Steps 2.2, 2.3; the paper does not say):
+ * PERSIST (default) - they replace those of every stage input in the SSP-RK3
+ *                     combination, U^n included (with this reading the
+ *                     modify-everywhere variant reproduces Tables 1 and 3);
+ * INTERNAL          - nowhere: the combination uses the stored moments;
+ * STAGE             - they replace those of the stage input, not of U^n. */
+typedef enum { MRHWENO_MOD_PERSIST = 0, MRHWENO_MOD_INTERNAL = 1, MRHWENO_MOD_STAGE = 2 } mrhweno_mod;
 
 /* A problem posed as the paper poses it (Secs. 2.1, 2.2, 3). */
 typedef struct {
@@ -93,6 +101,7 @@ typedef struct {
   double eps;              /* epsilon of the nonlinear weights (paper: 1e-10)    */
   int tc_mode;             /* mrhweno_tc                                         */
   int beta_on;             /* mrhweno_beta                                       */
+  int modification;        /* mrhweno_mod                                        */
 } mrhweno_problem;
 
 /* Device workspace needed for n instances (bytes, 256-byte aligned pieces).

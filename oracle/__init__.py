@@ -222,8 +222,17 @@ def dt(prob, U, cfl: Optional[float] = None) -> float:
     return float(lib().orc_dt(C.byref(cprob(prob)), _dp(U), prob.cfl if cfl is None else cfl))
 
 
-def rk3_step(prob, U, dt_: float, want_flags: bool = False, persist: int = 1):
-    """One SSP-RK3 step; returns U^{n+1} (and the flags of the 3 stages)."""
+# placement of the modified first moments (problem field `modification`:
+# 0 every stage input and U^n, 1 nowhere, 2 stage inputs only) -> the C
+# oracle's persist argument (1, 0, 2)
+_PERSIST = {0: 1, 1: 0, 2: 2}
+
+
+def rk3_step(prob, U, dt_: float, want_flags: bool = False, persist: Optional[int] = None):
+    """One SSP-RK3 step; returns U^{n+1} (and the flags of the 3 stages).
+    persist defaults to the problem's modification placement."""
+    if persist is None:
+        persist = _PERSIST[getattr(prob, "modification", 0)]
     U = _arr(U).reshape(prob.shape()).copy()
     flags = np.zeros(3 * prob.ncell, dtype=np.uint8) if want_flags else None
     lib().orc_rk3_step_p(C.byref(cprob(prob)), _dp(U), dt_, _bp(flags), persist)
@@ -248,7 +257,8 @@ def modify(prob, U, flags) -> np.ndarray:
     return out
 
 
-def run(prob, U, t_final: Optional[float] = None, max_steps: int = 10 ** 9, dt_fn=None, persist: int = 1):
+def run(prob, U, t_final: Optional[float] = None, max_steps: int = 10 ** 9, dt_fn=None,
+        persist: Optional[int] = None):
     """March to t_final with the CFL time step (clipped at t_final)."""
     T = prob.t_final if t_final is None else t_final
     U = _arr(U).reshape(prob.shape()).copy()

@@ -280,6 +280,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
     for (int c = 0; c < NC; ++c) {
       const double um = mr_ld(g, c, 0, x - 1, 0), u0 = mr_ld(g, c, 0, x, 0), up = mr_ld(g, c, 0, x + 1, 0);
       double vm = mr_ld(g, c, 1, x - 1, 0), v0 = mr_ld(g, c, 1, x, 0), vp = mr_ld(g, c, 1, x + 1, 0);
+      const double v0s = v0;   /* stored first moment */
       if (f0) {
         /* Steps 2.2/2.3: Step 1 again with the troubled cells' first moments modified */
         if (fm) vm = mr_modified_moment(mr_ld(g, c, 0, x - 2, 0), u0, mr_ld(g, c, 1, x - 2, 0), v0);
@@ -287,7 +288,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
         v0 = mr_modified_moment(um, up, mr_ld(g, c, 1, x - 1, 0), mr_ld(g, c, 1, x + 1, 0));
       }
       vt[c][0] = u0;
-      vt[c][1] = v0;
+      vt[c][1] = I.mod == 1 ? v0s : v0;   /* internal to L: the combination keeps the stored moment */
       mr_recon1d<BP>(um, u0, up, vm, v0, vp, I.W, val[c]);
       s_tr[cs * NC + c] = val[c][3];
     }
@@ -321,7 +322,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
       const long long P = I.plane;
       const double dt = I.dt;
       const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
-      const int f1 = (mode == 1 || mode == 2) ? mr_flag(mr_gp(I.flags[0]), I.fex, 1, fh, x, 0) : 0;
+      /* U^n with the stage-1 modification (stored first moments unless it persists) */
+      const int f1 = (mode == 1 || mode == 2) && I.mod == 0 ? mr_flag(mr_gp(I.flags[0]), I.fex, 1, fh, x, 0) : 0;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const double fm_ = s_fl[cs * NC + c], fp_ = s_fl[(cs + 1) * NC + c];

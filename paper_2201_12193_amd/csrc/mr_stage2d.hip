@@ -184,8 +184,10 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
             }
         }
         cu = u[4];
-        cv = v[4];
-        cw = w[4];
+        /* the combination takes the modified first moments unless the
+           modification stays internal to L */
+        cv = I.mod == 1 ? sh.mB[rb[1]][comp][c0] : v[4];
+        cw = I.mod == 1 ? sh.mA[ra[2]][2 * comp + 1][c0] : w[4];
         double val[16];
         mr_recon2d<BP>(u, v, w, I.W, val);
 #pragma unroll
@@ -278,13 +280,19 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
         else if (mode == 0) {
           r0 = pU + dt * Lu; r1 = pV + dt * Lv; r2 = pW + dt * Lw;
           /* U^n after Step 2.2 (its first moments) for stages 2 and 3 */
-          unm[(long long)(comp * 2 + 0) * P + cell] = pV;
-          unm[(long long)(comp * 2 + 1) * P + cell] = pW;
+          if (I.mod == 0) {
+            unm[(long long)(comp * 2 + 0) * P + cell] = pV;
+            unm[(long long)(comp * 2 + 1) * P + cell] = pW;
+          }
         } else {
           const double a = mode == 1 ? 0.75 : 1.0 / 3.0, b = mode == 1 ? 0.25 : 2.0 / 3.0;
           const double un = gn.U[(long long)(comp * 3) * P + cell];
-          const double vn = unm[(long long)(comp * 2 + 0) * P + cell];
-          const double wn = unm[(long long)(comp * 2 + 1) * P + cell];
+          /* first moments of U^n: modified ones kept by stage 1 if the
+             modification persists, else the stored ones (the y moment is
+             the next plane in either layout) */
+          const MR_GLB double* vs = I.mod == 0 ? unm + (long long)(comp * 2) * P : gn.U + (long long)(comp * 3 + 1) * P;
+          const double vn = vs[cell];
+          const double wn = vs[P + cell];
           r0 = a * un + b * pU + b * dt * Lu;
           r1 = a * vn + b * pV + b * dt * Lv;
           r2 = a * wn + b * pW + b * dt * Lw;

@@ -27,6 +27,8 @@ struct mr_inst {
   int bcx, bcy;     /* 0 = periodic, 1 = transmissive                          */
   int tc;           /* 0 none, 1 KXRCF, 2 all cells, 3 learned                 */
   int beta_on;      /* 0 = q_l, 1 = p_l                                        */
+  int mod;          /* where modified first moments go: 0 stage inputs and U^n,
+                       1 nowhere (internal to L), 2 stage inputs only         */
   int fhalo, shalo; /* halo widths of the flag and summary planes              */
   int fex, fey;     /* flag plane extents                                      */
   int sex, sey;     /* summary plane extents                                   */

@@ -32,6 +32,9 @@ TC_ALL = 2      # HWENO6-M5-NI
 TC_LEARNED = 3  # learned indicator with KXRCF fallback
 BETA_ON_Q = 0
 BETA_ON_P = 1
+MOD_PERSIST = 0   # modified first moments replace those of every stage input, U^n included
+MOD_INTERNAL = 1  # modification internal to L(U)
+MOD_STAGE = 2     # replace those of the stage input only
 
 
 @dataclasses.dataclass
@@ -54,6 +57,7 @@ class Problem:
     eps: float = 1e-10
     tc_mode: int = TC_KXRCF
     beta_on: int = BETA_ON_Q
+    modification: int = MOD_PERSIST
 
     @property
     def dx(self) -> float:

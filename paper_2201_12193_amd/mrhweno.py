@@ -41,7 +41,7 @@ class MrProblem(C.Structure):
                 ("bc_x", C.c_int), ("bc_y", C.c_int), ("flux", C.c_int),
                 ("gamma_gas", C.c_double), ("cfl", C.c_double), ("t_final", C.c_double),
                 ("gamma_bar", C.c_double * 4), ("eps", C.c_double),
-                ("tc_mode", C.c_int), ("beta_on", C.c_int)]
+                ("tc_mode", C.c_int), ("beta_on", C.c_int), ("modification", C.c_int)]
 
 
 def to_c(p: Problem) -> MrProblem:
@@ -53,7 +53,7 @@ def to_c(p: Problem) -> MrProblem:
     c.t_final = p.t_final if math.isfinite(p.t_final) else float("inf")
     for k in range(4):
         c.gamma_bar[k] = p.gbar[k]
-    c.eps, c.tc_mode, c.beta_on = p.eps, p.tc_mode, p.beta_on
+    c.eps, c.tc_mode, c.beta_on, c.modification = p.eps, p.tc_mode, p.beta_on, p.modification
     return c
 
 

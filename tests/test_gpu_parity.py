@@ -106,6 +106,31 @@ def test_steps_per_step_parity(name, prob, U):
     s.close()
 
 
+MOD_CASES = [c for c in CASES if c[0] in ("euler1d_riemann_n1000", "euler2d_quadrants_70", "burgers1d_n200")]
+
+
+@pytest.mark.parametrize("name,prob,U", MOD_CASES, ids=[c[0] for c in MOD_CASES])
+@pytest.mark.parametrize("mod", [I.MOD_INTERNAL, I.MOD_STAGE])
+@pytest.mark.parametrize("tc", [I.TC_KXRCF, I.TC_ALL])
+def test_modification_placement_parity(name, prob, U, mod, tc):
+    """The other two placements of the modified first moments (internal to
+    L; stage inputs only), step by step against the oracle."""
+    prob = prob.replace(modification=mod, tc_mode=tc)
+    s, Ut = _solver(prob, U)
+    sc = comp_scale(prob, U)
+    prev = U.copy()
+    for k in range(4 if prob.dim == 1 else 2):
+        s.step(1)
+        dt = s.last_dt()[0]
+        s.sync()
+        got = Ut.cpu().numpy()
+        ref = oracle.rk3_step(prob, prev, dt)
+        e = rel_state_err(prob, got, ref, sc)
+        assert e <= TOL, (k, e)
+        prev = got
+    s.close()
+
+
 def test_dt_bitwise_and_time_clipping():
     prob, U, _ = I.burgers_smooth_1d(seed=11, n=200)
     s, Ut = _solver(prob, U)

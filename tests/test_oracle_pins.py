@@ -360,6 +360,42 @@ def test_conservation_periodic(case):
     assert np.allclose(s0, s1, rtol=0, atol=1e-12 * np.abs(U[:, 0]).reshape(prob.ncomp, -1).sum(axis=1).max())
 
 
+@pytest.mark.parametrize("mod", [I.MOD_PERSIST, I.MOD_INTERNAL, I.MOD_STAGE])
+def test_modification_placements(mod):
+    """Placement of the modified first moments (Steps 2.2, 2.3; the paper is
+    silent on whether they reach the stored moments): every placement keeps
+    the cell averages conservative; with a zero time step the step is the
+    identity when the modification stays internal to L, and otherwise moves
+    only the first moments of troubled cells (all cells under TC_ALL); with
+    linear data the modification reproduces the stored first moments, so all
+    placements agree."""
+    prob, U, _ = I.euler_riemann_1d(seed=2, n=96)
+    prob = prob.replace(bc_x=I.PERIODIC, tc_mode=I.TC_ALL, modification=mod)
+    s0 = U[:, 0].sum(axis=1)
+    V = U
+    for _ in range(10):
+        V = oracle.rk3_step(prob, V, oracle.dt(prob, V))
+    assert np.allclose(s0, V[:, 0].sum(axis=1), rtol=0, atol=1e-12 * np.abs(U[:, 0]).sum(axis=1).max())
+    Z = oracle.rk3_step(prob, U, 0.0)
+    near = lambda a, b: np.allclose(a, b, rtol=0, atol=4e-16 * np.abs(U).max())   # RK weights' rounding
+    assert near(Z[:, 0], U[:, 0])
+    if mod == I.MOD_INTERNAL:
+        assert near(Z, U)
+    else:
+        assert np.abs(Z[:, 1] - U[:, 1]).max() > 1e-6
+    # linear data (a uniform density gradient): exact first moments survive
+    prob_l = I.Problem(dim=1, nx=40, system=I.BURGERS, tc_mode=I.TC_ALL, modification=mod,
+                       bc_x=I.PERIODIC)
+    x = (np.arange(40) + 0.5) / 40
+    Ul = np.zeros(prob_l.shape())
+    Ul[0, 0] = 1.0 + 0.5 * x
+    Ul[0, 1] = 0.5 / 40 / 12
+    ref = oracle.rk3_step(prob_l.replace(modification=I.MOD_INTERNAL), Ul, 0.0)
+    got = oracle.rk3_step(prob_l, Ul, 0.0)
+    inner = slice(5, 35)   # away from the periodic kink of the ramp (it spreads a cell per stage)
+    assert np.allclose(got[0, :, inner], ref[0, :, inner], rtol=0, atol=1e-15 * np.abs(Ul).max())
+
+
 def test_free_stream_preserved():
     """A constant state is an exact steady solution: all fluxes are equal and
     the moment residuals vanish."""
