@@ -66,12 +66,19 @@ typedef enum { MRHWENO_BC_PERIODIC = 0, MRHWENO_BC_TRANSMISSIVE = 1 } mrhweno_bc
  * cell).  LEARNED (2D Euler only; not part of the paper) takes the
  * troubled-cell decision of Step 2.1 from a small network trained on KXRCF
  * flags (mrhweno_set_indicator) and falls back to KXRCF for cells whose
- * score lies in an uncertainty band. */
+ * score lies in an uncertainty band.  TVB uses the minmod-based TVB limiter
+ * as the indicator, one of the alternatives of Remark 2: on the indicator
+ * variable (density; u for Burgers) a cell is troubled when the modified
+ * minmod m~(a, d+, d-) = (|a| <= M h^2 ? a : minmod(a, d+, d-)) changes a
+ * face deviation a (face value minus average, or average minus face value;
+ * 2D: Gauss-Lobatto face averages, per direction), with d+- the differences
+ * of the neighbouring cell averages, h = dx and M = tvb_m. */
 typedef enum {
   MRHWENO_TC_NONE = 0,
   MRHWENO_TC_KXRCF = 1,
   MRHWENO_TC_ALL = 2,
-  MRHWENO_TC_LEARNED = 3
+  MRHWENO_TC_LEARNED = 3,
+  MRHWENO_TC_TVB = 4
 } mrhweno_tc;
 /* Smoothness indicators of eq. (beta)/(2D-beta) taken on q_l (default; the
  * reading under which Remark 1's expansion holds) or on p_l as printed. */
@@ -102,6 +109,7 @@ typedef struct {
   int tc_mode;             /* mrhweno_tc                                         */
   int beta_on;             /* mrhweno_beta                                       */
   int modification;        /* mrhweno_mod                                        */
+  double tvb_m;            /* M of the TVB indicator (>= 0; other modes ignore it) */
 } mrhweno_problem;
 
 /* Device workspace needed for n instances (bytes, 256-byte aligned pieces).
@@ -152,7 +160,8 @@ mrhweno_status mrhweno_reconstruct(mrhweno_ctx* ctx, int instance, const void* m
 /* Step 2.1 (troubled-cell indicator) once on a given state:
  *   flags_dev  device uint8 [ny][nx];
  *   aleph_dev  device FP64 [ny][nx][2]: numerator |J| and denominator
- *              h^2 |dI^-| ||u|| of the KXRCF ratio (1D: h^2 ||u||), or NULL. */
+ *              h^2 |dI^-| ||u|| of the KXRCF ratio (1D: h^2 ||u||), or NULL;
+ *              KXRCF instances only (UNSUPPORTED otherwise). */
 mrhweno_status mrhweno_flag(mrhweno_ctx* ctx, int instance, const void* moments_dev,
                             void* flags_dev, void* aleph_dev);
 

@@ -47,7 +47,7 @@ class _Prob(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("system", C.c_int),
                 ("bc_x", C.c_int), ("bc_y", C.c_int), ("tc_mode", C.c_int), ("beta_on", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("gamma", C.c_double),
-                ("gbar", C.c_double * 4), ("eps", C.c_double)]
+                ("gbar", C.c_double * 4), ("eps", C.c_double), ("tvb_m", C.c_double)]
 
 
 _lib = None
@@ -107,6 +107,7 @@ def cprob(prob) -> _Prob:
     p.dx, p.dy, p.gamma, p.eps = prob.dx, prob.dy, prob.gamma, prob.eps
     for k in range(4):
         p.gbar[k] = prob.gbar[k]
+    p.tvb_m = getattr(prob, "tvb_m", 0.0)
     return p
 
 

@@ -47,6 +47,13 @@
  *   R13 transmissive ghosts: cell average copied from the nearest interior
  *       cell, first moments zero; every step of the operator is applied to
  *       ghost cells exactly as to interior cells.
+ *   R14 the TVB minmod indicator (tc_mode 4, one of Remark 2's
+ *       alternatives, defined in its reference rather than the paper) acts
+ *       on the indicator variable (density; u for Burgers) with h = dx; in
+ *       2D per direction, on the Gauss-Lobatto averages of the face values.
+ *       Parity of its thresholds against published values is unpinned: the
+ *       pins are its closed forms (linear data never troubled, a jump above
+ *       M h^2 troubled, M large disables it).
  *
  * Coordinates: every polynomial lives in the target cell's reference
  * coordinates xi = (x - x_i)/dx, eta = (y - y_j)/dy, so that cell (i+d) is
@@ -71,13 +78,33 @@ typedef struct {
   int system;     /* 0 = scalar Burgers + Lax-Friedrichs, 1 = Euler + HLLC   */
   int bc_x, bc_y; /* 0 = periodic, 1 = transmissive                          */
   int tc_mode;    /* 0 = no modification (HWENO6), 1 = KXRCF (M5-I),
-                     2 = modify every cell (M5-NI)                           */
+                     2 = modify every cell (M5-NI), 4 = TVB minmod indicator */
   int beta_on;    /* 0 = beta on q_l (R1), 1 = beta on p_l as printed       */
   double dx, dy;
   double gamma;   /* ratio of specific heats (Euler)                         */
   double gbar[4]; /* unnormalised linear weights, eq. (linear-weight)        */
   double eps;     /* 1e-10 in eq. (w1_-LR) and eq. (non-linear-weight)       */
+  double tvb_m;   /* TVB constant M of the minmod indicator (tc_mode 4)      */
 } orc_problem;
+
+/* ------------------------------------------------------------------------ */
+/* TVB minmod troubled-cell indicator (one of the alternatives Remark 2      */
+/* names; Cockburn and Shu's total-variation-bounded minmod limiter used as */
+/* an indicator).  On the indicator variable, a face deviation a (face value */
+/* minus the cell average, or the average minus the face value) is left     */
+/* alone by the modified minmod m~(a, d+, d-) = a if |a| <= M h^2, else      */
+/* minmod(a, d+, d-), with d+- the differences of neighbouring averages; the */
+/* cell is troubled when m~ changes one of its deviations.                   */
+/* ------------------------------------------------------------------------ */
+static double minmod3(double a, double b, double c) {
+  if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+  if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+  return 0.0;
+}
+static int tvb_changes(double a, double dp, double dm, double mh2) {
+  if (fabs(a) <= mh2) return 0;
+  return minmod3(a, dp, dm) != a;
+}
 
 static int ncomp_of(const orc_problem* P) {
   if (P->system == 0) return 1;
@@ -720,7 +747,13 @@ static void op1d_values(const orc_problem* P, const double* U, work1_t* W) {
     int f = 0;
     double num = 0.0, den = 0.0;
     if (P->tc_mode == 2) f = 1;
-    else if (P->tc_mode == 1) {
+    else if (P->tc_mode == 4) {
+      /* face values own[0] (left), own[3] (right) of the indicator variable */
+      const double ub = mom(&G, 0, 0, i, 0);
+      const double dp = mom(&G, 0, 0, i + 1, 0) - ub, dm = ub - mom(&G, 0, 0, i - 1, 0);
+      const double mh2 = P->tvb_m * P->dx * P->dx;
+      f = tvb_changes(own[3] - ub, dp, dm, mh2) || tvb_changes(ub - own[0], dp, dm, mh2);
+    } else if (P->tc_mode == 1) {
       double ptO[4] = {0, 0, 0, 0}, ptN[4] = {0, 0, 0, 0};
       /* left face x_{i-1/2}: u^+ = own left value, u^- = left neighbour's right value */
       for (int c = 0; c < nc; ++c) { ptO[c] = own[c * 4 + 0]; ptN[c] = lef[c * 4 + 3]; }
@@ -895,6 +928,26 @@ static void kxrcf_2d(const orc_problem* P, const work2_t* W, int i, int j,
   *den_out = den;
 }
 
+/* TVB minmod indicator in 2D: per direction, the Gauss-Lobatto averages of
+   the Step-1 values over the two faces against the differences of the
+   neighbouring cell averages; h = dx (square cells). */
+static int tvb_2d(const grid_t* G, const double* own /* 16 values, comp 0 */, int i, int j) {
+  const orc_problem* P = G->P;
+  double fl = 0.0, fr = 0.0, fb = 0.0, ft = 0.0;
+  for (int m = 0; m < 4; ++m) {
+    fl += gl_weight(m) * own[0 + 4 * m];
+    fr += gl_weight(m) * own[3 + 4 * m];
+    fb += gl_weight(m) * own[m];
+    ft += gl_weight(m) * own[12 + m];
+  }
+  const double ub = mom(G, 0, 0, i, j);
+  const double dpx = mom(G, 0, 0, i + 1, j) - ub, dmx = ub - mom(G, 0, 0, i - 1, j);
+  const double dpy = mom(G, 0, 0, i, j + 1) - ub, dmy = ub - mom(G, 0, 0, i, j - 1);
+  const double mh2 = P->tvb_m * P->dx * P->dx;
+  return tvb_changes(fr - ub, dpx, dmx, mh2) || tvb_changes(ub - fl, dpx, dmx, mh2) ||
+         tvb_changes(ft - ub, dpy, dmy, mh2) || tvb_changes(ub - fb, dpy, dmy, mh2);
+}
+
 /* given: optional troubled-cell map of cells [-2, n+2)^2 supplied by the
    caller ((nx+4) x (ny+4), x fastest) in place of Step 2.1 */
 static void op2d_values(const orc_problem* P, const double* U, work2_t* W, const unsigned char* given) {
@@ -918,6 +971,7 @@ static void op2d_values(const orc_problem* P, const double* U, work2_t* W, const
       if (given) { W->fl[k] = given[(size_t)(j + 2) * (P->nx + 4) + (i + 2)] != 0; continue; }
       if (P->tc_mode == 0) { W->fl[k] = 0; continue; }
       if (P->tc_mode == 2) { W->fl[k] = 1; continue; }
+      if (P->tc_mode == 4) { W->fl[k] = (unsigned char)tvb_2d(&G, &W->g0[k * nc * 16], i, j); continue; }
       kxrcf_2d(P, W, i, j, &W->fl[k], &W->anum[k], &W->aden[k]);
     }
 #pragma omp parallel for schedule(dynamic, 1)
@@ -1201,6 +1255,11 @@ static int flag_cell2(const grid_t* G, int i, int j) {
   const orc_problem* P = G->P;
   if (P->tc_mode == 0) return 0;
   if (P->tc_mode == 2) return 1;
+  if (P->tc_mode == 4) {
+    double own[64];
+    g0_cell2(G, i, j, own);
+    return tvb_2d(G, own, i, j);
+  }
   /* a 3x3 work2_t window centred on (i, j) */
   work2_t W;
   W.nc = G->nc;

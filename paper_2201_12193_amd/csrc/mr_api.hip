@@ -66,8 +66,11 @@ bool learned(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_LEARNED;
 /* KXRCF face summaries over the whole extended plane (the learned
    indicator keeps a summary plane too, filled only around band cells) */
 bool kxrcf(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_KXRCF; }
+bool tvb(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_TVB; }
+/* an indicator pass of its own (KXRCF or TVB; the learned one has its kernel) */
+bool indicator_pass(const mrhweno_problem& p) { return kxrcf(p) || tvb(p); }
 /* 1D KXRCF keeps face summaries in a plane; 2D KXRCF computes them in LDS */
-bool needs_summ(const mrhweno_problem& p) { return kxrcf(p) && p.dim == 1; }
+bool needs_summ(const mrhweno_problem& p) { return indicator_pass(p) && p.dim == 1; }
 bool has_summ(const mrhweno_problem& p) { return needs_summ(p) || learned(p); }
 /* work items of the learned indicator: strips over [-2, n+2)^2 */
 int learn_tiles(const mrhweno_problem& p) {
@@ -76,7 +79,7 @@ int learn_tiles(const mrhweno_problem& p) {
 int strip_cells(const mrhweno_problem& p) { return kBlock / ncomp_of(p); }   /* 2D strip width incl. ring */
 /* 2D KXRCF work items: strips over [-2, n+2)^2 */
 int kx_tiles(const mrhweno_problem& p) {
-  return p.dim == 2 && kxrcf(p) ? ceil_div_i(ext(p.nx, kFHalo), kKxW) * ceil_div_i(ext(p.ny, kFHalo), kKxRows) : 0;
+  return p.dim == 2 && indicator_pass(p) ? ceil_div_i(ext(p.nx, kFHalo), kKxW) * ceil_div_i(ext(p.ny, kFHalo), kKxRows) : 0;
 }
 
 std::string validate(const mrhweno_problem& p) {
@@ -90,7 +93,8 @@ std::string validate(const mrhweno_problem& p) {
   for (int l = 0; l < 4; ++l)
     if (!(p.gamma_bar[l] > 0.0) || !std::isfinite(p.gamma_bar[l])) return "linear weights must be positive";
   if (!(p.eps > 0.0)) return "eps must be positive";
-  if (p.tc_mode < 0 || p.tc_mode > 3) return "unknown troubled-cell mode";
+  if (p.tc_mode < 0 || p.tc_mode > 4) return "unknown troubled-cell mode";
+  if (!(p.tvb_m >= 0.0) || !std::isfinite(p.tvb_m)) return "tvb_m must be finite and non-negative";
   if (p.beta_on != 0 && p.beta_on != 1) return "unknown beta_on";
   if (p.modification < 0 || p.modification > 2) return "unknown modification placement";
   if (p.tc_mode == MRHWENO_TC_LEARNED && (p.dim != 2 || p.flux != MRHWENO_EULER_HLLC))
@@ -181,7 +185,7 @@ struct Group {
   bool any_summ = false, any_lf = false;
   std::vector<int> insts;
   int t_summ = 0, n_summ = 0, t_flag = 0, n_flag = 0, t_st1 = 0, n_st1 = 0;
-  int t_st2 = 0, n_st2 = 0, t_kx = 0, n_kx = 0;
+  int t_st2 = 0, n_st2 = 0, t_kx = 0, n_kx = 0, t_tvb = 0, n_tvb = 0;
 };
 
 /* learned-indicator work items of one instance (instance id `slot`) */
@@ -258,8 +262,8 @@ static void add_cells(std::vector<mr_tile1>& v, int inst, long long count) {
     v.push_back(mr_tile1{inst, (int)s, (int)std::min<long long>(kBlock, count - s), 0});
 }
 
-static void add_kx_tiles_if(std::vector<mr_tile2>& v, int q, const mrhweno_problem& p) {
-  if (kx_tiles(p) > 0) add_kx_tiles(v, q, p);
+static void add_kx_tiles_if(std::vector<mr_tile2>& v, int q, const mrhweno_problem& p, bool want_tvb) {
+  if (kx_tiles(p) > 0 && tvb(p) == want_tvb) add_kx_tiles(v, q, p);
 }
 
 static void build_lists(mrhweno_ctx* c) {
@@ -275,8 +279,8 @@ static void build_lists(mrhweno_ctx* c) {
       if (needs_summ(c->probs[q])) add_cells(c->h_t1, q, (long long)sex(c->probs[q]) * sey(c->probs[q]));
     g.n_summ = (int)c->h_t1.size() - g.t_summ;
     g.t_flag = (int)c->h_t1.size();
-    for (int q : g.insts)   /* 2D KXRCF flags come from the fused kernel */
-      if (!learned(c->probs[q]) && !(g.dim == 2 && kxrcf(c->probs[q])))
+    for (int q : g.insts)   /* 2D KXRCF and TVB flags come from the fused kernel */
+      if (!learned(c->probs[q]) && !(g.dim == 2 && indicator_pass(c->probs[q])))
         add_cells(c->h_t1, q, (long long)fex(c->probs[q]) * fey(c->probs[q]));
     g.n_flag = (int)c->h_t1.size() - g.t_flag;
     g.t_st1 = (int)c->h_t1.size();
@@ -302,8 +306,11 @@ static void build_lists(mrhweno_ctx* c) {
     }
     g.n_st2 = (int)c->h_t2.size() - g.t_st2;
     g.t_kx = (int)c->h_t2.size();
-    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q]);
+    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], false);
     g.n_kx = (int)c->h_t2.size() - g.t_kx;
+    g.t_tvb = (int)c->h_t2.size();
+    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], true);
+    g.n_tvb = (int)c->h_t2.size() - g.t_tvb;
   }
 }
 
@@ -352,11 +359,16 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
         any = true;
         if ((e = mr_launch_summary(s, g.dim, g.bp, c->d, c->t1 + g.t_summ, g.n_summ, st)) != hipSuccess) return e;
       }
-    for (auto& g : c->groups)
+    for (auto& g : c->groups) {
       if (g.n_kx > 0) {
         any = true;
         if ((e = mr_launch_kxrcf2(s, g.nc == 4 ? 3 : 1, g.bp, c->d, c->t2 + g.t_kx, g.n_kx, st)) != hipSuccess) return e;
       }
+      if (g.n_tvb > 0) {   /* the TVB test reads the indicator variable only */
+        any = true;
+        if ((e = mr_launch_kxrcf2(s, 1, g.bp, c->d, c->t2 + g.t_tvb, g.n_tvb, st)) != hipSuccess) return e;
+      }
+    }
     if (c->any_learned) {
       any = true;
       if ((e = mr_launch_learned(s, c->d, c->tl, c->n_tl, st, c->lw, c->band, c->cnt, c->grid_l)) != hipSuccess)
@@ -445,6 +457,7 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     I.rdx = 1.0 / I.dx;
     I.rdy = 1.0 / I.dy;
     I.band_lo = 0.2; I.band_hi = 0.8;
+    I.tvb_mh2 = p.tvb_m * I.dx * I.dx;
     fill_wconst(p, I.W);
     I.buf[0] = (double*)moments_dev[q];
     I.buf[1] = (double*)(c->ws + c->L.buf1[q]);
@@ -714,7 +727,8 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   if (lrn && !c->weights_set)
     return fail(c, MRHWENO_ERR_NOT_READY, "learned indicator has no weights (mrhweno_set_indicator)");
   if (kind == 3 && !lrn) return fail(c, MRHWENO_ERR_INVALID_ARG, "instance does not use the learned indicator");
-  if (lrn && aleph) return fail(c, MRHWENO_ERR_UNSUPPORTED, "KXRCF ratios are not formed for learned-indicator instances");
+  if (aleph && !kxrcf(p))
+    return fail(c, MRHWENO_ERR_UNSUPPORTED, "KXRCF ratios are formed for KXRCF instances only");
   mrhweno_status st = pull(c);   /* the probe reuses the instance's scratch planes */
   if (st != MRHWENO_OK) return st;
   mr_inst I = c->h[q];
@@ -737,7 +751,7 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   if (needs_summ(p)) add_cells(t1, slot, (long long)sex(p) * sey(p));
   const int n_sum = (int)t1.size() - t_sum;
   const int t_flg = (int)t1.size();
-  const bool kx2 = kx_tiles(p) > 0;   /* 2D KXRCF: flags from the fused kernel */
+  const bool kx2 = kx_tiles(p) > 0;   /* 2D KXRCF / TVB: flags from the fused kernel */
   if (!lrn && !kx2) add_cells(t1, slot, (long long)fex(p) * fey(p));
   const int n_flg = (int)t1.size() - t_flg;
   const int t_val = (int)t1.size();
@@ -782,7 +796,7 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   } else {
     MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, c->d, d1 + t_sum, n_sum, 3));
     MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));
-    if (kx2) MR_CHECK(c, mr_launch_kxrcf2(s, ncomp_of(p) == 4 ? 3 : 1, p.beta_on, c->d, d3, (int)tl.size(), 3));
+    if (kx2) MR_CHECK(c, mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? 3 : 1, p.beta_on, c->d, d3, (int)tl.size(), 3));
   }
   const int nc = ncomp_of(p);
   if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + t_val, n_val, (double*)out));

@@ -89,6 +89,17 @@ MR_HD double mr_rcp(double x) {
 #endif
 }
 
+/* TVB minmod indicator (Remark 2's alternative): does the modified minmod
+ * m~(a, dp, dm) = (|a| <= mh2 ? a : minmod(a, dp, dm)) change the face
+ * deviation a?  minmod returns a itself exactly when the three arguments
+ * share a's sign and |a| is the smallest, so no value is compared for
+ * equality. */
+MR_HD bool mr_tvb_changes(double a, double dp, double dm, double mh2) {
+  if (fabs(a) <= mh2) return false;
+  const bool same = (a > 0.0 && dp > 0.0 && dm > 0.0) || (a < 0.0 && dp < 0.0 && dm < 0.0);
+  return !(same && fabs(a) <= fabs(dp) && fabs(a) <= fabs(dm));
+}
+
 /* ------------------------------------------------------------ nonlinear weights */
 /* 1D Step 1 for one component, data on cells i-1, i, i+1 -> 4 GL values. */
 template <bool BETA_P>

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
     const mr_tile1 tl = tiles[t];
     const mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
-    if (I.tc != 1 && I.tc != 3) continue;
+    if (I.tc != 1 && I.tc != 3 && I.tc != 4) continue;
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
     const int i = e - I.shalo;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
     mr_recon1d<BP>(mr_ld(g, 0, 0, i - 1, 0), mr_ld(g, 0, 0, i, 0), mr_ld(g, 0, 0, i + 1, 0),
                    mr_ld(g, 0, 1, i - 1, 0), mr_ld(g, 0, 1, i, 0), mr_ld(g, 0, 1, i + 1, 0), I.W, r);
     double vl = r[0], vr = r[3];
-    if (I.flux == 1) {
+    if (I.flux == 1 && I.tc != 4) {   /* the TVB test needs no velocity */
       double m[4];
       mr_recon1d<BP>(mr_ld(g, 1, 0, i - 1, 0), mr_ld(g, 1, 0, i, 0), mr_ld(g, 1, 0, i + 1, 0),
                      mr_ld(g, 1, 1, i - 1, 0), mr_ld(g, 1, 1, i, 0), mr_ld(g, 1, 1, i + 1, 0), I.W, m);
@@ -224,8 +224,9 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
   }
 }
 
-/* Troubled-cell flags, eq. (KXRCF) with eq. (line-integral-average), over
- * [-2, nx+2); tc = 0 / 2 write all-zero / all-one maps. */
+/* Troubled-cell flags, eq. (KXRCF) with eq. (line-integral-average), or the
+ * TVB minmod test, over [-2, nx+2); tc = 0 / 2 write all-zero / all-one
+ * maps. */
 __global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
 #pragma clang fp contract(off)
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -239,6 +240,16 @@ __global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_ti
     const int s = e + (I.shalo - I.fhalo);   /* same cell in the summary plane */
     const long long SE = I.sex;
     const MR_GLB double* S = mr_gp(I.summ);
+    if (I.tc == 4) {
+      /* TVB minmod test on the face deviations of the indicator variable */
+      const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+      const int i = e - I.fhalo;
+      const double ub = mr_ld(g, 0, 0, i, 0);
+      const double dp = mr_ld(g, 0, 0, i + 1, 0) - ub, dm = ub - mr_ld(g, 0, 0, i - 1, 0);
+      fl[e] = (unsigned char)(mr_tvb_changes(S[1 * SE + s] - ub, dp, dm, I.tvb_mh2) ||
+                              mr_tvb_changes(ub - S[0 * SE + s], dp, dm, I.tvb_mh2));
+      continue;
+    }
     const double jl = S[0 * SE + s] - S[1 * SE + s - 1];
     const double vl = 0.5 * (S[2 * SE + s] + S[3 * SE + s - 1]);
     const double jr = S[1 * SE + s] - S[0 * SE + s + 1];

@@ -360,7 +360,7 @@ MR_INL int kx_slot(int y, int n) { return (y + 12 * n) % n; }
    reciprocals of the density at the twelve face points) */
 template <int NK, bool BP>
 MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, int s2, int col,
-                         const mr_wconst& W, double f[9]) {
+                         const mr_wconst& W, double tvb_mh2, double f[9]) {
   double irl[4], irr[4], irm[4];   /* 1/rho at points 0,4,8,12 | 3,7,11,15 | 1,2,13,14 */
   double sl = 0.0, sr = 0.0, sb = 0.0, st = 0.0, nrm = 0.0;
   double vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
@@ -389,7 +389,15 @@ MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, in
 #pragma unroll
       for (int k = 0; k < 16; ++k) nrm = fmax(nrm, fabs(q[k]));
       if (NK == 1) { vl = sl; vr = sr; vb = sb; vt = st; }   /* Burgers: f'(u) = u */
-      else {
+      if (NK == 1 && tvb_mh2 >= 0.0) {
+        /* TVB minmod test on the face averages (x then y); the verdict goes
+           in f[0] */
+        const double dpx = u[5] - u[4], dmx = u[4] - u[3], dpy = u[7] - u[4], dmy = u[4] - u[1];
+        sl = (mr_tvb_changes(sr - u[4], dpx, dmx, tvb_mh2) || mr_tvb_changes(u[4] - sl, dpx, dmx, tvb_mh2) ||
+              mr_tvb_changes(st - u[4], dpy, dmy, tvb_mh2) || mr_tvb_changes(u[4] - sb, dpy, dmy, tvb_mh2))
+                 ? 1.0 : 0.0;
+      }
+      if (NK > 1) {
         mr_recip4(q[0], q[4], q[8], q[12], irl);
         mr_recip4(q[3], q[7], q[11], q[15], irr);
         mr_recip4(q[1], q[2], q[13], q[14], irm);
@@ -411,7 +419,8 @@ MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, in
 }
 
 /* NK: components the indicator reads (1 Burgers, 3 Euler: rho and the
-   momenta).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
+   momenta; 1 for the TVB minmod test, which reads the indicator variable
+   only and decides each cell from its own face averages).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
    of the extended flag range [-2, n+2)^2 (y0 >= -2). */
 template <int NK, bool BP>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, const mr_tile2* tiles, int ntiles, int stage) {
@@ -479,7 +488,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
       const int r = r0 + ry;
       if (r <= ylast) {
         double f[9];
-        kx_face_data<NK, BP>(mom, kx_slot(r - 1, KX_MR), kx_slot(r, KX_MR), kx_slot(r + 1, KX_MR), cx + 1, I.W, f);
+        kx_face_data<NK, BP>(mom, kx_slot(r - 1, KX_MR), kx_slot(r, KX_MR), kx_slot(r + 1, KX_MR), cx + 1, I.W,
+                             I.tc == 4 ? I.tvb_mh2 : -1.0, f);
         const int sf = kx_slot(r, KX_FR);
 #pragma unroll
         for (int k = 0; k < 9; ++k) fd[sf][k][cx] = f[k];
@@ -497,22 +507,26 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
       if (rf >= tl.y0 && rf < tl.y0 + tl.rows && cx >= 1 && cx <= KX_W - 2 && x < I.nx + I.fhalo) {
 #pragma clang fp contract(off)
         const int a = kx_slot(rf, KX_FR), b = kx_slot(rf - 1, KX_FR), u = kx_slot(rf + 1, KX_FR);
-        double J = 0.0, len = 0.0;
-        const double vl = 0.5 * (fd[a][4][cx] + fd[a][5][cx - 1]);
-        if (vl > 0.0) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
-        const double vr = 0.5 * (fd[a][5][cx] + fd[a][4][cx + 1]);
-        if (-vr > 0.0) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
-        const double vb = 0.5 * (fd[a][6][cx] + fd[b][7][cx]);
-        if (vb > 0.0) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
-        const double vt = 0.5 * (fd[a][7][cx] + fd[u][6][cx]);
-        if (-vt > 0.0) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
-        const double num = fabs(J);
-        const double den = I.dx * I.dx * len * fd[a][8][cx];
-        fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(num > den);
-        if (aleph && x >= 0 && x < I.nx && rf >= 0 && rf < I.ny) {
-          const long long cell = (long long)rf * I.nx + x;
-          aleph[2 * cell] = num;
-          aleph[2 * cell + 1] = den;
+        if (I.tc == 4) {   /* TVB: the cell's own verdict */
+          fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(fd[a][0][cx] != 0.0);
+        } else {
+          double J = 0.0, len = 0.0;
+          const double vl = 0.5 * (fd[a][4][cx] + fd[a][5][cx - 1]);
+          if (vl > 0.0) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
+          const double vr = 0.5 * (fd[a][5][cx] + fd[a][4][cx + 1]);
+          if (-vr > 0.0) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
+          const double vb = 0.5 * (fd[a][6][cx] + fd[b][7][cx]);
+          if (vb > 0.0) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
+          const double vt = 0.5 * (fd[a][7][cx] + fd[u][6][cx]);
+          if (-vt > 0.0) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
+          const double num = fabs(J);
+          const double den = I.dx * I.dx * len * fd[a][8][cx];
+          fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(num > den);
+          if (aleph && x >= 0 && x < I.nx && rf >= 0 && rf < I.ny) {
+            const long long cell = (long long)rf * I.nx + x;
+            aleph[2 * cell] = num;
+            aleph[2 * cell + 1] = den;
+          }
         }
       }
 #pragma unroll

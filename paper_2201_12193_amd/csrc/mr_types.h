@@ -25,7 +25,7 @@ struct mr_inst {
   int dim, nx, ny, nc;
   int flux;         /* 0 = Burgers + Lax-Friedrichs, 1 = Euler + HLLC          */
   int bcx, bcy;     /* 0 = periodic, 1 = transmissive                          */
-  int tc;           /* 0 none, 1 KXRCF, 2 all cells, 3 learned                 */
+  int tc;           /* 0 none, 1 KXRCF, 2 all cells, 3 learned, 4 TVB minmod    */
   int beta_on;      /* 0 = q_l, 1 = p_l                                        */
   int mod;          /* where modified first moments go: 0 stage inputs and U^n,
                        1 nowhere (internal to L), 2 stage inputs only         */
@@ -36,6 +36,7 @@ struct mr_inst {
   double dx, dy, gam, cfl, t_final;
   double rdx, rdy;            /* 1/dx, 1/dy                                    */
   double band_lo, band_hi;  /* learned-indicator uncertainty band              */
+  double tvb_mh2;           /* M h^2 of the TVB indicator                      */
   mr_wconst W;
   double* buf[3];             /* state rotation; buf[0] = caller's moments     */
   unsigned char* flags[2];    /* [0] stage-1 flags, [1] stage-2/3 flags        */

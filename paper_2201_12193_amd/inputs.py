@@ -30,6 +30,7 @@ TC_NONE = 0     # HWENO6: no first-moment modification
 TC_KXRCF = 1    # HWENO6-M5-I
 TC_ALL = 2      # HWENO6-M5-NI
 TC_LEARNED = 3  # learned indicator with KXRCF fallback
+TC_TVB = 4      # TVB minmod indicator (one of Remark 2's alternatives)
 BETA_ON_Q = 0
 BETA_ON_P = 1
 MOD_PERSIST = 0   # modified first moments replace those of every stage input, U^n included
@@ -58,6 +59,7 @@ class Problem:
     tc_mode: int = TC_KXRCF
     beta_on: int = BETA_ON_Q
     modification: int = MOD_PERSIST
+    tvb_m: float = 0.0   # TVB constant M of the minmod indicator (TC_TVB)
 
     @property
     def dx(self) -> float:

@@ -12,7 +12,7 @@ import math
 import os
 from typing import List, Optional, Sequence, Tuple
 
-from .inputs import Problem
+from .inputs import TC_KXRCF, Problem
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmrhweno.so")
@@ -41,7 +41,8 @@ class MrProblem(C.Structure):
                 ("bc_x", C.c_int), ("bc_y", C.c_int), ("flux", C.c_int),
                 ("gamma_gas", C.c_double), ("cfl", C.c_double), ("t_final", C.c_double),
                 ("gamma_bar", C.c_double * 4), ("eps", C.c_double),
-                ("tc_mode", C.c_int), ("beta_on", C.c_int), ("modification", C.c_int)]
+                ("tc_mode", C.c_int), ("beta_on", C.c_int), ("modification", C.c_int),
+                ("tvb_m", C.c_double)]
 
 
 def to_c(p: Problem) -> MrProblem:
@@ -54,6 +55,7 @@ def to_c(p: Problem) -> MrProblem:
     for k in range(4):
         c.gamma_bar[k] = p.gbar[k]
     c.eps, c.tc_mode, c.beta_on, c.modification = p.eps, p.tc_mode, p.beta_on, p.modification
+    c.tvb_m = p.tvb_m
     return c
 
 
@@ -212,9 +214,12 @@ class Solver:
         torch.cuda.synchronize()
         p = self.problems[instance]
         fl = torch.empty(p.shape()[2:], dtype=torch.uint8, device=U.device)
-        al = torch.empty(p.shape()[2:] + (2,), dtype=torch.float64, device=U.device)
+        # the KXRCF ratio (numerator, denominator) exists for KXRCF instances only
+        al = (torch.empty(p.shape()[2:] + (2,), dtype=torch.float64, device=U.device)
+              if p.tc_mode == TC_KXRCF else None)
         _check(self.ctx, lib().mrhweno_flag(self.ctx, instance, C.c_void_p(U.data_ptr()),
-                                            C.c_void_p(fl.data_ptr()), C.c_void_p(al.data_ptr())))
+                                            C.c_void_p(fl.data_ptr()),
+                                            C.c_void_p(al.data_ptr() if al is not None else None)))
         return fl, al
 
     def residual(self, instance: int, U):

@@ -131,6 +131,48 @@ def test_modification_placement_parity(name, prob, U, mod, tc):
     s.close()
 
 
+@pytest.mark.parametrize("name,prob,U", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("M", [1.0, 20.0])
+def test_tvb_indicator_parity(name, prob, U, M):
+    """The TVB minmod indicator (Remark 2's alternative): flags equal to the
+    oracle's except at near-ties of the minmod comparisons, then the
+    residual and a few steps at the 1e-12 bar."""
+    from tests.parity_util import tvb_tie_map
+    import torch
+    prob = prob.replace(tc_mode=I.TC_TVB, tvb_m=M)
+    U = _advance_oracle(prob, U, 3 if prob.dim == 2 else 10)
+    s, Ut = _solver(prob, U)
+    Uin = torch.from_numpy(U).to(_dev())
+    R, fl = s.residual(0, Uin)
+    fl2, al = s.flag(0, Uin)
+    assert al is None
+    R, fl, fl2 = R.cpu().numpy(), fl.cpu().numpy().astype(bool), fl2.cpu().numpy().astype(bool)
+    assert np.array_equal(fl, fl2)
+    Lref, flref = oracle.residual(prob, U)
+    glref, _, _, _ = oracle.reconstruct(prob, U)
+    tie = tvb_tie_map(prob, U, glref)
+    diff = fl != flref.astype(bool)
+    assert (diff & ~tie).sum() == 0 and (diff & tie).sum() <= 2, ((diff & ~tie).sum(), (diff & tie).sum())
+    if prob.system == I.EULER:
+        assert flref.sum() > 0   # the discontinuous cases exercise the indicator
+    sc = comp_scale(prob, U)
+    dt = oracle.dt(prob, U)
+    if diff.sum() == 0:
+        dR = np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)
+        assert dR.max() <= TOL, dR
+        prev = U.copy()
+        for k in range(4 if prob.dim == 1 else 2):
+            s.step(1)
+            d = s.last_dt()[0]
+            s.sync()
+            got = Ut.cpu().numpy()
+            ref = oracle.rk3_step(prob, prev, d)
+            e = rel_state_err(prob, got, ref, sc)
+            assert e <= TOL, (k, e)
+            prev = got
+    s.close()
+
+
 def test_dt_bitwise_and_time_clipping():
     prob, U, _ = I.burgers_smooth_1d(seed=11, n=200)
     s, Ut = _solver(prob, U)

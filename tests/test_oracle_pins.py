@@ -396,6 +396,85 @@ def test_modification_placements(mod):
     assert np.allclose(got[0, :, inner], ref[0, :, inner], rtol=0, atol=1e-15 * np.abs(Ul).max())
 
 
+# ------------------------------------------------- TVB minmod indicator
+def _ramp_1d(n, a=1.0, b=0.5):
+    """Moments of the linear data u = a + b x on [0, 1] (first moment
+    b h / 12 in reference coordinates)."""
+    prob = I.Problem(dim=1, nx=n, system=I.BURGERS, bc_x=I.PERIODIC, tc_mode=I.TC_TVB)
+    x = (np.arange(n) + 0.5) / n
+    U = np.zeros(prob.shape())
+    U[0, 0] = a + b * x
+    U[0, 1] = b / n / 12.0
+    return prob, U
+
+
+def test_tvb_linear_data_never_troubled():
+    """The minmod test leaves linear data alone for any M >= 0 (each face
+    deviation is half of the neighbouring differences, with their sign);
+    only the cells next to the periodic kink of the ramp are troubled."""
+    for M in (0.0, 5.0):
+        prob, U = _ramp_1d(40)
+        _, fl = oracle.residual(prob.replace(tvb_m=M), U)
+        assert fl[2:38].sum() == 0
+        if M == 0.0:
+            assert fl[[0, 39]].all()
+    prob = I.Problem(dim=2, nx=24, ny=24, system=I.BURGERS, tc_mode=I.TC_TVB)
+    h = 1.0 / 24
+    c = (np.arange(24) + 0.5) * h
+    U = np.zeros(prob.shape())
+    U[0, 0] = 1.0 + 0.3 * c[None, :] - 0.2 * c[:, None]
+    U[0, 1] = 0.3 * h / 12.0
+    U[0, 2] = -0.2 * h / 12.0
+    _, fl = oracle.residual(prob, U)
+    assert fl[2:22, 2:22].sum() == 0
+
+
+def test_tvb_jump_and_threshold():
+    """A jump of height H = 0.8 inside cell 32 (its exact average and first
+    moment): that cell's face deviations are O(H), so it is troubled while
+    M h^2 < H and not once M h^2 exceeds H; its constant neighbours carry
+    rounding-level deviations only.  (M = 1 here: with M = 0 any rounding-
+    level deviation of a constant state whose value is not a binary
+    fraction counts, since minmod sends it to zero.)"""
+    n = 64
+    h = 1.0 / n
+    prob = I.Problem(dim=1, nx=n, system=I.BURGERS, bc_x=I.TRANSMISSIVE, tc_mode=I.TC_TVB, tvb_m=1.0)
+    U = np.zeros(prob.shape())
+    U[0, 0] = np.where(np.arange(n) < 32, 1.0, 0.2)
+    td = -0.2 * h   # jump position relative to the centre of cell 32
+    U[0, 0, 32] = (1.0 * (td + h / 2) + 0.2 * (h / 2 - td)) / h
+    U[0, 1, 32] = (1.0 - 0.2) * (td ** 2 - h * h / 4) / (2 * h * h)
+    _, fl = oracle.residual(prob, U)
+    assert np.array_equal(np.flatnonzero(fl), [32])
+    _, fl = oracle.residual(prob.replace(tvb_m=1.01 * 0.8 / h ** 2), U)
+    assert fl.sum() == 0
+
+
+def test_tvb_smooth_extrema():
+    """On sin(2 pi x): with M = 0 the minmod clips the smooth extrema (the
+    neighbouring differences change sign there), so troubled cells appear
+    only next to x = 1/4 and 3/4; once M h^2 exceeds the largest face
+    deviation (about h/2 max|u'| = pi h) nothing is troubled."""
+    n = 100
+    prob = I.Problem(dim=1, nx=n, system=I.BURGERS, bc_x=I.PERIODIC, tc_mode=I.TC_TVB)
+    xe = np.arange(n + 1) / n
+    x = (np.arange(n) + 0.5) / n
+    U = np.zeros(prob.shape())
+    # exact cell averages and first moments of sin(2 pi x)
+    k = 2 * np.pi
+    U[0, 0] = (np.cos(k * xe[:-1]) - np.cos(k * xe[1:])) / (k / n)
+    h = 1.0 / n
+    # first moment: (1/h) int sin(k x) (x - x_i)/h dx over the cell
+    s = np.sin(k * h / 2)
+    U[0, 1] = np.cos(k * x) * (s / (k * h) ** 2 * 2 - np.cos(k * h / 2) / (k * h))
+    _, fl0 = oracle.residual(prob, U)
+    idx = np.flatnonzero(fl0)
+    assert idx.size > 0
+    assert np.all(np.minimum(np.abs(x[idx] - 0.25), np.abs(x[idx] - 0.75)) < 0.03)
+    _, fl1 = oracle.residual(prob.replace(tvb_m=1.1 * np.pi / h), U)
+    assert fl1.sum() == 0
+
+
 def test_free_stream_preserved():
     """A constant state is an exact steady solution: all fluxes are equal and
     the moment residuals vanish."""
