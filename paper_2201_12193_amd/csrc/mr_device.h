@@ -21,9 +21,9 @@
 #define MR_KT_MAX 128
 #if defined(__HIP_DEVICE_COMPILE__) && defined(MR_KT_IN_LDS)
 #define MR_KT(i) (mr_kt_lds[i])
-#define MR_KT_DECLARE                                            \
-  __constant__ double mr_kt_dev[MR_NKT + 1] = {MR_KT_VALUES};    \
-  __shared__ __attribute__((aligned(256))) double mr_kt_lds[MR_KT_MAX];
+#define MR_KT_DECLARE                                                   \
+  static __constant__ double mr_kt_dev[MR_NKT + 1] = {MR_KT_VALUES};    \
+  static __shared__ __attribute__((aligned(256))) double mr_kt_lds[MR_KT_MAX];
 #else
 #define MR_KT(i) (mr_kt_lit[i])
 #define MR_KT_DECLARE static constexpr double mr_kt_lit[MR_NKT + 1] = {MR_KT_VALUES};

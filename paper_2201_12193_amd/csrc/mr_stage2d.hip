@@ -1,5 +1,6 @@
 /* The 2D stage kernel (its own translation unit: it keeps the constant
- * table of the reconstruction in LDS, see mr_device.h). */
+ * table of the reconstruction in LDS, see mr_device.h, and is compiled
+ * with its own scheduling options, see build.py). */
 #define MR_KT_IN_LDS 1
 #include "mr_common.h"
 
@@ -330,220 +331,5 @@ extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, mr_inst* d
   else if (nc == 4) { if (bp) MR_L2(4, true); else MR_L2(4, false); }
   else return hipErrorInvalidValue;
 #undef MR_L2
-  return hipGetLastError();
-}
-
-
-/* ================================================= fused KXRCF (2D, tc = 1) */
-/* Troubled-cell flags of eq. (KXRCF_) with the face averages of eq.
- * (line-integral-average_), in one pass: a work group owns a strip of 62
- * flag columns and sweeps it upward four rows at a time.  Each thread
- * reconstructs one cell (Step 1 on the unmodified stage input) of the
- * strip plus one ring column each side and keeps its face data in LDS; once
- * the rows above and below are there, the flags of the strip's cells follow
- * from the face data of the cell and its four neighbours.
- *
- * Moments of the strip (64 + 2 columns, the planes the indicator reads) sit
- * in a ten-row LDS ring, each loaded from HBM once per work group with the
- * boundary condition applied: a step reads six rows and writes the four
- * that the next step adds.  The face data sit in a six-row ring. */
-#define KX_W 64                       /* reconstructed columns of a strip */
-#define KX_XW (KX_W + 2)              /* staged columns                   */
-#define KX_MR 10                      /* moment ring rows                 */
-#define KX_FR 6                       /* face data ring rows              */
-
-/* ring slot of row y >= -12 */
-MR_INL int kx_slot(int y, int n) { return (y + 12 * n) % n; }
-
-/* face data of the cell at staged column col whose rows y-1, y, y+1 sit in
-   ring slots s0, s1, s2 (f as mr2_face_summary; the velocities use shared
-   reciprocals of the density at the twelve face points) */
-template <int NK, bool BP>
-MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, int s2, int col,
-                         const mr_wconst& W, double tvb_mh2, double f[9]) {
-  double irl[4], irr[4], irm[4];   /* 1/rho at points 0,4,8,12 | 3,7,11,15 | 1,2,13,14 */
-  double sl = 0.0, sr = 0.0, sb = 0.0, st = 0.0, nrm = 0.0;
-  double vl = 0.0, vr = 0.0, vb = 0.0, vt = 0.0;
-#pragma unroll 1
-  for (int c = 0; c < NK; ++c) {
-    /* the constant table stays in LDS: no loads of it are hoisted out of
-       the component loop (they would hold its entries in registers) */
-    __asm__ volatile("" ::: "memory");
-    double u[9], v[9], w[9], q[16];
-#pragma unroll
-    for (int l = 0; l < 9; ++l) {
-      const int dx = l % 3 - 1, slot = l < 3 ? s0 : (l < 6 ? s1 : s2);
-      u[l] = mom[slot][(3 * c + 0) * KX_XW + col + dx];
-      v[l] = mom[slot][(3 * c + 1) * KX_XW + col + dx];
-      w[l] = mom[slot][(3 * c + 2) * KX_XW + col + dx];
-    }
-    mr_recon2d<BP>(u, v, w, W, q);
-    if (c == 0) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        sl += glw(m) * q[0 + 4 * m];
-        sr += glw(m) * q[3 + 4 * m];
-        sb += glw(m) * q[m];
-        st += glw(m) * q[12 + m];
-      }
-#pragma unroll
-      for (int k = 0; k < 16; ++k) nrm = fmax(nrm, fabs(q[k]));
-      if (NK == 1) { vl = sl; vr = sr; vb = sb; vt = st; }   /* Burgers: f'(u) = u */
-      if (NK == 1 && tvb_mh2 >= 0.0) {
-        /* TVB minmod test on the face averages (x then y); the verdict goes
-           in f[0] */
-        const double dpx = u[5] - u[4], dmx = u[4] - u[3], dpy = u[7] - u[4], dmy = u[4] - u[1];
-        sl = (mr_tvb_changes(sr - u[4], dpx, dmx, tvb_mh2) || mr_tvb_changes(u[4] - sl, dpx, dmx, tvb_mh2) ||
-              mr_tvb_changes(st - u[4], dpy, dmy, tvb_mh2) || mr_tvb_changes(u[4] - sb, dpy, dmy, tvb_mh2))
-                 ? 1.0 : 0.0;
-      }
-      if (NK > 1) {
-        mr_recip4(q[0], q[4], q[8], q[12], irl);
-        mr_recip4(q[3], q[7], q[11], q[15], irr);
-        mr_recip4(q[1], q[2], q[13], q[14], irm);
-      }
-    } else if (c == 1) {
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        vl += glw(m) * (q[0 + 4 * m] * irl[m]);
-        vr += glw(m) * (q[3 + 4 * m] * irr[m]);
-      }
-    } else {
-      vb = glw(0) * (q[0] * irl[0]) + glw(1) * (q[1] * irm[0]) + glw(2) * (q[2] * irm[1]) + glw(3) * (q[3] * irr[0]);
-      vt = glw(0) * (q[12] * irl[3]) + glw(1) * (q[13] * irm[2]) + glw(2) * (q[14] * irm[3]) + glw(3) * (q[15] * irr[3]);
-    }
-  }
-  f[0] = sl; f[1] = sr; f[2] = sb; f[3] = st;
-  f[4] = vl; f[5] = vr; f[6] = vb; f[7] = vt;
-  f[8] = nrm;
-}
-
-/* NK: components the indicator reads (1 Burgers, 3 Euler: rho and the
-   momenta; 1 for the TVB minmod test, which reads the indicator variable
-   only and decides each cell from its own face averages).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
-   of the extended flag range [-2, n+2)^2 (y0 >= -2). */
-template <int NK, bool BP>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, const mr_tile2* tiles, int ntiles, int stage) {
-  mr_kt_fill();
-  constexpr int NPL = 3 * NK;
-  constexpr int NROW = NPL * KX_XW;                       /* staged values per row */
-  constexpr int NQ = (NROW + MR_BLOCK - 1) / MR_BLOCK;    /* ... per thread        */
-  __shared__ double mom[KX_MR][NROW];                     /* [row][plane][column]  */
-  __shared__ double fd[KX_FR][9][KX_W];
-  const int tid = threadIdx.x, cx = tid % KX_W, ry = tid / KX_W;
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const mr_tile2 tl = tiles[t];
-    const mr_inst& I = insts[tl.inst];
-    if (stage < 3 && !I.active) continue;
-    const MR_GLB double* U = mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]);
-    MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
-    MR_GLB double* aleph = mr_gp(I.aleph);
-    const int xs = tl.x0 - 2;              /* staged column 0 */
-    const int ylast = tl.y0 + tl.rows;     /* last reconstructed row */
-    /* staged element q of this thread in every row: plane offset plus folded
-       column, and whether it is a first moment (of a transmissive x ghost) */
-    int soff[NQ];
-    unsigned szero = 0u, sfm = 0u;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int e = min(tid + q * MR_BLOCK, NROW - 1);
-      const int pl = e / KX_XW, i = xs + e % KX_XW;
-      const bool ox = i < 0 || i >= I.nx;
-      int ii = I.bcx == 0 ? (i < 0 ? i + I.nx : (i >= I.nx ? i - I.nx : i)) : i;
-      ii = min(max(ii, 0), I.nx - 1);
-      soff[q] = (pl / 3 * 3 + pl % 3) * (int)I.plane + ii;
-      if (pl % 3 != 0) sfm |= 1u << q;
-      if (pl % 3 != 0 && ox && I.bcx != 0) szero |= 1u << q;
-    }
-    /* fetch moment row y into v; the elements that read as zero (first
-       moments of transmissive ghosts) are marked in *z and cleared when
-       stored.  The fold of y is uniform over the work group. */
-    auto fetch = [&](int y, double* v, unsigned* z) {
-      const bool oy = y < 0 || y >= I.ny;
-      int jj = I.bcy == 0 ? (y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y)) : y;
-      jj = min(max(jj, 0), I.ny - 1) * I.nx;
-      *z = szero | ((oy && I.bcy != 0) ? sfm : 0u);
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) v[q] = U[soff[q] + jj];
-    };
-    auto store = [&](int y, const double* v, unsigned z) {
-      double* d = mom[kx_slot(y, KX_MR)];
-#pragma unroll
-      for (int q = 0; q < NQ; ++q)
-        if (tid + q * MR_BLOCK < NROW) d[tid + q * MR_BLOCK] = ((z >> q) & 1u) ? 0.0 : v[q];
-    };
-    /* prologue: moment rows y0-2 .. y0+3 */
-#pragma unroll 1
-    for (int y = tl.y0 - 2; y <= tl.y0 + 3; y += 2) {
-      double a[NQ], b[NQ];
-      unsigned za, zb;
-      fetch(y, a, &za);
-      fetch(y + 1, b, &zb);
-      store(y, a, za);
-      store(y + 1, b, zb);
-    }
-    __syncthreads();
-    for (int s = 0; 4 * s <= tl.rows + 1; ++s) {
-      const int r0 = tl.y0 - 1 + 4 * s;    /* rows r0 .. r0+3 are reconstructed */
-      const int r = r0 + ry;
-      if (r <= ylast) {
-        double f[9];
-        kx_face_data<NK, BP>(mom, kx_slot(r - 1, KX_MR), kx_slot(r, KX_MR), kx_slot(r + 1, KX_MR), cx + 1, I.W,
-                             I.tc == 4 ? I.tvb_mh2 : -1.0, f);
-        const int sf = kx_slot(r, KX_FR);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) fd[sf][k][cx] = f[k];
-      }
-      /* moment rows r0+5 .. r0+8 (up to ylast+1) for the next step: fetched
-         now, stored (into the slots of rows r0-5 .. r0-2, which this step
-         does not read) once the flags below are formed */
-      double v[4][NQ];
-      unsigned z[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) fetch(r0 + 5 + k, v[k], &z[k]);   /* rows past ylast+1: clamped, unused */
-      __syncthreads();
-      /* flags of row r0-1+ry from the face data of rows rf-1 .. rf+1 */
-      const int rf = r0 - 1 + ry, x = xs + 1 + cx;
-      if (rf >= tl.y0 && rf < tl.y0 + tl.rows && cx >= 1 && cx <= KX_W - 2 && x < I.nx + I.fhalo) {
-#pragma clang fp contract(off)
-        const int a = kx_slot(rf, KX_FR), b = kx_slot(rf - 1, KX_FR), u = kx_slot(rf + 1, KX_FR);
-        if (I.tc == 4) {   /* TVB: the cell's own verdict */
-          fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(fd[a][0][cx] != 0.0);
-        } else {
-          double J = 0.0, len = 0.0;
-          const double vl = 0.5 * (fd[a][4][cx] + fd[a][5][cx - 1]);
-          if (vl > 0.0) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
-          const double vr = 0.5 * (fd[a][5][cx] + fd[a][4][cx + 1]);
-          if (-vr > 0.0) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
-          const double vb = 0.5 * (fd[a][6][cx] + fd[b][7][cx]);
-          if (vb > 0.0) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
-          const double vt = 0.5 * (fd[a][7][cx] + fd[u][6][cx]);
-          if (-vt > 0.0) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
-          const double num = fabs(J);
-          const double den = I.dx * I.dx * len * fd[a][8][cx];
-          fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(num > den);
-          if (aleph && x >= 0 && x < I.nx && rf >= 0 && rf < I.ny) {
-            const long long cell = (long long)rf * I.nx + x;
-            aleph[2 * cell] = num;
-            aleph[2 * cell + 1] = den;
-          }
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-        if (r0 + 5 + k <= ylast + 1) store(r0 + 5 + k, v[k], z[k]);
-      __syncthreads();
-    }
-  }
-}
-
-extern "C" hipError_t mr_launch_kxrcf2(hipStream_t s, int nk, int bp, mr_inst* d, const mr_tile2* t, int nt, int stage) {
-  if (nt <= 0) return hipSuccess;
-  const dim3 G(nt), B(MR_BLOCK);
-#define MR_LK(NK_, BP_) hipLaunchKernelGGL((k2_kxrcf<NK_, BP_>), G, B, 0, s, d, t, nt, stage)
-  if (nk == 1) { if (bp) MR_LK(1, true); else MR_LK(1, false); }
-  else if (nk == 3) { if (bp) MR_LK(3, true); else MR_LK(3, false); }
-  else return hipErrorInvalidValue;
-#undef MR_LK
   return hipGetLastError();
 }
