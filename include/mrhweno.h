@@ -110,6 +110,11 @@ typedef struct {
   int beta_on;             /* mrhweno_beta                                       */
   int modification;        /* mrhweno_mod                                        */
   double tvb_m;            /* M of the TVB indicator (>= 0; other modes ignore it) */
+  int charwise;            /* 1D Euler only: 1 = Step 1 on the characteristic
+                              fields of the flux Jacobian at the target cell's
+                              average (left eigenvectors project the stencil
+                              moments, right ones map the values back); 0 =
+                              component by component, as the paper does     */
 } mrhweno_problem;
 
 /* Device workspace needed for n instances (bytes, 256-byte aligned pieces).

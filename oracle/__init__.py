@@ -47,7 +47,8 @@ class _Prob(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int), ("system", C.c_int),
                 ("bc_x", C.c_int), ("bc_y", C.c_int), ("tc_mode", C.c_int), ("beta_on", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("gamma", C.c_double),
-                ("gbar", C.c_double * 4), ("eps", C.c_double), ("tvb_m", C.c_double)]
+                ("gbar", C.c_double * 4), ("eps", C.c_double), ("tvb_m", C.c_double),
+                ("charwise", C.c_int)]
 
 
 _lib = None
@@ -108,6 +109,7 @@ def cprob(prob) -> _Prob:
     for k in range(4):
         p.gbar[k] = prob.gbar[k]
     p.tvb_m = getattr(prob, "tvb_m", 0.0)
+    p.charwise = getattr(prob, "charwise", 0)
     return p
 
 
@@ -144,6 +146,14 @@ def modmap_1d() -> np.ndarray:
     out = np.zeros(6)
     lib().orc_modmap_1d(_dp(out))
     return out
+
+
+def euler1_eigen(u, gamma: float) -> Tuple[np.ndarray, np.ndarray]:
+    """Left and right eigenvector matrices of the 1D Euler flux Jacobian at
+    the conserved state u (rows of L, columns of R)."""
+    L, R = np.zeros(9), np.zeros(9)
+    lib().orc_euler1_eigen(_dp(np.ascontiguousarray(u, dtype=np.float64)), C.c_double(gamma), _dp(L), _dp(R))
+    return L.reshape(3, 3), R.reshape(3, 3)
 
 
 def monomials_2d() -> Tuple[np.ndarray, np.ndarray]:

@@ -47,6 +47,12 @@
  *   R13 transmissive ghosts: cell average copied from the nearest interior
  *       cell, first moments zero; every step of the operator is applied to
  *       ghost cells exactly as to interior cells.
+ *   R15 characteristic-wise Step 1 (1D Euler, charwise = 1; the paper
+ *       reconstructs component by component, R2): for target cell i the
+ *       stencil moments of every cell are projected with the left
+ *       eigenvectors of the Euler flux Jacobian at the average of cell i,
+ *       each field is reconstructed by Step 1, and the Gauss-Lobatto values
+ *       are mapped back with the right eigenvectors.
  *   R14 the TVB minmod indicator (tc_mode 4, one of Remark 2's
  *       alternatives, defined in its reference rather than the paper) acts
  *       on the indicator variable (density; u for Burgers) with h = dx; in
@@ -85,6 +91,7 @@ typedef struct {
   double gbar[4]; /* unnormalised linear weights, eq. (linear-weight)        */
   double eps;     /* 1e-10 in eq. (w1_-LR) and eq. (non-linear-weight)       */
   double tvb_m;   /* TVB constant M of the minmod indicator (tc_mode 4)      */
+  int charwise;   /* 1D Euler: Step 1 on characteristic fields (R15)         */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -711,6 +718,55 @@ static double kx_velocity(const orc_problem* P, const double* upt, int dir) {
   return upt[1 + dir] / upt[0];
 }
 
+/* Eigenvectors of the 1D Euler flux Jacobian at the conserved state u:
+   columns of R are r_k = (1, v - c, H - v c), (1, v, v^2/2), (1, v + c,
+   H + v c); the rows of L = R^-1 follow with b1 = (gamma-1)/c^2,
+   b2 = b1 v^2 / 2. */
+static void euler1_eigen(const double* u, double gam, double L[3][3], double R[3][3]) {
+  double rho = u[0], v = u[1] / rho;
+  double p = (gam - 1.0) * (u[2] - 0.5 * rho * v * v);
+  double c = sqrt(gam * p / rho), H = (u[2] + p) / rho;
+  R[0][0] = 1.0;           R[0][1] = 1.0;         R[0][2] = 1.0;
+  R[1][0] = v - c;         R[1][1] = v;           R[1][2] = v + c;
+  R[2][0] = H - v * c;     R[2][1] = 0.5 * v * v; R[2][2] = H + v * c;
+  double b1 = (gam - 1.0) / (c * c), b2 = 0.5 * b1 * v * v;
+  L[0][0] = 0.5 * (b2 + v / c); L[0][1] = -0.5 * (b1 * v + 1.0 / c); L[0][2] = 0.5 * b1;
+  L[1][0] = 1.0 - b2;           L[1][1] = b1 * v;                    L[1][2] = -b1;
+  L[2][0] = 0.5 * (b2 - v / c); L[2][1] = -0.5 * (b1 * v - 1.0 / c); L[2][2] = 0.5 * b1;
+}
+
+/* Step 1 of the 1D target cell for all components from stencil moments
+   ub[c][3], vb[c][3]: component by component (R2) or on the characteristic
+   fields (R15).  out[c*4 + k]. */
+static void step1_1d_all(const orc_problem* P, double ub[][3], double vb[][3], double* out) {
+  int nc = ncomp_of(P);
+  if (!(P->charwise && P->system == 1)) {
+    for (int c = 0; c < nc; ++c) orc_step1_1d(P, ub[c], vb[c], &out[c * 4], NULL, NULL);
+    return;
+  }
+  double L[3][3], R[3][3], u0[3] = {ub[0][1], ub[1][1], ub[2][1]};
+  euler1_eigen(u0, P->gamma, L, R);
+  double w[3][4];
+  for (int k = 0; k < 3; ++k) {
+    double wu[3], wv[3];
+    for (int j = 0; j < 3; ++j) {
+      wu[j] = L[k][0] * ub[0][j] + L[k][1] * ub[1][j] + L[k][2] * ub[2][j];
+      wv[j] = L[k][0] * vb[0][j] + L[k][1] * vb[1][j] + L[k][2] * vb[2][j];
+    }
+    orc_step1_1d(P, wu, wv, w[k], NULL, NULL);
+  }
+  for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < 4; ++q) out[c * 4 + q] = R[c][0] * w[0][q] + R[c][1] * w[1][q] + R[c][2] * w[2][q];
+}
+
+/* eigenvector pair at a state, for the pins */
+void orc_euler1_eigen(const double* u, double gam, double* L9, double* R9) {
+  double L[3][3], R[3][3];
+  euler1_eigen(u, gam, L, R);
+  memcpy(L9, L, sizeof L);
+  memcpy(R9, R, sizeof R);
+}
+
 /* Work arrays for the 1D operator: ranges include R ghost cells each side. */
 #define R1G 4
 typedef struct {
@@ -731,12 +787,12 @@ static void op1d_values(const orc_problem* P, const double* U, work1_t* W) {
   W->nc = nc;
   /* Step 1 on the original field */
 #pragma omp parallel for schedule(static)
-  for (int i = lo; i < hi; ++i)
-    for (int c = 0; c < nc; ++c) {
-      double ub[3] = {mom(&G, c, 0, i - 1, 0), mom(&G, c, 0, i, 0), mom(&G, c, 0, i + 1, 0)};
-      double vb[3] = {mom(&G, c, 1, i - 1, 0), mom(&G, c, 1, i, 0), mom(&G, c, 1, i + 1, 0)};
-      orc_step1_1d(P, ub, vb, &W->g0[(((size_t)(i - lo)) * nc + c) * 4], NULL, NULL);
-    }
+  for (int i = lo; i < hi; ++i) {
+    double ub[4][3], vb[4][3];
+    for (int c = 0; c < nc; ++c)
+      for (int d = -1; d <= 1; ++d) { ub[c][d + 1] = mom(&G, c, 0, i + d, 0); vb[c][d + 1] = mom(&G, c, 1, i + d, 0); }
+    step1_1d_all(P, ub, vb, &W->g0[((size_t)(i - lo)) * nc * 4]);
+  }
   /* Step 2.1: KXRCF (eq. KXRCF with eq. line-integral-average) on the
      indicator variable, component 0, for cells [lo+1, hi-1) */
 #pragma omp parallel for schedule(static)
@@ -777,19 +833,18 @@ static void op1d_values(const orc_problem* P, const double* U, work1_t* W) {
   /* Steps 2.2 and 2.3 for cells [lo+2, hi-2) */
 #pragma omp parallel for schedule(static)
   for (int i = lo + 2; i < hi - 2; ++i) {
-    for (int c = 0; c < nc; ++c) {
-      double* out = &W->gf[(((size_t)(i - lo)) * nc + c) * 4];
-      if (!W->fl[i - lo]) {
-        memcpy(out, &W->g0[(((size_t)(i - lo)) * nc + c) * 4], 4 * sizeof(double));
-        continue;
-      }
-      double ub[3], vb[3];
-      for (int d = -1; d <= 1; ++d) {
-        ub[d + 1] = mom(&G, c, 0, i + d, 0);
-        vb[d + 1] = W->fl[i + d - lo] ? modified_v1(&G, c, i + d) : mom(&G, c, 1, i + d, 0);
-      }
-      orc_step1_1d(P, ub, vb, out, NULL, NULL);
+    double* out = &W->gf[((size_t)(i - lo)) * nc * 4];
+    if (!W->fl[i - lo]) {
+      memcpy(out, &W->g0[((size_t)(i - lo)) * nc * 4], (size_t)nc * 4 * sizeof(double));
+      continue;
     }
+    double ub[4][3], vb[4][3];
+    for (int c = 0; c < nc; ++c)
+      for (int d = -1; d <= 1; ++d) {
+        ub[c][d + 1] = mom(&G, c, 0, i + d, 0);
+        vb[c][d + 1] = W->fl[i + d - lo] ? modified_v1(&G, c, i + d) : mom(&G, c, 1, i + d, 0);
+      }
+    step1_1d_all(P, ub, vb, out);
   }
 }
 

@@ -97,6 +97,9 @@ std::string validate(const mrhweno_problem& p) {
   if (!(p.tvb_m >= 0.0) || !std::isfinite(p.tvb_m)) return "tvb_m must be finite and non-negative";
   if (p.beta_on != 0 && p.beta_on != 1) return "unknown beta_on";
   if (p.modification < 0 || p.modification > 2) return "unknown modification placement";
+  if (p.charwise != 0 && p.charwise != 1) return "charwise must be 0 or 1";
+  if (p.charwise && !(p.dim == 1 && p.flux == MRHWENO_EULER_HLLC))
+    return "characteristic-wise reconstruction is implemented for 1D Euler";
   if (p.tc_mode == MRHWENO_TC_LEARNED && (p.dim != 2 || p.flux != MRHWENO_EULER_HLLC))
     return "the learned indicator is for 2D Euler";
   if (p.dim == 2) {
@@ -447,7 +450,7 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     std::memset(&I, 0, sizeof I);
     I.dim = p.dim; I.nx = p.nx; I.ny = p.dim == 2 ? p.ny : 1; I.nc = ncomp_of(p);
     I.flux = p.flux; I.bcx = p.bc_x; I.bcy = p.dim == 2 ? p.bc_y : 0;
-    I.tc = p.tc_mode; I.beta_on = p.beta_on; I.mod = p.modification;
+    I.tc = p.tc_mode; I.beta_on = p.beta_on; I.mod = p.modification; I.charwise = p.charwise;
     I.fhalo = kFHalo; I.shalo = kSHalo;
     I.fex = fex(p); I.fey = fey(p); I.sex = sex(p); I.sey = sey(p);
     I.plane = plane_of(p);

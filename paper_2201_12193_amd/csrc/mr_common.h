@@ -35,6 +35,44 @@ MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
   return g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
 }
 
+/* Step 1 of a 1D cell for its NC components from the three-cell stencil
+ * (averages um, u0, up and first moments vm, v0, vp per component):
+ * component by component, or, for Euler with I.charwise, on the
+ * characteristic fields of the flux Jacobian at the cell's average u0 --
+ * every stencil moment is projected with the left eigenvectors, each field
+ * reconstructed, and the four values mapped back with the right ones.
+ * Right eigenvectors (columns): (1, v-c, H-vc), (1, v, v^2/2), (1, v+c,
+ * H+vc); left ones (rows) with b1 = (gamma-1)/c^2, b2 = b1 v^2/2:
+ * ((b2 + v/c)/2, -(b1 v + 1/c)/2, b1/2), (1 - b2, b1 v, -b1),
+ * ((b2 - v/c)/2, -(b1 v - 1/c)/2, b1/2). */
+template <int NC, bool BP>
+MR_INL void mr1_recon_sys(const double* um, const double* u0, const double* up, const double* vm,
+                          const double* v0, const double* vp, const mr_inst& I, double (*out)[4]) {
+  if (NC == 3 && I.charwise) {
+    const double rho = u0[0], v = u0[1] / rho;
+    const double p = (I.gam - 1.0) * (u0[2] - 0.5 * rho * v * v);
+    const double c = sqrt(I.gam * p / rho), H = (u0[2] + p) / rho;
+    const double b1 = (I.gam - 1.0) / (c * c), b2 = 0.5 * b1 * v * v;
+    const double L[3][3] = {{0.5 * (b2 + v / c), -0.5 * (b1 * v + 1.0 / c), 0.5 * b1},
+                            {1.0 - b2, b1 * v, -b1},
+                            {0.5 * (b2 - v / c), -0.5 * (b1 * v - 1.0 / c), 0.5 * b1}};
+    const double R[3][3] = {{1.0, 1.0, 1.0}, {v - c, v, v + c}, {H - v * c, 0.5 * v * v, H + v * c}};
+    double w[3][4];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      auto pr = [&](const double* x) { return L[k][0] * x[0] + L[k][1] * x[1] + L[k][2] * x[2]; };
+      mr_recon1d<BP>(pr(um), pr(u0), pr(up), pr(vm), pr(v0), pr(vp), I.W, w[k]);
+    }
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) out[cc][q] = R[cc][0] * w[0][q] + R[cc][1] * w[1][q] + R[cc][2] * w[2][q];
+    return;
+  }
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) mr_recon1d<BP>(um[cc], u0[cc], up[cc], vm[cc], v0[cc], vp[cc], I.W, out[cc]);
+}
+
 /* flag of cell (i, j) from an extended plane with halo h (clamped) */
 template <class P>
 MR_INL int mr_flag(P fl, int ex, int ey, int h, int i, int j) {

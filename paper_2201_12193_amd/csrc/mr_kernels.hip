@@ -201,15 +201,30 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
     const int i = e - I.shalo;
     mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
     double r[4];
-    mr_recon1d<BP>(mr_ld(g, 0, 0, i - 1, 0), mr_ld(g, 0, 0, i, 0), mr_ld(g, 0, 0, i + 1, 0),
-                   mr_ld(g, 0, 1, i - 1, 0), mr_ld(g, 0, 1, i, 0), mr_ld(g, 0, 1, i + 1, 0), I.W, r);
-    double vl = r[0], vr = r[3];
-    if (I.flux == 1 && I.tc != 4) {   /* the TVB test needs no velocity */
-      double m[4];
-      mr_recon1d<BP>(mr_ld(g, 1, 0, i - 1, 0), mr_ld(g, 1, 0, i, 0), mr_ld(g, 1, 0, i + 1, 0),
-                     mr_ld(g, 1, 1, i - 1, 0), mr_ld(g, 1, 1, i, 0), mr_ld(g, 1, 1, i + 1, 0), I.W, m);
-      vl = m[0] / r[0];
-      vr = m[3] / r[3];
+    double vl, vr;
+    if (I.charwise) {
+      /* characteristic-wise Step 1 gives all components together */
+      double um[3], u0[3], up[3], vm[3], v0[3], vp[3], rr[3][4];
+      for (int c = 0; c < 3; ++c) {
+        um[c] = mr_ld(g, c, 0, i - 1, 0); u0[c] = mr_ld(g, c, 0, i, 0); up[c] = mr_ld(g, c, 0, i + 1, 0);
+        vm[c] = mr_ld(g, c, 1, i - 1, 0); v0[c] = mr_ld(g, c, 1, i, 0); vp[c] = mr_ld(g, c, 1, i + 1, 0);
+      }
+      mr1_recon_sys<3, BP>(um, u0, up, vm, v0, vp, I, rr);
+      for (int k = 0; k < 4; ++k) r[k] = rr[0][k];
+      vl = rr[1][0] / r[0];
+      vr = rr[1][3] / r[3];
+    } else {
+      mr_recon1d<BP>(mr_ld(g, 0, 0, i - 1, 0), mr_ld(g, 0, 0, i, 0), mr_ld(g, 0, 0, i + 1, 0),
+                     mr_ld(g, 0, 1, i - 1, 0), mr_ld(g, 0, 1, i, 0), mr_ld(g, 0, 1, i + 1, 0), I.W, r);
+      vl = r[0];
+      vr = r[3];
+      if (I.flux == 1 && I.tc != 4) {   /* the TVB test needs no velocity */
+        double m[4];
+        mr_recon1d<BP>(mr_ld(g, 1, 0, i - 1, 0), mr_ld(g, 1, 0, i, 0), mr_ld(g, 1, 0, i + 1, 0),
+                       mr_ld(g, 1, 1, i - 1, 0), mr_ld(g, 1, 1, i, 0), mr_ld(g, 1, 1, i + 1, 0), I.W, m);
+        vl = m[0] / r[0];
+        vr = m[3] / r[3];
+      }
     }
     double nrm = 0.0;
 #pragma unroll
@@ -287,22 +302,24 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
     int fm = 0, fp = 0;
     if (f0) { fm = mr_flag(fl, I.fex, 1, fh, x - 1, 0); fp = mr_flag(fl, I.fex, 1, fh, x + 1, 0); }
     double val[NC][4], vt[NC][2];
+    double um[NC], u0[NC], up[NC], vm[NC], v0[NC], vp[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const double um = mr_ld(g, c, 0, x - 1, 0), u0 = mr_ld(g, c, 0, x, 0), up = mr_ld(g, c, 0, x + 1, 0);
-      double vm = mr_ld(g, c, 1, x - 1, 0), v0 = mr_ld(g, c, 1, x, 0), vp = mr_ld(g, c, 1, x + 1, 0);
-      const double v0s = v0;   /* stored first moment */
+      um[c] = mr_ld(g, c, 0, x - 1, 0); u0[c] = mr_ld(g, c, 0, x, 0); up[c] = mr_ld(g, c, 0, x + 1, 0);
+      vm[c] = mr_ld(g, c, 1, x - 1, 0); v0[c] = mr_ld(g, c, 1, x, 0); vp[c] = mr_ld(g, c, 1, x + 1, 0);
+      const double v0s = v0[c];   /* stored first moment */
       if (f0) {
         /* Steps 2.2/2.3: Step 1 again with the troubled cells' first moments modified */
-        if (fm) vm = mr_modified_moment(mr_ld(g, c, 0, x - 2, 0), u0, mr_ld(g, c, 1, x - 2, 0), v0);
-        vp = fp ? mr_modified_moment(u0, mr_ld(g, c, 0, x + 2, 0), v0, mr_ld(g, c, 1, x + 2, 0)) : vp;
-        v0 = mr_modified_moment(um, up, mr_ld(g, c, 1, x - 1, 0), mr_ld(g, c, 1, x + 1, 0));
+        if (fm) vm[c] = mr_modified_moment(mr_ld(g, c, 0, x - 2, 0), u0[c], mr_ld(g, c, 1, x - 2, 0), v0[c]);
+        vp[c] = fp ? mr_modified_moment(u0[c], mr_ld(g, c, 0, x + 2, 0), v0[c], mr_ld(g, c, 1, x + 2, 0)) : vp[c];
+        v0[c] = mr_modified_moment(um[c], up[c], mr_ld(g, c, 1, x - 1, 0), mr_ld(g, c, 1, x + 1, 0));
       }
-      vt[c][0] = u0;
-      vt[c][1] = I.mod == 1 ? v0s : v0;   /* internal to L: the combination keeps the stored moment */
-      mr_recon1d<BP>(um, u0, up, vm, v0, vp, I.W, val[c]);
-      s_tr[cs * NC + c] = val[c][3];
+      vt[c][0] = u0[c];
+      vt[c][1] = I.mod == 1 ? v0s : v0[c];   /* internal to L: the combination keeps the stored moment */
     }
+    mr1_recon_sys<NC, BP>(um, u0, up, vm, v0, vp, I, val);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) s_tr[cs * NC + c] = val[c][3];
     __syncthreads();
     const double alpha = (NC == 1) ? mr_bitsd(I.lfa[st]) : 0.0;
     double fh_[NC];
@@ -374,18 +391,19 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, con
     const int fh = I.fhalo;
     const int f0 = mr_flag(fl, I.fex, 1, fh, x, 0);
     const int fm = mr_flag(fl, I.fex, 1, fh, x - 1, 0), fp = mr_flag(fl, I.fex, 1, fh, x + 1, 0);
+    double um[NC], u0[NC], up[NC], vm[NC], v0[NC], vp[NC], r[NC][4];
     for (int c = 0; c < NC; ++c) {
-      const double um = mr_ld(g, c, 0, x - 1, 0), u0 = mr_ld(g, c, 0, x, 0), up = mr_ld(g, c, 0, x + 1, 0);
-      double vm = mr_ld(g, c, 1, x - 1, 0), v0 = mr_ld(g, c, 1, x, 0), vp = mr_ld(g, c, 1, x + 1, 0);
+      um[c] = mr_ld(g, c, 0, x - 1, 0); u0[c] = mr_ld(g, c, 0, x, 0); up[c] = mr_ld(g, c, 0, x + 1, 0);
+      vm[c] = mr_ld(g, c, 1, x - 1, 0); v0[c] = mr_ld(g, c, 1, x, 0); vp[c] = mr_ld(g, c, 1, x + 1, 0);
       if (f0) {
-        if (fm) vm = mr_modified_moment(mr_ld(g, c, 0, x - 2, 0), u0, mr_ld(g, c, 1, x - 2, 0), v0);
-        if (fp) vp = mr_modified_moment(u0, mr_ld(g, c, 0, x + 2, 0), v0, mr_ld(g, c, 1, x + 2, 0));
-        v0 = mr_modified_moment(um, up, mr_ld(g, c, 1, x - 1, 0), mr_ld(g, c, 1, x + 1, 0));
+        if (fm) vm[c] = mr_modified_moment(mr_ld(g, c, 0, x - 2, 0), u0[c], mr_ld(g, c, 1, x - 2, 0), v0[c]);
+        if (fp) vp[c] = mr_modified_moment(u0[c], mr_ld(g, c, 0, x + 2, 0), v0[c], mr_ld(g, c, 1, x + 2, 0));
+        v0[c] = mr_modified_moment(um[c], up[c], mr_ld(g, c, 1, x - 1, 0), mr_ld(g, c, 1, x + 1, 0));
       }
-      double r[4];
-      mr_recon1d<BP>(um, u0, up, vm, v0, vp, I.W, r);
-      for (int k = 0; k < 4; ++k) gl[(long long)(c * 4 + k) * I.plane + x] = r[k];
     }
+    mr1_recon_sys<NC, BP>(um, u0, up, vm, v0, vp, I, r);
+    for (int c = 0; c < NC; ++c)
+      for (int k = 0; k < 4; ++k) gl[(long long)(c * 4 + k) * I.plane + x] = r[c][k];
   }
 }
 

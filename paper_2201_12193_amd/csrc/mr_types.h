@@ -27,6 +27,7 @@ struct mr_inst {
   int bcx, bcy;     /* 0 = periodic, 1 = transmissive                          */
   int tc;           /* 0 none, 1 KXRCF, 2 all cells, 3 learned, 4 TVB minmod    */
   int beta_on;      /* 0 = q_l, 1 = p_l                                        */
+  int charwise;     /* 1D Euler: Step 1 on characteristic fields               */
   int mod;          /* where modified first moments go: 0 stage inputs and U^n,
                        1 nowhere (internal to L), 2 stage inputs only         */
   int fhalo, shalo; /* halo widths of the flag and summary planes              */

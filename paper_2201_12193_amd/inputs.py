@@ -60,6 +60,7 @@ class Problem:
     beta_on: int = BETA_ON_Q
     modification: int = MOD_PERSIST
     tvb_m: float = 0.0   # TVB constant M of the minmod indicator (TC_TVB)
+    charwise: int = 0    # 1D Euler: Step 1 on characteristic fields (0: component-wise)
 
     @property
     def dx(self) -> float:

@@ -42,7 +42,7 @@ class MrProblem(C.Structure):
                 ("gamma_gas", C.c_double), ("cfl", C.c_double), ("t_final", C.c_double),
                 ("gamma_bar", C.c_double * 4), ("eps", C.c_double),
                 ("tc_mode", C.c_int), ("beta_on", C.c_int), ("modification", C.c_int),
-                ("tvb_m", C.c_double)]
+                ("tvb_m", C.c_double), ("charwise", C.c_int)]
 
 
 def to_c(p: Problem) -> MrProblem:
@@ -56,6 +56,7 @@ def to_c(p: Problem) -> MrProblem:
         c.gamma_bar[k] = p.gbar[k]
     c.eps, c.tc_mode, c.beta_on, c.modification = p.eps, p.tc_mode, p.beta_on, p.modification
     c.tvb_m = p.tvb_m
+    c.charwise = p.charwise
     return c
 
 

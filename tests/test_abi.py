@@ -34,7 +34,10 @@ def test_workspace_bytes_validates_problems():
     assert M.workspace_bytes([good]) > 0
     bad = [I.Problem(dim=3, nx=64), I.Problem(dim=2, nx=4, ny=64), I.Problem(dim=2, nx=64, ny=32),
            good.replace(cfl=0.0), good.replace(gbar=(1, -1, 1, 1)), good.replace(eps=0.0),
-           good.replace(tc_mode=7), I.Problem(dim=1, nx=64, gamma=1.0)]
+           good.replace(tc_mode=7), I.Problem(dim=1, nx=64, gamma=1.0),
+           good.replace(modification=3), good.replace(tvb_m=-1.0), good.replace(tvb_m=float("nan")),
+           good.replace(charwise=1),                                  # characteristic-wise: 1D Euler only
+           I.Problem(dim=1, nx=64, system=I.BURGERS, charwise=1), I.Problem(dim=1, nx=64, charwise=2)]
     for b in bad:
         assert M.workspace_bytes([b]) == 0, b
     assert M.workspace_bytes([good, bad[0]]) == 0

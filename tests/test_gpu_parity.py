@@ -173,6 +173,45 @@ def test_tvb_indicator_parity(name, prob, U, M):
     s.close()
 
 
+@pytest.mark.parametrize("tc", [I.TC_KXRCF, I.TC_ALL, I.TC_TVB])
+def test_charwise_1d_parity(tc):
+    """Characteristic-wise Step 1 (1D Euler): values, flags, residual and
+    steps against the oracle."""
+    from tests.parity_util import tvb_tie_map
+    import torch
+    prob, U, _ = I.euler_riemann_1d(seed=5, n=1000)
+    prob = prob.replace(charwise=1, tc_mode=tc, tvb_m=20.0)
+    U = _advance_oracle(prob, U, 10)
+    s, Ut = _solver(prob, U)
+    Uin = torch.from_numpy(U).to(_dev())
+    R, fl = s.residual(0, Uin)
+    gl, _ = s.reconstruct(0, Uin)
+    R, fl, gl = R.cpu().numpy(), fl.cpu().numpy(), gl.cpu().numpy()
+    Lref, flref = oracle.residual(prob, U)
+    glref, _, num, den = oracle.reconstruct(prob, U)
+    if tc == I.TC_TVB:
+        tie = tvb_tie_map(prob, U, glref)
+        diff = fl.astype(bool) != flref.astype(bool)
+        bad, ties = int((diff & ~tie).sum()), int((diff & tie).sum())
+    else:
+        bad, ties = flag_mismatch(fl, flref, num, den)
+    assert bad == 0 and ties <= 2, (bad, ties)
+    sc = comp_scale(prob, U)
+    dt = oracle.dt(prob, U)
+    assert (np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc).max() <= TOL
+    assert (np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)).max() <= TOL
+    prev = U.copy()
+    for k in range(8):
+        s.step(1)
+        d = s.last_dt()[0]
+        s.sync()
+        got = Ut.cpu().numpy()
+        e = rel_state_err(prob, got, oracle.rk3_step(prob, prev, d), sc)
+        assert e <= TOL, (k, e)
+        prev = got
+    s.close()
+
+
 def test_dt_bitwise_and_time_clipping():
     prob, U, _ = I.burgers_smooth_1d(seed=11, n=200)
     s, Ut = _solver(prob, U)

@@ -559,6 +559,46 @@ def test_table3_euler_1d_gamma3():
         assert _orders(errs)[-1] > order, errs
 
 
+def test_charwise_eigenvectors_and_exactness():
+    """Characteristic-wise Step 1 (1D Euler): L R = I for physical states;
+    the projection is linear and Step 1 reproduces linear data, so linear
+    conserved data are reconstructed exactly either way."""
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        rho, v, p = rng.uniform(0.2, 2.0), rng.uniform(-1.5, 1.5), rng.uniform(0.2, 2.0)
+        u = np.array([rho, rho * v, p / 0.4 + 0.5 * rho * v * v])
+        L, R = oracle.euler1_eigen(u, 1.4)
+        assert np.abs(L @ R - np.eye(3)).max() < 1e-13
+    n = 32
+    prob = I.Problem(dim=1, nx=n, system=I.EULER, bc_x=I.PERIODIC, tc_mode=I.TC_NONE, charwise=1)
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    slope = np.array([0.3, 0.1, 0.5])
+    base = np.array([1.0, 0.2, 2.5])
+    U = np.zeros(prob.shape())
+    for c in range(3):
+        U[c, 0] = base[c] + slope[c] * x
+        U[c, 1] = slope[c] * h / 12.0
+    gl, _, _, _ = oracle.reconstruct(prob, U)
+    xn, _ = oracle.gl_rule()
+    for c in range(3):
+        exact = base[c] + slope[c] * (x[None, :] + xn[:, None] * h)
+        assert np.allclose(gl[c][:, 3:-3], exact[:, 3:-3], rtol=0, atol=1e-13)
+
+
+def test_charwise_table3_order():
+    """Characteristic-wise reconstruction keeps the sixth order of M5-I on
+    the smooth gamma = 3 Euler test of Table 3."""
+    errs = []
+    for n in (40, 80, 160):
+        prob, U = I.example_euler_1d(n, tc_mode=I.TC_KXRCF)
+        prob = prob.replace(charwise=1)
+        V = _run_to(prob, U, 2 * math.pi / 10)
+        ex = I.cell_averages_1d(prob, lambda x: X.euler1d_gamma3(x, prob.t_final)[0])
+        errs.append(np.abs(V[0, 0] - ex).mean())
+    assert _orders(errs)[-1] > 5.5, errs
+
+
 def test_2d_burgers_order():
     """Table 2: sixth-order convergence of M5-I in 2D (Example 3.2), and the
     printed magnitude at 80 x 80 within a factor 3."""
