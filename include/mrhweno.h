@@ -60,7 +60,12 @@ typedef enum {
 } mrhweno_status;
 
 typedef enum { MRHWENO_BURGERS_LF = 0, MRHWENO_EULER_HLLC = 1 } mrhweno_flux;
-typedef enum { MRHWENO_BC_PERIODIC = 0, MRHWENO_BC_TRANSMISSIVE = 1 } mrhweno_bc;
+/* Boundary conditions per axis (both ends).  TRANSMISSIVE ghosts copy the
+ * boundary cell's averages with zero first moments; REFLECTIVE (Euler only)
+ * ghosts are the mirror images of the interior cells across the wall: the
+ * wall-normal momentum and the first moment along the normal change sign
+ * (a moment flips when exactly one of the two applies). */
+typedef enum { MRHWENO_BC_PERIODIC = 0, MRHWENO_BC_TRANSMISSIVE = 1, MRHWENO_BC_REFLECTIVE = 2 } mrhweno_bc;
 /* Step 2 variants named as in the paper's Sec. 3: HWENO6 (no
  * modification), HWENO6-M5-I (KXRCF-flagged cells), HWENO6-M5-NI (every
  * cell).  LEARNED (2D Euler only; not part of the paper) takes the

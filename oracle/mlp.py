@@ -22,7 +22,8 @@ row wy = 2 belongs to lane group g = c and slot s = 60 + 5 m + (wx + 2);
 log2(h)/16 is lane group 0, slot 75; the position is
 f = 32 (s // 8) + 8 g + (s % 8).  Ghost cells follow the solver's boundary
 conditions: periodic wrap, or (transmissive) the nearest interior cell's
-average with zero first moments.
+average with zero first moments, or (reflective) the mirror image with the
+wall-normal momentum and the first moment along the normal flipped.
 
 Network: z = W3 . relu(W2 relu(W1 x + b1) + b2) + b3, score sigmoid(z);
 parameter vector W1 [64][320], b1 [64], W2 [64][64], b2 [64], W3 [64], b3,
@@ -65,21 +66,31 @@ LOGH_INDEX = 32 * (75 // 8) + 8 * 0 + 75 % 8
 
 
 def _moment(prob, U, c: int, m: int, i: int, j: int) -> float:
-    """Moment m of component c at cell (i, j), ghosts by the boundary rule."""
-    ii, jj, ghost = i, j, False
+    """Moment m of component c at cell (i, j), ghosts by the boundary rule
+    (periodic wrap; transmissive: nearest average, first moments zero;
+    reflective: mirror image, the wall-normal momentum and the first moment
+    along the normal flip)."""
+    ii, jj, ghost, flip = i, j, False, False
     if not 0 <= ii < prob.nx:
         if prob.bc_x == 0:
             ii %= prob.nx
-        else:
+        elif prob.bc_x == 1:
             ii, ghost = min(max(ii, 0), prob.nx - 1), True
+        else:
+            ii = -1 - ii if ii < 0 else 2 * prob.nx - 1 - ii
+            flip ^= (c == 1) != (m == 1)
     if not 0 <= jj < prob.ny:
         if prob.bc_y == 0:
             jj %= prob.ny
-        else:
+        elif prob.bc_y == 1:
             jj, ghost = min(max(jj, 0), prob.ny - 1), True
+        else:
+            jj = -1 - jj if jj < 0 else 2 * prob.ny - 1 - jj
+            flip ^= (c == 2) != (m == 2)
     if ghost and m > 0:
         return 0.0
-    return float(U[c, m, jj, ii])
+    v = float(U[c, m, jj, ii])
+    return -v if flip else v
 
 
 def features(prob, U, cells) -> np.ndarray:

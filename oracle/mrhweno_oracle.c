@@ -47,6 +47,15 @@
  *   R13 transmissive ghosts: cell average copied from the nearest interior
  *       cell, first moments zero; every step of the operator is applied to
  *       ghost cells exactly as to interior cells.
+ *   R16 reflective walls (bc = 2, Euler): a ghost cell is the mirror image
+ *       of the interior cell across the wall, with the wall-normal momentum
+ *       negated; its moments follow from the mirrored polynomial -- the
+ *       first moment along the normal flips, the tangential one does not --
+ *       so a moment changes sign when exactly one of "normal momentum" and
+ *       "normal first moment" applies.  At the wall face itself the two
+ *       traces carry opposite normal velocities, so their average is zero
+ *       and the face is never an inflow face of the KXRCF sum; it is set
+ *       to zero rather than left to the sign of a rounding residue.
  *   R15 characteristic-wise Step 1 (1D Euler, charwise = 1; the paper
  *       reconstructs component by component, R2): for target cell i the
  *       stencil moments of every cell are projected with the left
@@ -82,7 +91,7 @@ typedef struct {
   int dim;        /* 1 or 2                                                  */
   int nx, ny;     /* cells; ny = 1 in 1D                                     */
   int system;     /* 0 = scalar Burgers + Lax-Friedrichs, 1 = Euler + HLLC   */
-  int bc_x, bc_y; /* 0 = periodic, 1 = transmissive                          */
+  int bc_x, bc_y; /* 0 = periodic, 1 = transmissive, 2 = reflective wall (R16) */
   int tc_mode;    /* 0 = no modification (HWENO6), 1 = KXRCF (M5-I),
                      2 = modify every cell (M5-NI), 4 = TVB minmod indicator */
   int beta_on;    /* 0 = beta on q_l (R1), 1 = beta on p_l as printed       */
@@ -683,21 +692,36 @@ static double lf_flux(double a, double b, double alpha) {
 /* ======================================================================== */
 typedef struct { const orc_problem* P; const double* U; int nc, nm; } grid_t;
 
-/* Moment m of component c at cell (i, j), any integer (i, j). */
+/* Moment m of component c at cell (i, j), any integer (i, j).  A
+   reflective ghost is the mirror image of the interior cell across the
+   wall: the momentum normal to the wall and the first moment along the
+   normal change sign, so a moment flips when exactly one of the two holds
+   (R16). */
 static double mom(const grid_t* G, int c, int m, int i, int j) {
   const orc_problem* P = G->P;
-  int zero = 0;
+  int zero = 0, flip = 0;
   if (i < 0 || i >= P->nx) {
     if (P->bc_x == 0) i = ((i % P->nx) + P->nx) % P->nx;
-    else { zero = 1; i = i < 0 ? 0 : P->nx - 1; }
+    else if (P->bc_x == 1) { zero = 1; i = i < 0 ? 0 : P->nx - 1; }
+    else {
+      i = i < 0 ? -1 - i : 2 * P->nx - 1 - i;
+      i = i < 0 ? 0 : (i >= P->nx ? P->nx - 1 : i);
+      flip ^= (c == 1) ^ (m == 1);
+    }
   }
   if (P->dim == 2 && (j < 0 || j >= P->ny)) {
     if (P->bc_y == 0) j = ((j % P->ny) + P->ny) % P->ny;
-    else { zero = 1; j = j < 0 ? 0 : P->ny - 1; }
+    else if (P->bc_y == 1) { zero = 1; j = j < 0 ? 0 : P->ny - 1; }
+    else {
+      j = j < 0 ? -1 - j : 2 * P->ny - 1 - j;
+      j = j < 0 ? 0 : (j >= P->ny ? P->ny - 1 : j);
+      flip ^= (c == 2) ^ (m == 2);
+    }
   }
   if (P->dim == 1) j = 0;
   if (zero && m > 0) return 0.0;
-  return G->U[((size_t)(c * G->nm + m) * P->ny + j) * P->nx + i];
+  const double v = G->U[((size_t)(c * G->nm + m) * P->ny + j) * P->nx + i];
+  return flip ? -v : v;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -711,6 +735,10 @@ static double modified_v1(const grid_t* G, int c, int i) {
   for (int k = 0; k < 6; ++k) s += M1mod[k] * d[k];
   return s;
 }
+
+/* face f of an axis with n cells and boundary condition bc (the face
+   between cells f-1 and f) is a reflective wall (R16) */
+static int wall_face(int f, int n, int bc) { return bc == 2 && (f == 0 || f == n); }
 
 /* velocity used by the KXRCF indicator at a point (Remark 2) */
 static double kx_velocity(const orc_problem* P, const double* upt, int dir) {
@@ -813,11 +841,11 @@ static void op1d_values(const orc_problem* P, const double* U, work1_t* W) {
       double ptO[4] = {0, 0, 0, 0}, ptN[4] = {0, 0, 0, 0};
       /* left face x_{i-1/2}: u^+ = own left value, u^- = left neighbour's right value */
       for (int c = 0; c < nc; ++c) { ptO[c] = own[c * 4 + 0]; ptN[c] = lef[c * 4 + 3]; }
-      double vl = 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
+      double vl = wall_face(i, P->nx, P->bc_x) ? 0.0 : 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
       double jl = ptO[0] - ptN[0];
       /* right face x_{i+1/2}: u^- = own right value, u^+ = right neighbour's left value */
       for (int c = 0; c < nc; ++c) { ptO[c] = own[c * 4 + 3]; ptN[c] = rig[c * 4 + 0]; }
-      double vr = 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
+      double vr = wall_face(i + 1, P->nx, P->bc_x) ? 0.0 : 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
       double jr = ptO[0] - ptN[0];
       double J = jl * (vl > 0.0 ? 1.0 : 0.0) + jr * (-vr > 0.0 ? 1.0 : 0.0);
       double nrm = 0.0;
@@ -946,13 +974,14 @@ static void modified_vw2(const grid_t* G, int c, int i, int j, double* v, double
   *w = sw;
 }
 
-/* KXRCF in 2D, eqs. (KXRCF_), (line-integral-average_), readings R5, R6. */
-static void kxrcf_2d(const orc_problem* P, const work2_t* W, int i, int j,
+/* KXRCF in 2D, eqs. (KXRCF_), (line-integral-average_), readings R5, R6:
+   cell (i, j) of the grid, whose Step-1 values sit at (wi, wj) of W. */
+static void kxrcf_2d(const orc_problem* P, const work2_t* W, int wi, int wj, int i, int j,
                      unsigned char* flag, double* num_out, double* den_out) {
   int nc = W->nc;
-  const double* own = &W->g0[w2idx(W, i, j) * nc * 16];
-  const double* nb[4] = {&W->g0[w2idx(W, i - 1, j) * nc * 16], &W->g0[w2idx(W, i + 1, j) * nc * 16],
-                         &W->g0[w2idx(W, i, j - 1) * nc * 16], &W->g0[w2idx(W, i, j + 1) * nc * 16]};
+  const double* own = &W->g0[w2idx(W, wi, wj) * nc * 16];
+  const double* nb[4] = {&W->g0[w2idx(W, wi - 1, wj) * nc * 16], &W->g0[w2idx(W, wi + 1, wj) * nc * 16],
+                         &W->g0[w2idx(W, wi, wj - 1) * nc * 16], &W->g0[w2idx(W, wi, wj + 1) * nc * 16]};
   /* faces: 0 = left (x_{i-1/2}), 1 = right, 2 = bottom (y_{j-1/2}), 3 = top.
      own point index and neighbour point index for the m-th face point */
   double J = 0.0, len = 0.0;
@@ -971,6 +1000,8 @@ static void kxrcf_2d(const orc_problem* P, const work2_t* W, int i, int j,
       jump += flen * gl_weight(m) * (ptO[0] - ptN[0]);
       vel += gl_weight(m) * 0.5 * (kx_velocity(P, ptO, dir) + kx_velocity(P, ptN, dir));
     }
+    /* a reflective wall face carries no normal velocity (R16) */
+    if (dir == 0 ? wall_face(i + (f == 1), P->nx, P->bc_x) : wall_face(j + (f == 3), P->ny, P->bc_y)) vel = 0.0;
     /* inflow: left/bottom if v > 0, right/top if v < 0 (sf of the printed signs) */
     double arg = (f == 0 || f == 2) ? vel : -vel;
     if (arg > 0.0) { J += jump; len += flen; }
@@ -1027,7 +1058,7 @@ static void op2d_values(const orc_problem* P, const double* U, work2_t* W, const
       if (P->tc_mode == 0) { W->fl[k] = 0; continue; }
       if (P->tc_mode == 2) { W->fl[k] = 1; continue; }
       if (P->tc_mode == 4) { W->fl[k] = (unsigned char)tvb_2d(&G, &W->g0[k * nc * 16], i, j); continue; }
-      kxrcf_2d(P, W, i, j, &W->fl[k], &W->anum[k], &W->aden[k]);
+      kxrcf_2d(P, W, i, j, i, j, &W->fl[k], &W->anum[k], &W->aden[k]);
     }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int j = -1; j < P->ny + 1; ++j)
@@ -1325,11 +1356,10 @@ static int flag_cell2(const grid_t* G, int i, int j) {
   const int off[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
   for (int k = 0; k < 5; ++k)
     g0_cell2(G, i + off[k][0], j + off[k][1], &W.g0[w2idx(&W, off[k][0], off[k][1]) * W.nc * 16]);
-  /* kxrcf_2d indexes relative to (0,0) of the window */
+  /* the window holds cell (i, j) at its (0, 0) */
   unsigned char f;
   double num, den;
-  orc_problem Q = *P;
-  kxrcf_2d(&Q, &W, 0, 0, &f, &num, &den);
+  kxrcf_2d(P, &W, 0, 0, i, j, &f, &num, &den);
   free(W.g0);
   return f;
 }

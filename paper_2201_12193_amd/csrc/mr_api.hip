@@ -87,7 +87,10 @@ std::string validate(const mrhweno_problem& p) {
   if (p.nx < 8 || (p.dim == 2 && p.ny < 8)) return "grid must have at least 8 cells per direction";
   if (!(p.x1 > p.x0) || (p.dim == 2 && !(p.y1 > p.y0))) return "empty domain";
   if (p.flux != MRHWENO_BURGERS_LF && p.flux != MRHWENO_EULER_HLLC) return "unknown flux";
-  if (p.bc_x < 0 || p.bc_x > 1 || (p.dim == 2 && (p.bc_y < 0 || p.bc_y > 1))) return "unknown boundary condition";
+  if (p.bc_x < 0 || p.bc_x > 2 || (p.dim == 2 && (p.bc_y < 0 || p.bc_y > 2))) return "unknown boundary condition";
+  if ((p.bc_x == MRHWENO_BC_REFLECTIVE || (p.dim == 2 && p.bc_y == MRHWENO_BC_REFLECTIVE)) &&
+      p.flux != MRHWENO_EULER_HLLC)
+    return "reflective walls are for the Euler equations";
   if (p.flux == MRHWENO_EULER_HLLC && !(p.gamma_gas > 1.0)) return "gamma_gas must exceed 1";
   if (!(p.cfl > 0.0) || !(p.t_final > 0.0)) return "cfl and t_final must be positive";
   for (int l = 0; l < 4; ++l)

@@ -28,11 +28,12 @@ struct mr_grid {
 
 /* moment m of component c at cell (i, j) with ghost handling */
 MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
-  bool z = false;
-  const int ii = mr_fold(i, g.nx, g.bcx, &z);
-  const int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &z) : 0;
-  if (z && m > 0) return 0.0;
-  return g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
+  int kx = 0, ky = 0;
+  const int ii = mr_fold(i, g.nx, g.bcx, &kx);
+  const int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &ky) : 0;
+  if ((kx == 1 || ky == 1) && m > 0) return 0.0;
+  const double v = g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
+  return ((kx == 2 && mr_refl_flip(c, m, 0)) != (ky == 2 && mr_refl_flip(c, m, 1))) ? -v : v;
 }
 
 /* Step 1 of a 1D cell for its NC components from the three-cell stencil

@@ -57,20 +57,38 @@ MR_INL double gln(int k) {
 }
 
 /* ------------------------------------------------------------------ ghosts */
-/* Index of cell i in [0, n) under the boundary condition; *zero is set when
- * the cell is a transmissive ghost (first moments vanish there).  Offsets up
- * to one period either side are folded; anything further is clamped (such
- * cells never feed an output). */
-MR_INL int mr_fold(int i, int n, int bc, bool* zero) {
+/* Index of the interior cell whose moments cell i (possibly outside
+ * [0, n)) takes under the boundary condition bc, with *kind set to 1 for a
+ * transmissive ghost (average copied, first moments zero) and 2 for a
+ * reflective one (mirror image across the wall; see mr_refl_flip); left
+ * alone for interior cells and periodic images.  Offsets up to one period
+ * either side are folded; anything further is clamped (such cells never
+ * feed an output). */
+MR_INL int mr_fold(int i, int n, int bc, int* kind) {
   if (i >= 0 && i < n) return i;
   if (bc == 0) {
     if (i < 0) i += n;
     else i -= n;
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+  } else if (bc == 1) {
+    *kind = 1;
+  } else {
+    *kind = 2;
+    i = i < 0 ? -1 - i : 2 * n - 1 - i;
   }
-  *zero = true;
-  return i < 0 ? 0 : n - 1;
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
+
+/* Mirror image across a wall normal to axis a (0 = x, 1 = y): the momentum
+ * along the normal (component 1 + a) and the first moment along the normal
+ * (moment 1 + a) change sign, so moment m of component c flips when exactly
+ * one of the two holds. */
+MR_HD bool mr_refl_flip(int c, int m, int a) { return (c == 1 + a) != (m == 1 + a); }
+
+/* Face f (between cells f-1 and f) of an axis of n cells is a reflective
+ * wall.  Its two traces carry opposite normal velocities, so their average
+ * is exactly zero: the KXRCF test never counts it as an inflow face (the
+ * computed average would only hold a rounding residue of either sign). */
+MR_INL bool mr_wall(int f, int n, int bc) { return bc == 2 && (f == 0 || f == n); }
 
 /* 1/x for a positive (or negative) normal x of moderate size: the hardware
  * reciprocal estimate refined by two Newton steps (within about one ulp of

@@ -269,14 +269,13 @@ __global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_ti
     const double vl = 0.5 * (S[2 * SE + s] + S[3 * SE + s - 1]);
     const double jr = S[1 * SE + s] - S[0 * SE + s + 1];
     const double vr = 0.5 * (S[3 * SE + s] + S[2 * SE + s + 1]);
-    const double J = jl * (vl > 0.0 ? 1.0 : 0.0) + jr * (-vr > 0.0 ? 1.0 : 0.0);
+    const int i = e - I.fhalo;
+    const bool il = vl > 0.0 && !mr_wall(i, I.nx, I.bcx), ir = -vr > 0.0 && !mr_wall(i + 1, I.nx, I.bcx);
+    const double J = jl * (il ? 1.0 : 0.0) + jr * (ir ? 1.0 : 0.0);
     const double num = fabs(J);
     const double den = I.dx * I.dx * S[4 * SE + s];
     fl[e] = (unsigned char)(num > den);
-    if (I.aleph) {
-      const int i = e - I.fhalo;
-      if (i >= 0 && i < I.nx) { I.aleph[2 * i] = num; I.aleph[2 * i + 1] = den; }
-    }
+    if (I.aleph && i >= 0 && i < I.nx) { I.aleph[2 * i] = num; I.aleph[2 * i + 1] = den; }
   }
 }
 

@@ -110,28 +110,30 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
     const int xs = tl.x0 - 2;              /* staged column 0 */
     const int ylast = tl.y0 + tl.rows;     /* last reconstructed row */
     /* staged element q of this thread in every row: plane offset plus folded
-       column, and whether it is a first moment (of a transmissive x ghost) */
+       column; whether it is a first moment (of a transmissive x ghost:
+       zero), flips as a reflective x ghost, flips in a reflective y row */
     int soff[NQ];
-    unsigned szero = 0u, sfm = 0u;
+    unsigned szero = 0u, sfm = 0u, sneg = 0u, syflip = 0u;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int e = min(tid + q * MR_BLOCK, NROW - 1);
-      const int pl = e / KX_XW, i = xs + e % KX_XW;
-      const bool ox = i < 0 || i >= I.nx;
-      int ii = I.bcx == 0 ? (i < 0 ? i + I.nx : (i >= I.nx ? i - I.nx : i)) : i;
-      ii = min(max(ii, 0), I.nx - 1);
-      soff[q] = (pl / 3 * 3 + pl % 3) * (int)I.plane + ii;
-      if (pl % 3 != 0) sfm |= 1u << q;
-      if (pl % 3 != 0 && ox && I.bcx != 0) szero |= 1u << q;
+      const int pl = e / KX_XW, c = pl / 3, m = pl % 3;
+      int kx = 0;
+      const int ii = mr_fold(xs + e % KX_XW, I.nx, I.bcx, &kx);
+      soff[q] = pl * (int)I.plane + ii;
+      if (m != 0) sfm |= 1u << q;
+      if (m != 0 && kx == 1) szero |= 1u << q;
+      if (kx == 2 && mr_refl_flip(c, m, 0)) sneg |= 1u << q;
+      if (mr_refl_flip(c, m, 1)) syflip |= 1u << q;
     }
     /* fetch moment row y into v; the elements that read as zero (first
-       moments of transmissive ghosts) are marked in *z and cleared when
+       moments of transmissive ghosts) are marked in the low bits of *z, the
+       ones that flip sign (reflective ghosts) from bit 16, both applied when
        stored.  The fold of y is uniform over the work group. */
     auto fetch = [&](int y, double* v, unsigned* z) {
-      const bool oy = y < 0 || y >= I.ny;
-      int jj = I.bcy == 0 ? (y < 0 ? y + I.ny : (y >= I.ny ? y - I.ny : y)) : y;
-      jj = min(max(jj, 0), I.ny - 1) * I.nx;
-      *z = szero | ((oy && I.bcy != 0) ? sfm : 0u);
+      int ky = 0;
+      const int jj = mr_fold(y, I.ny, I.bcy, &ky) * I.nx;
+      *z = (szero | (ky == 1 ? sfm : 0u)) | ((sneg ^ (ky == 2 ? syflip : 0u)) << 16);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) v[q] = U[soff[q] + jj];
     };
@@ -139,7 +141,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
       double* d = mom[kx_slot(y, KX_MR)];
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        if (tid + q * MR_BLOCK < NROW) d[tid + q * MR_BLOCK] = ((z >> q) & 1u) ? 0.0 : v[q];
+        if (tid + q * MR_BLOCK < NROW)
+          d[tid + q * MR_BLOCK] = ((z >> q) & 1u) ? 0.0 : (((z >> (16 + q)) & 1u) ? -v[q] : v[q]);
     };
     /* prologue: moment rows y0-2 .. y0+3 */
 #pragma unroll 1
@@ -181,13 +184,13 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
         } else {
           double J = 0.0, len = 0.0;
           const double vl = 0.5 * (fd[a][4][cx] + fd[a][5][cx - 1]);
-          if (vl > 0.0) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
+          if (vl > 0.0 && !mr_wall(x, I.nx, I.bcx)) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
           const double vr = 0.5 * (fd[a][5][cx] + fd[a][4][cx + 1]);
-          if (-vr > 0.0) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
+          if (-vr > 0.0 && !mr_wall(x + 1, I.nx, I.bcx)) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
           const double vb = 0.5 * (fd[a][6][cx] + fd[b][7][cx]);
-          if (vb > 0.0) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
+          if (vb > 0.0 && !mr_wall(rf, I.ny, I.bcy)) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
           const double vt = 0.5 * (fd[a][7][cx] + fd[u][6][cx]);
-          if (-vt > 0.0) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
+          if (-vt > 0.0 && !mr_wall(rf + 1, I.ny, I.bcy)) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
           const double num = fabs(J);
           const double den = I.dx * I.dx * len * fd[a][8][cx];
           fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(num > den);

@@ -151,26 +151,25 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
     const float blo = (float)I.band_lo, bhi = (float)I.band_hi;
     /* staging of four rows: every thread issues its loads together (into
        registers) so that their latencies overlap, then converts and stores;
-       first moments of transmissive ghosts read as zero */
-    const int xi = xs + scol;
-    const bool zx = sm != 0 && (xi < 0 || xi >= I.nx) && I.bcx != 0;
-    int ii = I.bcx == 0 ? (xi < 0 ? xi + I.nx : (xi >= I.nx ? xi - I.nx : xi)) : xi;
-    ii = min(max(ii, 0), I.nx - 1);
+       first moments of transmissive ghosts read as zero, reflective ghosts
+       flip the moments mr_refl_flip names */
+    int kx = 0;
+    const int ii = mr_fold(xs + scol, I.nx, I.bcx, &kx);
+    const bool zx = sm != 0 && kx == 1;
     const MR_GLB double* ub = gr.U + (long long)sm * I.plane + ii;
     double pf[16];
     auto fetch = [&](int row0) {
       if (!stager) return;
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) {
-        const int j = row0 + rr;
-        const bool oy = j < 0 || j >= I.ny;
-        int jj = I.bcy == 0 ? (j < 0 ? j + I.ny : (j >= I.ny ? j - I.ny : j)) : j;
-        jj = min(max(jj, 0), I.ny - 1);
-        const bool zero = zx || (sm != 0 && oy && I.bcy != 0);
+        int ky = 0;
+        const int jj = mr_fold(row0 + rr, I.ny, I.bcy, &ky);
+        const bool zero = zx || (sm != 0 && ky == 1);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const double v = ub[(3 * c) * I.plane + (long long)jj * I.nx];
-          pf[4 * rr + c] = zero ? 0.0 : v;
+          const bool neg = (kx == 2 && mr_refl_flip(c, sm, 0)) != (ky == 2 && mr_refl_flip(c, sm, 1));
+          pf[4 * rr + c] = zero ? 0.0 : (neg ? -v : v);
         }
       }
     };
@@ -421,13 +420,13 @@ __global__ __launch_bounds__(MR_BLOCK) void k_fb_flags(mr_inst* insts, const mr_
     const long long o = (long long)(j + I.shalo) * sx + (i + I.shalo);
     double J = 0.0, len = 0.0;
     const double vl = 0.5 * (S[4 * SE + o] + S[5 * SE + o - 1]);
-    if (vl > 0.0) { J += I.dy * (S[0 * SE + o] - S[1 * SE + o - 1]); len += I.dy; }
+    if (vl > 0.0 && !mr_wall(i, I.nx, I.bcx)) { J += I.dy * (S[0 * SE + o] - S[1 * SE + o - 1]); len += I.dy; }
     const double vr = 0.5 * (S[5 * SE + o] + S[4 * SE + o + 1]);
-    if (-vr > 0.0) { J += I.dy * (S[1 * SE + o] - S[0 * SE + o + 1]); len += I.dy; }
+    if (-vr > 0.0 && !mr_wall(i + 1, I.nx, I.bcx)) { J += I.dy * (S[1 * SE + o] - S[0 * SE + o + 1]); len += I.dy; }
     const double vb = 0.5 * (S[6 * SE + o] + S[7 * SE + o - sx]);
-    if (vb > 0.0) { J += I.dx * (S[2 * SE + o] - S[3 * SE + o - sx]); len += I.dx; }
+    if (vb > 0.0 && !mr_wall(j, I.ny, I.bcy)) { J += I.dx * (S[2 * SE + o] - S[3 * SE + o - sx]); len += I.dx; }
     const double vt = 0.5 * (S[7 * SE + o] + S[6 * SE + o + sx]);
-    if (-vt > 0.0) { J += I.dx * (S[3 * SE + o] - S[2 * SE + o + sx]); len += I.dx; }
+    if (-vt > 0.0 && !mr_wall(j + 1, I.ny, I.bcy)) { J += I.dx * (S[3 * SE + o] - S[2 * SE + o + sx]); len += I.dx; }
     fl[b.e] = (unsigned char)(fabs(J) > I.dx * I.dx * len * S[8 * SE + o]);
   }
 }

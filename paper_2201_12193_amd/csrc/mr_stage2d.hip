@@ -88,23 +88,25 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
     const int x = tl.x0 - 1 + cs;
     const bool outx = cs >= 1 && cs <= CW - 2 && x < I.nx;
     /* staged element q of this thread in every row step: plane and folded
-       column as one element offset (A planes: bit 30 set), and whether it is
-       a first moment of a transmissive x ghost (reads as zero) */
+       column as one element offset (A planes: bit 30 set); whether it is a
+       first moment of a transmissive x ghost (reads as zero) or flips sign
+       as a reflective x ghost; whether it is a first moment, and whether it
+       flips in a reflective y ghost row */
     int soff[NE];
-    unsigned szero = 0u, sfm = 0u;
+    unsigned szero = 0u, sfm = 0u, sneg = 0u, syflip = 0u;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
       const int e = min(tid + q * MR_BLOCK, NP * XW - 1);
       const int pl = e / XW, col = e % XW;
       const bool isA = pl < 2 * NC;
       const int c = isA ? pl / 2 : pl - 2 * NC, m = isA ? (pl % 2) * 2 : 1;
-      const int i = xs0 + col;
-      const bool ox = i < 0 || i >= I.nx;
-      int ii = I.bcx == 0 ? (i < 0 ? i + I.nx : (i >= I.nx ? i - I.nx : i)) : i;
-      ii = min(max(ii, 0), I.nx - 1);
+      int kx = 0;
+      const int ii = mr_fold(xs0 + col, I.nx, I.bcx, &kx);
       soff[q] = ((c * 3 + m) * (int)P + ii) | (isA ? (1 << 30) : 0);
       if (m != 0) sfm |= 1u << q;
-      if (m != 0 && ox && I.bcx != 0) szero |= 1u << q;
+      if (m != 0 && kx == 1) szero |= 1u << q;
+      if (kx == 2 && mr_refl_flip(c, m, 0)) sneg |= 1u << q;
+      if (mr_refl_flip(c, m, 1)) syflip |= 1u << q;
     }
     /* ---- prologue: A rows y0-3 .. y0+1, B and flag rows y0-2 .. y0 ---- */
     for (int r = tl.y0 - 3; r <= tl.y0 - 2; ++r)
@@ -126,27 +128,24 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
       /* prefetch A row y+3, B and flag row y+2 (stored once rows y-2 and
          y-1 are consumed) */
       double pre[NE];
-      unsigned pzero = 0u;   /* elements that read as zero (applied when stored) */
+      unsigned pzero = 0u, pneg = 0u;   /* elements that read as zero / flip (applied when stored) */
       unsigned char pref = 0;
       {
         /* row folds are uniform over the work group */
-        int jA = y + 3, jB = y + 2;
-        const bool oyA = jA < 0 || jA >= I.ny, oyB = jB < 0 || jB >= I.ny;
-        if (I.bcy == 0) {
-          jA = jA < 0 ? jA + I.ny : (jA >= I.ny ? jA - I.ny : jA);
-          jB = jB < 0 ? jB + I.ny : (jB >= I.ny ? jB - I.ny : jB);
-        }
-        jA = min(max(jA, 0), I.ny - 1) * I.nx;
-        jB = min(max(jB, 0), I.ny - 1) * I.nx;
-        const bool zyA = oyA && I.bcy != 0, zyB = oyB && I.bcy != 0;
+        int kA = 0, kB = 0;
+        const int jA = mr_fold(y + 3, I.ny, I.bcy, &kA) * I.nx;
+        const int jB = mr_fold(y + 2, I.ny, I.bcy, &kB) * I.nx;
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
           const int o = soff[q];
           const bool isA = (o >> 30) & 1;
           const int off = (o & ((1 << 30) - 1)) + (isA ? jA : jB);
           pre[q] = g.U[off];
-          /* first moments of transmissive ghosts are zero */
-          if (((szero >> q) & 1u) || (((sfm >> q) & 1u) && (isA ? zyA : zyB))) pzero |= 1u << q;
+          const int ky = isA ? kA : kB;
+          /* first moments of transmissive ghosts are zero; reflective ghosts
+             flip the moments mr_refl_flip names */
+          if (((szero >> q) & 1u) || (((sfm >> q) & 1u) && ky == 1)) pzero |= 1u << q;
+          if (((sneg >> q) & 1u) != (ky == 2 && ((syflip >> q) & 1u))) pneg |= 1u << q;
         }
       }
       if (tid < XW) pref = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + tid, y + 2);
@@ -203,7 +202,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
         for (int q = 0; q < NE; ++q) {
           const int e = tid + q * MR_BLOCK;
           if (e < NP * XW) {
-            const double v = ((pzero >> q) & 1u) ? 0.0 : pre[q];
+            const double v = ((pzero >> q) & 1u) ? 0.0 : (((pneg >> q) & 1u) ? -pre[q] : pre[q]);
             if (e / XW < 2 * NC) sh.mA[sa][e / XW][e % XW] = v;
             else sh.mB[sb][e / XW - 2 * NC][e % XW] = v;
           }

@@ -24,7 +24,7 @@ struct mr_inst {
   /* ---- static ---- */
   int dim, nx, ny, nc;
   int flux;         /* 0 = Burgers + Lax-Friedrichs, 1 = Euler + HLLC          */
-  int bcx, bcy;     /* 0 = periodic, 1 = transmissive                          */
+  int bcx, bcy;     /* 0 = periodic, 1 = transmissive, 2 = reflective wall      */
   int tc;           /* 0 none, 1 KXRCF, 2 all cells, 3 learned, 4 TVB minmod    */
   int beta_on;      /* 0 = q_l, 1 = p_l                                        */
   int charwise;     /* 1D Euler: Step 1 on characteristic fields               */

@@ -26,6 +26,7 @@ BURGERS = 0
 EULER = 1
 PERIODIC = 0
 TRANSMISSIVE = 1
+REFLECTIVE = 2   # Euler: mirror-image ghosts (wall-normal momentum and normal first moment flip)
 TC_NONE = 0     # HWENO6: no first-moment modification
 TC_KXRCF = 1    # HWENO6-M5-I
 TC_ALL = 2      # HWENO6-M5-NI

@@ -37,7 +37,8 @@ def test_workspace_bytes_validates_problems():
            good.replace(tc_mode=7), I.Problem(dim=1, nx=64, gamma=1.0),
            good.replace(modification=3), good.replace(tvb_m=-1.0), good.replace(tvb_m=float("nan")),
            good.replace(charwise=1),                                  # characteristic-wise: 1D Euler only
-           I.Problem(dim=1, nx=64, system=I.BURGERS, charwise=1), I.Problem(dim=1, nx=64, charwise=2)]
+           I.Problem(dim=1, nx=64, system=I.BURGERS, charwise=1), I.Problem(dim=1, nx=64, charwise=2),
+           I.Problem(dim=1, nx=64, system=I.BURGERS, bc_x=I.REFLECTIVE), good.replace(bc_y=3)]
     for b in bad:
         assert M.workspace_bytes([b]) == 0, b
     assert M.workspace_bytes([good, bad[0]]) == 0

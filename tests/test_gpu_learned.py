@@ -106,7 +106,7 @@ def test_mfma_gemm_matches_fp64(M, N, K, trans):
     assert np.all(np.abs(C - ref) <= bound + 1e-30)
 
 
-@pytest.mark.parametrize("bc", [I.PERIODIC, I.TRANSMISSIVE])
+@pytest.mark.parametrize("bc", [I.PERIODIC, I.TRANSMISSIVE, I.REFLECTIVE])
 def test_features_match_oracle(bc):
     import torch
     from paper_2201_12193_amd.mrhweno import Solver
@@ -227,11 +227,13 @@ def test_adam_matches_oracle():
 
 
 # ------------------------------------------------------------- fused path
-def test_indicator_decisions_and_flags():
+@pytest.mark.parametrize("bc", [I.PERIODIC, I.REFLECTIVE])
+def test_indicator_decisions_and_flags(bc):
     """Fused inference decisions against the training forward pass (same
-    BF16 arithmetic) and the FP64 reference; band cells get the KXRCF flag."""
+    BF16 arithmetic) and the FP64 reference; band cells get the KXRCF flag.
+    Reflective walls exercise the fused kernel's mirrored ghost staging."""
     import torch
-    prob, U = _state(seed=31, n=64, steps=2)
+    prob, U = _state(seed=31, n=64, bc=bc, steps=2)
     P = _centred_params(prob, U)
     lo, hi = 0.3, 0.7
     s, Ut, pl = _learned_solver(prob, U, P, lo, hi)

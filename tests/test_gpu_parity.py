@@ -212,6 +212,65 @@ def test_charwise_1d_parity(tc):
     s.close()
 
 
+def _reflective_cases():
+    out = []
+    n = 400
+    # Example 3.7's blast waves between walls; the component-wise reconstruction
+    # drives the pressure negative within two steps (in the oracle too), the
+    # characteristic-wise one keeps it positive.
+    prob = I.Problem(dim=1, nx=n, system=I.EULER, bc_x=I.REFLECTIVE, tc_mode=I.TC_KXRCF,
+                     charwise=1)
+    x = (np.arange(n) + 0.5) / n
+    U = np.zeros(prob.shape())
+    U[0, 0] = 1.0
+    U[2, 0] = np.where(x < 0.1, 1e3, np.where(x < 0.9, 1e-2, 1e2)) / 0.4
+    out.append(("blast1d_reflective", prob, U))
+    prob, U, _ = I.euler_quadrants_2d(seed=7, n=70, nq=2)
+    out.append(("euler2d_walls", prob.replace(bc_x=I.REFLECTIVE, bc_y=I.REFLECTIVE), U))
+    out.append(("euler2d_channel", prob.replace(bc_x=I.PERIODIC, bc_y=I.REFLECTIVE), U))
+    out.append(("euler2d_mixed", prob.replace(bc_x=I.TRANSMISSIVE, bc_y=I.REFLECTIVE), U))
+    return out
+
+
+REFL = _reflective_cases()
+
+
+@pytest.mark.parametrize("name,prob,U", REFL, ids=[c[0] for c in REFL])
+def test_reflective_walls_parity(name, prob, U):
+    """Reflective walls (mirror-image ghosts): values, flags, residual and
+    steps against the oracle, plus mass and energy conservation between
+    walls."""
+    import torch
+    U = _advance_oracle(prob, U, 3 if prob.dim == 2 else 10)
+    s, Ut = _solver(prob, U)
+    Uin = torch.from_numpy(U).to(_dev())
+    R, fl = s.residual(0, Uin)
+    gl, _ = s.reconstruct(0, Uin)
+    R, fl, gl = R.cpu().numpy(), fl.cpu().numpy(), gl.cpu().numpy()
+    Lref, flref = oracle.residual(prob, U)
+    glref, _, num, den = oracle.reconstruct(prob, U)
+    bad, ties = flag_mismatch(fl, flref, num, den)
+    assert bad == 0 and ties <= 2, (bad, ties)
+    sc = comp_scale(prob, U)
+    dt = oracle.dt(prob, U)
+    assert (np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc).max() <= TOL
+    assert (np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)).max() <= TOL
+    prev = U.copy()
+    for k in range(6 if prob.dim == 1 else 2):
+        s.step(1)
+        d = s.last_dt()[0]
+        s.sync()
+        got = Ut.cpu().numpy()
+        e = rel_state_err(prob, got, oracle.rk3_step(prob, prev, d), sc)
+        assert e <= TOL, (k, e)
+        prev = got
+    if prob.bc_x == I.REFLECTIVE:   # closed in x (and y): no mass or energy leaves
+        m0, m1 = U[0, 0].sum(), prev[0, 0].sum()
+        e0, e1 = U[-1, 0].sum(), prev[-1, 0].sum()
+        assert abs(m1 - m0) <= 1e-12 * m0 and abs(e1 - e0) <= 1e-12 * e0
+    s.close()
+
+
 def test_dt_bitwise_and_time_clipping():
     prob, U, _ = I.burgers_smooth_1d(seed=11, n=200)
     s, Ut = _solver(prob, U)
