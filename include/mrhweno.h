@@ -64,8 +64,43 @@ typedef enum { MRHWENO_BURGERS_LF = 0, MRHWENO_EULER_HLLC = 1 } mrhweno_flux;
  * boundary cell's averages with zero first moments; REFLECTIVE (Euler only)
  * ghosts are the mirror images of the interior cells across the wall: the
  * wall-normal momentum and the first moment along the normal change sign
- * (a moment flips when exactly one of the two applies). */
-typedef enum { MRHWENO_BC_PERIODIC = 0, MRHWENO_BC_TRANSMISSIVE = 1, MRHWENO_BC_REFLECTIVE = 2 } mrhweno_bc;
+ * (a moment flips when exactly one of the two applies); at a wall face the
+ * two traces carry opposite normal velocities, so the KXRCF test never
+ * counts it as an inflow face.  SIDES: each end of the axis takes its own
+ * data from mrhweno_problem.side (not with the learned indicator). */
+typedef enum {
+  MRHWENO_BC_PERIODIC = 0,
+  MRHWENO_BC_TRANSMISSIVE = 1,
+  MRHWENO_BC_REFLECTIVE = 2,
+  MRHWENO_BC_SIDES = 3
+} mrhweno_bc;
+/* Kind of one end of an axis whose bc is SIDES.  INFLOW ghosts hold a
+ * prescribed constant state: average = state, first moments zero (e.g. the
+ * post-shock inflow of the double Mach reflection, Example 3.9). */
+typedef enum {
+  MRHWENO_SIDE_TRANSMISSIVE = 1,
+  MRHWENO_SIDE_REFLECTIVE = 2,
+  MRHWENO_SIDE_INFLOW = 3
+} mrhweno_side_kind;
+/* Boundary data of one side: side[0] left, [1] right, [2] bottom, [3] top.
+ * On the bottom and top sides a front may split the ghost cells: with
+ * front = 1, a ghost whose centre (x, y) has x < split[0] + split[1] t +
+ * split[2] y holds `pre` (a straight front moving at constant speed,
+ * sampled at ghost centres; t = t^n, t^n + dt, t^n + dt/2 in the three
+ * SSP-RK3 stages), the others follow `kind` -- e.g. the exact motion of the
+ * Mach 10 shock along the top of the double Mach reflection, or the
+ * post-shock part of its bottom.  A ghost outside in both directions takes
+ * the bottom/top side's prescribed state if that side prescribes one
+ * there, else the left/right side's, else folds in both directions.  A
+ * reflective side's face is a wall only where the ghost across it holds no
+ * prescribed state. */
+typedef struct {
+  int kind;                /* mrhweno_side_kind                                  */
+  int front;               /* 1: the front applies (bottom and top sides only)  */
+  double state[4];         /* INFLOW: conserved state (first ncomp entries)      */
+  double pre[4];           /* state of the ghosts before the front               */
+  double split[3];         /* front: s0, st, sn                                  */
+} mrhweno_side;
 /* Step 2 variants named as in the paper's Sec. 3: HWENO6 (no
  * modification), HWENO6-M5-I (KXRCF-flagged cells), HWENO6-M5-NI (every
  * cell).  LEARNED (2D Euler only; not part of the paper) takes the
@@ -120,6 +155,7 @@ typedef struct {
                               average (left eigenvectors project the stencil
                               moments, right ones map the values back); 0 =
                               component by component, as the paper does     */
+  mrhweno_side side[4];    /* per-side data of an axis whose bc is SIDES       */
 } mrhweno_problem;
 
 /* Device workspace needed for n instances (bytes, 256-byte aligned pieces).

@@ -12,6 +12,7 @@ or the mathematics fixes.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from typing import Optional, Tuple
@@ -48,7 +49,10 @@ class _Prob(C.Structure):
                 ("bc_x", C.c_int), ("bc_y", C.c_int), ("tc_mode", C.c_int), ("beta_on", C.c_int),
                 ("dx", C.c_double), ("dy", C.c_double), ("gamma", C.c_double),
                 ("gbar", C.c_double * 4), ("eps", C.c_double), ("tvb_m", C.c_double),
-                ("charwise", C.c_int)]
+                ("charwise", C.c_int),
+                ("x0", C.c_double), ("y0", C.c_double), ("t", C.c_double),
+                ("side_kind", C.c_int * 4), ("side_state", C.c_double * 16),
+                ("side_pre", C.c_double * 16), ("side_split", C.c_double * 12)]
 
 
 _lib = None
@@ -77,6 +81,8 @@ def lib():
         L.orc_dt.argtypes = [P, D, C.c_double]
         L.orc_dt.restype = C.c_double
         L.orc_rk3_step.argtypes = [P, D, C.c_double, B]
+        L.orc_moment.argtypes = [P, D, C.c_int, C.c_int, C.c_int, C.c_int]
+        L.orc_moment.restype = C.c_double
         L.orc_rk3_step_p.argtypes = [P, D, C.c_double, B, C.c_int]
         L.orc_modify.argtypes = [P, D, B, D]
         L.orc_residual_cell_2d.argtypes = [P, D, C.c_double, C.c_int, C.c_int, D]
@@ -99,7 +105,8 @@ def _bp(a: Optional[np.ndarray]):
     return a.ctypes.data_as(C.POINTER(C.c_ubyte))
 
 
-def cprob(prob) -> _Prob:
+def cprob(prob, t: float = 0.0) -> _Prob:
+    """The oracle's problem struct; t is the time of the boundary data."""
     p = _Prob()
     p.dim, p.nx, p.ny = prob.dim, prob.nx, (prob.ny if prob.dim == 2 else 1)
     p.system, p.bc_x, p.bc_y = prob.system, prob.bc_x, prob.bc_y
@@ -110,6 +117,23 @@ def cprob(prob) -> _Prob:
         p.gbar[k] = prob.gbar[k]
     p.tvb_m = getattr(prob, "tvb_m", 0.0)
     p.charwise = getattr(prob, "charwise", 0)
+    p.x0, p.y0, p.t = prob.x0, prob.y0, float(t)
+    for k in range(4):
+        p.side_split[3 * k] = -math.inf
+    sides = getattr(prob, "sides", None)
+    if sides is not None:
+        for k, sd in enumerate(sides):
+            if sd is None:
+                continue
+            if k < 2 and sd.split[0] != -math.inf:
+                raise ValueError("a split is defined on the bottom and top sides only")
+            p.side_kind[k] = sd.kind
+            for c in range(len(sd.state)):
+                p.side_state[4 * k + c] = sd.state[c]
+            for c in range(len(sd.pre)):
+                p.side_pre[4 * k + c] = sd.pre[c]
+            for q in range(3):
+                p.side_split[3 * k + q] = sd.split[q]
     return p
 
 
@@ -185,16 +209,17 @@ def hllc(uL, uR, gamma: float, direction: int = 0) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- whole grid
-def residual(prob, U) -> Tuple[np.ndarray, np.ndarray]:
-    """L(U) and the troubled-cell flags of the interior."""
+def residual(prob, U, t: float = 0.0) -> Tuple[np.ndarray, np.ndarray]:
+    """L(U) and the troubled-cell flags of the interior (boundary data at
+    time t)."""
     U = _arr(U).reshape(prob.shape())
     L = np.zeros_like(U)
     flags = np.zeros(prob.ncell, dtype=np.uint8)
-    lib().orc_residual(C.byref(cprob(prob)), _dp(U), _dp(L), _bp(flags))
+    lib().orc_residual(C.byref(cprob(prob, t)), _dp(U), _dp(L), _bp(flags))
     return L, flags.reshape(prob.shape()[2:])
 
 
-def residual_given(prob, U, flags_ext) -> np.ndarray:
+def residual_given(prob, U, flags_ext, t: float = 0.0) -> np.ndarray:
     """2D L(U) with the troubled-cell map of cells [-2, n+2)^2 supplied as a
     (ny+4, nx+4) uint8 array instead of Step 2.1."""
     U = _arr(U).reshape(prob.shape())
@@ -202,12 +227,12 @@ def residual_given(prob, U, flags_ext) -> np.ndarray:
     if prob.dim != 2 or fe.shape != (prob.ny + 4, prob.nx + 4):
         raise ValueError("2D problem and a (ny+4, nx+4) flag map required")
     L = np.zeros_like(U)
-    if lib().orc_residual_given(C.byref(cprob(prob)), _dp(U), _bp(fe), _dp(L)) != 0:
+    if lib().orc_residual_given(C.byref(cprob(prob, t)), _dp(U), _bp(fe), _dp(L)) != 0:
         raise RuntimeError("orc_residual_given failed")
     return L
 
 
-def reconstruct(prob, U):
+def reconstruct(prob, U, t: float = 0.0):
     """Final Gauss-Lobatto values (1D [comp][4][nx], 2D [comp][16][ny][nx]),
     flags, and the KXRCF numerator and denominator."""
     U = _arr(U).reshape(prob.shape())
@@ -216,9 +241,16 @@ def reconstruct(prob, U):
     flags = np.zeros(prob.ncell, dtype=np.uint8)
     num = np.zeros(prob.ncell)
     den = np.zeros(prob.ncell)
-    lib().orc_reconstruct(C.byref(cprob(prob)), _dp(U), _dp(gl), _bp(flags), _dp(num), _dp(den))
+    lib().orc_reconstruct(C.byref(cprob(prob, t)), _dp(U), _dp(gl), _bp(flags), _dp(num), _dp(den))
     sh = prob.shape()[2:]
     return gl, flags.reshape(sh), num.reshape(sh), den.reshape(sh)
+
+
+def moment(prob, U, c: int, m: int, i: int, j: int = 0, t: float = 0.0) -> float:
+    """Moment m of component c at cell (i, j), ghost cells included, with
+    the boundary data at time t."""
+    U = _arr(U).reshape(prob.shape())
+    return float(lib().orc_moment(C.byref(cprob(prob, t)), _dp(U), c, m, i, j))
 
 
 def wave_speeds(prob, U) -> Tuple[float, float]:
@@ -239,45 +271,46 @@ def dt(prob, U, cfl: Optional[float] = None) -> float:
 _PERSIST = {0: 1, 1: 0, 2: 2}
 
 
-def rk3_step(prob, U, dt_: float, want_flags: bool = False, persist: Optional[int] = None):
-    """One SSP-RK3 step; returns U^{n+1} (and the flags of the 3 stages).
-    persist defaults to the problem's modification placement."""
+def rk3_step(prob, U, dt_: float, want_flags: bool = False, persist: Optional[int] = None,
+             t: float = 0.0):
+    """One SSP-RK3 step from time t; returns U^{n+1} (and the flags of the
+    3 stages).  persist defaults to the problem's modification placement."""
     if persist is None:
         persist = _PERSIST[getattr(prob, "modification", 0)]
     U = _arr(U).reshape(prob.shape()).copy()
     flags = np.zeros(3 * prob.ncell, dtype=np.uint8) if want_flags else None
-    lib().orc_rk3_step_p(C.byref(cprob(prob)), _dp(U), dt_, _bp(flags), persist)
+    lib().orc_rk3_step_p(C.byref(cprob(prob, t)), _dp(U), dt_, _bp(flags), persist)
     if want_flags:
         return U, flags.reshape((3,) + prob.shape()[2:])
     return U
 
 
-def residual_cell_2d(prob, U, i: int, j: int, alpha: float = 0.0) -> np.ndarray:
+def residual_cell_2d(prob, U, i: int, j: int, alpha: float = 0.0, t: float = 0.0) -> np.ndarray:
     """L(U) at one cell of a 2D grid, recomputed from scratch (for sampling)."""
     out = np.zeros((prob.ncomp, 3))
-    lib().orc_residual_cell_2d(C.byref(cprob(prob)), _dp(U), alpha, i, j, _dp(out))
+    lib().orc_residual_cell_2d(C.byref(cprob(prob, t)), _dp(U), alpha, i, j, _dp(out))
     return out
 
 
-def modify(prob, U, flags) -> np.ndarray:
+def modify(prob, U, flags, t: float = 0.0) -> np.ndarray:
     """Stage input with troubled cells' first moments replaced (Step 2.2)."""
     U = _arr(U).reshape(prob.shape())
     fl = np.ascontiguousarray(np.asarray(flags, dtype=np.uint8).ravel())
     out = np.zeros_like(U)
-    lib().orc_modify(C.byref(cprob(prob)), _dp(U), _bp(fl), _dp(out))
+    lib().orc_modify(C.byref(cprob(prob, t)), _dp(U), _bp(fl), _dp(out))
     return out
 
 
 def run(prob, U, t_final: Optional[float] = None, max_steps: int = 10 ** 9, dt_fn=None,
-        persist: Optional[int] = None):
-    """March to t_final with the CFL time step (clipped at t_final)."""
+        persist: Optional[int] = None, t0: float = 0.0):
+    """March from t0 to t_final with the CFL time step (clipped at t_final)."""
     T = prob.t_final if t_final is None else t_final
     U = _arr(U).reshape(prob.shape()).copy()
-    t, steps = 0.0, 0
+    t, steps = t0, 0
     while t < T and steps < max_steps:
         d = dt(prob, U) if dt_fn is None else dt_fn(prob, U)
         d = min(d, T - t)
-        U = rk3_step(prob, U, d, persist=persist)
+        U = rk3_step(prob, U, d, persist=persist, t=t)
         t += d
         steps += 1
     return U, t, steps

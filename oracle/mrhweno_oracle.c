@@ -56,6 +56,20 @@
  *       traces carry opposite normal velocities, so their average is zero
  *       and the face is never an inflow face of the KXRCF sum; it is set
  *       to zero rather than left to the sign of a rounding residue.
+ *   R17 per-side boundary data (bc = 3; the double Mach reflection of
+ *       Example 3.9 needs it): each side is transmissive, reflective or
+ *       inflow.  An inflow ghost holds a prescribed constant state, so its
+ *       average is that state and its first moments are zero.  The bottom
+ *       and top sides may prescribe a second state on the ghosts whose
+ *       centre has tangential coordinate tau < s0 + st t + sn nu (nu: the
+ *       normal coordinate of the centre), a straight front moving at a
+ *       constant speed, sampled at cell centres (the paper gives no rule
+ *       for cut ghost cells) at the time of the stage: t^n, t^n + dt and
+ *       t^n + dt/2 in SSP-RK3.  A ghost outside in both directions takes
+ *       the bottom or top side's prescribed state if that side prescribes
+ *       one there, else the left or right side's, else folds in both
+ *       directions.  A reflective side's face is a wall (R16) only where
+ *       the ghost across it is not prescribed.
  *   R15 characteristic-wise Step 1 (1D Euler, charwise = 1; the paper
  *       reconstructs component by component, R2): for target cell i the
  *       stencil moments of every cell are projected with the left
@@ -91,7 +105,8 @@ typedef struct {
   int dim;        /* 1 or 2                                                  */
   int nx, ny;     /* cells; ny = 1 in 1D                                     */
   int system;     /* 0 = scalar Burgers + Lax-Friedrichs, 1 = Euler + HLLC   */
-  int bc_x, bc_y; /* 0 = periodic, 1 = transmissive, 2 = reflective wall (R16) */
+  int bc_x, bc_y; /* 0 = periodic, 1 = transmissive, 2 = reflective wall (R16),
+                     3 = per-side data (R17)                                 */
   int tc_mode;    /* 0 = no modification (HWENO6), 1 = KXRCF (M5-I),
                      2 = modify every cell (M5-NI), 4 = TVB minmod indicator */
   int beta_on;    /* 0 = beta on q_l (R1), 1 = beta on p_l as printed       */
@@ -101,6 +116,14 @@ typedef struct {
   double eps;     /* 1e-10 in eq. (w1_-LR) and eq. (non-linear-weight)       */
   double tvb_m;   /* TVB constant M of the minmod indicator (tc_mode 4)      */
   int charwise;   /* 1D Euler: Step 1 on characteristic fields (R15)         */
+  /* per-side boundary data, used on an axis whose bc is 3 (R17)             */
+  double x0, y0;            /* lower-left corner of the domain              */
+  double t;                 /* time of the boundary data                    */
+  int side_kind[4];         /* sides 0 left, 1 right, 2 bottom, 3 top:
+                               1 transmissive, 2 reflective, 3 inflow       */
+  double side_state[4][4];  /* inflow state (conserved variables)           */
+  double side_pre[4][4];    /* state of the ghosts before the split         */
+  double side_split[4][3];  /* s0, st, sn of the split (bottom and top)     */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -692,6 +715,30 @@ static double lf_flux(double a, double b, double alpha) {
 /* ======================================================================== */
 typedef struct { const orc_problem* P; const double* U; int nc, nm; } grid_t;
 
+/* kind of side s (0 left, 1 right, 2 bottom, 3 top): 0 periodic,
+   1 transmissive, 2 reflective, 3 inflow */
+static int side_kind(const orc_problem* P, int s) {
+  int bc = s < 2 ? P->bc_x : P->bc_y;
+  return bc == 3 ? P->side_kind[s] : bc;
+}
+
+/* Prescribed state of component c in the ghost cell (i, j), R17: returns 1
+   and sets *val if the cell takes one. */
+static int prescribed(const orc_problem* P, int c, int i, int j, double* val) {
+  if (P->dim == 2 && (j < 0 || j >= P->ny) && P->bc_y == 3) {
+    int s = j < 0 ? 2 : 3;
+    double tau = P->x0 + (i + 0.5) * P->dx, nu = P->y0 + (j + 0.5) * P->dy;
+    const double* sp = P->side_split[s];
+    if (tau < sp[0] + sp[1] * P->t + sp[2] * nu) { *val = P->side_pre[s][c]; return 1; }
+    if (P->side_kind[s] == 3) { *val = P->side_state[s][c]; return 1; }
+  }
+  if ((i < 0 || i >= P->nx) && P->bc_x == 3) {
+    int s = i < 0 ? 0 : 1;
+    if (P->side_kind[s] == 3) { *val = P->side_state[s][c]; return 1; }
+  }
+  return 0;
+}
+
 /* Moment m of component c at cell (i, j), any integer (i, j).  A
    reflective ghost is the mirror image of the interior cell across the
    wall: the momentum normal to the wall and the first moment along the
@@ -700,9 +747,13 @@ typedef struct { const orc_problem* P; const double* U; int nc, nm; } grid_t;
 static double mom(const grid_t* G, int c, int m, int i, int j) {
   const orc_problem* P = G->P;
   int zero = 0, flip = 0;
+  double pv;
+  if ((i < 0 || i >= P->nx || (P->dim == 2 && (j < 0 || j >= P->ny))) && prescribed(P, c, i, j, &pv))
+    return m == 0 ? pv : 0.0;
   if (i < 0 || i >= P->nx) {
-    if (P->bc_x == 0) i = ((i % P->nx) + P->nx) % P->nx;
-    else if (P->bc_x == 1) { zero = 1; i = i < 0 ? 0 : P->nx - 1; }
+    const int k = side_kind(P, i < 0 ? 0 : 1);
+    if (k == 0) i = ((i % P->nx) + P->nx) % P->nx;
+    else if (k != 2) { zero = 1; i = i < 0 ? 0 : P->nx - 1; }
     else {
       i = i < 0 ? -1 - i : 2 * P->nx - 1 - i;
       i = i < 0 ? 0 : (i >= P->nx ? P->nx - 1 : i);
@@ -710,8 +761,9 @@ static double mom(const grid_t* G, int c, int m, int i, int j) {
     }
   }
   if (P->dim == 2 && (j < 0 || j >= P->ny)) {
-    if (P->bc_y == 0) j = ((j % P->ny) + P->ny) % P->ny;
-    else if (P->bc_y == 1) { zero = 1; j = j < 0 ? 0 : P->ny - 1; }
+    const int k = side_kind(P, j < 0 ? 2 : 3);
+    if (k == 0) j = ((j % P->ny) + P->ny) % P->ny;
+    else if (k != 2) { zero = 1; j = j < 0 ? 0 : P->ny - 1; }
     else {
       j = j < 0 ? -1 - j : 2 * P->ny - 1 - j;
       j = j < 0 ? 0 : (j >= P->ny ? P->ny - 1 : j);
@@ -736,9 +788,18 @@ static double modified_v1(const grid_t* G, int c, int i) {
   return s;
 }
 
-/* face f of an axis with n cells and boundary condition bc (the face
-   between cells f-1 and f) is a reflective wall (R16) */
-static int wall_face(int f, int n, int bc) { return bc == 2 && (f == 0 || f == n); }
+/* the x face f of row j (between cells (f-1, j) and (f, j)), or the y face
+   f of column i, is a reflective wall (R16, R17) */
+static int wall_x(const orc_problem* P, int f, int j) {
+  double pv;
+  if (f != 0 && f != P->nx) return 0;
+  return side_kind(P, f == 0 ? 0 : 1) == 2 && !prescribed(P, 0, f == 0 ? -1 : P->nx, j, &pv);
+}
+static int wall_y(const orc_problem* P, int i, int f) {
+  double pv;
+  if (P->dim != 2 || (f != 0 && f != P->ny)) return 0;
+  return side_kind(P, f == 0 ? 2 : 3) == 2 && !prescribed(P, 0, i, f == 0 ? -1 : P->ny, &pv);
+}
 
 /* velocity used by the KXRCF indicator at a point (Remark 2) */
 static double kx_velocity(const orc_problem* P, const double* upt, int dir) {
@@ -841,11 +902,11 @@ static void op1d_values(const orc_problem* P, const double* U, work1_t* W) {
       double ptO[4] = {0, 0, 0, 0}, ptN[4] = {0, 0, 0, 0};
       /* left face x_{i-1/2}: u^+ = own left value, u^- = left neighbour's right value */
       for (int c = 0; c < nc; ++c) { ptO[c] = own[c * 4 + 0]; ptN[c] = lef[c * 4 + 3]; }
-      double vl = wall_face(i, P->nx, P->bc_x) ? 0.0 : 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
+      double vl = wall_x(P, i, 0) ? 0.0 : 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
       double jl = ptO[0] - ptN[0];
       /* right face x_{i+1/2}: u^- = own right value, u^+ = right neighbour's left value */
       for (int c = 0; c < nc; ++c) { ptO[c] = own[c * 4 + 3]; ptN[c] = rig[c * 4 + 0]; }
-      double vr = wall_face(i + 1, P->nx, P->bc_x) ? 0.0 : 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
+      double vr = wall_x(P, i + 1, 0) ? 0.0 : 0.5 * (kx_velocity(P, ptO, 0) + kx_velocity(P, ptN, 0));
       double jr = ptO[0] - ptN[0];
       double J = jl * (vl > 0.0 ? 1.0 : 0.0) + jr * (-vr > 0.0 ? 1.0 : 0.0);
       double nrm = 0.0;
@@ -1001,7 +1062,7 @@ static void kxrcf_2d(const orc_problem* P, const work2_t* W, int wi, int wj, int
       vel += gl_weight(m) * 0.5 * (kx_velocity(P, ptO, dir) + kx_velocity(P, ptN, dir));
     }
     /* a reflective wall face carries no normal velocity (R16) */
-    if (dir == 0 ? wall_face(i + (f == 1), P->nx, P->bc_x) : wall_face(j + (f == 3), P->ny, P->bc_y)) vel = 0.0;
+    if (dir == 0 ? wall_x(P, i + (f == 1), j) : wall_y(P, i, j + (f == 3))) vel = 0.0;
     /* inflow: left/bottom if v > 0, right/top if v < 0 (sf of the printed signs) */
     double arg = (f == 0 || f == 2) ? vel : -vel;
     if (arg > 0.0) { J += jump; len += flen; }
@@ -1172,6 +1233,13 @@ static void residual_2d(const orc_problem* P, const double* U, double* L, unsign
 /* ======================================================================== */
 int orc_ncomp(const orc_problem* P) { return ncomp_of(P); }
 
+/* Moment m of component c at any cell (i, j), ghost cells included, with
+   the boundary data at time P->t. */
+double orc_moment(const orc_problem* P, const double* U, int c, int m, int i, int j) {
+  grid_t G = {P, U, ncomp_of(P), P->dim + 1};
+  return mom(&G, c, m, i, j);
+}
+
 /* L(U); flags (optional) receive the troubled-cell map of the interior. */
 int orc_residual(const orc_problem* P, const double* U, double* L, unsigned char* flags) {
   if (P->dim == 1) residual_1d(P, U, L, flags);
@@ -1303,15 +1371,22 @@ int orc_rk3_step_p(const orc_problem* P, double* U, double dt, unsigned char* fl
   double* Ut = malloc(n * sizeof(double));
   double* Un = malloc(n * sizeof(double));
   unsigned char* fl = malloc(cells);
+  /* boundary data at the stage times t^n, t^n + dt, t^n + dt/2 (R17) */
+  orc_problem S0 = *P, S1 = *P, S2 = *P;
+  S1.t = P->t + dt;
+  S2.t = P->t + 0.5 * dt;
+  P = &S0;
   orc_residual(P, U, L, fl);
   if (flags) memcpy(flags, fl, cells);
   if (persist) orc_modify(P, U, fl, Ut); else memcpy(Ut, U, n * sizeof(double));
   if (persist == 1) memcpy(Un, Ut, n * sizeof(double)); else memcpy(Un, U, n * sizeof(double));
   for (size_t k = 0; k < n; ++k) U1[k] = Ut[k] + dt * L[k];
+  P = &S1;
   orc_residual(P, U1, L, fl);
   if (flags) memcpy(flags + cells, fl, cells);
   if (persist) orc_modify(P, U1, fl, Ut); else memcpy(Ut, U1, n * sizeof(double));
   for (size_t k = 0; k < n; ++k) U2[k] = 3.0 / 4.0 * Un[k] + 1.0 / 4.0 * Ut[k] + 1.0 / 4.0 * dt * L[k];
+  P = &S2;
   orc_residual(P, U2, L, fl);
   if (flags) memcpy(flags + 2 * cells, fl, cells);
   if (persist) orc_modify(P, U2, fl, Ut); else memcpy(Ut, U2, n * sizeof(double));

@@ -87,10 +87,33 @@ std::string validate(const mrhweno_problem& p) {
   if (p.nx < 8 || (p.dim == 2 && p.ny < 8)) return "grid must have at least 8 cells per direction";
   if (!(p.x1 > p.x0) || (p.dim == 2 && !(p.y1 > p.y0))) return "empty domain";
   if (p.flux != MRHWENO_BURGERS_LF && p.flux != MRHWENO_EULER_HLLC) return "unknown flux";
-  if (p.bc_x < 0 || p.bc_x > 2 || (p.dim == 2 && (p.bc_y < 0 || p.bc_y > 2))) return "unknown boundary condition";
-  if ((p.bc_x == MRHWENO_BC_REFLECTIVE || (p.dim == 2 && p.bc_y == MRHWENO_BC_REFLECTIVE)) &&
-      p.flux != MRHWENO_EULER_HLLC)
-    return "reflective walls are for the Euler equations";
+  if (p.bc_x < 0 || p.bc_x > 3 || (p.dim == 2 && (p.bc_y < 0 || p.bc_y > 3))) return "unknown boundary condition";
+  for (int s = 0; s < (p.dim == 2 ? 4 : 2); ++s) {
+    const int bc = s < 2 ? p.bc_x : p.bc_y;
+    const int kind = bc == MRHWENO_BC_SIDES ? p.side[s].kind : bc;
+    if (kind == MRHWENO_BC_REFLECTIVE && p.flux != MRHWENO_EULER_HLLC) return "reflective walls are for the Euler equations";
+    if (bc != MRHWENO_BC_SIDES) continue;
+    const mrhweno_side& sd = p.side[s];
+    if (sd.kind < MRHWENO_SIDE_TRANSMISSIVE || sd.kind > MRHWENO_SIDE_INFLOW) return "unknown side kind";
+    if (sd.front != 0 && sd.front != 1) return "side front must be 0 or 1";
+    if (sd.front && s < 2) return "a front is defined on the bottom and top sides only";
+    for (int q = 0; q < 3; ++q)
+      if (sd.front && !std::isfinite(sd.split[q])) return "side front coefficients must be finite";
+    for (int w = 0; w < 2; ++w) {
+      if (w == 0 ? sd.kind != MRHWENO_SIDE_INFLOW : !sd.front) continue;
+      const double* u = w == 0 ? sd.state : sd.pre;
+      for (int c = 0; c < ncomp_of(p); ++c)
+        if (!std::isfinite(u[c])) return "prescribed side states must be finite";
+      if (p.flux == MRHWENO_EULER_HLLC) {
+        const int nc = ncomp_of(p);
+        double ke = 0.0;
+        for (int c = 1; c < nc - 1; ++c) ke += 0.5 * u[c] * u[c] / u[0];
+        if (!(u[0] > 0.0) || !(u[nc - 1] - ke > 0.0)) return "prescribed side states must have positive density and pressure";
+      }
+    }
+  }
+  if (p.tc_mode == MRHWENO_TC_LEARNED && (p.bc_x == MRHWENO_BC_SIDES || p.bc_y == MRHWENO_BC_SIDES))
+    return "the learned indicator takes no per-side boundary data";
   if (p.flux == MRHWENO_EULER_HLLC && !(p.gamma_gas > 1.0)) return "gamma_gas must exceed 1";
   if (!(p.cfl > 0.0) || !(p.t_final > 0.0)) return "cfl and t_final must be positive";
   for (int l = 0; l < 4; ++l)
@@ -452,7 +475,27 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     mr_inst& I = c->h[q];
     std::memset(&I, 0, sizeof I);
     I.dim = p.dim; I.nx = p.nx; I.ny = p.dim == 2 ? p.ny : 1; I.nc = ncomp_of(p);
-    I.flux = p.flux; I.bcx = p.bc_x; I.bcy = p.dim == 2 ? p.bc_y : 0;
+    I.flux = p.flux;
+    I.x0 = p.x0; I.y0 = p.dim == 2 ? p.y0 : 0.0;
+    /* fold kinds per side (low side in bits 0-1, high side in bits 2-3; an
+       inflow side folds as a transmissive one and its ghosts are then
+       overwritten) and the prescribed-ghost data */
+    int fold[4] = {0, 0, 0, 0};
+    for (int s = 0; s < (p.dim == 2 ? 4 : 2); ++s) {
+      const int bc = s < 2 ? p.bc_x : p.bc_y;
+      const int kind = bc == MRHWENO_BC_SIDES ? p.side[s].kind : bc;
+      fold[s] = kind == MRHWENO_SIDE_INFLOW ? 1 : kind;
+      I.skind[s] = kind;
+      I.ssplit[s][0] = -HUGE_VAL;
+      if (bc != MRHWENO_BC_SIDES) continue;
+      const mrhweno_side& sd = p.side[s];
+      for (int c = 0; c < 4; ++c) { I.sstate[s][c] = sd.state[c]; I.spre[s][c] = sd.pre[c]; }
+      if (sd.front)
+        for (int q = 0; q < 3; ++q) I.ssplit[s][q] = sd.split[q];
+      if (sd.kind == MRHWENO_SIDE_INFLOW || sd.front) I.pres |= 1 << s;
+    }
+    I.bcx = fold[0] | (fold[1] << 2);
+    I.bcy = fold[2] | (fold[3] << 2);
     I.tc = p.tc_mode; I.beta_on = p.beta_on; I.mod = p.modification; I.charwise = p.charwise;
     I.fhalo = kFHalo; I.shalo = kSHalo;
     I.fex = fex(p); I.fey = fey(p); I.sex = sex(p); I.sey = sey(p);

@@ -20,14 +20,63 @@
 template <class T>
 MR_INL MR_GLB T* mr_gp(T* p) { return (MR_GLB T*)p; }
 
+/* Time of the boundary data in stage s of the step (t^n, t^n + dt,
+ * t^n + dt/2), or the current time for a one-off evaluation (s = 3). */
+MR_INL double mr_stage_time(const mr_inst& I, int s) {
+#pragma clang fp contract(off)
+  return s == 0 ? I.t_prev : (s == 1 ? I.t_prev + I.dt : (s == 2 ? I.t_prev + 0.5 * I.dt : I.t));
+}
+
+/* State held by the ghost cell (i, j) at time t if a side prescribes one
+ * (average = state, first moments zero), else null.  The bottom and top
+ * sides prescribe `spre` on the ghosts whose centre has tangential
+ * coordinate below the front s0 + st t + sn nu (nu: normal coordinate of
+ * the centre; a straight front moving at constant speed, sampled at cell
+ * centres) and their inflow state beyond it; they take precedence over the
+ * left and right sides in the corners. */
+MR_INL const double* mr_presc(const mr_inst& I, int i, int j, double t) {
+#pragma clang fp contract(off)
+  if (I.dim == 2 && (j < 0 || j >= I.ny)) {
+    const int s = j < 0 ? 2 : 3;
+    if ((I.pres >> s) & 1) {
+      const double tau = I.x0 + (i + 0.5) * I.dx, nu = I.y0 + (j + 0.5) * I.dy;
+      if (tau < I.ssplit[s][0] + I.ssplit[s][1] * t + I.ssplit[s][2] * nu) return I.spre[s];
+      if (I.skind[s] == 3) return I.sstate[s];
+    }
+  }
+  if (i < 0 || i >= I.nx) {
+    const int s = i < 0 ? 0 : 1;
+    if (((I.pres >> s) & 1) && I.skind[s] == 3) return I.sstate[s];
+  }
+  return nullptr;
+}
+
+/* The x face f of row j (between cells (f-1, j) and (f, j)), or the y face
+ * f of column i, is a reflective wall at time t: the side is reflective and
+ * the ghost across the face holds no prescribed state. */
+MR_INL bool mr_wall_x(const mr_inst& I, int f, int j, double t) {
+  if (!mr_wall(f, I.nx, I.bcx)) return false;
+  return !((I.pres >> (f == 0 ? 0 : 1)) & 1) || !mr_presc(I, f == 0 ? -1 : I.nx, j, t);
+}
+MR_INL bool mr_wall_y(const mr_inst& I, int i, int f, double t) {
+  if (!mr_wall(f, I.ny, I.bcy)) return false;
+  return !((I.pres >> (f == 0 ? 2 : 3)) & 1) || !mr_presc(I, i, f == 0 ? -1 : I.ny, t);
+}
+
 struct mr_grid {
   const MR_GLB double* U;  /* state base: comp c, moment m plane at U + (c*nm + m)*P */
   long long P;
   int nx, ny, bcx, bcy, nm;
+  const mr_inst* I;        /* instance (prescribed ghosts), time of its data */
+  double t;
 };
 
 /* moment m of component c at cell (i, j) with ghost handling */
 MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
+  if ((i < 0 || i >= g.nx || (g.nm == 3 && (j < 0 || j >= g.ny))) && g.I->pres) {
+    const double* st = mr_presc(*g.I, i, j, g.t);
+    if (st) return m == 0 ? st[c] : 0.0;
+  }
   int kx = 0, ky = 0;
   const int ii = mr_fold(i, g.nx, g.bcx, &kx);
   const int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &ky) : 0;

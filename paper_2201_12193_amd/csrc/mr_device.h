@@ -58,14 +58,16 @@ MR_INL double gln(int k) {
 
 /* ------------------------------------------------------------------ ghosts */
 /* Index of the interior cell whose moments cell i (possibly outside
- * [0, n)) takes under the boundary condition bc, with *kind set to 1 for a
+ * [0, n)) takes under the boundary conditions bcs (kind of the low side in
+ * bits 0-1, of the high side in bits 2-3), with *kind set to 1 for a
  * transmissive ghost (average copied, first moments zero) and 2 for a
  * reflective one (mirror image across the wall; see mr_refl_flip); left
  * alone for interior cells and periodic images.  Offsets up to one period
  * either side are folded; anything further is clamped (such cells never
  * feed an output). */
-MR_INL int mr_fold(int i, int n, int bc, int* kind) {
+MR_INL int mr_fold(int i, int n, int bcs, int* kind) {
   if (i >= 0 && i < n) return i;
+  const int bc = i < 0 ? (bcs & 3) : ((bcs >> 2) & 3);
   if (bc == 0) {
     if (i < 0) i += n;
     else i -= n;
@@ -88,7 +90,9 @@ MR_HD bool mr_refl_flip(int c, int m, int a) { return (c == 1 + a) != (m == 1 + 
  * wall.  Its two traces carry opposite normal velocities, so their average
  * is exactly zero: the KXRCF test never counts it as an inflow face (the
  * computed average would only hold a rounding residue of either sign). */
-MR_INL bool mr_wall(int f, int n, int bc) { return bc == 2 && (f == 0 || f == n); }
+MR_INL bool mr_wall(int f, int n, int bcs) {
+  return (f == 0 && (bcs & 3) == 2) || (f == n && ((bcs >> 2) & 3) == 2);
+}
 
 /* 1/x for a positive (or negative) normal x of moderate size: the hardware
  * reciprocal estimate refined by two Newton steps (within about one ulp of

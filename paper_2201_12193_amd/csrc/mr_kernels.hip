@@ -199,7 +199,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
     const int i = e - I.shalo;
-    mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+    mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2, &I, mr_stage_time(I, stage)};
     double r[4];
     double vl, vr;
     if (I.charwise) {
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_ti
     const MR_GLB double* S = mr_gp(I.summ);
     if (I.tc == 4) {
       /* TVB minmod test on the face deviations of the indicator variable */
-      const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+      const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2, &I, mr_stage_time(I, stage)};
       const int i = e - I.fhalo;
       const double ub = mr_ld(g, 0, 0, i, 0);
       const double dp = mr_ld(g, 0, 0, i + 1, 0) - ub, dm = ub - mr_ld(g, 0, 0, i - 1, 0);
@@ -270,7 +270,8 @@ __global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_ti
     const double jr = S[1 * SE + s] - S[0 * SE + s + 1];
     const double vr = 0.5 * (S[3 * SE + s] + S[2 * SE + s + 1]);
     const int i = e - I.fhalo;
-    const bool il = vl > 0.0 && !mr_wall(i, I.nx, I.bcx), ir = -vr > 0.0 && !mr_wall(i + 1, I.nx, I.bcx);
+    const double tb = mr_stage_time(I, stage);
+    const bool il = vl > 0.0 && !mr_wall_x(I, i, 0, tb), ir = -vr > 0.0 && !mr_wall_x(I, i + 1, 0, tb);
     const double J = jl * (il ? 1.0 : 0.0) + jr * (ir ? 1.0 : 0.0);
     const double num = fabs(J);
     const double den = I.dx * I.dx * S[4 * SE + s];
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
     const mr_inst& I = insts[tl.inst];
     if (mode < 3 && !I.active) continue;
     const int st = mode == 3 ? 0 : mode;
-    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, 1, I.bcx, I.bcy, 2, &I, mr_stage_time(I, mode)};
     const MR_GLB unsigned char* fl = mr_gp(I.flags[(mode == 0 || mode == 3) ? 0 : 1]);
     const int x = tl.start - 1 + cs;
     const int fh = I.fhalo;
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
       MR_GLB double* O = mr_gp(I.p_out[st]);
       const long long P = I.plane;
       const double dt = I.dt;
-      const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+      const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, 1, I.bcx, I.bcy, 2, &I, mr_stage_time(I, 0)};
       /* U^n with the stage-1 modification (stored first moments unless it persists) */
       const int f1 = (mode == 1 || mode == 2) && I.mod == 0 ? mr_flag(mr_gp(I.flags[0]), I.fex, 1, fh, x, 0) : 0;
 #pragma unroll
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, con
     const mr_inst& I = insts[tl.inst];
     const int x = tl.start + (int)threadIdx.x;
     if (x >= tl.start + tl.count) continue;
-    const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2};
+    const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2, &I, mr_stage_time(I, 3)};
     const MR_GLB unsigned char* fl = mr_gp(I.flags[0]);
     const int fh = I.fhalo;
     const int f0 = mr_flag(fl, I.fex, 1, fh, x, 0);
@@ -431,7 +432,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_values(mr_inst* insts, con
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
     const int x = e % I.nx, y = e / I.nx;
-    const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, 3)};
     for (int c = 0; c < NC; ++c) {
       double val[16], a, b, d;
       mr2_cell_values<BP>(g, I, mr_gp(I.flags[0]), c, x, y, val, &a, &b, &d);

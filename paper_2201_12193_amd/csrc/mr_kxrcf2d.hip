@@ -109,6 +109,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
     MR_GLB double* aleph = mr_gp(I.aleph);
     const int xs = tl.x0 - 2;              /* staged column 0 */
     const int ylast = tl.y0 + tl.rows;     /* last reconstructed row */
+    const double tb = mr_stage_time(I, stage);
     /* staged element q of this thread in every row: plane offset plus folded
        column; whether it is a first moment (of a transmissive x ghost:
        zero), flips as a reflective x ghost, flips in a reflective y row */
@@ -144,6 +145,19 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
         if (tid + q * MR_BLOCK < NROW)
           d[tid + q * MR_BLOCK] = ((z >> q) & 1u) ? 0.0 : (((z >> (16 + q)) & 1u) ? -v[q] : v[q]);
     };
+    /* ghosts of the stored rows y .. y+nr-1 that hold a prescribed state
+       (average; first moments zero), overwritten by the threads that
+       stored them */
+    auto prescribe = [&](int y, int nr) {
+#pragma unroll 1
+      for (int r = y; r < y + nr; ++r)
+#pragma unroll 1
+        for (int k = tid; k < NROW; k += MR_BLOCK) {
+          const int pl = k / KX_XW;
+          const double* st = mr_presc(I, xs + k % KX_XW, r, tb);
+          if (st) mom[kx_slot(r, KX_MR)][k] = pl % 3 == 0 ? st[pl / 3] : 0.0;
+        }
+    };
     /* prologue: moment rows y0-2 .. y0+3 */
 #pragma unroll 1
     for (int y = tl.y0 - 2; y <= tl.y0 + 3; y += 2) {
@@ -154,6 +168,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
       store(y, a, za);
       store(y + 1, b, zb);
     }
+    if (I.pres) prescribe(tl.y0 - 2, 6);
     __syncthreads();
     for (int s = 0; 4 * s <= tl.rows + 1; ++s) {
       const int r0 = tl.y0 - 1 + 4 * s;    /* rows r0 .. r0+3 are reconstructed */
@@ -184,13 +199,13 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
         } else {
           double J = 0.0, len = 0.0;
           const double vl = 0.5 * (fd[a][4][cx] + fd[a][5][cx - 1]);
-          if (vl > 0.0 && !mr_wall(x, I.nx, I.bcx)) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
+          if (vl > 0.0 && !mr_wall_x(I, x, rf, tb)) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
           const double vr = 0.5 * (fd[a][5][cx] + fd[a][4][cx + 1]);
-          if (-vr > 0.0 && !mr_wall(x + 1, I.nx, I.bcx)) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
+          if (-vr > 0.0 && !mr_wall_x(I, x + 1, rf, tb)) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
           const double vb = 0.5 * (fd[a][6][cx] + fd[b][7][cx]);
-          if (vb > 0.0 && !mr_wall(rf, I.ny, I.bcy)) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
+          if (vb > 0.0 && !mr_wall_y(I, x, rf, tb)) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
           const double vt = 0.5 * (fd[a][7][cx] + fd[u][6][cx]);
-          if (-vt > 0.0 && !mr_wall(rf + 1, I.ny, I.bcy)) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
+          if (-vt > 0.0 && !mr_wall_y(I, x, rf + 1, tb)) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
           const double num = fabs(J);
           const double den = I.dx * I.dx * len * fd[a][8][cx];
           fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(num > den);
@@ -204,6 +219,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (r0 + 5 + k <= ylast + 1) store(r0 + 5 + k, v[k], z[k]);
+      if (I.pres) prescribe(r0 + 5, min(4, ylast - r0 - 3));
       __syncthreads();
     }
   }

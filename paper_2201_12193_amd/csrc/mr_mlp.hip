@@ -81,7 +81,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k_features(const mr_inst* insts, int
   if (e >= (long long)n * MR_KP) return;
   const int smp = (int)(e / MR_KP), f = (int)(e % MR_KP);
   const mr_inst& I = insts[inst];
-  const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+  const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, 3)};
   const int cell = cells[smp];
   if (cell < 0 || (long long)cell >= I.plane) {   /* not an interior cell */
     out[e] = (__bf16)0.0f;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
     mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
     if (I.tc != 3) continue;
-    const mr_grid gr{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const mr_grid gr{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, stage)};
     MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
     const int fh = I.fhalo, fex = I.fex;
     const int xs = tl.x0 - 2, ylo = tl.y0, yhi = tl.y0 + tl.rows;
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k_fb_summary(mr_inst* insts, 
     const mr_band b = list[k];
     mr_inst& I = insts[b.inst];
     if ((I.beta_on != 0) != BP) continue;
-    const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, stage)};
     mr_fb_summary_cell<BP>(I, g, b.e);
   }
 }
@@ -418,15 +418,16 @@ __global__ __launch_bounds__(MR_BLOCK) void k_fb_flags(mr_inst* insts, const mr_
     const long long SE = (long long)sx * I.sey;
     const MR_GLB double* S = mr_gp(I.summ);
     const long long o = (long long)(j + I.shalo) * sx + (i + I.shalo);
+    const double tb = mr_stage_time(I, stage);
     double J = 0.0, len = 0.0;
     const double vl = 0.5 * (S[4 * SE + o] + S[5 * SE + o - 1]);
-    if (vl > 0.0 && !mr_wall(i, I.nx, I.bcx)) { J += I.dy * (S[0 * SE + o] - S[1 * SE + o - 1]); len += I.dy; }
+    if (vl > 0.0 && !mr_wall_x(I, i, j, tb)) { J += I.dy * (S[0 * SE + o] - S[1 * SE + o - 1]); len += I.dy; }
     const double vr = 0.5 * (S[5 * SE + o] + S[4 * SE + o + 1]);
-    if (-vr > 0.0 && !mr_wall(i + 1, I.nx, I.bcx)) { J += I.dy * (S[1 * SE + o] - S[0 * SE + o + 1]); len += I.dy; }
+    if (-vr > 0.0 && !mr_wall_x(I, i + 1, j, tb)) { J += I.dy * (S[1 * SE + o] - S[0 * SE + o + 1]); len += I.dy; }
     const double vb = 0.5 * (S[6 * SE + o] + S[7 * SE + o - sx]);
-    if (vb > 0.0 && !mr_wall(j, I.ny, I.bcy)) { J += I.dx * (S[2 * SE + o] - S[3 * SE + o - sx]); len += I.dx; }
+    if (vb > 0.0 && !mr_wall_y(I, i, j, tb)) { J += I.dx * (S[2 * SE + o] - S[3 * SE + o - sx]); len += I.dx; }
     const double vt = 0.5 * (S[7 * SE + o] + S[6 * SE + o + sx]);
-    if (-vt > 0.0 && !mr_wall(j + 1, I.ny, I.bcy)) { J += I.dx * (S[3 * SE + o] - S[2 * SE + o + sx]); len += I.dx; }
+    if (-vt > 0.0 && !mr_wall_y(I, i, j + 1, tb)) { J += I.dx * (S[3 * SE + o] - S[2 * SE + o + sx]); len += I.dx; }
     fl[b.e] = (unsigned char)(fabs(J) > I.dx * I.dx * len * S[8 * SE + o]);
   }
 }

@@ -76,8 +76,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
     const mr_inst& I = insts[tl.inst];
     if (mode < 3 && !I.active) continue;
     const int st = mode == 3 ? 0 : mode;
-    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
-    const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3};
+    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, mode)};
+    const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, 0)};
     const MR_GLB unsigned char* fl = mr_gp(I.flags[(mode == 0 || mode == 3) ? 0 : 1]);
     MR_GLB double* unm = mr_gp(I.unm);
     const double rdx = I.rdx, rdy = I.rdy, dt = I.dt, gam = I.gam;
@@ -208,6 +208,25 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
           }
         }
         if (tid < XW) sh.flg[sb][tid] = pref;
+        if (I.pres) {
+          /* ghosts that hold a prescribed state (average; first moments 0) */
+          const double tb = mr_stage_time(I, mode);
+#pragma unroll 1
+          for (int q = 0; q < NE; ++q) {
+            const int e = tid + q * MR_BLOCK;
+            if (e < NP * XW) {
+              const int pl = e / XW, col = e % XW;
+              const bool isA = pl < 2 * NC;
+              const int c = isA ? pl / 2 : pl - 2 * NC, m = isA ? (pl % 2) * 2 : 1;
+              const double* st = mr_presc(I, xs0 + col, isA ? y + 3 : y + 2, tb);
+              if (st) {
+                const double v = m == 0 ? st[c] : 0.0;
+                if (isA) sh.mA[sa][pl][col] = v;
+                else sh.mB[sb][pl - 2 * NC][col] = v;
+              }
+            }
+          }
+        }
       }
       /* ---- volume integrals and the fluxes this lane owns ---- */
       double F[NC], G[NC], XL0[NC], XL1[NC], YB0[NC], YB1[NC];

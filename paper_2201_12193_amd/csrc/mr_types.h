@@ -24,7 +24,12 @@ struct mr_inst {
   /* ---- static ---- */
   int dim, nx, ny, nc;
   int flux;         /* 0 = Burgers + Lax-Friedrichs, 1 = Euler + HLLC          */
-  int bcx, bcy;     /* 0 = periodic, 1 = transmissive, 2 = reflective wall      */
+  int bcx, bcy;     /* fold kinds of the low (bits 0-1) and high (bits 2-3) side:
+                       0 = periodic, 1 = transmissive (also inflow sides, whose
+                       ghosts are then overwritten), 2 = reflective wall      */
+  int pres;         /* bit s: side s (0 left, 1 right, 2 bottom, 3 top) has
+                       ghosts that hold a prescribed state                     */
+  int skind[4];     /* side kinds: 1 transmissive, 2 reflective, 3 inflow      */
   int tc;           /* 0 none, 1 KXRCF, 2 all cells, 3 learned, 4 TVB minmod    */
   int beta_on;      /* 0 = q_l, 1 = p_l                                        */
   int charwise;     /* 1D Euler: Step 1 on characteristic fields               */
@@ -38,6 +43,10 @@ struct mr_inst {
   double rdx, rdy;            /* 1/dx, 1/dy                                    */
   double band_lo, band_hi;  /* learned-indicator uncertainty band              */
   double tvb_mh2;           /* M h^2 of the TVB indicator                      */
+  double x0, y0;            /* lower-left corner of the domain                 */
+  double sstate[4][4];      /* inflow state of each side                       */
+  double spre[4][4];        /* state of the ghosts before a side's front       */
+  double ssplit[4][3];      /* front s0 + st t + sn nu (bottom and top)        */
   mr_wconst W;
   double* buf[3];             /* state rotation; buf[0] = caller's moments     */
   unsigned char* flags[2];    /* [0] stage-1 flags, [1] stage-2/3 flags        */

@@ -27,6 +27,8 @@ EULER = 1
 PERIODIC = 0
 TRANSMISSIVE = 1
 REFLECTIVE = 2   # Euler: mirror-image ghosts (wall-normal momentum and normal first moment flip)
+SIDES = 3        # per-side boundary data in Problem.sides (bc_x / bc_y)
+INFLOW = 3       # side kind: ghosts hold a prescribed constant state
 TC_NONE = 0     # HWENO6: no first-moment modification
 TC_KXRCF = 1    # HWENO6-M5-I
 TC_ALL = 2      # HWENO6-M5-NI
@@ -37,6 +39,21 @@ BETA_ON_P = 1
 MOD_PERSIST = 0   # modified first moments replace those of every stage input, U^n included
 MOD_INTERNAL = 1  # modification internal to L(U)
 MOD_STAGE = 2     # replace those of the stage input only
+
+
+@dataclasses.dataclass(frozen=True)
+class Side:
+    """Boundary data of one side (used where bc_x or bc_y is SIDES).
+
+    kind: TRANSMISSIVE, REFLECTIVE or INFLOW (ghosts hold `state`, first
+    moments zero).  On the bottom and top sides the ghosts whose centre has
+    tangential coordinate tau < s0 + st t + sn nu (nu the normal coordinate
+    of the centre; split = (s0, st, sn)) hold `pre` instead: a straight
+    front moving at a constant speed."""
+    kind: int = TRANSMISSIVE
+    state: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0)
+    pre: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0)
+    split: Tuple[float, float, float] = (-math.inf, 0.0, 0.0)
 
 
 @dataclasses.dataclass
@@ -62,6 +79,7 @@ class Problem:
     modification: int = MOD_PERSIST
     tvb_m: float = 0.0   # TVB constant M of the minmod indicator (TC_TVB)
     charwise: int = 0    # 1D Euler: Step 1 on characteristic fields (0: component-wise)
+    sides: Optional[Tuple[Side, Side, Side, Side]] = None   # left, right, bottom, top (SIDES)
 
     @property
     def dx(self) -> float:
@@ -363,3 +381,89 @@ def batched_instances(seed: int, n1d: int = 192, n2d: int = 64,
         prob, U, _ = euler_quadrants_2d(int(rng.integers(1 << 31)), n=n, nq=2)
         out.append((prob, U))
     return out
+
+
+# --------------------------------------------------------------------------
+# Double Mach reflection (Example 3.9)
+# --------------------------------------------------------------------------
+def _clip_moments(a: float, b: float, c: float) -> Tuple[float, float, float]:
+    """Area and first moments (of xi and eta) of the part of the reference
+    cell [-1/2, 1/2]^2 where a*xi + b*eta < c: the square clipped by the
+    half-plane (Sutherland-Hodgman) and integrated with the polygon
+    (shoelace) formulas, which are exact for polygons."""
+    sq = [(-0.5, -0.5), (0.5, -0.5), (0.5, 0.5), (-0.5, 0.5)]
+    out = []
+    for k in range(4):
+        p, q = sq[k], sq[(k + 1) % 4]
+        fp, fq = a * p[0] + b * p[1] - c, a * q[0] + b * q[1] - c
+        if fp < 0.0:
+            out.append(p)
+        if (fp < 0.0) != (fq < 0.0):
+            s = fp / (fp - fq)
+            out.append((p[0] + s * (q[0] - p[0]), p[1] + s * (q[1] - p[1])))
+    area = mx = my = 0.0
+    for k in range(len(out)):
+        (x0, y0), (x1, y1) = out[k], out[(k + 1) % len(out)]
+        cr = x0 * y1 - x1 * y0
+        area += cr
+        mx += (x0 + x1) * cr
+        my += (y0 + y1) * cr
+    return area / 2.0, mx / 6.0, my / 6.0
+
+
+def mach_shock_states(mach: float = 10.0, gamma: float = 1.4):
+    """Primitive states (rho, u_n, p) on both sides of a normal shock of
+    Mach number `mach` running into gas at rest with rho = gamma, p = 1
+    (sound speed 1), from the Rankine-Hugoniot relations; and the shock
+    speed."""
+    m2 = mach * mach
+    rho2 = gamma * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = 1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0)
+    un = mach * (1.0 - gamma / rho2)
+    return (gamma, 0.0, 1.0), (rho2, un, p2), mach
+
+
+def double_mach_2d(ny: int = 400, tc_mode: int = TC_KXRCF, t_final: float = 0.2, **kw):
+    """Example 3.9: [0, 4] x [0, 1], 4*ny x ny cells, a Mach 10 shock
+    (gamma 1.4) through (1/6, 0) at 60 degrees to the x axis moving right
+    into gas at rest (rho = 1.4, p = 1).  Bottom: the post-shock state for
+    x < 1/6, a reflective wall beyond; top: the exact motion of the shock
+    (post-shock ghosts left of x = 1/6 + (y + 20 t)/sqrt(3), pre-shock
+    ghosts right of it, sampled at ghost centres); left: post-shock inflow;
+    right: transmissive.  Initial moments are exact: cells cut by the front
+    are clipped by it.  Returns (problem, U)."""
+    gamma = 1.4
+    (r1, _, p1), (r2, un, p2), ms = mach_shock_states(10.0, gamma)
+    th = math.pi / 6.0                          # the shock normal is 30 degrees below the x axis
+    u2, v2 = un * math.cos(th), -un * math.sin(th)
+    pre = tuple(float(z) for z in euler2d_cons(np.array(r1), np.array(0.0), np.array(0.0), np.array(p1), gamma))
+    post = tuple(float(z) for z in euler2d_cons(np.array(r2), np.array(u2), np.array(v2), np.array(p2), gamma))
+    s3 = math.sqrt(3.0)
+    speed = ms / math.sin(math.pi / 3.0)       # horizontal speed of the front: 20/sqrt(3)
+    sides = (Side(kind=INFLOW, state=post),
+             Side(kind=TRANSMISSIVE),
+             Side(kind=REFLECTIVE, pre=post, split=(1.0 / 6.0, 0.0, 0.0)),
+             Side(kind=INFLOW, state=pre, pre=post, split=(1.0 / 6.0, speed, 1.0 / s3)))
+    prob = Problem(dim=2, nx=4 * ny, ny=ny, x0=0.0, x1=4.0, y0=0.0, y1=1.0, system=EULER,
+                   bc_x=SIDES, bc_y=SIDES, gamma=gamma, t_final=t_final, tc_mode=tc_mode,
+                   sides=sides, **kw)
+    dx, dy = prob.dx, prob.dy
+    # post-shock where x - y/sqrt(3) < 1/6; in reference coordinates of cell
+    # (i, j): dx xi - dy eta / sqrt(3) < 1/6 - xc + yc / sqrt(3)
+    U = np.zeros(prob.shape())
+    xc = prob.x0 + (np.arange(prob.nx) + 0.5) * dx
+    yc = prob.y0 + (np.arange(prob.ny) + 0.5) * dy
+    reach = 0.5 * dx + 0.5 * dy / s3
+    pre_a, post_a = np.array(pre), np.array(post)
+    for j in range(prob.ny):
+        g = 1.0 / 6.0 - xc + yc[j] / s3           # > 0: centre on the post-shock side
+        full = g >= reach
+        none = g <= -reach
+        U[:, 0, j, full] = post_a[:, None]
+        U[:, 0, j, none] = pre_a[:, None]
+        for i in np.nonzero(~full & ~none)[0]:
+            a, mx, my = _clip_moments(dx, -dy / s3, g[i])
+            U[:, 0, j, i] = post_a * a + pre_a * (1.0 - a)
+            U[:, 1, j, i] = (post_a - pre_a) * mx
+            U[:, 2, j, i] = (post_a - pre_a) * my
+    return prob, U

@@ -35,6 +35,11 @@ EXPORTS = ["mrhweno_workspace_bytes", "mrhweno_create", "mrhweno_step", "mrhweno
            "mrhweno_last_error", "mrhweno_destroy"]
 
 
+class MrSide(C.Structure):
+    _fields_ = [("kind", C.c_int), ("front", C.c_int), ("state", C.c_double * 4),
+                ("pre", C.c_double * 4), ("split", C.c_double * 3)]
+
+
 class MrProblem(C.Structure):
     _fields_ = [("dim", C.c_int), ("nx", C.c_int), ("ny", C.c_int),
                 ("x0", C.c_double), ("x1", C.c_double), ("y0", C.c_double), ("y1", C.c_double),
@@ -42,7 +47,7 @@ class MrProblem(C.Structure):
                 ("gamma_gas", C.c_double), ("cfl", C.c_double), ("t_final", C.c_double),
                 ("gamma_bar", C.c_double * 4), ("eps", C.c_double),
                 ("tc_mode", C.c_int), ("beta_on", C.c_int), ("modification", C.c_int),
-                ("tvb_m", C.c_double), ("charwise", C.c_int)]
+                ("tvb_m", C.c_double), ("charwise", C.c_int), ("side", MrSide * 4)]
 
 
 def to_c(p: Problem) -> MrProblem:
@@ -57,6 +62,18 @@ def to_c(p: Problem) -> MrProblem:
     c.eps, c.tc_mode, c.beta_on, c.modification = p.eps, p.tc_mode, p.beta_on, p.modification
     c.tvb_m = p.tvb_m
     c.charwise = p.charwise
+    if p.sides is not None:
+        for k, sd in enumerate(p.sides):
+            if sd is None:
+                continue
+            c.side[k].kind = sd.kind
+            c.side[k].front = 1 if sd.split[0] != -math.inf else 0
+            for q, v in enumerate(sd.state):
+                c.side[k].state[q] = v
+            for q, v in enumerate(sd.pre):
+                c.side[k].pre[q] = v
+            for q in range(3):
+                c.side[k].split[q] = sd.split[q] if c.side[k].front else 0.0
     return c
 
 

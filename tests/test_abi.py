@@ -32,13 +32,24 @@ def test_library_exports_every_declared_symbol():
 def test_workspace_bytes_validates_problems():
     good = I.Problem(dim=2, nx=64, ny=64)
     assert M.workspace_bytes([good]) > 0
+    dmr, _ = I.double_mach_2d(ny=16)
+    W = dmr.sides[0].state
     bad = [I.Problem(dim=3, nx=64), I.Problem(dim=2, nx=4, ny=64), I.Problem(dim=2, nx=64, ny=32),
            good.replace(cfl=0.0), good.replace(gbar=(1, -1, 1, 1)), good.replace(eps=0.0),
            good.replace(tc_mode=7), I.Problem(dim=1, nx=64, gamma=1.0),
            good.replace(modification=3), good.replace(tvb_m=-1.0), good.replace(tvb_m=float("nan")),
            good.replace(charwise=1),                                  # characteristic-wise: 1D Euler only
            I.Problem(dim=1, nx=64, system=I.BURGERS, charwise=1), I.Problem(dim=1, nx=64, charwise=2),
-           I.Problem(dim=1, nx=64, system=I.BURGERS, bc_x=I.REFLECTIVE), good.replace(bc_y=3)]
+           I.Problem(dim=1, nx=64, system=I.BURGERS, bc_x=I.REFLECTIVE), good.replace(bc_y=4),
+           good.replace(bc_y=I.SIDES),                                  # side kinds left unset
+           dmr.replace(sides=(I.Side(kind=I.INFLOW, state=W, split=(0.1, 0.0, 0.0)),) + dmr.sides[1:]),
+           dmr.replace(sides=dmr.sides[:3] + (I.Side(kind=I.INFLOW, state=(1.0, 0.0, 0.0, -1.0)),)),
+           dmr.replace(sides=dmr.sides[:2] + (I.Side(kind=I.REFLECTIVE, pre=W, split=(0.1, math.inf, 0.0)),)
+                       + dmr.sides[3:]),
+           dmr.replace(tc_mode=I.TC_LEARNED),                           # no per-side data with it
+           I.Problem(dim=1, nx=64, system=I.BURGERS, bc_x=I.SIDES,
+                     sides=(I.Side(kind=I.REFLECTIVE), I.Side(), None, None))]
+    assert M.workspace_bytes([dmr]) > 0
     for b in bad:
         assert M.workspace_bytes([b]) == 0, b
     assert M.workspace_bytes([good, bad[0]]) == 0

@@ -1,0 +1,158 @@
+"""GPU vs oracle with per-side boundary data: inflow sides, moving fronts
+(the double Mach reflection of Example 3.9 and a plane shock crossing a box
+with exact data on every side), at the time of each stage.
+
+Same bar as the other parity tests: FP64 values within 1e-12 of the
+component's scale per step, flags bit-exact except at near-ties."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_12193_amd import inputs as I
+from tests.parity_util import comp_scale, rel_state_err, flag_mismatch, tvb_tie_map
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _dev():
+    import torch
+    return torch.device("cuda:0")
+
+
+def _box(n):
+    pd, Ud = I.double_mach_2d(ny=n)
+    post, pre = pd.sides[0].state, pd.sides[3].state
+    front = (1.0 / 6.0, 20.0 / math.sqrt(3.0), 1.0 / math.sqrt(3.0))
+    sides = (I.Side(kind=I.INFLOW, state=post), I.Side(kind=I.INFLOW, state=pre),
+             I.Side(kind=I.INFLOW, state=pre, pre=post, split=front),
+             I.Side(kind=I.INFLOW, state=pre, pre=post, split=front))
+    prob = I.Problem(dim=2, nx=n, ny=n, x0=0.0, x1=1.0, y0=0.0, y1=1.0, bc_x=I.SIDES, bc_y=I.SIDES,
+                     sides=sides)
+    return prob, np.ascontiguousarray(Ud[:, :, :, :n])
+
+
+def _channel():
+    """Quadrant data in a channel: post-shock-like inflow on the left,
+    transmissive right, reflective bottom and top."""
+    prob, U, _ = I.euler_quadrants_2d(seed=11, n=64, nq=2)
+    W = tuple(float(z) for z in I.euler2d_cons(np.array(1.2), np.array(0.9), np.array(0.1), np.array(1.4), 1.4))
+    sides = (I.Side(kind=I.INFLOW, state=W), I.Side(kind=I.TRANSMISSIVE),
+             I.Side(kind=I.REFLECTIVE), I.Side(kind=I.REFLECTIVE))
+    return prob.replace(bc_x=I.SIDES, bc_y=I.SIDES, sides=sides), U
+
+
+def _riemann_inflow_1d():
+    prob, U, _ = I.euler_riemann_1d(seed=9, n=400)
+    W = tuple(float(z) for z in U[:, 0, 0])
+    sides = (I.Side(kind=I.INFLOW, state=W), I.Side(kind=I.TRANSMISSIVE), None, None)
+    return prob.replace(bc_x=I.SIDES, sides=sides), U
+
+
+def _cases():
+    out = []
+    prob, U = I.double_mach_2d(ny=40)
+    out.append(("dmr_160x40_t0", prob, U, 0))
+    out.append(("dmr_160x40_k12", prob, U, 12))
+    out.append(("shock_box_48_k6", *_box(48), 6))
+    out.append(("channel_inflow_64_k3", *_channel(), 3))
+    out.append(("euler1d_inflow_400_k10", *_riemann_inflow_1d(), 10))
+    return out
+
+
+CASES = _cases()
+
+
+def _advance(prob, U, k):
+    t = 0.0
+    for _ in range(k):
+        d = oracle.dt(prob, U)
+        U = oracle.rk3_step(prob, U, d, t=t)
+        t += d
+    return U, t
+
+
+def _check_tc(prob, U, k, tc, nsteps):
+    import torch
+    from paper_2201_12193_amd.mrhweno import Solver
+    prob = prob.replace(tc_mode=tc, tvb_m=1.0 if tc == I.TC_TVB else 0.0)
+    U, t = _advance(prob, U, k)
+    Ut = torch.from_numpy(np.ascontiguousarray(U)).to(_dev())
+    s = Solver([prob], [Ut])
+    s.set_time(0, t, k)
+    Uin = torch.from_numpy(U).to(_dev())
+    R, fl = s.residual(0, Uin)
+    gl, _ = s.reconstruct(0, Uin)
+    R, fl, gl = R.cpu().numpy(), fl.cpu().numpy(), gl.cpu().numpy()
+    Lref, flref = oracle.residual(prob, U, t)
+    glref, _, num, den = oracle.reconstruct(prob, U, t)
+    if tc == I.TC_TVB:
+        tie = tvb_tie_map(prob, U, glref)
+        diff = fl.astype(bool) != flref.astype(bool)
+        bad, ties = int((diff & ~tie).sum()), int((diff & tie).sum())
+    else:
+        bad, ties = flag_mismatch(fl, flref, num, den)
+    assert bad == 0 and ties <= 2, (bad, ties)
+    sc = comp_scale(prob, U)
+    dt = oracle.dt(prob, U)
+    if ties == 0:
+        assert (np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc).max() <= TOL
+        assert (np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)).max() <= TOL
+    prev, tp = U.copy(), t
+    for j in range(nsteps):
+        s.step(1)
+        d = s.last_dt()[0]
+        times, _, _ = s.sync()
+        got = Ut.cpu().numpy()
+        e = rel_state_err(prob, got, oracle.rk3_step(prob, prev, d, t=tp), sc)
+        assert e <= TOL, (j, e)
+        prev, tp = got, times[0]
+    s.close()
+    return flref
+
+
+@pytest.mark.parametrize("name,prob,U,k", CASES, ids=[c[0] for c in CASES])
+def test_sides_parity(name, prob, U, k):
+    """Values, flags, residual and steps against the oracle with the
+    boundary data at the probe time and at every stage time."""
+    flref = _check_tc(prob, U, k, I.TC_KXRCF, 3 if prob.dim == 2 else 6)
+    if name.startswith("dmr") or name.startswith("shock"):
+        assert flref.sum() > 0
+
+
+@pytest.mark.parametrize("tc", [I.TC_ALL, I.TC_TVB, I.TC_NONE])
+def test_sides_other_indicators(tc):
+    prob, U = I.double_mach_2d(ny=40)
+    _check_tc(prob, U, 12, tc, 2)
+
+
+def test_double_mach_front_crossing_a_stage():
+    """Steps whose stages straddle the moment the front passes the centre of
+    a top ghost cell: stage 1 and 3 see different ghost states."""
+    prob, U = _box(32)
+    U, t = _advance(prob, U, 5)
+    import torch
+    from paper_2201_12193_amd.mrhweno import Solver
+    Ut = torch.from_numpy(np.ascontiguousarray(U)).to(_dev())
+    s = Solver([prob], [Ut])
+    s.set_time(0, t, 5)
+    sc = comp_scale(prob, U)
+    prev, tp = U.copy(), t
+    crossed = 0
+    h, s3 = prob.dx, math.sqrt(3.0)
+    for j in range(8):
+        s.step(1)
+        d = s.last_dt()[0]
+        times, _, _ = s.sync()
+        got = Ut.cpu().numpy()
+        e = rel_state_err(prob, got, oracle.rk3_step(prob, prev, d, t=tp), sc)
+        assert e <= TOL, (j, e)
+        # did a top ghost centre change sides within this step?
+        y = 1.0 + 0.5 * h
+        xa, xb = 1 / 6 + (y + 20 * tp) / s3, 1 / 6 + (y + 20 * (tp + d)) / s3
+        crossed += int(math.floor(xb / h - 0.5) != math.floor(xa / h - 0.5))
+        prev, tp = got, times[0]
+    s.close()
+    assert crossed > 0
