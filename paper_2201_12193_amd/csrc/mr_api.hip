@@ -21,8 +21,8 @@ hipError_t mr_launch_finalize(hipStream_t, mr_inst*, int, int);
 hipError_t mr_launch_summary(hipStream_t, int, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_flags(hipStream_t, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_stage1(hipStream_t, int, int, mr_inst*, const mr_tile1*, int, int, int);
-hipError_t mr_launch_stage2(hipStream_t, int, int, mr_inst*, const mr_tile2*, int, int, int);
-hipError_t mr_launch_kxrcf2(hipStream_t, int, int, mr_inst*, const mr_tile2*, int, int);
+hipError_t mr_launch_stage2(hipStream_t, int, int, int, mr_inst*, const mr_tile2*, int, int, int);
+hipError_t mr_launch_kxrcf2(hipStream_t, int, int, int, mr_inst*, const mr_tile2*, int, int);
 hipError_t mr_launch_values(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, double*);
 hipError_t mr_launch_fb_reset(hipStream_t, int*, int);
 hipError_t mr_launch_pack(hipStream_t, const void*, mr_learn_w*);
@@ -211,6 +211,7 @@ Layout layout(const mrhweno_problem* P, int n) {
 /* host-side description of one launch group (instances sharing a kernel) */
 struct Group {
   int dim, nc, bp;
+  int gb;           /* instances with ghosts that hold a prescribed state */
   bool any_summ = false, any_lf = false;
   std::vector<int> insts;
   int t_summ = 0, n_summ = 0, t_flag = 0, n_flag = 0, t_st1 = 0, n_st1 = 0;
@@ -391,11 +392,11 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
     for (auto& g : c->groups) {
       if (g.n_kx > 0) {
         any = true;
-        if ((e = mr_launch_kxrcf2(s, g.nc == 4 ? 3 : 1, g.bp, c->d, c->t2 + g.t_kx, g.n_kx, st)) != hipSuccess) return e;
+        if ((e = mr_launch_kxrcf2(s, g.nc == 4 ? 3 : 1, g.bp, g.gb, c->d, c->t2 + g.t_kx, g.n_kx, st)) != hipSuccess) return e;
       }
       if (g.n_tvb > 0) {   /* the TVB test reads the indicator variable only */
         any = true;
-        if ((e = mr_launch_kxrcf2(s, 1, g.bp, c->d, c->t2 + g.t_tvb, g.n_tvb, st)) != hipSuccess) return e;
+        if ((e = mr_launch_kxrcf2(s, 1, g.bp, g.gb, c->d, c->t2 + g.t_tvb, g.n_tvb, st)) != hipSuccess) return e;
       }
     }
     if (c->any_learned) {
@@ -412,7 +413,7 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
     if ((e = mark(c, P, 2)) != hipSuccess) return e;
     for (auto& g : c->groups) {
       if (g.dim == 1) e = mr_launch_stage1(s, g.nc, g.bp, c->d, c->t1 + g.t_st1, g.n_st1, st, 0);
-      else e = mr_launch_stage2(s, g.nc, g.bp, c->d, c->t2 + g.t_st2, g.n_st2, st, c->grid2);
+      else e = mr_launch_stage2(s, g.nc, g.bp, g.gb, c->d, c->t2 + g.t_st2, g.n_st2, st, c->grid2);
       if (e != hipSuccess) return e;
     }
     if ((e = mark(c, P, 3)) != hipSuccess) return e;
@@ -554,8 +555,8 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     const int nc = ncomp_of(p);
     Group* gp = nullptr;
     for (auto& g : c->groups)
-      if (g.dim == p.dim && g.nc == nc && g.bp == p.beta_on) gp = &g;
-    if (!gp) { c->groups.push_back(Group{p.dim, nc, p.beta_on}); gp = &c->groups.back(); }
+      if (g.dim == p.dim && g.nc == nc && g.bp == p.beta_on && g.gb == (c->h[q].pres != 0)) gp = &g;
+    if (!gp) { c->groups.push_back(Group{p.dim, nc, p.beta_on, c->h[q].pres != 0}); gp = &c->groups.back(); }
     gp->insts.push_back(q);
     gp->any_summ |= needs_summ(p);
   }
@@ -659,7 +660,7 @@ mrhweno_status mrhweno_autotune(mrhweno_ctx* c, const int* rows_cand, int n_rows
       auto launch = [&]() -> hipError_t {
         for (auto& g : c->groups)
           if (g.dim == 2) {
-            hipError_t e = mr_launch_stage2(c->stream, g.nc, g.bp, c->d, c->t2 + g.t_st2, g.n_st2, 3, c->grid2);
+            hipError_t e = mr_launch_stage2(c->stream, g.nc, g.bp, g.gb, c->d, c->t2 + g.t_st2, g.n_st2, 3, c->grid2);
             if (e != hipSuccess) return e;
           }
         return hipSuccess;
@@ -845,13 +846,14 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   } else {
     MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, c->d, d1 + t_sum, n_sum, 3));
     MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));
-    if (kx2) MR_CHECK(c, mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? 3 : 1, p.beta_on, c->d, d3, (int)tl.size(), 3));
+    if (kx2)
+      MR_CHECK(c, mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? 3 : 1, p.beta_on, I.pres != 0, c->d, d3, (int)tl.size(), 3));
   }
   const int nc = ncomp_of(p);
   if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + t_val, n_val, (double*)out));
   if (kind == 2) {
     if (p.dim == 1) MR_CHECK(c, mr_launch_stage1(s, nc, p.beta_on, c->d, d1 + t_st, n_st, 3, 0));
-    else MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, c->d, d2, (int)t2.size(), 3, 0));
+    else MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, c->d, d2, (int)t2.size(), 3, 0));
   }
   if (flags)
     MR_CHECK(c, hipMemcpy2DAsync(flags, p.nx, I.flags[0] + frow, I.fex, p.nx, p.dim == 2 ? p.ny : 1,

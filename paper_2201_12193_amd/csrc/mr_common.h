@@ -67,13 +67,14 @@ struct mr_grid {
   const MR_GLB double* U;  /* state base: comp c, moment m plane at U + (c*nm + m)*P */
   long long P;
   int nx, ny, bcx, bcy, nm;
-  const mr_inst* I;        /* instance (prescribed ghosts), time of its data */
+  const mr_inst* I;        /* instance with prescribed ghosts (or null), and
+                              the time of its boundary data */
   double t;
 };
 
 /* moment m of component c at cell (i, j) with ghost handling */
 MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
-  if ((i < 0 || i >= g.nx || (g.nm == 3 && (j < 0 || j >= g.ny))) && g.I->pres) {
+  if (g.I && (i < 0 || i >= g.nx || (g.nm == 3 && (j < 0 || j >= g.ny))) && g.I->pres) {
     const double* st = mr_presc(*g.I, i, j, g.t);
     if (st) return m == 0 ? st[c] : 0.0;
   }

@@ -91,7 +91,7 @@ MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, in
    momenta; 1 for the TVB minmod test, which reads the indicator variable
    only and decides each cell from its own face averages).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
    of the extended flag range [-2, n+2)^2 (y0 >= -2). */
-template <int NK, bool BP>
+template <int NK, bool BP, bool GB>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, const mr_tile2* tiles, int ntiles, int stage) {
   mr_kt_fill();
   constexpr int NPL = 3 * NK;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
       store(y, a, za);
       store(y + 1, b, zb);
     }
-    if (I.pres) prescribe(tl.y0 - 2, 6);
+    if (GB && I.pres) prescribe(tl.y0 - 2, 6);
     __syncthreads();
     for (int s = 0; 4 * s <= tl.rows + 1; ++s) {
       const int r0 = tl.y0 - 1 + 4 * s;    /* rows r0 .. r0+3 are reconstructed */
@@ -199,13 +199,13 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
         } else {
           double J = 0.0, len = 0.0;
           const double vl = 0.5 * (fd[a][4][cx] + fd[a][5][cx - 1]);
-          if (vl > 0.0 && !mr_wall_x(I, x, rf, tb)) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
+          if (vl > 0.0 && !(GB ? mr_wall_x(I, x, rf, tb) : mr_wall(x, I.nx, I.bcx))) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
           const double vr = 0.5 * (fd[a][5][cx] + fd[a][4][cx + 1]);
-          if (-vr > 0.0 && !mr_wall_x(I, x + 1, rf, tb)) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
+          if (-vr > 0.0 && !(GB ? mr_wall_x(I, x + 1, rf, tb) : mr_wall(x + 1, I.nx, I.bcx))) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
           const double vb = 0.5 * (fd[a][6][cx] + fd[b][7][cx]);
-          if (vb > 0.0 && !mr_wall_y(I, x, rf, tb)) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
+          if (vb > 0.0 && !(GB ? mr_wall_y(I, x, rf, tb) : mr_wall(rf, I.ny, I.bcy))) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
           const double vt = 0.5 * (fd[a][7][cx] + fd[u][6][cx]);
-          if (-vt > 0.0 && !mr_wall_y(I, x, rf + 1, tb)) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
+          if (-vt > 0.0 && !(GB ? mr_wall_y(I, x, rf + 1, tb) : mr_wall(rf + 1, I.ny, I.bcy))) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
           const double num = fabs(J);
           const double den = I.dx * I.dx * len * fd[a][8][cx];
           fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(num > den);
@@ -219,16 +219,22 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (r0 + 5 + k <= ylast + 1) store(r0 + 5 + k, v[k], z[k]);
-      if (I.pres) prescribe(r0 + 5, min(4, ylast - r0 - 3));
+      if (GB && I.pres) prescribe(r0 + 5, min(4, ylast - r0 - 3));
       __syncthreads();
     }
   }
 }
 
-extern "C" hipError_t mr_launch_kxrcf2(hipStream_t s, int nk, int bp, mr_inst* d, const mr_tile2* t, int nt, int stage) {
+/* gb: some instance of the list has ghosts that hold a prescribed state */
+extern "C" hipError_t mr_launch_kxrcf2(hipStream_t s, int nk, int bp, int gb, mr_inst* d, const mr_tile2* t, int nt,
+                                       int stage) {
   if (nt <= 0) return hipSuccess;
   const dim3 G(nt), B(MR_BLOCK);
-#define MR_LK(NK_, BP_) hipLaunchKernelGGL((k2_kxrcf<NK_, BP_>), G, B, 0, s, d, t, nt, stage)
+#define MR_LK(NK_, BP_)                                                                   \
+  do {                                                                                    \
+    if (gb) hipLaunchKernelGGL((k2_kxrcf<NK_, BP_, true>), G, B, 0, s, d, t, nt, stage);  \
+    else hipLaunchKernelGGL((k2_kxrcf<NK_, BP_, false>), G, B, 0, s, d, t, nt, stage);    \
+  } while (0)
   if (nk == 1) { if (bp) MR_LK(1, true); else MR_LK(1, false); }
   else if (nk == 3) { if (bp) MR_LK(3, true); else MR_LK(3, false); }
   else return hipErrorInvalidValue;

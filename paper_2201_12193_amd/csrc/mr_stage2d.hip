@@ -58,7 +58,7 @@ MR_INL double mr2_stage_ld(const mr_grid& g, int e, int xs0, int y) {
   return mr_ld(g, pl - 2 * NC, 1, xs0 + col, y);
 }
 
-template <int NC, bool BP>
+template <int NC, bool BP, bool GB>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, const mr_tile2* tiles, int ntiles, int mode) {
   mr_kt_fill();
   using S = mr2_lds<NC>;
@@ -76,8 +76,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
     const mr_inst& I = insts[tl.inst];
     if (mode < 3 && !I.active) continue;
     const int st = mode == 3 ? 0 : mode;
-    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, mode)};
-    const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, 0)};
+    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, GB ? &I : nullptr, mr_stage_time(I, mode)};
+    const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, GB ? &I : nullptr, mr_stage_time(I, 0)};
     const MR_GLB unsigned char* fl = mr_gp(I.flags[(mode == 0 || mode == 3) ? 0 : 1]);
     MR_GLB double* unm = mr_gp(I.unm);
     const double rdx = I.rdx, rdy = I.rdy, dt = I.dt, gam = I.gam;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
           }
         }
         if (tid < XW) sh.flg[sb][tid] = pref;
-        if (I.pres) {
+        if (GB && I.pres) {
           /* ghosts that hold a prescribed state (average; first moments 0) */
           const double tb = mr_stage_time(I, mode);
 #pragma unroll 1
@@ -341,10 +341,17 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
 #undef FSM
 }
 
-extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, mr_inst* d, const mr_tile2* t, int nt, int mode, int grid) {
+/* gb: some instance of the list has ghosts that hold a prescribed state
+   (the variant without that code runs everything else) */
+extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, int gb, mr_inst* d, const mr_tile2* t, int nt,
+                                       int mode, int grid) {
   if (nt <= 0) return hipSuccess;
   const dim3 G(grid > 0 && grid < nt ? grid : nt), B(MR_BLOCK);
-#define MR_L2(NC_, BP_) hipLaunchKernelGGL((k2_stage<NC_, BP_>), G, B, 0, s, d, t, nt, mode)
+#define MR_L2(NC_, BP_)                                                                  \
+  do {                                                                                   \
+    if (gb) hipLaunchKernelGGL((k2_stage<NC_, BP_, true>), G, B, 0, s, d, t, nt, mode);  \
+    else hipLaunchKernelGGL((k2_stage<NC_, BP_, false>), G, B, 0, s, d, t, nt, mode);    \
+  } while (0)
   if (nc == 1) { if (bp) MR_L2(1, true); else MR_L2(1, false); }
   else if (nc == 4) { if (bp) MR_L2(4, true); else MR_L2(4, false); }
   else return hipErrorInvalidValue;
