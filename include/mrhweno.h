@@ -84,12 +84,15 @@ typedef enum {
 } mrhweno_side_kind;
 /* Boundary data of one side: side[0] left, [1] right, [2] bottom, [3] top.
  * On the bottom and top sides a front may split the ghost cells: with
- * front = 1, a ghost whose centre (x, y) has x < split[0] + split[1] t +
- * split[2] y holds `pre` (a straight front moving at constant speed,
- * sampled at ghost centres; t = t^n, t^n + dt, t^n + dt/2 in the three
- * SSP-RK3 stages), the others follow `kind` -- e.g. the exact motion of the
- * Mach 10 shock along the top of the double Mach reflection, or the
- * post-shock part of its bottom.  A ghost outside in both directions takes
+ * front = 1, the part x < split[0] + split[1] t + split[2] y holds `pre`
+ * (a straight front moving at constant speed; t = t^n, t^n + dt,
+ * t^n + dt/2 in the three SSP-RK3 stages).  On an INFLOW side the ghosts
+ * hold the exact moments of the two-state field (a cut cell: area fraction
+ * and first moments of its part before the front) -- e.g. the exact motion
+ * of the Mach 10 shock along the top of the double Mach reflection; before
+ * a transmissive or reflective side a ghost holds `pre` if its centre lies
+ * before the front, else follows `kind` -- e.g. the post-shock part of
+ * that problem's bottom.  A ghost outside in both directions takes
  * the bottom/top side's prescribed state if that side prescribes one
  * there, else the left/right side's, else folds in both directions.  A
  * reflective side's face is a wall only where the ghost across it holds no

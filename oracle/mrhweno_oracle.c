@@ -60,12 +60,15 @@
  *       Example 3.9 needs it): each side is transmissive, reflective or
  *       inflow.  An inflow ghost holds a prescribed constant state, so its
  *       average is that state and its first moments are zero.  The bottom
- *       and top sides may prescribe a second state on the ghosts whose
- *       centre has tangential coordinate tau < s0 + st t + sn nu (nu: the
- *       normal coordinate of the centre), a straight front moving at a
- *       constant speed, sampled at cell centres (the paper gives no rule
- *       for cut ghost cells) at the time of the stage: t^n, t^n + dt and
- *       t^n + dt/2 in SSP-RK3.  A ghost outside in both directions takes
+ *       and top sides may carry a front x < s0 + st t + sn y, a straight
+ *       front moving at constant speed, with a second state before it; it
+ *       is taken at the time of the stage (t^n, t^n + dt, t^n + dt/2 in
+ *       SSP-RK3).  On an inflow side the ghosts hold the exact moments of
+ *       the two-state field (a cell cut by the front: area fraction and
+ *       first moments of the clipped cell), the paper's "exact motion of
+ *       the shock" along the top of Example 3.9; before a folded side
+ *       (transmissive, reflective) a ghost holds the second state if its
+ *       centre lies before the front.  A ghost outside in both directions takes
  *       the bottom or top side's prescribed state if that side prescribes
  *       one there, else the left or right side's, else folds in both
  *       directions.  A reflective side's face is a wall (R16) only where
@@ -722,19 +725,64 @@ static int side_kind(const orc_problem* P, int s) {
   return bc == 3 ? P->side_kind[s] : bc;
 }
 
-/* Prescribed state of component c in the ghost cell (i, j), R17: returns 1
-   and sets *val if the cell takes one. */
-static int prescribed(const orc_problem* P, int c, int i, int j, double* val) {
+/* Area and first moments (of xi and eta) of the part of the reference cell
+   [-1/2, 1/2]^2 where a xi + b eta < c: the square clipped by the
+   half-plane, integrated with the polygon formulas (exact for polygons). */
+static void clip_cell(double a, double b, double c, double* area, double* mx, double* my) {
+  const double px[4] = {-0.5, 0.5, 0.5, -0.5}, py[4] = {-0.5, -0.5, 0.5, 0.5};
+  double qx[8], qy[8];
+  int n = 0;
+  for (int k = 0; k < 4; ++k) {
+    int l = (k + 1) % 4;
+    double fk = a * px[k] + b * py[k] - c, fl = a * px[l] + b * py[l] - c;
+    if (fk < 0.0) { qx[n] = px[k]; qy[n] = py[k]; ++n; }
+    if ((fk < 0.0) != (fl < 0.0)) {
+      double s = fk / (fk - fl);
+      qx[n] = px[k] + s * (px[l] - px[k]);
+      qy[n] = py[k] + s * (py[l] - py[k]);
+      ++n;
+    }
+  }
+  double A = 0.0, X = 0.0, Y = 0.0;
+  for (int k = 0; k < n; ++k) {
+    int l = (k + 1) % n;
+    double cr = qx[k] * qy[l] - qx[l] * qy[k];
+    A += cr;
+    X += (qx[k] + qx[l]) * cr;
+    Y += (qy[k] + qy[l]) * cr;
+  }
+  *area = A / 2.0;
+  *mx = X / 6.0;
+  *my = Y / 6.0;
+}
+
+/* Prescribed moment m of component c in the ghost cell (i, j), R17: returns
+   1 and sets *val if the cell holds prescribed data.  A front between two
+   prescribed states gives the cells it cuts the exact moments of the
+   two-state field; a front before a folded side is sampled at the centre. */
+static int prescribed(const orc_problem* P, int c, int m, int i, int j, double* val) {
   if (P->dim == 2 && (j < 0 || j >= P->ny) && P->bc_y == 3) {
     int s = j < 0 ? 2 : 3;
-    double tau = P->x0 + (i + 0.5) * P->dx, nu = P->y0 + (j + 0.5) * P->dy;
+    double xc = P->x0 + (i + 0.5) * P->dx, yc = P->y0 + (j + 0.5) * P->dy;
     const double* sp = P->side_split[s];
-    if (tau < sp[0] + sp[1] * P->t + sp[2] * nu) { *val = P->side_pre[s][c]; return 1; }
-    if (P->side_kind[s] == 3) { *val = P->side_state[s][c]; return 1; }
+    const double* A = P->side_pre[s];
+    if (P->side_kind[s] == 3) {
+      const double* B = P->side_state[s];
+      double a = 1.0, mx = 0.0, my = 0.0;   /* no front: all of the cell beyond it */
+      if (sp[0] > -HUGE_VAL) {
+        /* x < s0 + st t + sn y  <=>  dx xi - sn dy eta < s0 + st t + sn yc - xc */
+        clip_cell(P->dx, -sp[2] * P->dy, sp[0] + sp[1] * P->t + sp[2] * yc - xc, &a, &mx, &my);
+      } else {
+        a = 0.0;
+      }
+      *val = m == 0 ? B[c] + (A[c] - B[c]) * a : (A[c] - B[c]) * (m == 1 ? mx : my);
+      return 1;
+    }
+    if (xc < sp[0] + sp[1] * P->t + sp[2] * yc) { *val = m == 0 ? A[c] : 0.0; return 1; }
   }
   if ((i < 0 || i >= P->nx) && P->bc_x == 3) {
     int s = i < 0 ? 0 : 1;
-    if (P->side_kind[s] == 3) { *val = P->side_state[s][c]; return 1; }
+    if (P->side_kind[s] == 3) { *val = m == 0 ? P->side_state[s][c] : 0.0; return 1; }
   }
   return 0;
 }
@@ -748,8 +796,8 @@ static double mom(const grid_t* G, int c, int m, int i, int j) {
   const orc_problem* P = G->P;
   int zero = 0, flip = 0;
   double pv;
-  if ((i < 0 || i >= P->nx || (P->dim == 2 && (j < 0 || j >= P->ny))) && prescribed(P, c, i, j, &pv))
-    return m == 0 ? pv : 0.0;
+  if ((i < 0 || i >= P->nx || (P->dim == 2 && (j < 0 || j >= P->ny))) && prescribed(P, c, m, i, j, &pv))
+    return pv;
   if (i < 0 || i >= P->nx) {
     const int k = side_kind(P, i < 0 ? 0 : 1);
     if (k == 0) i = ((i % P->nx) + P->nx) % P->nx;
@@ -793,12 +841,12 @@ static double modified_v1(const grid_t* G, int c, int i) {
 static int wall_x(const orc_problem* P, int f, int j) {
   double pv;
   if (f != 0 && f != P->nx) return 0;
-  return side_kind(P, f == 0 ? 0 : 1) == 2 && !prescribed(P, 0, f == 0 ? -1 : P->nx, j, &pv);
+  return side_kind(P, f == 0 ? 0 : 1) == 2 && !prescribed(P, 0, 0, f == 0 ? -1 : P->nx, j, &pv);
 }
 static int wall_y(const orc_problem* P, int i, int f) {
   double pv;
   if (P->dim != 2 || (f != 0 && f != P->ny)) return 0;
-  return side_kind(P, f == 0 ? 2 : 3) == 2 && !prescribed(P, 0, i, f == 0 ? -1 : P->ny, &pv);
+  return side_kind(P, f == 0 ? 2 : 3) == 2 && !prescribed(P, 0, 0, i, f == 0 ? -1 : P->ny, &pv);
 }
 
 /* velocity used by the KXRCF indicator at a point (Remark 2) */

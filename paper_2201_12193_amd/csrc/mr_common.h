@@ -27,28 +27,96 @@ MR_INL double mr_stage_time(const mr_inst& I, int s) {
   return s == 0 ? I.t_prev : (s == 1 ? I.t_prev + I.dt : (s == 2 ? I.t_prev + 0.5 * I.dt : I.t));
 }
 
-/* State held by the ghost cell (i, j) at time t if a side prescribes one
- * (average = state, first moments zero), else null.  The bottom and top
- * sides prescribe `spre` on the ghosts whose centre has tangential
- * coordinate below the front s0 + st t + sn nu (nu: normal coordinate of
- * the centre; a straight front moving at constant speed, sampled at cell
- * centres) and their inflow state beyond it; they take precedence over the
- * left and right sides in the corners. */
-MR_INL const double* mr_presc(const mr_inst& I, int i, int j, double t) {
+/* Area and first moments (of xi and eta) of the part of the reference cell
+ * [-1/2, 1/2]^2 where a xi + b eta < c.  The polygon formulas are sums over
+ * its directed edges: the parts of the square's edges inside the
+ * half-plane plus the chord from where the boundary leaves the half-plane
+ * to where it comes back. */
+MR_INL void mr_clip(double a, double b, double c, double* area, double* mx, double* my) {
+#pragma clang fp contract(off)
+  const double cx[4] = {-0.5, 0.5, 0.5, -0.5}, cy[4] = {-0.5, -0.5, 0.5, 0.5};
+  double A = 0.0, X = 0.0, Y = 0.0, ox = 0.0, oy = 0.0, ix = 0.0, iy = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int l = (k + 1) & 3;
+    const double fk = a * cx[k] + b * cy[k] - c, fl = a * cx[l] + b * cy[l] - c;
+    const bool ink = fk < 0.0, inl = fl < 0.0;
+    double x0 = cx[k], y0 = cy[k], x1 = cx[l], y1 = cy[l];
+    if (ink != inl) {
+      const double r = fk / (fk - fl);
+      const double xs = cx[k] + r * (cx[l] - cx[k]), ys = cy[k] + r * (cy[l] - cy[k]);
+      if (ink) { x1 = xs; y1 = ys; ox = xs; oy = ys; }   /* leaves the half-plane */
+      else { x0 = xs; y0 = ys; ix = xs; iy = ys; }       /* comes back           */
+    }
+    if (ink || inl) {
+      const double cr = x0 * y1 - x1 * y0;
+      A += cr; X += (x0 + x1) * cr; Y += (y0 + y1) * cr;
+    }
+  }
+  const double cr = ox * iy - ix * oy;   /* the chord (zero if the cell is not cut) */
+  A += cr; X += (ox + ix) * cr; Y += (oy + iy) * cr;
+  *area = A / 2.0;
+  *mx = X / 6.0;
+  *my = Y / 6.0;
+}
+
+/* Prescribed data of the ghost cell (i, j) at time t.  The bottom and top
+ * sides may carry a front x < s0 + st t + sn y (a straight front moving at
+ * constant speed).  On an inflow side the cells it cuts hold the exact
+ * moments of the two-state field (`spre` before the front, the inflow
+ * state beyond); before a folded side (transmissive, reflective) the ghost
+ * holds `spre` if its centre lies before the front.  Left and right inflow
+ * sides hold their state; the bottom and top sides take precedence in the
+ * corners.  A constant state has zero first moments. */
+MR_INL bool mr_presc_any(const mr_inst& I, int i, int j, double t) {
 #pragma clang fp contract(off)
   if (I.dim == 2 && (j < 0 || j >= I.ny)) {
     const int s = j < 0 ? 2 : 3;
     if ((I.pres >> s) & 1) {
-      const double tau = I.x0 + (i + 0.5) * I.dx, nu = I.y0 + (j + 0.5) * I.dy;
-      if (tau < I.ssplit[s][0] + I.ssplit[s][1] * t + I.ssplit[s][2] * nu) return I.spre[s];
-      if (I.skind[s] == 3) return I.sstate[s];
+      if (I.skind[s] == 3) return true;
+      const double xc = I.x0 + (i + 0.5) * I.dx, yc = I.y0 + (j + 0.5) * I.dy;
+      if (xc < I.ssplit[s][0] + I.ssplit[s][1] * t + I.ssplit[s][2] * yc) return true;
     }
   }
   if (i < 0 || i >= I.nx) {
     const int s = i < 0 ? 0 : 1;
-    if (((I.pres >> s) & 1) && I.skind[s] == 3) return I.sstate[s];
+    if (((I.pres >> s) & 1) && I.skind[s] == 3) return true;
   }
-  return nullptr;
+  return false;
+}
+
+/* moment m of component c of a ghost cell with prescribed data (see
+   mr_presc_any); false if the cell holds none */
+MR_INL bool mr_presc(const mr_inst& I, int c, int m, int i, int j, double t, double* val) {
+#pragma clang fp contract(off)
+  if (I.dim == 2 && (j < 0 || j >= I.ny)) {
+    const int s = j < 0 ? 2 : 3;
+    if ((I.pres >> s) & 1) {
+      const double xc = I.x0 + (i + 0.5) * I.dx, yc = I.y0 + (j + 0.5) * I.dy;
+      const double A = I.spre[s][c];
+      if (I.skind[s] == 3) {
+        const double B = I.sstate[s][c];
+        double a = 0.0, mx = 0.0, my = 0.0;
+        if (I.ssplit[s][0] > -HUGE_VAL)
+          mr_clip(I.dx, -I.ssplit[s][2] * I.dy, I.ssplit[s][0] + I.ssplit[s][1] * t + I.ssplit[s][2] * yc - xc,
+                  &a, &mx, &my);
+        *val = m == 0 ? B + (A - B) * a : (A - B) * (m == 1 ? mx : my);
+        return true;
+      }
+      if (xc < I.ssplit[s][0] + I.ssplit[s][1] * t + I.ssplit[s][2] * yc) {
+        *val = m == 0 ? A : 0.0;
+        return true;
+      }
+    }
+  }
+  if (i < 0 || i >= I.nx) {
+    const int s = i < 0 ? 0 : 1;
+    if (((I.pres >> s) & 1) && I.skind[s] == 3) {
+      *val = m == 0 ? I.sstate[s][c] : 0.0;
+      return true;
+    }
+  }
+  return false;
 }
 
 /* The x face f of row j (between cells (f-1, j) and (f, j)), or the y face
@@ -56,11 +124,11 @@ MR_INL const double* mr_presc(const mr_inst& I, int i, int j, double t) {
  * the ghost across the face holds no prescribed state. */
 MR_INL bool mr_wall_x(const mr_inst& I, int f, int j, double t) {
   if (!mr_wall(f, I.nx, I.bcx)) return false;
-  return !((I.pres >> (f == 0 ? 0 : 1)) & 1) || !mr_presc(I, f == 0 ? -1 : I.nx, j, t);
+  return !((I.pres >> (f == 0 ? 0 : 1)) & 1) || !mr_presc_any(I, f == 0 ? -1 : I.nx, j, t);
 }
 MR_INL bool mr_wall_y(const mr_inst& I, int i, int f, double t) {
   if (!mr_wall(f, I.ny, I.bcy)) return false;
-  return !((I.pres >> (f == 0 ? 2 : 3)) & 1) || !mr_presc(I, i, f == 0 ? -1 : I.ny, t);
+  return !((I.pres >> (f == 0 ? 2 : 3)) & 1) || !mr_presc_any(I, i, f == 0 ? -1 : I.ny, t);
 }
 
 struct mr_grid {
@@ -75,8 +143,8 @@ struct mr_grid {
 /* moment m of component c at cell (i, j) with ghost handling */
 MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
   if (g.I && (i < 0 || i >= g.nx || (g.nm == 3 && (j < 0 || j >= g.ny))) && g.I->pres) {
-    const double* st = mr_presc(*g.I, i, j, g.t);
-    if (st) return m == 0 ? st[c] : 0.0;
+    double v;
+    if (mr_presc(*g.I, c, m, i, j, g.t, &v)) return v;
   }
   int kx = 0, ky = 0;
   const int ii = mr_fold(i, g.nx, g.bcx, &kx);

@@ -145,17 +145,16 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
         if (tid + q * MR_BLOCK < NROW)
           d[tid + q * MR_BLOCK] = ((z >> q) & 1u) ? 0.0 : (((z >> (16 + q)) & 1u) ? -v[q] : v[q]);
     };
-    /* ghosts of the stored rows y .. y+nr-1 that hold a prescribed state
-       (average; first moments zero), overwritten by the threads that
-       stored them */
+    /* ghosts of the stored rows y .. y+nr-1 that hold prescribed data,
+       overwritten by the threads that stored them */
     auto prescribe = [&](int y, int nr) {
 #pragma unroll 1
       for (int r = y; r < y + nr; ++r)
 #pragma unroll 1
         for (int k = tid; k < NROW; k += MR_BLOCK) {
           const int pl = k / KX_XW;
-          const double* st = mr_presc(I, xs + k % KX_XW, r, tb);
-          if (st) mom[kx_slot(r, KX_MR)][k] = pl % 3 == 0 ? st[pl / 3] : 0.0;
+          double v;
+          if (mr_presc(I, pl / 3, pl % 3, xs + k % KX_XW, r, tb, &v)) mom[kx_slot(r, KX_MR)][k] = v;
         }
     };
     /* prologue: moment rows y0-2 .. y0+3 */

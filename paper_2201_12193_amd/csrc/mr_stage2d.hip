@@ -209,7 +209,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
         }
         if (tid < XW) sh.flg[sb][tid] = pref;
         if (GB && I.pres) {
-          /* ghosts that hold a prescribed state (average; first moments 0) */
+          /* ghosts that hold prescribed data */
           const double tb = mr_stage_time(I, mode);
 #pragma unroll 1
           for (int q = 0; q < NE; ++q) {
@@ -218,9 +218,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
               const int pl = e / XW, col = e % XW;
               const bool isA = pl < 2 * NC;
               const int c = isA ? pl / 2 : pl - 2 * NC, m = isA ? (pl % 2) * 2 : 1;
-              const double* st = mr_presc(I, xs0 + col, isA ? y + 3 : y + 2, tb);
-              if (st) {
-                const double v = m == 0 ? st[c] : 0.0;
+              double v;
+              if (mr_presc(I, c, m, xs0 + col, isA ? y + 3 : y + 2, tb, &v)) {
                 if (isA) sh.mA[sa][pl][col] = v;
                 else sh.mB[sb][pl - 2 * NC][col] = v;
               }

@@ -46,10 +46,11 @@ class Side:
     """Boundary data of one side (used where bc_x or bc_y is SIDES).
 
     kind: TRANSMISSIVE, REFLECTIVE or INFLOW (ghosts hold `state`, first
-    moments zero).  On the bottom and top sides the ghosts whose centre has
-    tangential coordinate tau < s0 + st t + sn nu (nu the normal coordinate
-    of the centre; split = (s0, st, sn)) hold `pre` instead: a straight
-    front moving at a constant speed."""
+    moments zero).  On the bottom and top sides a front x < s0 + st t + sn y
+    (split = (s0, st, sn); a straight front moving at a constant speed) puts
+    `pre` before it: on an INFLOW side ghosts hold the exact moments of the
+    two-state field, before a folded side a ghost whose centre lies before
+    the front holds `pre`."""
     kind: int = TRANSMISSIVE
     state: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0)
     pre: Tuple[float, ...] = (0.0, 0.0, 0.0, 0.0)
@@ -427,10 +428,9 @@ def double_mach_2d(ny: int = 400, tc_mode: int = TC_KXRCF, t_final: float = 0.2,
     """Example 3.9: [0, 4] x [0, 1], 4*ny x ny cells, a Mach 10 shock
     (gamma 1.4) through (1/6, 0) at 60 degrees to the x axis moving right
     into gas at rest (rho = 1.4, p = 1).  Bottom: the post-shock state for
-    x < 1/6, a reflective wall beyond; top: the exact motion of the shock
-    (post-shock ghosts left of x = 1/6 + (y + 20 t)/sqrt(3), pre-shock
-    ghosts right of it, sampled at ghost centres); left: post-shock inflow;
-    right: transmissive.  Initial moments are exact: cells cut by the front
+    x < 1/6 (ghost centres), a reflective wall beyond; top: the exact motion
+    of the shock x = 1/6 + (y + 20 t)/sqrt(3) (ghosts hold the exact moments
+    of the two states); left: post-shock inflow; right: transmissive.  Initial moments are exact: cells cut by the front
     are clipped by it.  Returns (problem, U)."""
     gamma = 1.4
     (r1, _, p1), (r2, un, p2), ms = mach_shock_states(10.0, gamma)
