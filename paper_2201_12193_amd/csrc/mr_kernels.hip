@@ -42,12 +42,19 @@ MR_INL void mr_block_max2(double* ax, double* ay, double* sh) {
 /* Each work group takes a contiguous run of `chunk` work items, keeps a
  * running max per instance and publishes it with one atomic per instance
  * run (max is exact, so the result does not depend on the order).  The
- * loads of four work items are issued together so that their latencies
+ * descriptors of up to MR_BLOCK work items (instance, base of the data,
+ * cell count) are read in parallel, one per thread, into LDS first: the
+ * chain item -> instance -> state pointer -> data then costs one round of
+ * latencies per batch instead of one per item.  The loads of
+ * MR_RED_ITEMS work items are issued together so that their latencies
  * overlap. */
+#define MR_RED_ITEMS 8
 __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_tile1* tiles, int ntiles,
                                                      int stage, int chunk) {
 #pragma clang fp contract(off)
   __shared__ double sh[2 * (MR_BLOCK / 64)];
+  __shared__ unsigned long long s_base[MR_BLOCK];   /* data of the item (0: skipped) */
+  __shared__ int s_inst[MR_BLOCK], s_cnt[MR_BLOCK];
   const int t0 = blockIdx.x * chunk, t1 = min(ntiles, t0 + chunk);
   int cur = -1;
   double ax = 0.0, ay = 0.0;
@@ -69,59 +76,69 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
     ax = ay = 0.0;
     bad = 0;
   };
-  for (int g0 = t0; g0 < t1; g0 += 4) {
-    double u[4][4];
-    int inst[4], use[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int t = g0 + q;
-      inst[q] = -1;
-      use[q] = 0;
-      if (t >= t1) continue;
-      const mr_tile1 tl = tiles[t];
+  for (int b0 = t0; b0 < t1; b0 += MR_BLOCK) {
+    const int nb = min(MR_BLOCK, t1 - b0);
+    __syncthreads();   /* the previous batch's descriptors are consumed */
+    if ((int)threadIdx.x < nb) {
+      const mr_tile1 tl = tiles[b0 + threadIdx.x];
       const mr_inst& I = insts[tl.inst];
-      inst[q] = tl.inst;
-      const MR_GLB double* U;
+      const double* U = nullptr;
       if (stage == 0) {
-        if (I.err) continue;
-        U = mr_gp(I.buf[I.cur]);
-      } else {
-        if (!I.active || I.flux != 0) continue;
-        U = mr_gp(I.p_out[stage - 1]);
+        if (!I.err) U = I.buf[I.cur];
+      } else if (I.active && I.flux == 0) {
+        U = I.p_out[stage - 1];
       }
-      const int k = tl.start + (int)threadIdx.x;
-      if (k >= tl.start + tl.count) continue;
-      use[q] = 1;
-      const long long P = I.plane;
-      const int nm = I.dim + 1;
-#pragma unroll
-      for (int c = 0; c < 4; ++c) u[q][c] = c < I.nc ? U[(long long)c * nm * P + k] : 0.0;
+      s_base[threadIdx.x] = U ? (unsigned long long)(U + tl.start) : 0ull;
+      s_inst[threadIdx.x] = tl.inst;
+      s_cnt[threadIdx.x] = tl.count;
     }
+    __syncthreads();
+    for (int g0 = 0; g0 < nb; g0 += MR_RED_ITEMS) {
+      double u[MR_RED_ITEMS][4];
+      int inst[MR_RED_ITEMS], use[MR_RED_ITEMS];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (inst[q] < 0) break;
-      if (inst[q] != cur) {
-        if (cur >= 0) flush();
-        cur = inst[q];
+      for (int q = 0; q < MR_RED_ITEMS; ++q) {
+        const int t = g0 + q;
+        inst[q] = -1;
+        use[q] = 0;
+        if (t >= nb) continue;
+        inst[q] = s_inst[t];
+        const unsigned long long base = s_base[t];
+        if (!base || (int)threadIdx.x >= s_cnt[t]) continue;
+        const mr_inst& I = insts[inst[q]];
+        const MR_GLB double* U = mr_gp((const double*)base) + threadIdx.x;
+        use[q] = 1;
+        const long long P = I.plane;
+        const int nm = I.dim + 1;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) u[q][c] = c < I.nc ? U[(long long)c * nm * P] : 0.0;
       }
-      if (!use[q]) continue;
-      const mr_inst& I = insts[inst[q]];
-      if (I.flux == 0) {
-        const double a = fabs(u[q][0]);
-        ax = fmax(ax, a);
-        ay = fmax(ay, a);
-        bad |= !(a <= 1.0e300);
-      } else {
-        double ke = u[q][1] * u[q][1];
-        if (I.nc == 4) ke += u[q][2] * u[q][2];
-        const double E = I.nc == 4 ? u[q][3] : u[q][2];
-        const double p = (I.gam - 1.0) * (E - 0.5 * ke / u[q][0]);
-        const double cs = sqrt(I.gam * p / u[q][0]);
-        const double sx = fabs(u[q][1] / u[q][0]) + cs;
-        const double sy = (I.nc == 4) ? fabs(u[q][2] / u[q][0]) + cs : 0.0;
-        const int b = !(u[q][0] > 0.0) || !(p > 0.0) || !(sx <= 1.0e300) || !(sy <= 1.0e300);
-        bad |= b;
-        if (!b) { ax = fmax(ax, sx); ay = fmax(ay, sy); }
+#pragma unroll
+      for (int q = 0; q < MR_RED_ITEMS; ++q) {
+        if (inst[q] < 0) break;
+        if (inst[q] != cur) {
+          if (cur >= 0) flush();
+          cur = inst[q];
+        }
+        if (!use[q]) continue;
+        const mr_inst& I = insts[inst[q]];
+        if (I.flux == 0) {
+          const double a = fabs(u[q][0]);
+          ax = fmax(ax, a);
+          ay = fmax(ay, a);
+          bad |= !(a <= 1.0e300);
+        } else {
+          double ke = u[q][1] * u[q][1];
+          if (I.nc == 4) ke += u[q][2] * u[q][2];
+          const double E = I.nc == 4 ? u[q][3] : u[q][2];
+          const double p = (I.gam - 1.0) * (E - 0.5 * ke / u[q][0]);
+          const double cs = sqrt(I.gam * p / u[q][0]);
+          const double sx = fabs(u[q][1] / u[q][0]) + cs;
+          const double sy = (I.nc == 4) ? fabs(u[q][2] / u[q][0]) + cs : 0.0;
+          const int b = !(u[q][0] > 0.0) || !(p > 0.0) || !(sx <= 1.0e300) || !(sy <= 1.0e300);
+          bad |= b;
+          if (!b) { ax = fmax(ax, sx); ay = fmax(ay, sy); }
+        }
       }
     }
   }
