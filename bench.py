@@ -40,7 +40,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2
 # at their minimal operation counts: 5.9 kFLOP
 STAGE_BYTES_PER_CELL = (2 * 96 + 3 * 96 + 3 * 96) / 3.0
 STAGE_FLOP_PER_CELL = 5900.0
-STAGE_KERNEL = "k2_stage<4,false>"
+STAGE_KERNEL = "k2_stage<4,false,false>"
 COUNTERS = os.path.join(ROOT, "profiles", "k2_stage_euler2d_2048_counters.json")
 STAGE_SOURCES = ["mr_stage2d.hip", "mr_common.h", "mr_device.h", "mr_types.h", "recon_gen.h"]
 

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k_features(const mr_inst* insts, int
   if (e >= (long long)n * MR_KP) return;
   const int smp = (int)(e / MR_KP), f = (int)(e % MR_KP);
   const mr_inst& I = insts[inst];
-  const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, 3)};
+  const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, nullptr, 0.0};
   const int cell = cells[smp];
   if (cell < 0 || (long long)cell >= I.plane) {   /* not an interior cell */
     out[e] = (__bf16)0.0f;
@@ -142,7 +142,7 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
     mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
     if (I.tc != 3) continue;
-    const mr_grid gr{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, stage)};
+    const mr_grid gr{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, nullptr, 0.0};
     MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
     const int fh = I.fhalo, fex = I.fex;
     const int xs = tl.x0 - 2, ylo = tl.y0, yhi = tl.y0 + tl.rows;
@@ -341,7 +341,11 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
   }
 }
 
-/* KXRCF for the cells the network left undecided (band list, count
+/* The learned indicator takes no per-side boundary data (the library
+ * rejects the combination), so its grids carry no instance for prescribed
+ * ghosts.
+ *
+ * KXRCF for the cells the network left undecided (band list, count
  * cnt[stage]), in three passes that share the face data of neighbouring band
  * cells:
  *   k_fb_mark:    every band cell claims itself and its four neighbours in
@@ -401,7 +405,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k_fb_summary(mr_inst* insts, 
     const mr_band b = list[k];
     mr_inst& I = insts[b.inst];
     if ((I.beta_on != 0) != BP) continue;
-    const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, stage)};
+    const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, nullptr, 0.0};
     mr_fb_summary_cell<BP>(I, g, b.e);
   }
 }
