@@ -59,11 +59,12 @@ def parse():
                     help="learned-indicator uncertainty band (KXRCF inside)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--workload", default="quadrants2d",
-                    choices=("quadrants2d", "batched", "riemann1d", "burgers1d"),
-                    help="quadrants2d: the benchmark above; the others time the batched and 1D "
-                         "configurations (256 instances of uneven sizes in one launch per kernel "
-                         "class; 1D Euler N = 4096; 1D Burgers N = 200) with every instance kept "
-                         "advancing")
+                    choices=("quadrants2d", "batched", "riemann1d", "burgers1d", "dmr2d"),
+                    help="quadrants2d: the benchmark above; batched, riemann1d, burgers1d time the "
+                         "batched and 1D configurations (256 instances of uneven sizes in one launch "
+                         "per kernel class; 1D Euler N = 4096; 1D Burgers N = 200) with every "
+                         "instance kept advancing; dmr2d times the whole double Mach reflection "
+                         "(Example 3.9, 1600 x 400) to T = 0.2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
@@ -233,12 +234,51 @@ def other_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def dmr_workload(args):
+    """The double Mach reflection of Example 3.9 at 1600 x 400 (HWENO6-M5-I,
+    CFL 0.6, modification internal to L), the whole run to T = 0.2 timed."""
+    import torch
+    from paper_2201_12193_amd import inputs as I
+    from paper_2201_12193_amd.mrhweno import Solver
+    from paper_2201_12193_amd import autotune
+    prob, U0 = I.double_mach_2d(ny=400)
+    Ut = torch.from_numpy(U0).cuda()
+    s = Solver([prob], [Ut])
+    shape = autotune.tune(s, use_cache=False, reps=3)[:2]
+    s.step(args.warmup)                   # warm-up, then back to the initial state
+    s.sync(raise_on_error=False)
+    Ut.copy_(torch.from_numpy(U0))
+    s.set_time(0, 0.0, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status = 0
+    while True:
+        s.step(500)
+        t, steps, status = s.sync(raise_on_error=False)
+        if status != 0 or t[0] >= prob.t_final:
+            break
+    wall = time.perf_counter() - t0
+    rho = Ut[0, 0]
+    out = {"metric": "MR-HWENO cell-updates/s (FP64)", "value": prob.ncell * 3 * steps[0] / wall,
+           "unit": "cell-updates/s", "n_gpus": 1, "steps": steps[0], "warmup": args.warmup,
+           "ms_per_step": wall / max(steps[0], 1) * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "double Mach reflection (Example 3.9), 1600 x 400, HLLC, KXRCF (M5-I), "
+                                  "CFL 0.6, to T = 0.2", "cells": prob.ncell, "t_reached": t[0],
+                      "status": status, "rho_max": float(rho.max().item()),
+                      "launch": {"rows_per_strip": shape[0], "grid": shape[1], "chosen_by": "autotuner"}}}
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU decomposition is a design, not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "dmr2d":
+        return dmr_workload(args)
     if args.workload != "quadrants2d":
         return other_workload(args)
     import torch

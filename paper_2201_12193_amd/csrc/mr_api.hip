@@ -44,7 +44,9 @@ constexpr int kFHalo = 2;   /* flags: final values of cells -1..n need flags -2.
 constexpr int kSHalo = 3;   /* summaries: flags of cells -2..n+1 need summaries -3..n+2 */
 constexpr int kMinRows = 8; /* smallest 2D strip height the work lists are sized for */
 constexpr int kKxW = 62;    /* 2D KXRCF work item: 62 flag columns ...                */
-constexpr int kKxRows = 46; /* ... x 46 flag rows of the extended flag range          */
+constexpr int kKxRows = 46; /* ... x up to 46 flag rows of the extended flag range    */
+constexpr int kKxMinRows = 8;
+constexpr int kKxFill = 512; /* work groups that fill the GPU (256 CUs x 2 resident)    */
 constexpr int kLearnW = 64;     /* learned-indicator work item: 64 columns ...       */
 constexpr int kLearnRows = 32;  /* ... x 32 rows of the extended flag range          */
 
@@ -77,9 +79,16 @@ int learn_tiles(const mrhweno_problem& p) {
   return learned(p) ? ceil_div_i(ext(p.nx, kFHalo), kLearnW) * ceil_div_i(ext(p.ny, kFHalo), kLearnRows) : 0;
 }
 int strip_cells(const mrhweno_problem& p) { return kBlock / ncomp_of(p); }   /* 2D strip width incl. ring */
+/* rows of a 2D KXRCF work item: 46 (each strip also reconstructs a ring row
+   above and below), fewer for grids too small to fill the GPU otherwise */
+int kx_rows(const mrhweno_problem& p) {
+  const int cols = ceil_div_i(ext(p.nx, kFHalo), kKxW);
+  const int r = ceil_div_i(ext(p.ny, kFHalo), ceil_div_i(kKxFill, cols));
+  return std::min(kKxRows, std::max(kKxMinRows, r));
+}
 /* 2D KXRCF work items: strips over [-2, n+2)^2 */
 int kx_tiles(const mrhweno_problem& p) {
-  return p.dim == 2 && indicator_pass(p) ? ceil_div_i(ext(p.nx, kFHalo), kKxW) * ceil_div_i(ext(p.ny, kFHalo), kKxRows) : 0;
+  return p.dim == 2 && indicator_pass(p) ? ceil_div_i(ext(p.nx, kFHalo), kKxW) * ceil_div_i(ext(p.ny, kFHalo), kx_rows(p)) : 0;
 }
 
 std::string validate(const mrhweno_problem& p) {
@@ -220,9 +229,10 @@ struct Group {
 
 /* learned-indicator work items of one instance (instance id `slot`) */
 void add_kx_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p) {
-  for (int y0 = -kFHalo; y0 < p.ny + kFHalo; y0 += kKxRows)
+  const int rows = kx_rows(p);
+  for (int y0 = -kFHalo; y0 < p.ny + kFHalo; y0 += rows)
     for (int x0 = -kFHalo; x0 < p.nx + kFHalo; x0 += kKxW)
-      v.push_back(mr_tile2{slot, x0, y0, std::min(kKxRows, p.ny + kFHalo - y0)});
+      v.push_back(mr_tile2{slot, x0, y0, std::min(rows, p.ny + kFHalo - y0)});
 }
 
 void add_learn_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p) {
