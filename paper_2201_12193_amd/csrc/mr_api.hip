@@ -18,9 +18,9 @@
 extern "C" {
 hipError_t mr_launch_reduce(hipStream_t, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_finalize(hipStream_t, mr_inst*, int, int);
-hipError_t mr_launch_summary(hipStream_t, int, int, mr_inst*, const mr_tile1*, int, int);
+hipError_t mr_launch_summary(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_flags(hipStream_t, int, mr_inst*, const mr_tile1*, int, int);
-hipError_t mr_launch_stage1(hipStream_t, int, int, mr_inst*, const mr_tile1*, int, int, int);
+hipError_t mr_launch_stage1(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, int, int);
 hipError_t mr_launch_stage2(hipStream_t, int, int, int, mr_inst*, const mr_tile2*, int, int, int);
 hipError_t mr_launch_kxrcf2(hipStream_t, int, int, int, mr_inst*, const mr_tile2*, int, int);
 hipError_t mr_launch_values(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, double*);
@@ -397,7 +397,7 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
     for (auto& g : c->groups)
       if (g.any_summ) {
         any = true;
-        if ((e = mr_launch_summary(s, g.dim, g.bp, c->d, c->t1 + g.t_summ, g.n_summ, st)) != hipSuccess) return e;
+        if ((e = mr_launch_summary(s, g.dim, g.bp, g.gb, c->d, c->t1 + g.t_summ, g.n_summ, st)) != hipSuccess) return e;
       }
     for (auto& g : c->groups) {
       if (g.n_kx > 0) {
@@ -422,7 +422,7 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
       return e;
     if ((e = mark(c, P, 2)) != hipSuccess) return e;
     for (auto& g : c->groups) {
-      if (g.dim == 1) e = mr_launch_stage1(s, g.nc, g.bp, c->d, c->t1 + g.t_st1, g.n_st1, st, 0);
+      if (g.dim == 1) e = mr_launch_stage1(s, g.nc, g.bp, g.gb, c->d, c->t1 + g.t_st1, g.n_st1, st, 0);
       else e = mr_launch_stage2(s, g.nc, g.bp, g.gb, c->d, c->t2 + g.t_st2, g.n_st2, st, c->grid2);
       if (e != hipSuccess) return e;
     }
@@ -854,7 +854,7 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
       MR_CHECK(c, hipMemcpy2DAsync(out, p.nx, I.flags[0] + frow, I.fex, p.nx, p.ny, hipMemcpyDeviceToDevice, s));
     MR_CHECK(c, mr_launch_fallback(s, c->d, c->band, c->slist, c->cnt, 3, c->grid_fb, p.beta_on));
   } else {
-    MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, c->d, d1 + t_sum, n_sum, 3));
+    MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, I.pres != 0, c->d, d1 + t_sum, n_sum, 3));
     MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));
     if (kx2)
       MR_CHECK(c, mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? 3 : 1, p.beta_on, I.pres != 0, c->d, d3, (int)tl.size(), 3));
@@ -862,7 +862,7 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   const int nc = ncomp_of(p);
   if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + t_val, n_val, (double*)out));
   if (kind == 2) {
-    if (p.dim == 1) MR_CHECK(c, mr_launch_stage1(s, nc, p.beta_on, c->d, d1 + t_st, n_st, 3, 0));
+    if (p.dim == 1) MR_CHECK(c, mr_launch_stage1(s, nc, p.beta_on, I.pres != 0, c->d, d1 + t_st, n_st, 3, 0));
     else MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, c->d, d2, (int)t2.size(), 3, 0));
   }
   if (flags)

@@ -140,18 +140,22 @@ struct mr_grid {
   double t;
 };
 
-/* moment m of component c at cell (i, j) with ghost handling */
+/* moment m of component c at cell (i, j) with ghost handling: the folded
+   cell is always loaded (it lies in the grid) and the ghost rules applied
+   to the value, so that a run of these loads issues without branches; the
+   prescribed data of an inflow side or front, rare, replace it last */
 MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
-  if (g.I && (i < 0 || i >= g.nx || (g.nm == 3 && (j < 0 || j >= g.ny))) && g.I->pres) {
-    double v;
-    if (mr_presc(*g.I, c, m, i, j, g.t, &v)) return v;
-  }
   int kx = 0, ky = 0;
   const int ii = mr_fold(i, g.nx, g.bcx, &kx);
   const int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &ky) : 0;
-  if ((kx == 1 || ky == 1) && m > 0) return 0.0;
-  const double v = g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
-  return ((kx == 2 && mr_refl_flip(c, m, 0)) != (ky == 2 && mr_refl_flip(c, m, 1))) ? -v : v;
+  double v = g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
+  v = ((kx == 2 && mr_refl_flip(c, m, 0)) != (ky == 2 && mr_refl_flip(c, m, 1))) ? -v : v;
+  v = ((kx == 1 || ky == 1) && m > 0) ? 0.0 : v;
+  if (g.I && (kx | ky) && g.I->pres) {
+    double pv;
+    if (mr_presc(*g.I, c, m, i, j, g.t, &pv)) v = pv;
+  }
+  return v;
 }
 
 /* Step 1 of a 1D cell for its NC components from the three-cell stencil

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
   };
   for (int b0 = t0; b0 < t1; b0 += MR_BLOCK) {
     const int nb = min(MR_BLOCK, t1 - b0);
-    __syncthreads();   /* the previous batch's descriptors are consumed */
+    if (b0 != t0) __syncthreads();   /* the previous batch's descriptors are consumed */
     if ((int)threadIdx.x < nb) {
       const mr_tile1 tl = tiles[b0 + threadIdx.x];
       const mr_inst& I = insts[tl.inst];
@@ -205,7 +205,7 @@ __global__ void k_finalize(mr_inst* insts, int n, int probe) {
 /* KXRCF face data per cell over the extended range [-3, nx+3):
  * plane 0: own value at x_{i-1/2}, 1: at x_{i+1/2}, 2: velocity at
  * x_{i-1/2}, 3: velocity at x_{i+1/2}, 4: max |u| over the 4 GL points. */
-template <bool BP>
+template <bool BP, bool GB>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
   mr_kt_fill();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -216,7 +216,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
     const int i = e - I.shalo;
-    mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2, &I, mr_stage_time(I, stage)};
+    mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, 1, I.bcx, I.bcy, 2, GB ? &I : nullptr,
+              mr_stage_time(I, stage)};
     double r[4];
     double vl, vr;
     if (I.charwise) {
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_ti
 /* 1D stage: one thread per cell of a block-sized tile; the two edge threads
  * are ring cells that only supply face values.  mode 0..2 = RK stage,
  * mode 3 = write L(U) (input p_in[0], output p_out[0]). */
-template <int NC, bool BP>
+template <int NC, bool BP, bool GB>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, const mr_tile1* tiles, int ntiles, int mode) {
   mr_kt_fill();
   __shared__ double s_tr[MR_BLOCK * NC];
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
     const mr_inst& I = insts[tl.inst];
     if (mode < 3 && !I.active) continue;
     const int st = mode == 3 ? 0 : mode;
-    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, 1, I.bcx, I.bcy, 2, &I, mr_stage_time(I, mode)};
+    const mr_grid g{mr_gp(I.p_in[st]), I.plane, I.nx, 1, I.bcx, I.bcy, 2, GB ? &I : nullptr, mr_stage_time(I, mode)};
     const MR_GLB unsigned char* fl = mr_gp(I.flags[(mode == 0 || mode == 3) ? 0 : 1]);
     const int x = tl.start - 1 + cs;
     const int fh = I.fhalo;
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
       MR_GLB double* O = mr_gp(I.p_out[st]);
       const long long P = I.plane;
       const double dt = I.dt;
-      const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, 1, I.bcx, I.bcy, 2, &I, mr_stage_time(I, 0)};
+      const mr_grid gn{mr_gp(I.p_un), I.plane, I.nx, 1, I.bcx, I.bcy, 2, GB ? &I : nullptr, mr_stage_time(I, 0)};
       /* U^n with the stage-1 modification (stored first moments unless it persists) */
       const int f1 = (mode == 1 || mode == 2) && I.mod == 0 ? mr_flag(mr_gp(I.flags[0]), I.fex, 1, fh, x, 0) : 0;
 #pragma unroll
@@ -475,11 +476,19 @@ hipError_t mr_launch_finalize(hipStream_t s, mr_inst* d, int n, int probe) {
   return hipGetLastError();
 }
 
-hipError_t mr_launch_summary(hipStream_t s, int dim, int bp, mr_inst* d, const mr_tile1* t, int nt, int stage) {
+/* gb: some instance of the list has ghosts that hold prescribed data (the
+   variants without that code run everything else) */
+hipError_t mr_launch_summary(hipStream_t s, int dim, int bp, int gb, mr_inst* d, const mr_tile1* t, int nt, int stage) {
   if (nt <= 0) return hipSuccess;
   if (dim != 1) return hipErrorInvalidValue;   /* 2D: k2_kxrcf */
-  if (bp) hipLaunchKernelGGL(k1_summary<true>, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
-  else hipLaunchKernelGGL(k1_summary<false>, dim3(nt), dim3(MR_BLOCK), 0, s, d, t, nt, stage);
+  const dim3 G(nt), B(MR_BLOCK);
+  if (bp) {
+    if (gb) hipLaunchKernelGGL((k1_summary<true, true>), G, B, 0, s, d, t, nt, stage);
+    else hipLaunchKernelGGL((k1_summary<true, false>), G, B, 0, s, d, t, nt, stage);
+  } else {
+    if (gb) hipLaunchKernelGGL((k1_summary<false, true>), G, B, 0, s, d, t, nt, stage);
+    else hipLaunchKernelGGL((k1_summary<false, false>), G, B, 0, s, d, t, nt, stage);
+  }
   return hipGetLastError();
 }
 
@@ -490,10 +499,15 @@ hipError_t mr_launch_flags(hipStream_t s, int dim, mr_inst* d, const mr_tile1* t
   return hipGetLastError();
 }
 
-hipError_t mr_launch_stage1(hipStream_t s, int nc, int bp, mr_inst* d, const mr_tile1* t, int nt, int mode, int grid) {
+hipError_t mr_launch_stage1(hipStream_t s, int nc, int bp, int gb, mr_inst* d, const mr_tile1* t, int nt, int mode,
+                            int grid) {
   if (nt <= 0) return hipSuccess;
   const dim3 G(grid > 0 && grid < nt ? grid : nt), B(MR_BLOCK);
-#define MR_L1(NC_, BP_) hipLaunchKernelGGL((k1_stage<NC_, BP_>), G, B, 0, s, d, t, nt, mode)
+#define MR_L1(NC_, BP_)                                                                  \
+  do {                                                                                   \
+    if (gb) hipLaunchKernelGGL((k1_stage<NC_, BP_, true>), G, B, 0, s, d, t, nt, mode);  \
+    else hipLaunchKernelGGL((k1_stage<NC_, BP_, false>), G, B, 0, s, d, t, nt, mode);    \
+  } while (0)
   if (nc == 1) { if (bp) MR_L1(1, true); else MR_L1(1, false); }
   else if (nc == 3) { if (bp) MR_L1(3, true); else MR_L1(3, false); }
   else return hipErrorInvalidValue;
