@@ -269,6 +269,38 @@ def example_lax(n: int = 200, tc_mode: int = TC_KXRCF, **kw):
     return prob, project_1d(prob, cons, jumps=[0.0]), (left, right)
 
 
+def example_shock_density(n: int = 400, tc_mode: int = TC_KXRCF, **kw):
+    """Example 3.6, a Mach 3 shock running into sine waves in the density on
+    [-5, 5], T = 1.8, gamma = 1.4; transmissive ends (the paper does not
+    state them)."""
+    prob = Problem(dim=1, nx=n, x0=-5.0, x1=5.0, system=EULER, gamma=1.4, bc_x=TRANSMISSIVE,
+                   t_final=1.8, tc_mode=tc_mode, **kw)
+    left = (3.857143, 2.629369, 10.333333)
+
+    def cons(x):
+        l = x < -4.0
+        rho = np.where(l, left[0], 1.0 + 0.2 * np.sin(5.0 * x))
+        u = np.where(l, left[1], 0.0)
+        p = np.where(l, left[2], 1.0)
+        return euler1d_cons(rho, u, p, 1.4)
+    return prob, project_1d(prob, cons, jumps=[-4.0]), left
+
+
+def example_sedov(n: int = 401, tc_mode: int = TC_KXRCF, **kw):
+    """Example 3.8, the Sedov blast wave on [-2, 2], T = 0.001, gamma = 1.4:
+    rho = 1, u = 0, E = 1e-12 except the centre cell, E = 3200000/dx there
+    (an odd cell count, so that there is a centre cell); transmissive ends."""
+    if n % 2 == 0:
+        raise ValueError("the Sedov problem needs an odd number of cells")
+    prob = Problem(dim=1, nx=n, x0=-2.0, x1=2.0, system=EULER, gamma=1.4, bc_x=TRANSMISSIVE,
+                   t_final=0.001, tc_mode=tc_mode, **kw)
+    U = np.zeros(prob.shape())
+    U[0, 0] = 1.0
+    U[2, 0] = 1e-12
+    U[2, 0, n // 2] = 3200000.0 / prob.dx
+    return prob, U
+
+
 # --------------------------------------------------------------------------
 # Seeded synthetic workloads
 # --------------------------------------------------------------------------
