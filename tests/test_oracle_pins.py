@@ -731,3 +731,29 @@ def test_lax_problem_against_exact_riemann():
     x = prob.x0 + (np.arange(prob.nx) + 0.5) * prob.dx
     # waves of the exact solution at t = 0.16 lie within x/t in [-2.7, 2.6]
     assert np.all(np.abs(x[fl.astype(bool)] / 0.16) < 3.0)
+
+
+def test_hllc_mirror_wall_holds_below_and_leaks_above_normal_mach_two():
+    """A reflective wall is the printed HLLC flux (R10) between a state and
+    its mirror image.  The linearised star pressure it prints,
+    p* = (pL + pR + (uL - uR) c* rho*)/2, underestimates the pressure of
+    the reflected shock: for a stream at rest pressure 1, density 1.4 (sound
+    speed 1) and normal Mach number M it gives s_L = M - coef with
+    coef = sqrt(1 + (gamma+1)(p*/p - 1)/(2 gamma)).  Below M ~ 1.8 s_L < 0
+    and the wall carries no mass; from M = 2 on s_L > 0 and the flux is the
+    upwind one, so the stream passes through the wall (why Example 3.10's
+    Mach 3 stream against the step cannot be run with this flux)."""
+    g = 1.4
+    for M, holds in ((0.5, True), (1.0, True), (1.5, True), (2.0, False), (3.0, False)):
+        W = np.array(I.euler2d_cons(np.array(1.4), np.array(M), np.array(0.0), np.array(1.0), g), dtype=float)
+        Wm = W.copy()
+        Wm[1] = -W[1]
+        pstar = (1.0 + 1.0 + (M + M) * 1.0 * 1.4) / 2.0
+        sL = M - math.sqrt(1.0 + (g + 1.0) * (pstar - 1.0) / (2.0 * g))
+        assert (sL < 0.0) == holds
+        f = oracle.hllc(W, Wm, g, 0)
+        if holds:
+            assert abs(f[0]) < 1e-14
+        else:
+            # the physical flux of the incoming state
+            assert np.allclose(f, [W[1], W[1] * M + 1.0, 0.0, M * (W[3] + 1.0)], rtol=1e-14)
