@@ -274,8 +274,8 @@ def dmr_workload(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU decomposition is a design, not part of this build)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU domain decomposition is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "dmr2d":
         return dmr_workload(args)
