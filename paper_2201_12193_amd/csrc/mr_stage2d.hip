@@ -125,6 +125,16 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
     double pAu = 0.0, pAv = 0.0, pAw = 0.0, pB0 = 0.0, pB1 = 0.0, pU = 0.0, pV = 0.0, pW = 0.0;
     for (int jr = -1; jr <= tl.rows; ++jr) {
       const int y = tl.y0 + jr;
+      /* stages 2 and 3: U^n of the row finished in this step, loaded now so
+         that the latency hides behind the reconstruction */
+      double qun = 0.0, qvn = 0.0, qwn = 0.0;
+      if ((mode == 1 || mode == 2) && jr >= 1 && outx) {
+        const long long cell = (long long)(y - 1) * I.nx + x;
+        const MR_GLB double* vs = I.mod == 0 ? unm + (long long)(comp * 2) * P : gn.U + (long long)(comp * 3 + 1) * P;
+        qun = gn.U[(long long)(comp * 3) * P + cell];
+        qvn = vs[cell];
+        qwn = vs[P + cell];
+      }
       /* prefetch A row y+3, B and flag row y+2 (stored once rows y-2 and
          y-1 are consumed) */
       double pre[NE];
@@ -304,13 +314,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
           }
         } else {
           const double a = mode == 1 ? 0.75 : 1.0 / 3.0, b = mode == 1 ? 0.25 : 2.0 / 3.0;
-          const double un = gn.U[(long long)(comp * 3) * P + cell];
-          /* first moments of U^n: modified ones kept by stage 1 if the
-             modification persists, else the stored ones (the y moment is
-             the next plane in either layout) */
-          const MR_GLB double* vs = I.mod == 0 ? unm + (long long)(comp * 2) * P : gn.U + (long long)(comp * 3 + 1) * P;
-          const double vn = vs[cell];
-          const double wn = vs[P + cell];
+          const double un = qun, vn = qvn, wn = qwn;
           r0 = a * un + b * pU + b * dt * Lu;
           r1 = a * vn + b * pV + b * dt * Lv;
           r2 = a * wn + b * pW + b * dt * Lw;
