@@ -27,7 +27,7 @@ hipError_t mr_launch_values(hipStream_t, int, int, int, mr_inst*, const mr_tile1
 hipError_t mr_launch_fb_reset(hipStream_t, int*, int);
 hipError_t mr_launch_pack(hipStream_t, const void*, mr_learn_w*);
 hipError_t mr_launch_learned(hipStream_t, mr_inst*, const mr_tile2*, int, int, const mr_learn_w*, mr_band*, int*, int);
-hipError_t mr_launch_fallback(hipStream_t, mr_inst*, const mr_band*, mr_band*, int*, int, int, int);
+hipError_t mr_launch_fallback(hipStream_t, mr_inst*, const mr_band*, int*, int, int, int);
 hipError_t mr_launch_features(hipStream_t, const mr_inst*, int, const int*, int, void*);
 size_t mr_mlp_cache_bytes(int);
 hipError_t mr_mlp_gemm(hipStream_t, int, int, int, const void*, long long, long long, const void*, long long,
@@ -65,15 +65,12 @@ int sex(const mrhweno_problem& p) { return ext(p.nx, kSHalo); }
 int sey(const mrhweno_problem& p) { return p.dim == 2 ? ext(p.ny, kSHalo) : 1; }
 int nsumm(const mrhweno_problem& p) { return p.dim == 1 ? 5 : 9; }
 bool learned(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_LEARNED; }
-/* KXRCF face summaries over the whole extended plane (the learned
-   indicator keeps a summary plane too, filled only around band cells) */
 bool kxrcf(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_KXRCF; }
 bool tvb(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_TVB; }
 /* an indicator pass of its own (KXRCF or TVB; the learned one has its kernel) */
 bool indicator_pass(const mrhweno_problem& p) { return kxrcf(p) || tvb(p); }
 /* 1D KXRCF keeps face summaries in a plane; 2D KXRCF computes them in LDS */
 bool needs_summ(const mrhweno_problem& p) { return indicator_pass(p) && p.dim == 1; }
-bool has_summ(const mrhweno_problem& p) { return needs_summ(p) || learned(p); }
 /* work items of the learned indicator: strips over [-2, n+2)^2 */
 int learn_tiles(const mrhweno_problem& p) {
   return learned(p) ? ceil_div_i(ext(p.nx, kFHalo), kLearnW) * ceil_div_i(ext(p.ny, kFHalo), kLearnRows) : 0;
@@ -150,9 +147,9 @@ std::string validate(const mrhweno_problem& p) {
 /* workspace layout, computed identically for sizing and for creation */
 struct Layout {
   size_t insts = 0, tiles1 = 0, tiles2 = 0, probe_tiles = 0, probe_aleph = 0, total = 0;
-  size_t lw = 0, cnt = 0, band = 0, slist = 0, tilesl = 0;   /* learned indicator */
-  std::vector<size_t> buf1, buf2, unm, fl0, fl1, summ, mark;
-  size_t n_tiles1 = 0, n_tiles2 = 0, n_probe_tiles = 0, n_tilesl = 0, n_band = 0, n_slist = 0;
+  size_t lw = 0, cnt = 0, band = 0, tilesl = 0;   /* learned indicator */
+  std::vector<size_t> buf1, buf2, unm, fl0, fl1, summ;
+  size_t n_tiles1 = 0, n_tiles2 = 0, n_probe_tiles = 0, n_tilesl = 0, n_band = 0;
 };
 
 int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
@@ -175,10 +172,7 @@ Layout layout(const mrhweno_problem* P, int n) {
     tmax = std::max(tmax, a + learn_tiles(p) + kx_tiles(p) +
                               (p.dim == 2 ? (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) : 0));
     L.n_tilesl += learn_tiles(p);
-    if (learned(p)) {
-      L.n_band += (size_t)fex(p) * fey(p);
-      L.n_slist += (size_t)sex(p) * sey(p);
-    }
+    if (learned(p)) L.n_band += (size_t)fex(p) * fey(p);
   }
   L.n_tiles1 = t1;
   L.n_tiles2 = t2;
@@ -193,7 +187,6 @@ Layout layout(const mrhweno_problem* P, int n) {
     L.lw = off; off += al(sizeof(mr_learn_w));
     L.cnt = off; off += al(16 * sizeof(int));
     L.band = off; off += al(sizeof(mr_band) * L.n_band);
-    L.slist = off; off += al(sizeof(mr_band) * L.n_slist);
     L.tilesl = off; off += al(sizeof(mr_tile2) * L.n_tilesl);
   }
   long long maxplane = 1;
@@ -209,9 +202,7 @@ Layout layout(const mrhweno_problem* P, int n) {
     L.fl0.push_back(off); off += al((size_t)fex(p) * fey(p));
     L.fl1.push_back(off); off += al((size_t)fex(p) * fey(p));
     L.summ.push_back(off);
-    if (has_summ(p)) off += al(sizeof(double) * nsumm(p) * (size_t)sex(p) * sey(p));
-    L.mark.push_back(off);
-    if (learned(p)) off += al(sizeof(int) * (size_t)sex(p) * sey(p));
+    if (needs_summ(p)) off += al(sizeof(double) * nsumm(p) * (size_t)sex(p) * sey(p));
   }
   L.total = off;
   return L;
@@ -263,7 +254,6 @@ struct mrhweno_ctx {
   mr_learn_w* lw = nullptr;
   int* cnt = nullptr;
   mr_band* band = nullptr;
-  mr_band* slist = nullptr;
   mr_tile2* tl = nullptr;
   int n_tl = 0, grid_l = 512, grid_fb = 1024;
   int learned_bp = 0;   /* some learned instance takes beta on p_l */
@@ -418,7 +408,7 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
     for (auto& g : c->groups)
       if (g.n_flag > 0 && (e = mr_launch_flags(s, g.dim, c->d, c->t1 + g.t_flag, g.n_flag, st)) != hipSuccess) return e;
     if (c->any_learned &&
-        (e = mr_launch_fallback(s, c->d, c->band, c->slist, c->cnt, st, c->grid_fb, c->learned_bp)) != hipSuccess)
+        (e = mr_launch_fallback(s, c->d, c->band, c->cnt, st, c->grid_fb, c->learned_bp)) != hipSuccess)
       return e;
     if ((e = mark(c, P, 2)) != hipSuccess) return e;
     for (auto& g : c->groups) {
@@ -525,8 +515,7 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     I.unm = p.dim == 2 ? (double*)(c->ws + c->L.unm[q]) : nullptr;
     I.flags[0] = (unsigned char*)(c->ws + c->L.fl0[q]);
     I.flags[1] = (unsigned char*)(c->ws + c->L.fl1[q]);
-    I.summ = has_summ(p) ? (double*)(c->ws + c->L.summ[q]) : nullptr;
-    I.mark = learned(p) ? (int*)(c->ws + c->L.mark[q]) : nullptr;
+    I.summ = needs_summ(p) ? (double*)(c->ws + c->L.summ[q]) : nullptr;
     I.aleph = nullptr;
     I.cur = 0;
     if (p.flux == MRHWENO_BURGERS_LF) c->any_lf = true;
@@ -538,7 +527,6 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     c->lw = (mr_learn_w*)(c->ws + c->L.lw);
     c->cnt = (int*)(c->ws + c->L.cnt);
     c->band = (mr_band*)(c->ws + c->L.band);
-    c->slist = (mr_band*)(c->ws + c->L.slist);
     c->tl = (mr_tile2*)(c->ws + c->L.tilesl);
     std::vector<mr_tile2> tl;
     for (int q = 0; q < n; ++q)
@@ -580,12 +568,6 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
         delete c;
         return fail(nullptr, MRHWENO_ERR_DEVICE, "flag plane clear failed");
       }
-    /* epoch marks of the learned indicator start below every epoch */
-    if (c->h[q].mark &&
-        hipMemset(c->h[q].mark, 0, sizeof(int) * (size_t)c->h[q].sex * c->h[q].sey) != hipSuccess) {
-      delete c;
-      return fail(nullptr, MRHWENO_ERR_DEVICE, "mark plane clear failed");
-    }
   }
   if (hipMemcpy(c->d, c->h.data(), sizeof(mr_inst) * (n + 1), hipMemcpyHostToDevice) != hipSuccess) {
     delete c;
@@ -852,7 +834,7 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
     MR_CHECK(c, mr_launch_learned(s, c->d, d3, (int)tl.size(), 3, c->lw, c->band, c->cnt, c->grid_l));
     if (kind == 3 && out)
       MR_CHECK(c, hipMemcpy2DAsync(out, p.nx, I.flags[0] + frow, I.fex, p.nx, p.ny, hipMemcpyDeviceToDevice, s));
-    MR_CHECK(c, mr_launch_fallback(s, c->d, c->band, c->slist, c->cnt, 3, c->grid_fb, p.beta_on));
+    MR_CHECK(c, mr_launch_fallback(s, c->d, c->band, c->cnt, 3, c->grid_fb, p.beta_on));
   } else {
     MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, I.pres != 0, c->d, d1 + t_sum, n_sum, 3));
     MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));

@@ -341,113 +341,75 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
   }
 }
 
-/* The learned indicator takes no per-side boundary data (the library
+/* KXRCF for the cells the network left undecided (band list, count
+ * cnt[stage]) in one pass: five threads per band cell compute the face data
+ * (mr2_face_summary) of the cell and of its four neighbours, and the first
+ * of them evaluates eq. (KXRCF_) on them as the fused indicator kernel does.
+ * One launch per smoothness-indicator variant; each skips the other's cells.
+ * The learned indicator takes no per-side boundary data (the library
  * rejects the combination), so its grids carry no instance for prescribed
- * ghosts.
- *
- * KXRCF for the cells the network left undecided (band list, count
- * cnt[stage]), in three passes that share the face data of neighbouring band
- * cells:
- *   k_fb_mark:    every band cell claims itself and its four neighbours in
- *                 the instance's mark plane (an atomic exchange with this
- *                 pass's epoch); the first claimant appends the cell to the
- *                 summary list (count cnt[4 + stage]);
- *   k_fb_summary: KXRCF face data (mr2_face_summary) of the listed cells;
- *   k_fb_flags:   eq. (KXRCF_) for the band cells, as the flag kernel
- *                 evaluates it.
- * The epoch of a pass is cnt[8] + stage + 1; cnt[8] advances by 4 before
- * every step and every probe, so marks never need clearing. */
-__global__ __launch_bounds__(MR_BLOCK) void k_fb_mark(mr_inst* insts, const mr_band* band, mr_band* list, int* cnt,
-                                                     int stage) {
+ * ghosts. */
+template <bool BP>
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k_fb_direct(mr_inst* insts, const mr_band* band, const int* cnt,
+                                                              int stage) {
+#pragma clang fp contract(off)
+  constexpr int PB = MR_BLOCK / 5;   /* band cells per block pass */
+  __shared__ double fs[PB][5][9];
   const int n = cnt[stage];
-  const int epoch = cnt[8] + stage + 1;
-  const int lane = threadIdx.x % 64;
-  /* wave-uniform trip count: the appends of a wave take one atomic */
-  for (int k0 = blockIdx.x * MR_BLOCK + (int)threadIdx.x - lane; k0 < n; k0 += gridDim.x * MR_BLOCK) {
-    const int k = k0 + lane;
-    const bool act = k < n;
-    const mr_band b = act ? band[k] : mr_band{0, 0};
-    const mr_inst& I = insts[b.inst];
-    const int i = b.e % I.fex - I.fhalo, j = b.e / I.fex - I.fhalo;
-    MR_GLB int* mark = mr_gp(I.mark);
+  const int tid = threadIdx.x, cb = tid / 5, d = tid % 5;
+  for (int base = blockIdx.x * PB; base < n; base += gridDim.x * PB) {
+    const int k = base + cb;
+    const bool act = tid < 5 * PB && k < n;
+    mr_band b{0, 0};
+    bool mine = false;
+    if (act) {
+      b = band[k];
+      const mr_inst& I = insts[b.inst];
+      mine = (I.beta_on != 0) == BP;
+      if (mine) {
+        const int i = b.e % I.fex - I.fhalo, j = b.e / I.fex - I.fhalo;
+        const int di = d == 1 ? -1 : (d == 2 ? 1 : 0), dj = d == 3 ? -1 : (d == 4 ? 1 : 0);
+        const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, nullptr, 0.0};
+        double f[9];
+        mr2_face_summary<BP>(g, I, i + di, j + dj, f);
 #pragma unroll
-    for (int d = 0; d < 5; ++d) {
-      const int di = d == 1 ? -1 : (d == 2 ? 1 : 0), dj = d == 3 ? -1 : (d == 4 ? 1 : 0);
-      const int es = (j + dj + I.shalo) * I.sex + (i + di + I.shalo);
-      const bool mine = act && __hip_atomic_exchange(&mark[es], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch;
-      const unsigned long long bm = __ballot(mine);
-      if (bm) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&cnt[4 + stage], __popcll(bm));
-        base = __shfl(base, 0);
-        if (mine) list[base + __popcll(bm & ((1ull << lane) - 1ull))] = mr_band{b.inst, es};
+        for (int q = 0; q < 9; ++q) fs[cb][d][q] = f[q];
       }
     }
+    __syncthreads();
+    if (mine && d == 0) {
+      const mr_inst& I = insts[b.inst];
+      MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
+      const int i = b.e % I.fex - I.fhalo, j = b.e / I.fex - I.fhalo;
+      const double tb = mr_stage_time(I, stage);
+      /* face data of a cell: 0..3 face averages (left, right, bottom, top),
+         4..7 the normal velocities there, 8 the norm of its values */
+      const double* o = fs[cb][0];
+      const double* l = fs[cb][1];
+      const double* r = fs[cb][2];
+      const double* bo = fs[cb][3];
+      const double* t = fs[cb][4];
+      double J = 0.0, len = 0.0;
+      const double vl = 0.5 * (o[4] + l[5]);
+      if (vl > 0.0 && !mr_wall_x(I, i, j, tb)) { J += I.dy * (o[0] - l[1]); len += I.dy; }
+      const double vr = 0.5 * (o[5] + r[4]);
+      if (-vr > 0.0 && !mr_wall_x(I, i + 1, j, tb)) { J += I.dy * (o[1] - r[0]); len += I.dy; }
+      const double vb = 0.5 * (o[6] + bo[7]);
+      if (vb > 0.0 && !mr_wall_y(I, i, j, tb)) { J += I.dx * (o[2] - bo[3]); len += I.dx; }
+      const double vt = 0.5 * (o[7] + t[6]);
+      if (-vt > 0.0 && !mr_wall_y(I, i, j + 1, tb)) { J += I.dx * (o[3] - t[2]); len += I.dx; }
+      fl[b.e] = (unsigned char)(fabs(J) > I.dx * I.dx * len * o[8]);
+    }
+    __syncthreads();
   }
 }
 
-template <bool BP>
-MR_INL void mr_fb_summary_cell(mr_inst& I, const mr_grid& g, int es) {
-  double f[9];
-  mr2_face_summary<BP>(g, I, es % I.sex - I.shalo, es / I.sex - I.shalo, f);
-  const long long SE = (long long)I.sex * I.sey;
-  MR_GLB double* S = mr_gp(I.summ);
-#pragma unroll
-  for (int k = 0; k < 9; ++k) S[k * SE + es] = f[k];
-}
-
-/* one launch per smoothness-indicator variant; each skips the other's cells */
-template <bool BP>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k_fb_summary(mr_inst* insts, const mr_band* list, const int* cnt,
-                                                               int stage) {
-  const int n = cnt[4 + stage];
-  for (int k = blockIdx.x * MR_BLOCK + threadIdx.x; k < n; k += gridDim.x * MR_BLOCK) {
-    const mr_band b = list[k];
-    mr_inst& I = insts[b.inst];
-    if ((I.beta_on != 0) != BP) continue;
-    const mr_grid g{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, nullptr, 0.0};
-    mr_fb_summary_cell<BP>(I, g, b.e);
-  }
-}
-
-__global__ __launch_bounds__(MR_BLOCK) void k_fb_flags(mr_inst* insts, const mr_band* band, const int* cnt, int stage) {
-#pragma clang fp contract(off)
-  const int n = cnt[stage];
-  for (int k = blockIdx.x * MR_BLOCK + threadIdx.x; k < n; k += gridDim.x * MR_BLOCK) {
-    const mr_band b = band[k];
-    const mr_inst& I = insts[b.inst];
-    MR_GLB unsigned char* fl = mr_gp(I.flags[(stage == 0 || stage == 3) ? 0 : 1]);
-    const int i = b.e % I.fex - I.fhalo, j = b.e / I.fex - I.fhalo;
-    const int sx = I.sex;
-    const long long SE = (long long)sx * I.sey;
-    const MR_GLB double* S = mr_gp(I.summ);
-    const long long o = (long long)(j + I.shalo) * sx + (i + I.shalo);
-    const double tb = mr_stage_time(I, stage);
-    double J = 0.0, len = 0.0;
-    const double vl = 0.5 * (S[4 * SE + o] + S[5 * SE + o - 1]);
-    if (vl > 0.0 && !mr_wall_x(I, i, j, tb)) { J += I.dy * (S[0 * SE + o] - S[1 * SE + o - 1]); len += I.dy; }
-    const double vr = 0.5 * (S[5 * SE + o] + S[4 * SE + o + 1]);
-    if (-vr > 0.0 && !mr_wall_x(I, i + 1, j, tb)) { J += I.dy * (S[1 * SE + o] - S[0 * SE + o + 1]); len += I.dy; }
-    const double vb = 0.5 * (S[6 * SE + o] + S[7 * SE + o - sx]);
-    if (vb > 0.0 && !mr_wall_y(I, i, j, tb)) { J += I.dx * (S[2 * SE + o] - S[3 * SE + o - sx]); len += I.dx; }
-    const double vt = 0.5 * (S[7 * SE + o] + S[6 * SE + o + sx]);
-    if (-vt > 0.0 && !mr_wall_y(I, i, j + 1, tb)) { J += I.dx * (S[3 * SE + o] - S[2 * SE + o + sx]); len += I.dx; }
-    fl[b.e] = (unsigned char)(fabs(J) > I.dx * I.dx * len * S[8 * SE + o]);
-  }
-}
-
-/* before a step (stages 0..2) or a probe (stage 3): clear the band and
- * summary-list counts of those stages and advance the epoch */
+/* before a step (stages 0..2) or a probe (stage 3): clear the band counts
+ * of those stages */
 __global__ void k_fb_reset(int* cnt, int probe) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  if (probe) {
-    cnt[3] = 0;
-    cnt[7] = 0;
-  } else {
-    cnt[0] = cnt[1] = cnt[2] = 0;
-    cnt[4] = cnt[5] = cnt[6] = 0;
-  }
-  cnt[8] += 4;
+  if (probe) cnt[3] = 0;
+  else cnt[0] = cnt[1] = cnt[2] = 0;
 }
 
 /* BF16 parameter vector -> operand-ordered weights of the fused kernel */
@@ -655,12 +617,10 @@ hipError_t mr_launch_learned(hipStream_t s, mr_inst* d, const mr_tile2* t, int n
   return hipGetLastError();
 }
 
-hipError_t mr_launch_fallback(hipStream_t s, mr_inst* d, const mr_band* band, mr_band* list, int* cnt, int stage,
-                              int grid, int any_bp) {
-  hipLaunchKernelGGL(k_fb_mark, dim3(grid), dim3(MR_BLOCK), 0, s, d, band, list, cnt, stage);
-  hipLaunchKernelGGL(k_fb_summary<false>, dim3(grid), dim3(MR_BLOCK), 0, s, d, list, cnt, stage);
-  if (any_bp) hipLaunchKernelGGL(k_fb_summary<true>, dim3(grid), dim3(MR_BLOCK), 0, s, d, list, cnt, stage);
-  hipLaunchKernelGGL(k_fb_flags, dim3(grid), dim3(MR_BLOCK), 0, s, d, band, cnt, stage);
+hipError_t mr_launch_fallback(hipStream_t s, mr_inst* d, const mr_band* band, int* cnt, int stage, int grid,
+                              int any_bp) {
+  hipLaunchKernelGGL(k_fb_direct<false>, dim3(grid), dim3(MR_BLOCK), 0, s, d, band, cnt, stage);
+  if (any_bp) hipLaunchKernelGGL(k_fb_direct<true>, dim3(grid), dim3(MR_BLOCK), 0, s, d, band, cnt, stage);
   return hipGetLastError();
 }
 

@@ -52,7 +52,6 @@ struct mr_inst {
   unsigned char* flags[2];    /* [0] stage-1 flags, [1] stage-2/3 flags        */
   double* summ;               /* KXRCF face summaries (extended planes)        */
   double* aleph;              /* optional KXRCF numerator/denominator output   */
-  int* mark;                  /* learned indicator: summary-plane epoch marks  */
   double* unm;                /* 2D: first moments of U^n after Step 2.2 of
                                  stage 1, [comp][2][ny][nx] (written by stage 1,
                                  read by the RK combination of stages 2, 3)   */
