@@ -227,13 +227,15 @@ def test_adam_matches_oracle():
 
 
 # ------------------------------------------------------------- fused path
-@pytest.mark.parametrize("bc", [I.PERIODIC, I.REFLECTIVE])
-def test_indicator_decisions_and_flags(bc):
+@pytest.mark.parametrize("bc,beta_on", [(I.PERIODIC, 0), (I.REFLECTIVE, 0), (I.PERIODIC, 1)])
+def test_indicator_decisions_and_flags(bc, beta_on):
     """Fused inference decisions against the training forward pass (same
-    BF16 arithmetic) and the FP64 reference; band cells get the KXRCF flag.
-    Reflective walls exercise the fused kernel's mirrored ghost staging."""
+    BF16 arithmetic) and the FP64 reference; band cells get the KXRCF flag
+    (with beta on q or on p, the fallback's two variants).  Reflective
+    walls exercise the fused kernel's mirrored ghost staging."""
     import torch
     prob, U = _state(seed=31, n=64, bc=bc, steps=2)
+    prob = prob.replace(beta_on=beta_on)
     P = _centred_params(prob, U)
     lo, hi = 0.3, 0.7
     s, Ut, pl = _learned_solver(prob, U, P, lo, hi)
@@ -354,6 +356,33 @@ def test_learned_batched_graph_equals_eager():
     s.sync()
     assert np.array_equal(Ut.cpu().numpy(), states[0][1])
     s.close()
+
+
+def test_learned_batch_mixing_beta_variants():
+    """Learned instances with beta on q and on p in one batch: the fallback
+    launches one kernel per variant, each skipping the other's band cells;
+    every instance ends bit for bit where it ends alone."""
+    from paper_2201_12193_amd.mrhweno import Solver
+    pa, Ua = _state(seed=45, n=64, steps=1)
+    pb, Ub = _state(seed=46, n=56, steps=1)
+    P = _centred_params(pa, Ua, seed=5)
+    pa = pa.replace(tc_mode=I.TC_LEARNED)
+    pb = pb.replace(tc_mode=I.TC_LEARNED, beta_on=1)
+    Us = [_t(Ua), _t(Ub)]
+    s = Solver([pa, pb], Us)
+    s.set_indicator(_bf16(P))
+    s.step(3)
+    s.sync()
+    both = [u.cpu().numpy() for u in Us]
+    s.close()
+    for prob, U0, got in ((pa, Ua, both[0]), (pb, Ub, both[1])):
+        Ut = _t(U0)
+        s = Solver([prob], [Ut])
+        s.set_indicator(_bf16(P))
+        s.step(3)
+        s.sync()
+        assert np.array_equal(Ut.cpu().numpy(), got)
+        s.close()
 
 
 def test_learned_requires_weights():
