@@ -85,6 +85,16 @@ MR_INL bool mr_presc_any(const mr_inst& I, int i, int j, double t) {
   return false;
 }
 
+/* whether any cell of columns x0 .. x0+w-1 and rows y0 .. y0+nr-1 can hold
+   prescribed data: a row outside [0, ny) with data on the bottom or top
+   side, or a column outside [0, nx) with data on the left or right side
+   (uniform over a work group: the rows and columns of its strip) */
+MR_INL bool mr_presc_rows(const mr_inst& I, int x0, int w, int y0, int nr) {
+  if (!I.pres || nr <= 0) return false;
+  if ((I.pres & 12) && (y0 < 0 || y0 + nr > I.ny)) return true;
+  return (I.pres & 3) && (x0 < 0 || x0 + w > I.nx);
+}
+
 /* moment m of component c of a ghost cell with prescribed data (see
    mr_presc_any); false if the cell holds none */
 MR_INL bool mr_presc(const mr_inst& I, int c, int m, int i, int j, double t, double* val) {

@@ -167,7 +167,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
       store(y, a, za);
       store(y + 1, b, zb);
     }
-    if (GB && I.pres) prescribe(tl.y0 - 2, 6);
+    if (GB && mr_presc_rows(I, xs, KX_XW, tl.y0 - 2, 6)) prescribe(tl.y0 - 2, 6);
     __syncthreads();
     for (int s = 0; 4 * s <= tl.rows + 1; ++s) {
       const int r0 = tl.y0 - 1 + 4 * s;    /* rows r0 .. r0+3 are reconstructed */
@@ -218,7 +218,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (r0 + 5 + k <= ylast + 1) store(r0 + 5 + k, v[k], z[k]);
-      if (GB && I.pres) prescribe(r0 + 5, min(4, ylast - r0 - 3));
+      if (GB && mr_presc_rows(I, xs, KX_XW, r0 + 5, min(4, ylast - r0 - 3))) prescribe(r0 + 5, min(4, ylast - r0 - 3));
       __syncthreads();
     }
   }

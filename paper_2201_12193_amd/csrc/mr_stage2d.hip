@@ -218,7 +218,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
           }
         }
         if (tid < XW) sh.flg[sb][tid] = pref;
-        if (GB && I.pres) {
+        if (GB && mr_presc_rows(I, xs0, XW, y + 2, 2)) {
           /* ghosts that hold prescribed data */
           const double tb = mr_stage_time(I, mode);
 #pragma unroll 1
