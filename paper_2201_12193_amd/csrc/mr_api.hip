@@ -71,6 +71,12 @@ bool tvb(const mrhweno_problem& p) { return p.tc_mode == MRHWENO_TC_TVB; }
 bool indicator_pass(const mrhweno_problem& p) { return kxrcf(p) || tvb(p); }
 /* 1D KXRCF keeps face summaries in a plane; 2D KXRCF computes them in LDS */
 bool needs_summ(const mrhweno_problem& p) { return indicator_pass(p) && p.dim == 1; }
+/* side s (0 left, 1 right, 2 bottom, 3 top) carries boundary data: an
+   inflow state or a front */
+bool side_data(const mrhweno_problem& p, int s) {
+  const int bc = s < 2 ? p.bc_x : p.bc_y;
+  return bc == MRHWENO_BC_SIDES && (p.side[s].kind == MRHWENO_SIDE_INFLOW || p.side[s].front);
+}
 /* work items of the learned indicator: strips over [-2, n+2)^2 */
 int learn_tiles(const mrhweno_problem& p) {
   return learned(p) ? ceil_div_i(ext(p.nx, kFHalo), kLearnW) * ceil_div_i(ext(p.ny, kFHalo), kLearnRows) : 0;
@@ -79,9 +85,18 @@ int strip_cells(const mrhweno_problem& p) { return kBlock / ncomp_of(p); }   /* 
 /* rows of a 2D KXRCF work item: 46 (each strip also reconstructs a ring row
    above and below), fewer for grids too small to fill the GPU otherwise */
 int kx_rows(const mrhweno_problem& p) {
-  const int cols = ceil_div_i(ext(p.nx, kFHalo), kKxW);
-  const int r = ceil_div_i(ext(p.ny, kFHalo), ceil_div_i(kKxFill, cols));
-  return std::min(kKxRows, std::max(kKxMinRows, r));
+  /* the height that minimises waves of kKxFill resident work groups times
+     the sweep steps (four rows each) of a strip; the tallest among equals.
+     A small last wave would double the kernel's time. */
+  const int cols = ceil_div_i(ext(p.nx, kFHalo), kKxW), ey = ext(p.ny, kFHalo);
+  int best = kKxMinRows;
+  long long bc = -1;
+  for (int r = kKxMinRows; r <= kKxRows; ++r) {
+    const long long tiles = (long long)cols * ceil_div_i(ey, r);
+    const long long cost = ((tiles + kKxFill - 1) / kKxFill) * ceil_div_i(r + 2, 4);
+    if (bc < 0 || cost <= bc) { bc = cost; best = r; }
+  }
+  return best;
 }
 /* 2D KXRCF work items: strips over [-2, n+2)^2 */
 int kx_tiles(const mrhweno_problem& p) {
@@ -329,9 +344,21 @@ static void build_lists(mrhweno_ctx* c) {
         const auto& p = c->probs[q];
         const int w = strip_cells(p) - 2;
         const int rows = std::max(kMinRows, c->rows2);
-        for (int y0 = 0; y0 < p.ny; y0 += rows)
-          for (int x0 = 0; x0 < p.nx; x0 += w)
-            c->h_t2.push_back(mr_tile2{q, x0, y0, std::min(rows, p.ny - y0)});
+        const bool lx = side_data(p, 0), rx = side_data(p, 1);
+        if (!lx && !rx) {
+          for (int y0 = 0; y0 < p.ny; y0 += rows)
+            for (int x0 = 0; x0 < p.nx; x0 += w)
+              c->h_t2.push_back(mr_tile2{q, x0, y0, std::min(rows, p.ny - y0)});
+          continue;
+        }
+        /* strips whose staged columns (x0-3 .. x0+w+2) reach a left or right
+           side with boundary data write those ghosts in every row step: half
+           the rows, so that they finish with the rest of the launch */
+        for (int x0 = 0; x0 < p.nx; x0 += w) {
+          const bool edge = (lx && x0 - 3 < 0) || (rx && x0 + w + 2 >= p.nx);
+          const int r = edge ? std::max(kMinRows, rows / 2) : rows;
+          for (int y0 = 0; y0 < p.ny; y0 += r) c->h_t2.push_back(mr_tile2{q, x0, y0, std::min(r, p.ny - y0)});
+        }
       }
     }
     g.n_st2 = (int)c->h_t2.size() - g.t_st2;
