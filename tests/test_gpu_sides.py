@@ -156,3 +156,22 @@ def test_double_mach_front_crossing_a_stage():
         prev, tp = got, times[0]
     s.close()
     assert crossed > 0
+
+
+def test_sides_launch_shape_invariance():
+    """The work split (strip height, the half-height strips along a side
+    with boundary data, persistent grid or not) leaves every bit of the
+    steps alone."""
+    import torch
+    from paper_2201_12193_amd.mrhweno import Solver
+    prob, U = I.double_mach_2d(ny=80)
+    outs = []
+    for rows, grid in ((8, 0), (16, 64), (40, 512)):
+        Ut = torch.from_numpy(np.ascontiguousarray(U)).to(_dev())
+        s = Solver([prob], [Ut])
+        s.set_launch(rows, grid)
+        s.step(5)
+        s.sync()
+        outs.append(Ut.cpu().numpy())
+        s.close()
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
