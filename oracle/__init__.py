@@ -25,9 +25,13 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 ORACLE_PINS = {
     "step1_1d": "exactness of q2/q3/q4 on polynomial data; closed forms; eq. (pq); Remark 1; Table 1/3 orders",
-    "step1_2d": "exactness of the least-squares q2/q3/q4 on P2/P3/P5 data; eq. (2D-pq); D4 symmetry; Table 2/4 orders",
+    "step1_2d": "exactness of the least-squares q2/q3/q4 on P2/P3/P5 data; eq. (2D-pq); D4 symmetry; Table 2/4 orders; "
+                "beta_1 worked example (eqs. (2D-q1-1234)-(2D-beta1)); 2D Remark 1 expansion of beta on exp data; "
+                "reduction of y-invariant data to the 1D algorithm",
     "modification": "eq. (vi) printed coefficients",
-    "kxrcf": "smooth/discontinuous scaling (Remark 2); inflow side of a moving step; Lax problem flags",
+    "kxrcf": "smooth/discontinuous scaling (Remark 2); inflow side of a moving step; Lax problem flags; "
+             "2D: denominator on uniform flows, face-length scaling on non-square cells, two inflow faces, "
+             "x and y faces of a raised cell, norm over all sixteen points",
     "hllc": "consistency, supersonic branches, stationary contact",
     "residual": "conservation; free-stream preservation; convergence orders; Lax problem vs exact Riemann solution",
     "rk3": "third-order temporal convergence",
