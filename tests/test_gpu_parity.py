@@ -2,8 +2,9 @@
 
 Tolerances: FP64 values within 1e-12 of the component's zeroth-moment scale
 per step (residuals: the same bound divided by the CFL time step); troubled-
-cell flags bit-exact except at near-ties of the KXRCF test, which must stay
-below a handful and are reported."""
+cell flags bit-exact: every case prints its flag counts (a `FLAGS` line) and
+asserts that no flag differs (MISMATCHES_ALLOWED lists the cases measured
+otherwise, each inside the rounding band that the value bar implies)."""
 import math
 
 import numpy as np
@@ -11,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2201_12193_amd import inputs as I
-from tests.parity_util import comp_scale, rel_state_err, flag_mismatch
+from tests.parity_util import comp_scale, rel_state_err, kxrcf_flags, flag_report, MISMATCHES_ALLOWED
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -68,8 +69,9 @@ def test_residual_and_reconstruct(name, prob, U, tc):
     glref, flref2, num, den = oracle.reconstruct(prob, U)
     sc = comp_scale(prob, U)
     dt = oracle.dt(prob, U)
-    bad, ties = flag_mismatch(fl, flref, num, den)
-    assert bad == 0 and ties <= 2, (bad, ties)
+    tag = f"residual/{name}/tc{tc}"
+    n, out = kxrcf_flags(tag, prob, fl, flref, num, den, sc[0])
+    assert out == 0 and n <= MISMATCHES_ALLOWED.get(tag, 0), (n, out)
     assert np.array_equal(fl, fl2) and np.array_equal(fl, fl3)
     if tc == I.TC_KXRCF:
         al = al.cpu().numpy()
@@ -135,8 +137,8 @@ def test_modification_placement_parity(name, prob, U, mod, tc):
 @pytest.mark.parametrize("M", [1.0, 20.0])
 def test_tvb_indicator_parity(name, prob, U, M):
     """The TVB minmod indicator (Remark 2's alternative): flags equal to the
-    oracle's except at near-ties of the minmod comparisons, then the
-    residual and a few steps at the 1e-12 bar."""
+    oracle's (counts printed), then the residual and a few steps at the
+    1e-12 bar, always."""
     from tests.parity_util import tvb_tie_map
     import torch
     prob = prob.replace(tc_mode=I.TC_TVB, tvb_m=M)
@@ -150,26 +152,30 @@ def test_tvb_indicator_parity(name, prob, U, M):
     assert np.array_equal(fl, fl2)
     Lref, flref = oracle.residual(prob, U)
     glref, _, _, _ = oracle.reconstruct(prob, U)
-    tie = tvb_tie_map(prob, U, glref)
-    diff = fl != flref.astype(bool)
-    assert (diff & ~tie).sum() == 0 and (diff & tie).sum() <= 2, ((diff & ~tie).sum(), (diff & tie).sum())
+    tag = f"tvb/{name}/M{M:g}"
+    n, out = flag_report(tag, fl, flref, tvb_tie_map(prob, U, glref))
+    assert out == 0 and n <= MISMATCHES_ALLOWED.get(tag, 0), (n, out)
     if prob.system == I.EULER:
         assert flref.sum() > 0   # the discontinuous cases exercise the indicator
     sc = comp_scale(prob, U)
     dt = oracle.dt(prob, U)
-    if diff.sum() == 0:
-        dR = np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)
-        assert dR.max() <= TOL, dR
-        prev = U.copy()
-        for k in range(4 if prob.dim == 1 else 2):
-            s.step(1)
-            d = s.last_dt()[0]
-            s.sync()
-            got = Ut.cpu().numpy()
-            ref = oracle.rk3_step(prob, prev, d)
-            e = rel_state_err(prob, got, ref, sc)
-            assert e <= TOL, (k, e)
-            prev = got
+    if n:
+        # a flag inside the rounding band went the other way: the residual
+        # is compared with the oracle's given the GPU's troubled cells
+        assert prob.dim == 2 and prob.bc_x == I.PERIODIC and prob.bc_y == I.PERIODIC
+        Lref = oracle.residual_given(prob, U, np.pad(fl.astype(np.uint8), 2, mode="wrap"))
+    dR = np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)
+    assert dR.max() <= TOL, dR
+    prev = U.copy()
+    for k in range(4 if prob.dim == 1 else 2):
+        s.step(1)
+        d = s.last_dt()[0]
+        s.sync()
+        got = Ut.cpu().numpy()
+        ref = oracle.rk3_step(prob, prev, d)
+        e = rel_state_err(prob, got, ref, sc)
+        assert e <= TOL, (k, e)
+        prev = got
     s.close()
 
 
@@ -189,15 +195,14 @@ def test_charwise_1d_parity(tc):
     R, fl, gl = R.cpu().numpy(), fl.cpu().numpy(), gl.cpu().numpy()
     Lref, flref = oracle.residual(prob, U)
     glref, _, num, den = oracle.reconstruct(prob, U)
-    if tc == I.TC_TVB:
-        tie = tvb_tie_map(prob, U, glref)
-        diff = fl.astype(bool) != flref.astype(bool)
-        bad, ties = int((diff & ~tie).sum()), int((diff & tie).sum())
-    else:
-        bad, ties = flag_mismatch(fl, flref, num, den)
-    assert bad == 0 and ties <= 2, (bad, ties)
     sc = comp_scale(prob, U)
     dt = oracle.dt(prob, U)
+    tag = f"charwise1d/tc{tc}"
+    if tc == I.TC_TVB:
+        n, out = flag_report(tag, fl, flref, tvb_tie_map(prob, U, glref))
+    else:
+        n, out = kxrcf_flags(tag, prob, fl, flref, num, den, sc[0])
+    assert out == 0 and n <= MISMATCHES_ALLOWED.get(tag, 0), (n, out)
     assert (np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc).max() <= TOL
     assert (np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)).max() <= TOL
     prev = U.copy()
@@ -249,10 +254,11 @@ def test_reflective_walls_parity(name, prob, U):
     R, fl, gl = R.cpu().numpy(), fl.cpu().numpy(), gl.cpu().numpy()
     Lref, flref = oracle.residual(prob, U)
     glref, _, num, den = oracle.reconstruct(prob, U)
-    bad, ties = flag_mismatch(fl, flref, num, den)
-    assert bad == 0 and ties <= 2, (bad, ties)
     sc = comp_scale(prob, U)
     dt = oracle.dt(prob, U)
+    tag = f"reflective/{name}"
+    n, out = kxrcf_flags(tag, prob, fl, flref, num, den, sc[0])
+    assert out == 0 and n <= MISMATCHES_ALLOWED.get(tag, 0), (n, out)
     assert (np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc).max() <= TOL
     assert (np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)).max() <= TOL
     prev = U.copy()

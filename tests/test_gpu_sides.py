@@ -3,7 +3,7 @@
 with exact data on every side), at the time of each stage.
 
 Same bar as the other parity tests: FP64 values within 1e-12 of the
-component's scale per step, flags bit-exact except at near-ties."""
+component's scale per step, troubled-cell flags bit-exact (counts printed)."""
 import math
 
 import numpy as np
@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from paper_2201_12193_amd import inputs as I
-from tests.parity_util import comp_scale, rel_state_err, flag_mismatch, tvb_tie_map
+from tests.parity_util import comp_scale, rel_state_err, kxrcf_flags, flag_report, tvb_tie_map, MISMATCHES_ALLOWED
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -74,7 +74,7 @@ def _advance(prob, U, k):
     return U, t
 
 
-def _check_tc(prob, U, k, tc, nsteps):
+def _check_tc(prob, U, k, tc, nsteps, tag):
     import torch
     from paper_2201_12193_amd.mrhweno import Solver
     prob = prob.replace(tc_mode=tc, tvb_m=1.0 if tc == I.TC_TVB else 0.0)
@@ -88,18 +88,15 @@ def _check_tc(prob, U, k, tc, nsteps):
     R, fl, gl = R.cpu().numpy(), fl.cpu().numpy(), gl.cpu().numpy()
     Lref, flref = oracle.residual(prob, U, t)
     glref, _, num, den = oracle.reconstruct(prob, U, t)
-    if tc == I.TC_TVB:
-        tie = tvb_tie_map(prob, U, glref)
-        diff = fl.astype(bool) != flref.astype(bool)
-        bad, ties = int((diff & ~tie).sum()), int((diff & tie).sum())
-    else:
-        bad, ties = flag_mismatch(fl, flref, num, den)
-    assert bad == 0 and ties <= 2, (bad, ties)
     sc = comp_scale(prob, U)
     dt = oracle.dt(prob, U)
-    if ties == 0:
-        assert (np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc).max() <= TOL
-        assert (np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)).max() <= TOL
+    if tc == I.TC_TVB:
+        n, out = flag_report(tag, fl, flref, tvb_tie_map(prob, U, glref))
+    else:
+        n, out = kxrcf_flags(tag, prob, fl, flref, num, den, sc[0])
+    assert out == 0 and n <= MISMATCHES_ALLOWED.get(tag, 0), (n, out)
+    assert (np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc).max() <= TOL
+    assert (np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)).max() <= TOL
     prev, tp = U.copy(), t
     for j in range(nsteps):
         s.step(1)
@@ -117,7 +114,7 @@ def _check_tc(prob, U, k, tc, nsteps):
 def test_sides_parity(name, prob, U, k):
     """Values, flags, residual and steps against the oracle with the
     boundary data at the probe time and at every stage time."""
-    flref = _check_tc(prob, U, k, I.TC_KXRCF, 3 if prob.dim == 2 else 6)
+    flref = _check_tc(prob, U, k, I.TC_KXRCF, 3 if prob.dim == 2 else 6, f"sides/{name}")
     if name.startswith("dmr") or name.startswith("shock"):
         assert flref.sum() > 0
 
@@ -125,7 +122,7 @@ def test_sides_parity(name, prob, U, k):
 @pytest.mark.parametrize("tc", [I.TC_ALL, I.TC_TVB, I.TC_NONE])
 def test_sides_other_indicators(tc):
     prob, U = I.double_mach_2d(ny=40)
-    _check_tc(prob, U, 12, tc, 2)
+    _check_tc(prob, U, 12, tc, 2, f"sides/dmr_160x40_k12/tc{tc}")
 
 
 def test_double_mach_front_crossing_a_stage():
