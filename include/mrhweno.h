@@ -21,8 +21,10 @@
  *     Runge-Kutta) at a CFL number (0.6 in the paper).
  *
  * Memory: every pointer documented as "device" is device memory owned by the
- * caller; the library never allocates device memory and never copies between
- * host and device inside a step.  Host pointers are read during the call
+ * caller; the library never allocates device memory (the only device memory
+ * of its own is the static scratch array of mrhweno_residual_noalloc, part
+ * of its code object) and never copies between host and device inside a
+ * step.  Host pointers are read during the call
  * only.  All entry points are asynchronous on the stream given at creation
  * except mrhweno_sync, mrhweno_last_dt and mrhweno_create.
  *
@@ -219,6 +221,27 @@ mrhweno_status mrhweno_flag(mrhweno_ctx* ctx, int instance, const void* moments_
  * NULL). */
 mrhweno_status mrhweno_residual(mrhweno_ctx* ctx, int instance, const void* moments_dev,
                                 void* residual_dev, void* flags_dev);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * operator L(U) of mrhweno_residual for one problem without a context and
+ * without any allocation.
+ *   prob        host problem (not the learned indicator: UNSUPPORTED);
+ *   moments_dev device FP64 state (layout above), read only;
+ *   residual_dev device FP64 output, same layout;
+ *   flags_dev   device uint8 troubled-cell map [ny][nx], or NULL;
+ *   hip_stream  hipStream_t to launch on (NULL = default stream).
+ * Its descriptor, work lists, troubled-cell plane and 1D face summaries
+ * live in a static device array of MRHWENO_NOALLOC_SCRATCH_BYTES that the
+ * library holds on every GPU it runs on until the process ends; a problem
+ * that needs more returns MRHWENO_ERR_INVALID_ARG with the size it needs
+ * (2D: about (nx+4)(ny+4) bytes plus the work lists; 1D KXRCF/TVB: about
+ * 40 (nx+6) bytes more).  Calls on one GPU share that array: two calls
+ * that overlap in time on the same GPU (different streams or threads)
+ * race and give undefined results.  Synchronises the stream. */
+#define MRHWENO_NOALLOC_SCRATCH_BYTES (32u << 20)
+mrhweno_status mrhweno_residual_noalloc(const mrhweno_problem* prob, const void* moments_dev,
+                                        void* residual_dev, void* flags_dev, void* hip_stream);
 
 /* Rows per work item of the 2D stage kernel and grid size (0 = one work
  * group per work item) -- the launch shape the autotuner chooses. */

@@ -8,6 +8,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -301,6 +302,46 @@ static void fill_wconst(const mrhweno_problem& p, mr_wconst& W) {
   W.eps = p.eps;
 }
 
+/* the static part of an instance descriptor (grid, boundary data, flux,
+   variants, weights); buffers and the dynamic part are left zero */
+static void fill_inst(const mrhweno_problem& p, mr_inst& I) {
+  std::memset(&I, 0, sizeof I);
+  I.dim = p.dim; I.nx = p.nx; I.ny = p.dim == 2 ? p.ny : 1; I.nc = ncomp_of(p);
+  I.flux = p.flux;
+  I.x0 = p.x0; I.y0 = p.dim == 2 ? p.y0 : 0.0;
+  /* fold kinds per side (low side in bits 0-1, high side in bits 2-3; an
+     inflow side folds as a transmissive one and its ghosts are then
+     overwritten) and the prescribed-ghost data */
+  int fold[4] = {0, 0, 0, 0};
+  for (int s = 0; s < (p.dim == 2 ? 4 : 2); ++s) {
+    const int bc = s < 2 ? p.bc_x : p.bc_y;
+    const int kind = bc == MRHWENO_BC_SIDES ? p.side[s].kind : bc;
+    fold[s] = kind == MRHWENO_SIDE_INFLOW ? 1 : kind;
+    I.skind[s] = kind;
+    I.ssplit[s][0] = -HUGE_VAL;
+    if (bc != MRHWENO_BC_SIDES) continue;
+    const mrhweno_side& sd = p.side[s];
+    for (int c = 0; c < 4; ++c) { I.sstate[s][c] = sd.state[c]; I.spre[s][c] = sd.pre[c]; }
+    if (sd.front)
+      for (int q = 0; q < 3; ++q) I.ssplit[s][q] = sd.split[q];
+    if (sd.kind == MRHWENO_SIDE_INFLOW || sd.front) I.pres |= 1 << s;
+  }
+  I.bcx = fold[0] | (fold[1] << 2);
+  I.bcy = fold[2] | (fold[3] << 2);
+  I.tc = p.tc_mode; I.beta_on = p.beta_on; I.mod = p.modification; I.charwise = p.charwise;
+  I.fhalo = kFHalo; I.shalo = kSHalo;
+  I.fex = fex(p); I.fey = fey(p); I.sex = sex(p); I.sey = sey(p);
+  I.plane = plane_of(p);
+  I.dx = (p.x1 - p.x0) / p.nx;
+  I.dy = p.dim == 2 ? (p.y1 - p.y0) / p.ny : 1.0;
+  I.gam = p.gamma_gas; I.cfl = p.cfl; I.t_final = p.t_final;
+  I.rdx = 1.0 / I.dx;
+  I.rdy = 1.0 / I.dy;
+  I.band_lo = 0.2; I.band_hi = 0.8;
+  I.tvb_mh2 = p.tvb_m * I.dx * I.dx;
+  fill_wconst(p, I.W);
+}
+
 /* per-cell work items over `count` cells starting at 0 */
 static void add_cells(std::vector<mr_tile1>& v, int inst, long long count) {
   for (long long s = 0; s < count; s += kBlock)
@@ -501,41 +542,7 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
   for (int q = 0; q < n; ++q) {
     const auto& p = probs[q];
     mr_inst& I = c->h[q];
-    std::memset(&I, 0, sizeof I);
-    I.dim = p.dim; I.nx = p.nx; I.ny = p.dim == 2 ? p.ny : 1; I.nc = ncomp_of(p);
-    I.flux = p.flux;
-    I.x0 = p.x0; I.y0 = p.dim == 2 ? p.y0 : 0.0;
-    /* fold kinds per side (low side in bits 0-1, high side in bits 2-3; an
-       inflow side folds as a transmissive one and its ghosts are then
-       overwritten) and the prescribed-ghost data */
-    int fold[4] = {0, 0, 0, 0};
-    for (int s = 0; s < (p.dim == 2 ? 4 : 2); ++s) {
-      const int bc = s < 2 ? p.bc_x : p.bc_y;
-      const int kind = bc == MRHWENO_BC_SIDES ? p.side[s].kind : bc;
-      fold[s] = kind == MRHWENO_SIDE_INFLOW ? 1 : kind;
-      I.skind[s] = kind;
-      I.ssplit[s][0] = -HUGE_VAL;
-      if (bc != MRHWENO_BC_SIDES) continue;
-      const mrhweno_side& sd = p.side[s];
-      for (int c = 0; c < 4; ++c) { I.sstate[s][c] = sd.state[c]; I.spre[s][c] = sd.pre[c]; }
-      if (sd.front)
-        for (int q = 0; q < 3; ++q) I.ssplit[s][q] = sd.split[q];
-      if (sd.kind == MRHWENO_SIDE_INFLOW || sd.front) I.pres |= 1 << s;
-    }
-    I.bcx = fold[0] | (fold[1] << 2);
-    I.bcy = fold[2] | (fold[3] << 2);
-    I.tc = p.tc_mode; I.beta_on = p.beta_on; I.mod = p.modification; I.charwise = p.charwise;
-    I.fhalo = kFHalo; I.shalo = kSHalo;
-    I.fex = fex(p); I.fey = fey(p); I.sex = sex(p); I.sey = sey(p);
-    I.plane = plane_of(p);
-    I.dx = (p.x1 - p.x0) / p.nx;
-    I.dy = p.dim == 2 ? (p.y1 - p.y0) / p.ny : 1.0;
-    I.gam = p.gamma_gas; I.cfl = p.cfl; I.t_final = p.t_final;
-    I.rdx = 1.0 / I.dx;
-    I.rdy = 1.0 / I.dy;
-    I.band_lo = 0.2; I.band_hi = 0.8;
-    I.tvb_mh2 = p.tvb_m * I.dx * I.dx;
-    fill_wconst(p, I.W);
+    fill_inst(p, I);
     I.buf[0] = (double*)moments_dev[q];
     I.buf[1] = (double*)(c->ws + c->L.buf1[q]);
     I.buf[2] = (double*)(c->ws + c->L.buf2[q]);
@@ -785,6 +792,83 @@ mrhweno_status mrhweno_last_dt(mrhweno_ctx* c, double* dt_out) {
   return MRHWENO_OK;
 }
 
+/* Work lists of a one-off evaluation of the instance in descriptor slot
+   `slot`: per-cell chunks (reduction, 1D face summaries, flags, values,
+   1D stage), 2D stage strips, and the learned or fused 2D KXRCF/TVB
+   strips. */
+struct ProbeLists {
+  std::vector<mr_tile1> t1;
+  std::vector<mr_tile2> t2, t3;
+  int n_red = 0, t_sum = 0, n_sum = 0, t_flg = 0, n_flg = 0, t_val = 0, n_val = 0, t_st = 0, n_st = 0;
+  bool kx2 = false;
+};
+
+static ProbeLists probe_lists(const mrhweno_problem& p, int slot) {
+  ProbeLists L;
+  const bool lrn = learned(p);
+  add_cells(L.t1, slot, plane_of(p));
+  L.n_red = (int)L.t1.size();
+  L.t_sum = (int)L.t1.size();
+  if (needs_summ(p)) add_cells(L.t1, slot, (long long)sex(p) * sey(p));
+  L.n_sum = (int)L.t1.size() - L.t_sum;
+  L.t_flg = (int)L.t1.size();
+  L.kx2 = kx_tiles(p) > 0;   /* 2D KXRCF / TVB: flags from the fused kernel */
+  if (!lrn && !L.kx2) add_cells(L.t1, slot, (long long)fex(p) * fey(p));
+  L.n_flg = (int)L.t1.size() - L.t_flg;
+  L.t_val = (int)L.t1.size();
+  add_cells(L.t1, slot, plane_of(p));
+  L.n_val = (int)L.t1.size() - L.t_val;
+  L.t_st = (int)L.t1.size();
+  if (p.dim == 1) {
+    for (int s = 0; s < p.nx; s += kBlock - 2) L.t1.push_back(mr_tile1{slot, s, std::min(kBlock - 2, p.nx - s), 0});
+  } else {
+    const int w = strip_cells(p) - 2;
+    for (int y0 = 0; y0 < p.ny; y0 += 32)
+      for (int x0 = 0; x0 < p.nx; x0 += w) L.t2.push_back(mr_tile2{slot, x0, y0, std::min(32, p.ny - y0)});
+  }
+  L.n_st = (int)L.t1.size() - L.t_st;
+  if (lrn) add_learn_tiles(L.t3, slot, p);
+  if (L.kx2) add_kx_tiles(L.t3, slot, p);
+  return L;
+}
+
+/* bytes of the device copies of a probe's lists (three 256-byte aligned
+   pieces) */
+static size_t probe_list_bytes(const ProbeLists& L, size_t* o2, size_t* o3) {
+  *o2 = al(sizeof(mr_tile1) * L.t1.size());
+  *o3 = *o2 + al(sizeof(mr_tile2) * std::max<size_t>(L.t2.size(), 1));
+  return *o3 + sizeof(mr_tile2) * std::max<size_t>(L.t3.size(), 1);
+}
+
+/* The kernels of a one-off evaluation of a non-learned instance whose
+   descriptor sits in d[slot] and whose lists were copied to d1/d2/d3:
+   wave speeds and dt, troubled cells (Step 2.1), then the final values
+   (kind 0, into out) or L(U) (kind 2, into the descriptor's p_out[0]). */
+static hipError_t probe_kernels(hipStream_t s, const mrhweno_problem& p, const mr_inst& I, mr_inst* d, int slot,
+                                const ProbeLists& L, const mr_tile1* d1, const mr_tile2* d2, const mr_tile2* d3,
+                                int kind, void* out) {
+  hipError_t e;
+  mr_tile1* t1 = const_cast<mr_tile1*>(d1);
+  mr_tile2* t2 = const_cast<mr_tile2*>(d2);
+  mr_tile2* t3 = const_cast<mr_tile2*>(d3);
+  if ((e = mr_launch_reduce(s, d, t1, L.n_red, 0)) != hipSuccess) return e;
+  if ((e = mr_launch_finalize(s, d + slot, 1, 1)) != hipSuccess) return e;
+  if ((e = mr_launch_summary(s, p.dim, p.beta_on, I.pres != 0, d, t1 + L.t_sum, L.n_sum, 3)) != hipSuccess) return e;
+  if ((e = mr_launch_flags(s, p.dim, d, t1 + L.t_flg, L.n_flg, 3)) != hipSuccess) return e;
+  if (L.kx2 && (e = mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? 3 : 1, p.beta_on, I.pres != 0, d, t3,
+                                     (int)L.t3.size(), 3)) != hipSuccess)
+    return e;
+  const int nc = ncomp_of(p);
+  if (kind == 0 && (e = mr_launch_values(s, p.dim, nc, p.beta_on, d, t1 + L.t_val, L.n_val, (double*)out)) != hipSuccess)
+    return e;
+  if (kind == 2) {
+    if (p.dim == 1) e = mr_launch_stage1(s, nc, p.beta_on, I.pres != 0, d, t1 + L.t_st, L.n_st, 3, 0);
+    else e = mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, d, t2, (int)L.t2.size(), 3, 0);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 /* kind: 0 = reconstruct, 1 = flag, 2 = residual, 3 = learned-indicator
    decisions (out = decision plane, may be NULL) */
 static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, void* flags, void* aleph, int kind) {
@@ -813,66 +897,35 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
   double* al_buf = (double*)(c->ws + c->L.probe_aleph);
   I.aleph = aleph ? al_buf : nullptr;
   const int slot = c->n;
-  std::vector<mr_tile1> t1;
-  add_cells(t1, slot, plane_of(p));
-  const int n_red = (int)t1.size();
-  const int t_sum = (int)t1.size();
-  if (needs_summ(p)) add_cells(t1, slot, (long long)sex(p) * sey(p));
-  const int n_sum = (int)t1.size() - t_sum;
-  const int t_flg = (int)t1.size();
-  const bool kx2 = kx_tiles(p) > 0;   /* 2D KXRCF / TVB: flags from the fused kernel */
-  if (!lrn && !kx2) add_cells(t1, slot, (long long)fex(p) * fey(p));
-  const int n_flg = (int)t1.size() - t_flg;
-  const int t_val = (int)t1.size();
-  add_cells(t1, slot, plane_of(p));
-  const int n_val = (int)t1.size() - t_val;
-  const int t_st = (int)t1.size();
-  std::vector<mr_tile2> t2, tl;
-  if (p.dim == 1) {
-    for (int s = 0; s < p.nx; s += kBlock - 2) t1.push_back(mr_tile1{slot, s, std::min(kBlock - 2, p.nx - s), 0});
-  } else {
-    const int w = strip_cells(p) - 2;
-    for (int y0 = 0; y0 < p.ny; y0 += 32)
-      for (int x0 = 0; x0 < p.nx; x0 += w) t2.push_back(mr_tile2{slot, x0, y0, std::min(32, p.ny - y0)});
-  }
-  const int n_st = (int)t1.size() - t_st;
-  if (lrn) add_learn_tiles(tl, slot, p);
-  if (kx2) add_kx_tiles(tl, slot, p);
+  const ProbeLists PL = probe_lists(p, slot);
   /* the probe area holds the 1D list, the 2D list and the learned or the
      2D KXRCF list */
   char* area = c->ws + c->L.probe_tiles;
-  const size_t o2 = al(sizeof(mr_tile1) * t1.size());
-  const size_t o3 = o2 + al(sizeof(mr_tile2) * std::max<size_t>(t2.size(), 1));
-  if (o3 + sizeof(mr_tile2) * tl.size() > sizeof(mr_tile2) * (c->L.n_probe_tiles + 64))
+  size_t o2 = 0, o3 = 0;
+  if (probe_list_bytes(PL, &o2, &o3) > sizeof(mr_tile2) * (c->L.n_probe_tiles + 64))
     return fail(c, MRHWENO_ERR_DEVICE, "probe list overflow");
   mr_tile1* d1 = (mr_tile1*)area;
   mr_tile2* d2 = (mr_tile2*)(area + o2);
   mr_tile2* d3 = (mr_tile2*)(area + o3);
   MR_CHECK(c, hipMemcpy(&c->d[slot], &I, sizeof(mr_inst), hipMemcpyHostToDevice));
-  MR_CHECK(c, hipMemcpy(d1, t1.data(), sizeof(mr_tile1) * t1.size(), hipMemcpyHostToDevice));
-  if (!t2.empty()) MR_CHECK(c, hipMemcpy(d2, t2.data(), sizeof(mr_tile2) * t2.size(), hipMemcpyHostToDevice));
-  if (!tl.empty()) MR_CHECK(c, hipMemcpy(d3, tl.data(), sizeof(mr_tile2) * tl.size(), hipMemcpyHostToDevice));
+  MR_CHECK(c, hipMemcpy(d1, PL.t1.data(), sizeof(mr_tile1) * PL.t1.size(), hipMemcpyHostToDevice));
+  if (!PL.t2.empty()) MR_CHECK(c, hipMemcpy(d2, PL.t2.data(), sizeof(mr_tile2) * PL.t2.size(), hipMemcpyHostToDevice));
+  if (!PL.t3.empty()) MR_CHECK(c, hipMemcpy(d3, PL.t3.data(), sizeof(mr_tile2) * PL.t3.size(), hipMemcpyHostToDevice));
   hipStream_t s = c->stream;
   const size_t frow = (size_t)(p.dim == 2 ? kFHalo : 0) * I.fex + kFHalo;   /* first interior flag */
-  MR_CHECK(c, mr_launch_reduce(s, c->d, d1, n_red, 0));
-  MR_CHECK(c, mr_launch_finalize(s, c->d + slot, 1, 1));
   if (lrn) {
+    MR_CHECK(c, mr_launch_reduce(s, c->d, d1, PL.n_red, 0));
+    MR_CHECK(c, mr_launch_finalize(s, c->d + slot, 1, 1));
     MR_CHECK(c, mr_launch_fb_reset(s, c->cnt, 1));
-    MR_CHECK(c, mr_launch_learned(s, c->d, d3, (int)tl.size(), 3, c->lw, c->band, c->cnt, c->grid_l));
+    MR_CHECK(c, mr_launch_learned(s, c->d, d3, (int)PL.t3.size(), 3, c->lw, c->band, c->cnt, c->grid_l));
     if (kind == 3 && out)
       MR_CHECK(c, hipMemcpy2DAsync(out, p.nx, I.flags[0] + frow, I.fex, p.nx, p.ny, hipMemcpyDeviceToDevice, s));
     MR_CHECK(c, mr_launch_fallback(s, c->d, c->band, c->cnt, 3, c->grid_fb, p.beta_on));
+    const int nc = ncomp_of(p);
+    if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + PL.t_val, PL.n_val, (double*)out));
+    if (kind == 2) MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, c->d, d2, (int)PL.t2.size(), 3, 0));
   } else {
-    MR_CHECK(c, mr_launch_summary(s, p.dim, p.beta_on, I.pres != 0, c->d, d1 + t_sum, n_sum, 3));
-    MR_CHECK(c, mr_launch_flags(s, p.dim, c->d, d1 + t_flg, n_flg, 3));
-    if (kx2)
-      MR_CHECK(c, mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? 3 : 1, p.beta_on, I.pres != 0, c->d, d3, (int)tl.size(), 3));
-  }
-  const int nc = ncomp_of(p);
-  if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + t_val, n_val, (double*)out));
-  if (kind == 2) {
-    if (p.dim == 1) MR_CHECK(c, mr_launch_stage1(s, nc, p.beta_on, I.pres != 0, c->d, d1 + t_st, n_st, 3, 0));
-    else MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, c->d, d2, (int)t2.size(), 3, 0));
+    MR_CHECK(c, probe_kernels(s, p, I, c->d, slot, PL, d1, d2, d3, kind, out));
   }
   if (flags)
     MR_CHECK(c, hipMemcpy2DAsync(flags, p.nx, I.flags[0] + frow, I.fex, p.nx, p.dim == 2 ? p.ny : 1,
@@ -892,6 +945,99 @@ mrhweno_status mrhweno_flag(mrhweno_ctx* c, int q, const void* U, void* flags, v
 }
 mrhweno_status mrhweno_residual(mrhweno_ctx* c, int q, const void* U, void* R, void* flags) {
   return probe(c, q, U, R, flags, nullptr, 2);
+}
+
+/* ---- L(U) without allocation: scratch in a file-scope device array ---- */
+/* Per device, the descriptor, the work lists, the troubled-cell plane and
+   the 1D face summaries of mrhweno_residual_noalloc live here.  Host code
+   never passes this name to a kernel or a copy: it takes the array's
+   device address from hipGetSymbolAddress once per device (each device
+   holds its own copy) and uses that. */
+static __device__ __align__(256) unsigned char scratch[MRHWENO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+/* device address of `scratch` on the current device (set up on first use) */
+static hipError_t scratch_ptr(unsigned char** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = (unsigned char*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+mrhweno_status mrhweno_residual_noalloc(const mrhweno_problem* pp, const void* U, void* R, void* flags,
+                                        void* hip_stream) {
+  if (!pp || !U || !R) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL problem, state or residual");
+  const mrhweno_problem& p = *pp;
+  const std::string m = validate(p);
+  if (!m.empty()) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, m);
+  if (learned(p)) return fail(nullptr, MRHWENO_ERR_UNSUPPORTED, "the learned indicator needs a context (mrhweno_create)");
+  if ((reinterpret_cast<uintptr_t>(U) & 7) != 0 || (reinterpret_cast<uintptr_t>(R) & 7) != 0)
+    return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "state and residual must be 8-byte aligned");
+  /* scratch layout: descriptor | lists | flag plane | 1D face summaries */
+  const ProbeLists PL = probe_lists(p, 0);
+  size_t o2 = 0, o3 = 0;
+  const size_t o_lists = al(sizeof(mr_inst));
+  const size_t o_fl = o_lists + al(probe_list_bytes(PL, &o2, &o3));
+  const size_t o_summ = o_fl + al((size_t)fex(p) * fey(p));
+  const size_t need = o_summ + (needs_summ(p) ? sizeof(double) * nsumm(p) * (size_t)sex(p) * sey(p) : 0);
+  if (need > (size_t)MRHWENO_NOALLOC_SCRATCH_BYTES)
+    return fail(nullptr, MRHWENO_ERR_INVALID_ARG,
+                "problem needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                    std::to_string((size_t)MRHWENO_NOALLOC_SCRATCH_BYTES));
+  unsigned char* base = nullptr;
+  hipError_t e = scratch_ptr(&base);
+  if (e != hipSuccess) return fail(nullptr, MRHWENO_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  mr_inst I;
+  fill_inst(p, I);
+  I.buf[0] = (double*)U;
+  I.p_in[0] = (const double*)U;
+  I.p_un = (const double*)U;
+  I.p_out[0] = (double*)R;
+  I.flags[0] = I.flags[1] = base + o_fl;
+  I.summ = needs_summ(p) ? (double*)(base + o_summ) : nullptr;
+  I.active = 1;
+  mr_inst* d = (mr_inst*)base;
+  mr_tile1* d1 = (mr_tile1*)(base + o_lists);
+  mr_tile2* d2 = (mr_tile2*)(base + o_lists + o2);
+  mr_tile2* d3 = (mr_tile2*)(base + o_lists + o3);
+  hipStream_t s = (hipStream_t)hip_stream;
+#define MR_NA(expr)                                                                                    \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return fail(nullptr, MRHWENO_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  /* every word the kernels read is written here or by an earlier kernel of
+     this call: the descriptor and lists are copied in, the flag plane is
+     written whole by the troubled-cell pass, the summaries by theirs */
+  MR_NA(hipMemcpyAsync(d, &I, sizeof(mr_inst), hipMemcpyHostToDevice, s));
+  MR_NA(hipMemcpyAsync(d1, PL.t1.data(), sizeof(mr_tile1) * PL.t1.size(), hipMemcpyHostToDevice, s));
+  if (!PL.t2.empty()) MR_NA(hipMemcpyAsync(d2, PL.t2.data(), sizeof(mr_tile2) * PL.t2.size(), hipMemcpyHostToDevice, s));
+  if (!PL.t3.empty()) MR_NA(hipMemcpyAsync(d3, PL.t3.data(), sizeof(mr_tile2) * PL.t3.size(), hipMemcpyHostToDevice, s));
+  MR_NA(probe_kernels(s, p, I, d, 0, PL, d1, d2, d3, 2, R));
+  if (flags) {
+    const size_t frow = (size_t)(p.dim == 2 ? kFHalo : 0) * I.fex + kFHalo;
+    MR_NA(hipMemcpy2DAsync(flags, p.nx, I.flags[0] + frow, I.fex, p.nx, p.dim == 2 ? p.ny : 1,
+                           hipMemcpyDeviceToDevice, s));
+  }
+  /* the host lists above must outlive their copies */
+  MR_NA(hipStreamSynchronize(s));
+#undef MR_NA
+  return MRHWENO_OK;
 }
 
 mrhweno_status mrhweno_indicator(mrhweno_ctx* c, int q, const void* U, void* decision, void* flags) {

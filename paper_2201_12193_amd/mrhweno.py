@@ -28,7 +28,7 @@ MLP_PARAMS = 24776
 
 EXPORTS = ["mrhweno_workspace_bytes", "mrhweno_create", "mrhweno_step", "mrhweno_sync",
            "mrhweno_set_time", "mrhweno_last_dt", "mrhweno_reconstruct", "mrhweno_flag",
-           "mrhweno_residual", "mrhweno_set_launch", "mrhweno_autotune", "mrhweno_profile",
+           "mrhweno_residual", "mrhweno_residual_noalloc", "mrhweno_set_launch", "mrhweno_autotune", "mrhweno_profile",
            "mrhweno_set_indicator", "mrhweno_indicator", "mrhweno_features",
            "mrhweno_mlp_param_count", "mrhweno_mlp_feature_count", "mrhweno_mlp_cache_bytes",
            "mrhweno_mlp_gemm", "mrhweno_mlp_forward", "mrhweno_mlp_backward", "mrhweno_mlp_adam",
@@ -104,6 +104,7 @@ def lib():
         L.mrhweno_reconstruct.argtypes = [vp, C.c_int, vp, vp, vp]
         L.mrhweno_flag.argtypes = [vp, C.c_int, vp, vp, vp]
         L.mrhweno_residual.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.mrhweno_residual_noalloc.argtypes = [PP, vp, vp, vp, vp]
         L.mrhweno_set_launch.argtypes = [vp, C.c_int, C.c_int]
         L.mrhweno_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int)]
         IP = C.POINTER(C.c_int)
@@ -138,6 +139,27 @@ def _check(ctx, status: int) -> None:
 def workspace_bytes(problems: Sequence[Problem]) -> int:
     arr = (MrProblem * len(problems))(*[to_c(p) for p in problems])
     return int(lib().mrhweno_workspace_bytes(arr, len(problems)))
+
+
+def residual_noalloc(problem: Problem, U, R=None, flags=None, stream=None):
+    """L(U) of one problem without a context or any allocation inside the
+    library (mrhweno_residual_noalloc).  U, R: contiguous float64 CUDA
+    tensors of shape problem.shape() (R allocated here if not given);
+    flags: uint8 CUDA tensor of the grid's shape, or None.  Returns
+    (R, flags)."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the MR-HWENO library runs on the device only")
+    if U.dtype != torch.float64 or not U.is_cuda or not U.is_contiguous() or tuple(U.shape) != problem.shape():
+        raise ValueError("U must be a contiguous float64 CUDA tensor of shape Problem.shape()")
+    if R is None:
+        R = torch.empty_like(U)
+    st = stream if stream is not None else torch.cuda.current_stream()
+    cp = to_c(problem)
+    _check(None, lib().mrhweno_residual_noalloc(C.byref(cp), C.c_void_p(U.data_ptr()), C.c_void_p(R.data_ptr()),
+                                                C.c_void_p(flags.data_ptr() if flags is not None else None),
+                                                C.c_void_p(st.cuda_stream)))
+    return R, flags
 
 
 class Solver:
