@@ -92,18 +92,45 @@ def measured_traffic(ncell: int):
     return c.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(prob, U0):
     """The CPU oracle as it stands, on this host's cores: one evaluation of
     the spatial operator L(U) (one RK stage of work) on the full grid of the
-    same workload."""
+    same workload with every thread OpenMP offers, and the same on a
+    512 x 512 window of that state (periodic) with one thread."""
+    import numpy as np
     import oracle
     threads = oracle.max_threads()
     t0 = time.perf_counter()
     oracle.residual(prob, U0)
     dt = time.perf_counter() - t0
+    m = min(512, prob.nx, prob.ny)
+    sub = prob.replace(nx=m, ny=m, x1=prob.x0 + m * prob.dx, y1=prob.y0 + m * prob.dy)
+    Us = np.ascontiguousarray(U0[:, :, :m, :m])
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.residual(sub, Us)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
     return {"value": prob.ncell / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one L(U) evaluation (one RK stage) of the full {prob.nx}x{prob.ny} initial state, "
-                      f"{dt:.1f} s on {threads} threads"}
+                      f"{dt:.1f} s on {threads} threads",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread": {"value": sub.ncell / dt1, "unit": "cell-updates/s", "cores": 1,
+                              "sample": f"one L(U) evaluation of a {m}x{m} window of the same state "
+                                        f"(periodic), {dt1:.1f} s on 1 thread"}}
 
 
 def timed_run(prob, U0, steps, warmup, rows=0, grid=0, weights=None, band=None, shape=None):
