@@ -14,9 +14,12 @@ Prints one JSON line.  value = cells x RK stages / wall time of the timed
 plain run (inputs resident in HBM).  The timed steps are launched one kernel
 class at a time with HIP events on the library's stream between classes,
 which gives the per-kernel averages of the roofline entry.  The learned
-path is then timed the same way and compared with the plain path at equal
-simulated time (relative L1 difference of the cell averages) and against
-KXRCF decisions on its own states (false-negative rate).
+path is then timed the same way and compared with the plain path after the
+configured 200 steps, at equal simulated time (relative L1 difference of the
+cell averages), and against KXRCF decisions on six snapshots of its own run
+(false-negative rate).  Extra keys: the batched configuration (256
+instances of uneven sizes in one launch per kernel class) and the CPU
+oracle's rate on the host (all threads and one thread).
 """
 from __future__ import annotations
 
@@ -43,6 +46,9 @@ STAGE_FLOP_PER_CELL = 5900.0
 STAGE_KERNEL = "k2_stage<4,false,false>"
 COUNTERS = os.path.join(ROOT, "profiles", "k2_stage_euler2d_2048_counters.json")
 STAGE_SOURCES = ["mr_stage2d.hip", "mr_common.h", "mr_device.h", "mr_types.h", "recon_gen.h"]
+BATCHED_DESC = ("256 Euler instances in one launch per kernel class (192 1D, N log-uniform 128..16384; "
+                "64 2D, side log-uniform 64..1024), HLLC, KXRCF, CFL 0.6")
+EQUAL_L1_STEPS = 200   # the learned-vs-plain comparison runs the configured 200 steps
 
 
 def parse():
@@ -66,6 +72,9 @@ def parse():
                          "instance kept advancing; dmr2d times the whole double Mach reflection "
                          "(Example 3.9, 1600 x 400) to T = 0.2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched configuration's throughput (extra key of the default run)")
+    ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration for profiles)")
     return ap.parse_args()
@@ -168,10 +177,25 @@ def timed_run(prob, U0, steps, warmup, rows=0, grid=0, weights=None, band=None, 
     return wall, ms, nl, t[0], Ut, shape
 
 
+def plain_reference(prob, U0, steps, shape):
+    """The plain (KXRCF) run of `steps` steps from U0 (graph replay);
+    returns (final time, final state)."""
+    import torch
+    from paper_2201_12193_amd.mrhweno import Solver
+    U = torch.from_numpy(U0).cuda()
+    s = Solver([prob], [U])
+    s.set_launch(*shape)
+    s.step(steps)
+    t, _, _ = s.sync()
+    s.close()
+    return t[0], U
+
+
 def learned_compare(prob, U0, Uk, T, weights, band, steps):
     """The learned path run to the plain run's final time T (graph replay),
     relative L1 difference of the cell averages per component, and the
-    KXRCF false-negative rate on snapshots of the learned run."""
+    KXRCF false-negative rate on six snapshots of the learned run (every
+    steps/5 steps, the first at t = 0), overall and per snapshot."""
     import numpy as np
     import torch
     from paper_2201_12193_amd import inputs as I
@@ -182,17 +206,19 @@ def learned_compare(prob, U0, Uk, T, weights, band, steps):
     s.set_indicator(weights, *band)
     judge = Solver([prob], [torch.from_numpy(U0).cuda()])
     fn = tp = fp = nband = ncell = 0
+    snaps = []
     every = max(steps // 5, 1)
     t = [0.0]
     for k in range(6):
         dec, fl = s.indicator(0, U)
         fk, _ = judge.flag(0, U)
         dec, fl, fk = dec.cpu().numpy(), fl.cpu().numpy().astype(bool), fk.cpu().numpy().astype(bool)
-        fn += int((fk & ~fl).sum())
-        tp += int((fk & fl).sum())
-        fp += int((~fk & fl).sum())
+        a, b, c = int((fk & ~fl).sum()), int((fk & fl).sum()), int((~fk & fl).sum())
+        fn, tp, fp = fn + a, tp + b, fp + c
         nband += int((dec == 2).sum())
         ncell += dec.size
+        snaps.append({"step": k * every, "kxrcf_flags": a + b, "false_negative_rate": a / max(a + b, 1),
+                      "false_positives": c, "band_fraction": float((dec == 2).mean())})
         if k < 5:
             s.step(every)
     done = 5 * every
@@ -206,9 +232,45 @@ def learned_compare(prob, U0, Uk, T, weights, band, steps):
     a = U.cpu().numpy()
     b = Uk.cpu().numpy()
     l1 = [float(np.abs(a[c, 0] - b[c, 0]).sum() / np.abs(b[c, 0]).sum()) for c in range(prob.ncomp)]
-    return {"t": t[0], "rel_l1_diff": l1, "false_negative_rate": fn / max(fn + tp, 1),
+    return {"steps": steps, "t": t[0], "rel_l1_diff": l1, "false_negative_rate": fn / max(fn + tp, 1),
             "false_positives_per_kxrcf_flag": fp / max(fn + tp, 1), "kxrcf_flags_judged": fn + tp,
-            "band_fraction": nband / max(ncell, 1)}
+            "band_fraction": nband / max(ncell, 1), "snapshots": snaps}
+
+
+def batched_measure(seed, steps, warmup):
+    """The batched configuration: 256 Euler instances of uneven sizes in one
+    launch per kernel class (graph replay of `steps` steps of every
+    instance, final times lifted so that all keep advancing; an instance
+    that meets a non-physical state stops and only the steps actually taken
+    count).  Returns (cell-updates/s, wall s, details)."""
+    import torch
+    from paper_2201_12193_amd import inputs as I
+    from paper_2201_12193_amd.mrhweno import Solver
+    from paper_2201_12193_amd import autotune
+    pairs = I.batched_instances(seed)
+    probs = [p.replace(t_final=float("inf")) for p, _ in pairs]
+    Us = [torch.from_numpy(U).cuda() for _, U in pairs]
+    s = Solver(probs, Us)
+    shape = autotune.tune(s, use_cache=False, reps=3)[:2]
+    s.step(warmup)
+    _, st0, _ = s.sync(raise_on_error=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    _, st1, _ = s.sync(raise_on_error=False)
+    wall = time.perf_counter() - t0
+    prof_steps = min(steps, 20)
+    ms, nl = s.profile(prof_steps)
+    s.close()
+    updates = sum(p.ncell * 3 * (b - a) for p, a, b in zip(probs, st0, st1))
+    stopped = sum(1 for a, b in zip(st0, st1) if b - a < steps)
+    info = {"instances": len(probs), "instances_1d": sum(1 for p in probs if p.dim == 1),
+            "instances_2d": sum(1 for p in probs if p.dim == 2), "cells": sum(p.ncell for p in probs),
+            "seed": seed, "instances_stopped_nonphysical": stopped,
+            "launch": {"rows_per_strip": shape[0], "grid": shape[1], "chosen_by": "autotuner"},
+            "kernels_ms_per_step": {"reduce_dt": ms[0] / prof_steps, "kxrcf": (ms[1] + ms[2]) / prof_steps,
+                                    "stage": ms[3] / prof_steps}}
+    return updates / wall, wall, info
 
 
 def other_workload(args):
@@ -218,44 +280,40 @@ def other_workload(args):
     import torch
     from paper_2201_12193_amd import inputs as I
     from paper_2201_12193_amd.mrhweno import Solver
-    from paper_2201_12193_amd import autotune
     if args.workload == "batched":
-        pairs = I.batched_instances(args.seed)
-        desc = "256 Euler instances (192 1D, N log-uniform 128..16384; 64 2D, side log-uniform 64..1024)"
-    elif args.workload == "riemann1d":
+        value, wall, info = batched_measure(args.seed, args.steps, args.warmup)
+        out = {"metric": "MR-HWENO cell-updates/s (FP64)", "value": value,
+               "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": dict({"workload": BATCHED_DESC}, **info)}
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "riemann1d":
         p, U, _ = I.euler_riemann_1d(args.seed, n=4096)
-        pairs = [(p, U)]
         desc = "1D Euler Riemann data, N = 4096, transmissive, HLLC"
     else:
         p, U, _ = I.burgers_smooth_1d(args.seed, n=200)
-        pairs = [(p, U)]
         desc = "1D Burgers, N = 200, periodic, Lax-Friedrichs"
-    probs = [p.replace(t_final=float("inf")) for p, _ in pairs]
-    Us = [torch.from_numpy(U).cuda() for _, U in pairs]
-    s = Solver(probs, Us)
-    shape = autotune.tune(s, use_cache=False, reps=3)[:2] if any(p.dim == 2 for p in probs) else None
+    prob = p.replace(t_final=float("inf"))
+    Ut = torch.from_numpy(U).cuda()
+    s = Solver([prob], [Ut])
     s.step(args.warmup)
     _, st0, _ = s.sync(raise_on_error=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(args.steps)
-    _, st1, status = s.sync(raise_on_error=False)
+    _, st1, _ = s.sync(raise_on_error=False)
     wall = time.perf_counter() - t0
     ms, nl = s.profile(min(args.steps, 20))
     s.close()
-    cells = sum(p.ncell for p in probs)
-    # an instance that meets a non-physical state stops advancing: count the
-    # steps each instance actually took
-    updates = sum(p.ncell * 3 * (b - a) for p, a, b in zip(probs, st0, st1))
-    stopped = sum(1 for a, b in zip(st0, st1) if b - a < args.steps)
+    updates = prob.ncell * 3 * (st1[0] - st0[0])
     out = {"metric": "MR-HWENO cell-updates/s (FP64)", "value": updates / wall,
            "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": desc, "instances": len(probs), "cells": cells, "seed": args.seed,
-                      "instances_stopped_nonphysical": stopped,
-                      "launch": None if shape is None else {"rows_per_strip": shape[0], "grid": shape[1]}},
-           "kernels_ms_per_step": {"reduce_dt": ms[0] / max(nl[0], 1) * (nl[0] / max(1, min(args.steps, 20))),
+           "config": {"workload": desc, "instances": 1, "cells": prob.ncell, "seed": args.seed},
+           "kernels_ms_per_step": {"reduce_dt": ms[0] / min(args.steps, 20),
                                    "kxrcf": (ms[1] + ms[2]) / min(args.steps, 20),
                                    "stage": ms[3] / min(args.steps, 20)}}
     print(json.dumps(out), flush=True)
@@ -355,7 +413,12 @@ def main():
         pl = prob.replace(tc_mode=I.TC_LEARNED)
         lw, lms, lnl, lT, _, _ = timed_run(pl, U0, args.steps, args.warmup, args.rows, args.grid, W, args.band, shape)
         lv = ncell * 3 * args.steps / lw
-        cmp = learned_compare(prob, U0, Uk, T, W, args.band, args.steps)
+        if args.steps == EQUAL_L1_STEPS:
+            Tc, Uc = T, Uk
+        else:
+            Tc, Uc = plain_reference(prob, U0, EQUAL_L1_STEPS, shape)
+        cmp = learned_compare(prob, U0, Uc, Tc, W, args.band, EQUAL_L1_STEPS)
+        del Uc
         out["learned"] = {"value": lv, "speedup_vs_plain": lv / value, "band": list(args.band),
                           "ms_per_step": lw / args.steps * 1e3,
                           "kernels_ms": {"reduce_dt": lms[0], "inference": lms[1], "band_fallback": lms[2],
@@ -374,6 +437,12 @@ def main():
         a.sum()                      # read-only pass over 1 GiB
         torch.cuda.synchronize()
         del a, b
+    if not args.no_batched:
+        bv, bwall, binfo = batched_measure(args.seed, args.batched_steps, args.warmup)
+        out["batched"] = dict({"value": bv, "unit": "cell-updates/s", "steps": args.batched_steps,
+                               "ms_per_step": bwall / args.batched_steps * 1e3, "workload": BATCHED_DESC},
+                              **binfo)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, U0)
     print(json.dumps(out), flush=True)

@@ -132,3 +132,46 @@ def test_nonphysical_state_is_latched():
     assert steps[0] == 0 and t[0] == 0.0 and np.array_equal(A.cpu().numpy(), bad)
     assert steps[1] == 3 and t[1] > 0.0
     s.close()
+
+
+@pytest.mark.slow
+def test_configured_batch_equals_standalone_and_oracle():
+    """The configured batch (256 Euler instances, 192 1D with N log-uniform
+    in [128, 16384] and 64 2D with side log-uniform in [64, 1024], the
+    benchmark's seed) advanced 8 steps in one context: a sample of instances
+    of both dimensions (the smallest and largest of each, instances that
+    meet a non-physical state within those steps, and a spread between)
+    equals the same instance run alone bit for bit, with the same time and
+    step count; the smallest instances' first step matches the oracle."""
+    from paper_2201_12193_amd.mrhweno import Solver
+    pairs = I.batched_instances(2048)
+    probs = [p.replace(t_final=float("inf")) for p, _ in pairs]
+    Ub = [_t(U) for _, U in pairs]
+    sb = Solver(probs, Ub)
+    sb.step(1)
+    dts = sb.last_dt()
+    t1, n1, _ = sb.sync(raise_on_error=False)
+    first = [U.cpu().numpy() for U in Ub]
+    sb.step(7)
+    tb, nb, st = sb.sync(raise_on_error=False)
+    sb.close()
+    latched = [q for q in range(len(probs)) if nb[q] < 8]
+    assert latched, "the configured batch has instances that stop within 8 steps"
+    one = [q for q in range(len(probs)) if probs[q].dim == 1]
+    two = [q for q in range(len(probs)) if probs[q].dim == 2]
+    size = lambda q: probs[q].ncell
+    sample = {min(one, key=size), max(one, key=size), min(two, key=size), max(two, key=size)}
+    sample |= set(one[::48]) | set(two[::16]) | set(latched[:3])
+    print(f"configured batch: {len(probs)} instances, latched {latched}, sample {sorted(sample)}", flush=True)
+    for q in sorted(sample):
+        Us = _t(pairs[q][1])
+        ss = Solver([probs[q]], [Us])
+        ss.step(8)
+        ts, ns, _ = ss.sync(raise_on_error=False)
+        ss.close()
+        assert ts[0] == tb[q] and ns[0] == nb[q], q
+        assert np.array_equal(Us.cpu().numpy(), Ub[q].cpu().numpy()), q
+    for q in (min(one, key=size), min(two, key=size)):
+        if n1[q] == 1:
+            ref = oracle.rk3_step(probs[q], pairs[q][1], dts[q])
+            assert rel_state_err(probs[q], first[q], ref, comp_scale(probs[q], pairs[q][1])) <= 1e-12, q
