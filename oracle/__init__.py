@@ -91,6 +91,8 @@ def lib():
         L.orc_modify.argtypes = [P, D, B, D]
         L.orc_residual_cell_2d.argtypes = [P, D, C.c_double, C.c_int, C.c_int, D]
         L.orc_gl.argtypes = [D, D]
+        L.orc_euler2_eigen.argtypes = [D, C.c_double, C.c_int, D, D]
+        L.orc_step1_2d_sys.argtypes = [P, D, D, D, C.c_int, D]
         L.orc_max_threads.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
@@ -163,6 +165,16 @@ def step1_2d(prob, ub, vb, wb) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     return gl, w, b
 
 
+def step1_2d_sys(prob, ub, vb, wb, direction: int = 0) -> np.ndarray:
+    """Step 1 (2D) for all components of one cell; ub/vb/wb [ncomp][9]
+    indexed by stencil label-1.  With prob.charwise on 2D Euler: the set of
+    values of the given direction (0: x, 1: y).  Returns [ncomp][16]."""
+    ub, vb, wb = _arr(ub), _arr(vb), _arr(wb)
+    out = np.zeros((ub.shape[0], 16))
+    lib().orc_step1_2d_sys(C.byref(cprob(prob)), _dp(ub), _dp(vb), _dp(wb), int(direction), _dp(out))
+    return out
+
+
 def qmap_1d(level: int) -> np.ndarray:
     deg = {2: 2, 3: 3, 4: 5}[level]
     out = np.zeros((deg + 1, 6))
@@ -182,6 +194,16 @@ def euler1_eigen(u, gamma: float) -> Tuple[np.ndarray, np.ndarray]:
     L, R = np.zeros(9), np.zeros(9)
     lib().orc_euler1_eigen(_dp(np.ascontiguousarray(u, dtype=np.float64)), C.c_double(gamma), _dp(L), _dp(R))
     return L.reshape(3, 3), R.reshape(3, 3)
+
+
+def euler2_eigen(u, gamma: float, direction: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Left and right eigenvector matrices of the 2D Euler flux Jacobian in
+    direction 0 (x) or 1 (y) at the conserved state u (rows of L, columns
+    of R)."""
+    L, R = np.zeros(16), np.zeros(16)
+    lib().orc_euler2_eigen(_dp(np.ascontiguousarray(u, dtype=np.float64)), C.c_double(gamma), int(direction),
+                           _dp(L), _dp(R))
+    return L.reshape(4, 4), R.reshape(4, 4)
 
 
 def monomials_2d() -> Tuple[np.ndarray, np.ndarray]:

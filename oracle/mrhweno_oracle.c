@@ -79,6 +79,19 @@
  *       eigenvectors of the Euler flux Jacobian at the average of cell i,
  *       each field is reconstructed by Step 1, and the Gauss-Lobatto values
  *       are mapped back with the right eigenvectors.
+ *   R18 characteristic-wise Step 1 in 2D (Euler, charwise = 1): every
+ *       cell carries two sets of Gauss-Lobatto values, one per direction d
+ *       (x, y).  For set d the stencil moments of all components are
+ *       projected with the left eigenvectors of the flux Jacobian in
+ *       direction d at the target cell's average, each field goes through
+ *       Step 1, and the values are mapped back with the right eigenvectors.
+ *       Everything that belongs to direction d takes set d: the numerical
+ *       fluxes on the faces normal to d, the volume integral of the flux
+ *       in direction d (F for x, G for y), and in the KXRCF test the jumps
+ *       and the normal velocity on those faces; the norm of the KXRCF test
+ *       is the maximum of |rho| over both sets' sixteen values.  Step 2.3
+ *       re-reconstructs both sets of a troubled cell from its modified
+ *       stencil.  With charwise = 0 the two sets coincide (R2).
  *   R14 the TVB minmod indicator (tc_mode 4, one of Remark 2's
  *       alternatives, defined in its reference rather than the paper) acts
  *       on the indicator variable (density; u for Burgers) with h = dx; in
@@ -904,6 +917,87 @@ void orc_euler1_eigen(const double* u, double gam, double* L9, double* R9) {
   memcpy(R9, R, sizeof R);
 }
 
+/* Eigenvectors of the 2D Euler flux Jacobian in direction dir (0: x,
+   1: y) at the conserved state u (R18).  With the normal velocity vn, the
+   tangential velocity vt, q^2 = u^2 + v^2, H = (E + p)/rho,
+   b1 = (gamma-1)/c^2, b2 = b1 q^2/2, the columns of R are the acoustic
+   waves (1, .., H -+ vn c) with the normal momentum entry vn -+ c, the
+   entropy wave (1, u, v, q^2/2) and the shear wave (0, .., 1, .., vt) with
+   the 1 in the tangential momentum slot; L = R^-1 row by row. */
+static void euler2_eigen(const double* u, double gam, int dir, double L[4][4], double R[4][4]) {
+  const double rho = u[0], vx = u[1] / rho, vy = u[2] / rho;
+  const double q2 = vx * vx + vy * vy;
+  const double p = (gam - 1.0) * (u[3] - 0.5 * rho * q2);
+  const double c = sqrt(gam * p / rho), H = (u[3] + p) / rho;
+  const double b1 = (gam - 1.0) / (c * c), b2 = 0.5 * b1 * q2;
+  const int n = 1 + dir, t = 2 - dir;          /* normal and tangential momentum slots */
+  const double vn = dir == 0 ? vx : vy, vt = dir == 0 ? vy : vx;
+  memset(R, 0, 16 * sizeof(double));
+  memset(L, 0, 16 * sizeof(double));
+  /* columns: 0 acoustic (vn - c), 1 entropy, 2 shear, 3 acoustic (vn + c) */
+  R[0][0] = 1.0; R[n][0] = vn - c; R[t][0] = vt; R[3][0] = H - vn * c;
+  R[0][1] = 1.0; R[n][1] = vn;     R[t][1] = vt; R[3][1] = 0.5 * q2;
+  R[0][2] = 0.0; R[n][2] = 0.0;    R[t][2] = 1.0; R[3][2] = vt;
+  R[0][3] = 1.0; R[n][3] = vn + c; R[t][3] = vt; R[3][3] = H + vn * c;
+  L[0][0] = 0.5 * (b2 + vn / c); L[0][n] = -0.5 * (b1 * vn + 1.0 / c); L[0][t] = -0.5 * b1 * vt; L[0][3] = 0.5 * b1;
+  L[1][0] = 1.0 - b2;            L[1][n] = b1 * vn;                    L[1][t] = b1 * vt;        L[1][3] = -b1;
+  L[2][0] = -vt;                 L[2][n] = 0.0;                        L[2][t] = 1.0;            L[2][3] = 0.0;
+  L[3][0] = 0.5 * (b2 - vn / c); L[3][n] = -0.5 * (b1 * vn - 1.0 / c); L[3][t] = -0.5 * b1 * vt; L[3][3] = 0.5 * b1;
+}
+
+void orc_euler2_eigen(const double* u, double gam, int dir, double* L16, double* R16) {
+  double L[4][4], R[4][4];
+  euler2_eigen(u, gam, dir, L, R);
+  memcpy(L16, L, sizeof L);
+  memcpy(R16, R, sizeof R);
+}
+
+/* Step 1 of a 2D target cell for all components from the stencil moments
+   ub/vb/wb[c][label-1]: component by component (R2), or, with charwise on
+   2D Euler, on the characteristic fields of direction `set` (R18).
+   out[c*16 + k + 4 l] at (xi_k, eta_l). */
+static void step1_2d_all(const orc_problem* P, double ub[][9], double vb[][9], double wb[][9], int set,
+                         double* out) {
+  const int nc = ncomp_of(P);
+  if (!(P->charwise && P->system == 1 && P->dim == 2)) {
+    for (int c = 0; c < nc; ++c) orc_step1_2d(P, ub[c], vb[c], wb[c], &out[c * 16], NULL, NULL);
+    return;
+  }
+  double L[4][4], R[4][4], u0[4] = {ub[0][4], ub[1][4], ub[2][4], ub[3][4]};
+  euler2_eigen(u0, P->gamma, set, L, R);
+  double w[4][16];
+  for (int k = 0; k < 4; ++k) {
+    double fu[9], fv[9], fw[9];
+    for (int l = 0; l < 9; ++l) {
+      fu[l] = fv[l] = fw[l] = 0.0;
+      for (int c = 0; c < 4; ++c) {
+        fu[l] += L[k][c] * ub[c][l];
+        fv[l] += L[k][c] * vb[c][l];
+        fw[l] += L[k][c] * wb[c][l];
+      }
+    }
+    orc_step1_2d(P, fu, fv, fw, w[k], NULL, NULL);
+  }
+  for (int c = 0; c < 4; ++c)
+    for (int q = 0; q < 16; ++q) {
+      double v = 0.0;
+      for (int k = 0; k < 4; ++k) v += R[c][k] * w[k][q];
+      out[c * 16 + q] = v;
+    }
+}
+
+/* Step 1 of one 2D target cell for all components (stencil moments
+   ub/vb/wb[c*9 + label-1]), set 0 (x) or 1 (y), for the pins. */
+void orc_step1_2d_sys(const orc_problem* P, const double* ub, const double* vb, const double* wb, int set,
+                      double* out) {
+  init_2d();
+  double u[4][9], v[4][9], w[4][9];
+  const int nc = ncomp_of(P);
+  for (int c = 0; c < nc; ++c)
+    for (int l = 0; l < 9; ++l) { u[c][l] = ub[c * 9 + l]; v[c][l] = vb[c * 9 + l]; w[c][l] = wb[c * 9 + l]; }
+  step1_2d_all(P, u, v, w, set, out);
+}
+
 /* Work arrays for the 1D operator: ranges include R ghost cells each side. */
 #define R1G 4
 typedef struct {
@@ -1053,7 +1147,8 @@ static void residual_1d(const orc_problem* P, const double* U, double* L, unsign
 #define R2G 4
 typedef struct {
   int nx, ny, nc, ex, ey;  /* extended sizes */
-  double* g0;              /* [cell][comp][16] */
+  int nset;                /* sets of values per cell: 2 with charwise (R18), else 1 */
+  double* g0;              /* [cell][set][comp][16] */
   double* gf;
   unsigned char* fl;
   double* anum;
@@ -1061,6 +1156,11 @@ typedef struct {
 } work2_t;
 
 static size_t w2idx(const work2_t* W, int i, int j) { return (size_t)(j + R2G) * W->ex + (i + R2G); }
+static int nset_of(const orc_problem* P) { return (P->charwise && P->system == 1 && P->dim == 2) ? 2 : 1; }
+/* values (comp-major, 16 per component) of set `set` of window cell (i, j) */
+static double* w2val(double* a, const work2_t* W, int i, int j, int set) {
+  return &a[(w2idx(W, i, j) * W->nset + (W->nset > 1 ? set : 0)) * W->nc * 16];
+}
 
 static void gather2(const grid_t* G, int c, int i, int j, double* ub, double* vb, double* wb) {
   for (int lab = 1; lab <= 9; ++lab) {
@@ -1088,13 +1188,15 @@ static void modified_vw2(const grid_t* G, int c, int i, int j, double* v, double
 static void kxrcf_2d(const orc_problem* P, const work2_t* W, int wi, int wj, int i, int j,
                      unsigned char* flag, double* num_out, double* den_out) {
   int nc = W->nc;
-  const double* own = &W->g0[w2idx(W, wi, wj) * nc * 16];
-  const double* nb[4] = {&W->g0[w2idx(W, wi - 1, wj) * nc * 16], &W->g0[w2idx(W, wi + 1, wj) * nc * 16],
-                         &W->g0[w2idx(W, wi, wj - 1) * nc * 16], &W->g0[w2idx(W, wi, wj + 1) * nc * 16]};
   /* faces: 0 = left (x_{i-1/2}), 1 = right, 2 = bottom (y_{j-1/2}), 3 = top.
-     own point index and neighbour point index for the m-th face point */
+     own point index and neighbour point index for the m-th face point; the
+     values of the face's direction (R18) */
   double J = 0.0, len = 0.0;
   for (int f = 0; f < 4; ++f) {
+    const int set = f / 2;
+    const double* own = w2val(W->g0, W, wi, wj, set);
+    const double* nb[4] = {w2val(W->g0, W, wi - 1, wj, set), w2val(W->g0, W, wi + 1, wj, set),
+                           w2val(W->g0, W, wi, wj - 1, set), w2val(W->g0, W, wi, wj + 1, set)};
     double jump = 0.0, vel = 0.0;
     int dir = f / 2;
     double flen = dir == 0 ? P->dy : P->dx;
@@ -1116,7 +1218,10 @@ static void kxrcf_2d(const orc_problem* P, const work2_t* W, int wi, int wj, int
     if (arg > 0.0) { J += jump; len += flen; }
   }
   double nrm = 0.0;
-  for (int k = 0; k < 16; ++k) if (fabs(own[k]) > nrm) nrm = fabs(own[k]);
+  for (int set = 0; set < W->nset; ++set) {
+    const double* own = w2val(W->g0, W, wi, wj, set);
+    for (int k = 0; k < 16; ++k) if (fabs(own[k]) > nrm) nrm = fabs(own[k]);
+  }
   double num = fabs(J), den = P->dx * P->dx * len * nrm;
   *flag = (unsigned char)(num > den);
   *num_out = num;
@@ -1126,14 +1231,15 @@ static void kxrcf_2d(const orc_problem* P, const work2_t* W, int wi, int wj, int
 /* TVB minmod indicator in 2D: per direction, the Gauss-Lobatto averages of
    the Step-1 values over the two faces against the differences of the
    neighbouring cell averages; h = dx (square cells). */
-static int tvb_2d(const grid_t* G, const double* own /* 16 values, comp 0 */, int i, int j) {
+static int tvb_2d(const grid_t* G, const double* own /* comp 0 of the x set */,
+                  const double* owny /* comp 0 of the y set */, int i, int j) {
   const orc_problem* P = G->P;
   double fl = 0.0, fr = 0.0, fb = 0.0, ft = 0.0;
   for (int m = 0; m < 4; ++m) {
     fl += gl_weight(m) * own[0 + 4 * m];
     fr += gl_weight(m) * own[3 + 4 * m];
-    fb += gl_weight(m) * own[m];
-    ft += gl_weight(m) * own[12 + m];
+    fb += gl_weight(m) * owny[m];
+    ft += gl_weight(m) * owny[12 + m];
   }
   const double ub = mom(G, 0, 0, i, j);
   const double dpx = mom(G, 0, 0, i + 1, j) - ub, dmx = ub - mom(G, 0, 0, i - 1, j);
@@ -1145,6 +1251,10 @@ static int tvb_2d(const grid_t* G, const double* own /* 16 values, comp 0 */, in
 
 /* given: optional troubled-cell map of cells [-2, n+2)^2 supplied by the
    caller ((nx+4) x (ny+4), x fastest) in place of Step 2.1 */
+static void gather2_all(const grid_t* G, int i, int j, double ub[][9], double vb[][9], double wb[][9]) {
+  for (int c = 0; c < G->nc; ++c) gather2(G, c, i, j, ub[c], vb[c], wb[c]);
+}
+
 static void op2d_values(const orc_problem* P, const double* U, work2_t* W, const unsigned char* given) {
   init_1d();
   init_2d();
@@ -1153,12 +1263,11 @@ static void op2d_values(const orc_problem* P, const double* U, work2_t* W, const
   /* g0 for cells [-3, n+3), flags [-2, n+2), final values [-1, n+1) */
 #pragma omp parallel for schedule(dynamic, 1)
   for (int j = -3; j < P->ny + 3; ++j)
-    for (int i = -3; i < P->nx + 3; ++i)
-      for (int c = 0; c < nc; ++c) {
-        double ub[9], vb[9], wb[9];
-        gather2(&G, c, i, j, ub, vb, wb);
-        orc_step1_2d(P, ub, vb, wb, &W->g0[(w2idx(W, i, j) * nc + c) * 16], NULL, NULL);
-      }
+    for (int i = -3; i < P->nx + 3; ++i) {
+      double ub[4][9], vb[4][9], wb[4][9];
+      gather2_all(&G, i, j, ub, vb, wb);
+      for (int set = 0; set < W->nset; ++set) step1_2d_all(P, ub, vb, wb, set, w2val(W->g0, W, i, j, set));
+    }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int j = -2; j < P->ny + 2; ++j)
     for (int i = -2; i < P->nx + 2; ++i) {
@@ -1166,34 +1275,39 @@ static void op2d_values(const orc_problem* P, const double* U, work2_t* W, const
       if (given) { W->fl[k] = given[(size_t)(j + 2) * (P->nx + 4) + (i + 2)] != 0; continue; }
       if (P->tc_mode == 0) { W->fl[k] = 0; continue; }
       if (P->tc_mode == 2) { W->fl[k] = 1; continue; }
-      if (P->tc_mode == 4) { W->fl[k] = (unsigned char)tvb_2d(&G, &W->g0[k * nc * 16], i, j); continue; }
+      if (P->tc_mode == 4) {
+        W->fl[k] = (unsigned char)tvb_2d(&G, w2val(W->g0, W, i, j, 0), w2val(W->g0, W, i, j, 1), i, j);
+        continue;
+      }
       kxrcf_2d(P, W, i, j, i, j, &W->fl[k], &W->anum[k], &W->aden[k]);
     }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int j = -1; j < P->ny + 1; ++j)
     for (int i = -1; i < P->nx + 1; ++i) {
       size_t k = w2idx(W, i, j);
-      for (int c = 0; c < nc; ++c) {
-        double* out = &W->gf[(k * nc + c) * 16];
-        if (!W->fl[k]) { memcpy(out, &W->g0[(k * nc + c) * 16], 16 * sizeof(double)); continue; }
-        /* Step 2.3: Step 1 again on the modified field (reading R3, R4) */
-        double ub[9], vb[9], wb[9];
-        gather2(&G, c, i, j, ub, vb, wb);
-        for (int lab = 1; lab <= 9; ++lab) {
-          int ii = i + lab_dx(lab), jj = j + lab_dy(lab);
-          if (W->fl[w2idx(W, ii, jj)]) modified_vw2(&G, c, ii, jj, &vb[lab - 1], &wb[lab - 1]);
-        }
-        orc_step1_2d(P, ub, vb, wb, out, NULL, NULL);
+      if (!W->fl[k]) {
+        for (int set = 0; set < W->nset; ++set)
+          memcpy(w2val(W->gf, W, i, j, set), w2val(W->g0, W, i, j, set), (size_t)nc * 16 * sizeof(double));
+        continue;
       }
+      /* Step 2.3: Step 1 again on the modified field (readings R3, R4) */
+      double ub[4][9], vb[4][9], wb[4][9];
+      gather2_all(&G, i, j, ub, vb, wb);
+      for (int lab = 1; lab <= 9; ++lab) {
+        int ii = i + lab_dx(lab), jj = j + lab_dy(lab);
+        if (W->fl[w2idx(W, ii, jj)])
+          for (int c = 0; c < nc; ++c) modified_vw2(&G, c, ii, jj, &vb[c][lab - 1], &wb[c][lab - 1]);
+      }
+      for (int set = 0; set < W->nset; ++set) step1_2d_all(P, ub, vb, wb, set, w2val(W->gf, W, i, j, set));
     }
 }
 
 static int work2_alloc(const orc_problem* P, work2_t* W) {
-  W->nx = P->nx; W->ny = P->ny; W->nc = ncomp_of(P);
+  W->nx = P->nx; W->ny = P->ny; W->nc = ncomp_of(P); W->nset = nset_of(P);
   W->ex = P->nx + 2 * R2G; W->ey = P->ny + 2 * R2G;
   size_t ncell = (size_t)W->ex * W->ey;
-  W->g0 = calloc(ncell * W->nc * 16, sizeof(double));
-  W->gf = calloc(ncell * W->nc * 16, sizeof(double));
+  W->g0 = calloc(ncell * W->nset * W->nc * 16, sizeof(double));
+  W->gf = calloc(ncell * W->nset * W->nc * 16, sizeof(double));
   W->fl = calloc(ncell, 1);
   W->anum = calloc(ncell, sizeof(double));
   W->aden = calloc(ncell, sizeof(double));
@@ -1220,11 +1334,13 @@ static void residual_2d(const orc_problem* P, const double* U, double* L, unsign
 #pragma omp parallel for schedule(dynamic, 1)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
-      const double* own = &W.gf[w2idx(&W, i, j) * nc * 16];
-      const double* lef = &W.gf[w2idx(&W, i - 1, j) * nc * 16];
-      const double* rig = &W.gf[w2idx(&W, i + 1, j) * nc * 16];
-      const double* bot = &W.gf[w2idx(&W, i, j - 1) * nc * 16];
-      const double* top = &W.gf[w2idx(&W, i, j + 1) * nc * 16];
+      /* x faces and F from the x set, y faces and G from the y set (R18) */
+      const double* own = w2val(W.gf, &W, i, j, 0);
+      const double* owy = w2val(W.gf, &W, i, j, 1);
+      const double* lef = w2val(W.gf, &W, i - 1, j, 0);
+      const double* rig = w2val(W.gf, &W, i + 1, j, 0);
+      const double* bot = w2val(W.gf, &W, i, j - 1, 1);
+      const double* top = w2val(W.gf, &W, i, j + 1, 1);
       /* face sums: X0 = sum_l w_l fhat, X1 = sum_l w_l eta_l fhat (x faces);
          Y0 = sum_k w_k ghat, Y1 = sum_k w_k xi_k ghat (y faces) */
       double XL0[4] = {0}, XL1[4] = {0}, XR0[4] = {0}, XR1[4] = {0};
@@ -1241,11 +1357,11 @@ static void residual_2d(const orc_problem* P, const double* U, double* L, unsign
         num_flux(P, a, b, 0, alpha, f);
         for (int c = 0; c < nc; ++c) { XR0[c] += wm * f[c]; XR1[c] += wm * xm * f[c]; }
         /* bottom face y_{j-1/2}, xi_m */
-        for (int c = 0; c < nc; ++c) { a[c] = bot[c * 16 + m + 12]; b[c] = own[c * 16 + m]; }
+        for (int c = 0; c < nc; ++c) { a[c] = bot[c * 16 + m + 12]; b[c] = owy[c * 16 + m]; }
         num_flux(P, a, b, 1, alpha, f);
         for (int c = 0; c < nc; ++c) { YB0[c] += wm * f[c]; YB1[c] += wm * xm * f[c]; }
         /* top face y_{j+1/2} */
-        for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + m + 12]; b[c] = top[c * 16 + m]; }
+        for (int c = 0; c < nc; ++c) { a[c] = owy[c * 16 + m + 12]; b[c] = top[c * 16 + m]; }
         num_flux(P, a, b, 1, alpha, f);
         for (int c = 0; c < nc; ++c) { YT0[c] += wm * f[c]; YT1[c] += wm * xm * f[c]; }
       }
@@ -1253,10 +1369,10 @@ static void residual_2d(const orc_problem* P, const double* U, double* L, unsign
       double F[4] = {0}, Gv[4] = {0};
       for (int l = 0; l < 4; ++l)
         for (int k = 0; k < 4; ++k) {
-          double pt[4], f[4], g[4];
-          for (int c = 0; c < nc; ++c) pt[c] = own[c * 16 + k + 4 * l];
+          double pt[4], pty[4], f[4], g[4];
+          for (int c = 0; c < nc; ++c) { pt[c] = own[c * 16 + k + 4 * l]; pty[c] = owy[c * 16 + k + 4 * l]; }
           if (P->system == 0) { f[0] = 0.5 * pt[0] * pt[0]; g[0] = f[0]; }
-          else { euler_flux(pt, nc, 0, P->gamma, f); euler_flux(pt, nc, 1, P->gamma, g); }
+          else { euler_flux(pt, nc, 0, P->gamma, f); euler_flux(pty, nc, 1, P->gamma, g); }
           for (int c = 0; c < nc; ++c) {
             F[c] += gl_weight(k) * gl_weight(l) * f[c];
             Gv[c] += gl_weight(k) * gl_weight(l) * g[c];
@@ -1333,7 +1449,7 @@ int orc_reconstruct(const orc_problem* P, const double* U, double* gl, unsigned 
         size_t k = w2idx(&W, i, j), cell = (size_t)j * P->nx + i;
         for (int c = 0; c < nc; ++c)
           for (int p = 0; p < 16; ++p)
-            if (gl) gl[((size_t)c * 16 + p) * plane + cell] = W.gf[(k * nc + c) * 16 + p];
+            if (gl) gl[((size_t)c * 16 + p) * plane + cell] = w2val(W.gf, &W, i, j, 0)[c * 16 + p];
         if (flags) flags[cell] = W.fl[k];
         if (anum) anum[cell] = W.anum[k];
         if (aden) aden[cell] = W.aden[k];
@@ -1451,12 +1567,10 @@ int orc_rk3_step(const orc_problem* P, double* U, double dt, unsigned char* flag
 /* Per-cell evaluation (for sampled checks on large grids): recomputes the  */
 /* whole dependency cone of one cell with no caching.                       */
 /* ======================================================================== */
-static void g0_cell2(const grid_t* G, int i, int j, double* out /* nc x 16 */) {
-  for (int c = 0; c < G->nc; ++c) {
-    double ub[9], vb[9], wb[9];
-    gather2(G, c, i, j, ub, vb, wb);
-    orc_step1_2d(G->P, ub, vb, wb, &out[c * 16], NULL, NULL);
-  }
+static void g0_cell2(const grid_t* G, int i, int j, int set, double* out /* nc x 16 */) {
+  double ub[4][9], vb[4][9], wb[4][9];
+  gather2_all(G, i, j, ub, vb, wb);
+  step1_2d_all(G->P, ub, vb, wb, set, out);
 }
 
 /* flag of cell (i, j) computed from scratch */
@@ -1465,20 +1579,23 @@ static int flag_cell2(const grid_t* G, int i, int j) {
   if (P->tc_mode == 0) return 0;
   if (P->tc_mode == 2) return 1;
   if (P->tc_mode == 4) {
-    double own[64];
-    g0_cell2(G, i, j, own);
-    return tvb_2d(G, own, i, j);
+    double own[64], owy[64];
+    g0_cell2(G, i, j, 0, own);
+    g0_cell2(G, i, j, 1, owy);
+    return tvb_2d(G, own, owy, i, j);
   }
   /* a 3x3 work2_t window centred on (i, j) */
   work2_t W;
   W.nc = G->nc;
+  W.nset = nset_of(P);
   W.ex = 1 + 2 * R2G;  /* indices -R2G..R2G around the centre */
   W.ey = W.ex;
   size_t ncell = (size_t)W.ex * W.ey;
-  W.g0 = calloc(ncell * W.nc * 16, sizeof(double));
+  W.g0 = calloc(ncell * W.nset * W.nc * 16, sizeof(double));
   const int off[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
   for (int k = 0; k < 5; ++k)
-    g0_cell2(G, i + off[k][0], j + off[k][1], &W.g0[w2idx(&W, off[k][0], off[k][1]) * W.nc * 16]);
+    for (int set = 0; set < W.nset; ++set)
+      g0_cell2(G, i + off[k][0], j + off[k][1], set, w2val(W.g0, &W, off[k][0], off[k][1], set));
   /* the window holds cell (i, j) at its (0, 0) */
   unsigned char f;
   double num, den;
@@ -1487,17 +1604,17 @@ static int flag_cell2(const grid_t* G, int i, int j) {
   return f;
 }
 
-static void final_cell2(const grid_t* G, int i, int j, double* out /* nc x 16 */) {
-  if (!flag_cell2(G, i, j)) { g0_cell2(G, i, j, out); return; }
+static void final_cell2(const grid_t* G, int i, int j, int set, double* out /* nc x 16 */) {
+  if (!flag_cell2(G, i, j)) { g0_cell2(G, i, j, set, out); return; }
   int fl[9];
   for (int lab = 1; lab <= 9; ++lab) fl[lab - 1] = flag_cell2(G, i + lab_dx(lab), j + lab_dy(lab));
-  for (int c = 0; c < G->nc; ++c) {
-    double ub[9], vb[9], wb[9];
-    gather2(G, c, i, j, ub, vb, wb);
-    for (int lab = 1; lab <= 9; ++lab)
-      if (fl[lab - 1]) modified_vw2(G, c, i + lab_dx(lab), j + lab_dy(lab), &vb[lab - 1], &wb[lab - 1]);
-    orc_step1_2d(G->P, ub, vb, wb, &out[c * 16], NULL, NULL);
-  }
+  double ub[4][9], vb[4][9], wb[4][9];
+  gather2_all(G, i, j, ub, vb, wb);
+  for (int lab = 1; lab <= 9; ++lab)
+    if (fl[lab - 1])
+      for (int c = 0; c < G->nc; ++c)
+        modified_vw2(G, c, i + lab_dx(lab), j + lab_dy(lab), &vb[c][lab - 1], &wb[c][lab - 1]);
+  step1_2d_all(G->P, ub, vb, wb, set, out);
 }
 
 /* L(U) at the single cell (i, j) of a 2D grid (alpha: Lax-Friedrichs
@@ -1507,12 +1624,16 @@ int orc_residual_cell_2d(const orc_problem* P, const double* U, double alpha, in
   init_2d();
   grid_t G = {P, U, ncomp_of(P), 3};
   int nc = G.nc;
-  double own[64], lef[64], rig[64], bot[64], top[64];
-  final_cell2(&G, i, j, own);
-  final_cell2(&G, i - 1, j, lef);
-  final_cell2(&G, i + 1, j, rig);
-  final_cell2(&G, i, j - 1, bot);
-  final_cell2(&G, i, j + 1, top);
+  /* x faces and F from the x set, y faces and G from the y set (R18) */
+  const int sy = nset_of(P) > 1 ? 1 : 0;
+  double own[64], owy[64], lef[64], rig[64], bot[64], top[64];
+  final_cell2(&G, i, j, 0, own);
+  if (sy) final_cell2(&G, i, j, 1, owy);
+  else memcpy(owy, own, sizeof own);
+  final_cell2(&G, i - 1, j, 0, lef);
+  final_cell2(&G, i + 1, j, 0, rig);
+  final_cell2(&G, i, j - 1, sy, bot);
+  final_cell2(&G, i, j + 1, sy, top);
   double XL0[4] = {0}, XL1[4] = {0}, XR0[4] = {0}, XR1[4] = {0};
   double YB0[4] = {0}, YB1[4] = {0}, YT0[4] = {0}, YT1[4] = {0};
   for (int m = 0; m < 4; ++m) {
@@ -1524,20 +1645,20 @@ int orc_residual_cell_2d(const orc_problem* P, const double* U, double alpha, in
     for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + 3 + 4 * m]; b[c] = rig[c * 16 + 0 + 4 * m]; }
     num_flux(P, a, b, 0, alpha, f);
     for (int c = 0; c < nc; ++c) { XR0[c] += wm * f[c]; XR1[c] += wm * xm * f[c]; }
-    for (int c = 0; c < nc; ++c) { a[c] = bot[c * 16 + m + 12]; b[c] = own[c * 16 + m]; }
+    for (int c = 0; c < nc; ++c) { a[c] = bot[c * 16 + m + 12]; b[c] = owy[c * 16 + m]; }
     num_flux(P, a, b, 1, alpha, f);
     for (int c = 0; c < nc; ++c) { YB0[c] += wm * f[c]; YB1[c] += wm * xm * f[c]; }
-    for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + m + 12]; b[c] = top[c * 16 + m]; }
+    for (int c = 0; c < nc; ++c) { a[c] = owy[c * 16 + m + 12]; b[c] = top[c * 16 + m]; }
     num_flux(P, a, b, 1, alpha, f);
     for (int c = 0; c < nc; ++c) { YT0[c] += wm * f[c]; YT1[c] += wm * xm * f[c]; }
   }
   double F[4] = {0}, Gv[4] = {0};
   for (int l = 0; l < 4; ++l)
     for (int k = 0; k < 4; ++k) {
-      double pt[4], f[4], g[4];
-      for (int c = 0; c < nc; ++c) pt[c] = own[c * 16 + k + 4 * l];
+      double pt[4], pty[4], f[4], g[4];
+      for (int c = 0; c < nc; ++c) { pt[c] = own[c * 16 + k + 4 * l]; pty[c] = owy[c * 16 + k + 4 * l]; }
       if (P->system == 0) { f[0] = 0.5 * pt[0] * pt[0]; g[0] = f[0]; }
-      else { euler_flux(pt, nc, 0, P->gamma, f); euler_flux(pt, nc, 1, P->gamma, g); }
+      else { euler_flux(pt, nc, 0, P->gamma, f); euler_flux(pty, nc, 1, P->gamma, g); }
       for (int c = 0; c < nc; ++c) {
         F[c] += gl_weight(k) * gl_weight(l) * f[c];
         Gv[c] += gl_weight(k) * gl_weight(l) * g[c];
