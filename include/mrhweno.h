@@ -155,11 +155,17 @@ typedef struct {
   int beta_on;             /* mrhweno_beta                                       */
   int modification;        /* mrhweno_mod                                        */
   double tvb_m;            /* M of the TVB indicator (>= 0; other modes ignore it) */
-  int charwise;            /* 1D Euler only: 1 = Step 1 on the characteristic
+  int charwise;            /* Euler only: 1 = Step 1 on the characteristic
                               fields of the flux Jacobian at the target cell's
                               average (left eigenvectors project the stencil
-                              moments, right ones map the values back); 0 =
-                              component by component, as the paper does     */
+                              moments, right ones map the values back); in 2D
+                              one set of values per direction (the x set for
+                              the x faces and the volume integral of f, the
+                              y set for the y faces and that of g; KXRCF
+                              takes each face's set and the norm over both;
+                              with the KXRCF, all-cells or no troubled-cell
+                              mode); 0 = component by component, as the paper
+                              does                                           */
   mrhweno_side side[4];    /* per-side data of an axis whose bc is SIDES       */
 } mrhweno_problem;
 
@@ -203,7 +209,8 @@ mrhweno_status mrhweno_last_dt(mrhweno_ctx* ctx, double* dt_out);
  *   gl_dev       device, final Gauss-Lobatto values after Step 2:
  *                1D [comp][4][nx], 2D [comp][16][ny][nx] with point
  *                k + 4 l at (xi_k, eta_l), xi, eta in
- *                {-1/2, -sqrt(5)/10, sqrt(5)/10, 1/2};
+ *                {-1/2, -sqrt(5)/10, sqrt(5)/10, 1/2} (2D
+ *                characteristic-wise: the x direction's set);
  *   flags_dev    device uint8 [ny][nx] troubled-cell map, or NULL. */
 mrhweno_status mrhweno_reconstruct(mrhweno_ctx* ctx, int instance, const void* moments_dev,
                                    void* gl_dev, void* flags_dev);

@@ -22,7 +22,7 @@ hipError_t mr_launch_finalize(hipStream_t, mr_inst*, int, int);
 hipError_t mr_launch_summary(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_flags(hipStream_t, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_stage1(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, int, int);
-hipError_t mr_launch_stage2(hipStream_t, int, int, int, mr_inst*, const mr_tile2*, int, int, int);
+hipError_t mr_launch_stage2(hipStream_t, int, int, int, int, mr_inst*, const mr_tile2*, int, int, int);
 hipError_t mr_launch_kxrcf2(hipStream_t, int, int, int, mr_inst*, const mr_tile2*, int, int);
 hipError_t mr_launch_values(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, double*);
 hipError_t mr_launch_fb_reset(hipStream_t, int*, int);
@@ -146,8 +146,9 @@ std::string validate(const mrhweno_problem& p) {
   if (p.beta_on != 0 && p.beta_on != 1) return "unknown beta_on";
   if (p.modification < 0 || p.modification > 2) return "unknown modification placement";
   if (p.charwise != 0 && p.charwise != 1) return "charwise must be 0 or 1";
-  if (p.charwise && !(p.dim == 1 && p.flux == MRHWENO_EULER_HLLC))
-    return "characteristic-wise reconstruction is implemented for 1D Euler";
+  if (p.charwise && p.flux != MRHWENO_EULER_HLLC) return "characteristic-wise reconstruction is for the Euler equations";
+  if (p.charwise && p.dim == 2 && (p.tc_mode == MRHWENO_TC_LEARNED || p.tc_mode == MRHWENO_TC_TVB))
+    return "2D characteristic-wise reconstruction takes the KXRCF, all-cells or no troubled-cell mode";
   if (p.tc_mode == MRHWENO_TC_LEARNED && (p.dim != 2 || p.flux != MRHWENO_EULER_HLLC))
     return "the learned indicator is for 2D Euler";
   if (p.dim == 2) {
@@ -228,6 +229,7 @@ Layout layout(const mrhweno_problem* P, int n) {
 struct Group {
   int dim, nc, bp;
   int gb;           /* instances with ghosts that hold a prescribed state */
+  int ch;           /* 2D characteristic-wise Step 1 */
   bool any_summ = false, any_lf = false;
   std::vector<int> insts;
   int t_summ = 0, n_summ = 0, t_flag = 0, n_flag = 0, t_st1 = 0, n_st1 = 0;
@@ -460,7 +462,9 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
     for (auto& g : c->groups) {
       if (g.n_kx > 0) {
         any = true;
-        if ((e = mr_launch_kxrcf2(s, g.nc == 4 ? 3 : 1, g.bp, g.gb, c->d, c->t2 + g.t_kx, g.n_kx, st)) != hipSuccess) return e;
+        if ((e = mr_launch_kxrcf2(s, g.nc == 4 ? (g.ch ? 4 : 3) : 1, g.bp, g.gb, c->d, c->t2 + g.t_kx, g.n_kx, st)) !=
+            hipSuccess)
+          return e;
       }
       if (g.n_tvb > 0) {   /* the TVB test reads the indicator variable only */
         any = true;
@@ -481,7 +485,7 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
     if ((e = mark(c, P, 2)) != hipSuccess) return e;
     for (auto& g : c->groups) {
       if (g.dim == 1) e = mr_launch_stage1(s, g.nc, g.bp, g.gb, c->d, c->t1 + g.t_st1, g.n_st1, st, 0);
-      else e = mr_launch_stage2(s, g.nc, g.bp, g.gb, c->d, c->t2 + g.t_st2, g.n_st2, st, c->grid2);
+      else e = mr_launch_stage2(s, g.nc, g.bp, g.gb, g.ch, c->d, c->t2 + g.t_st2, g.n_st2, st, c->grid2);
       if (e != hipSuccess) return e;
     }
     if ((e = mark(c, P, 3)) != hipSuccess) return e;
@@ -586,9 +590,10 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     const auto& p = probs[q];
     const int nc = ncomp_of(p);
     Group* gp = nullptr;
+    const int ch = p.dim == 2 && p.charwise;
     for (auto& g : c->groups)
-      if (g.dim == p.dim && g.nc == nc && g.bp == p.beta_on && g.gb == (c->h[q].pres != 0)) gp = &g;
-    if (!gp) { c->groups.push_back(Group{p.dim, nc, p.beta_on, c->h[q].pres != 0}); gp = &c->groups.back(); }
+      if (g.dim == p.dim && g.nc == nc && g.bp == p.beta_on && g.gb == (c->h[q].pres != 0) && g.ch == ch) gp = &g;
+    if (!gp) { c->groups.push_back(Group{p.dim, nc, p.beta_on, c->h[q].pres != 0, ch}); gp = &c->groups.back(); }
     gp->insts.push_back(q);
     gp->any_summ |= needs_summ(p);
   }
@@ -686,7 +691,8 @@ mrhweno_status mrhweno_autotune(mrhweno_ctx* c, const int* rows_cand, int n_rows
       auto launch = [&]() -> hipError_t {
         for (auto& g : c->groups)
           if (g.dim == 2) {
-            hipError_t e = mr_launch_stage2(c->stream, g.nc, g.bp, g.gb, c->d, c->t2 + g.t_st2, g.n_st2, 3, c->grid2);
+            hipError_t e = mr_launch_stage2(c->stream, g.nc, g.bp, g.gb, g.ch, c->d, c->t2 + g.t_st2, g.n_st2, 3,
+                                            c->grid2);
             if (e != hipSuccess) return e;
           }
         return hipSuccess;
@@ -855,15 +861,16 @@ static hipError_t probe_kernels(hipStream_t s, const mrhweno_problem& p, const m
   if ((e = mr_launch_finalize(s, d + slot, 1, 1)) != hipSuccess) return e;
   if ((e = mr_launch_summary(s, p.dim, p.beta_on, I.pres != 0, d, t1 + L.t_sum, L.n_sum, 3)) != hipSuccess) return e;
   if ((e = mr_launch_flags(s, p.dim, d, t1 + L.t_flg, L.n_flg, 3)) != hipSuccess) return e;
-  if (L.kx2 && (e = mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? 3 : 1, p.beta_on, I.pres != 0, d, t3,
-                                     (int)L.t3.size(), 3)) != hipSuccess)
+  const int ch = p.dim == 2 && p.charwise;
+  if (L.kx2 && (e = mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? (ch ? 4 : 3) : 1, p.beta_on, I.pres != 0, d,
+                                     t3, (int)L.t3.size(), 3)) != hipSuccess)
     return e;
   const int nc = ncomp_of(p);
   if (kind == 0 && (e = mr_launch_values(s, p.dim, nc, p.beta_on, d, t1 + L.t_val, L.n_val, (double*)out)) != hipSuccess)
     return e;
   if (kind == 2) {
     if (p.dim == 1) e = mr_launch_stage1(s, nc, p.beta_on, I.pres != 0, d, t1 + L.t_st, L.n_st, 3, 0);
-    else e = mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, d, t2, (int)L.t2.size(), 3, 0);
+    else e = mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, ch, d, t2, (int)L.t2.size(), 3, 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -923,7 +930,7 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
     MR_CHECK(c, mr_launch_fallback(s, c->d, c->band, c->cnt, 3, c->grid_fb, p.beta_on));
     const int nc = ncomp_of(p);
     if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + PL.t_val, PL.n_val, (double*)out));
-    if (kind == 2) MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, c->d, d2, (int)PL.t2.size(), 3, 0));
+    if (kind == 2) MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, 0, c->d, d2, (int)PL.t2.size(), 3, 0));
   } else {
     MR_CHECK(c, probe_kernels(s, p, I, c->d, slot, PL, d1, d2, d3, kind, out));
   }

@@ -206,6 +206,67 @@ MR_INL void mr1_recon_sys(const double* um, const double* u0, const double* up, 
   for (int cc = 0; cc < NC; ++cc) mr_recon1d<BP>(um[cc], u0[cc], up[cc], vm[cc], v0[cc], vp[cc], I.W, out[cc]);
 }
 
+/* Characteristic-wise Step 1 in 2D (2D Euler, I.charwise): every cell
+ * has one set of values per direction D (0: x, 1: y), reconstructed on the
+ * characteristic fields of the flux Jacobian in direction D at the cell's
+ * average.  With the normal velocity vn, the tangential velocity vt,
+ * q^2 = u^2 + v^2, H = (E + p)/rho, b1 = (gamma-1)/c^2, b2 = b1 q^2/2, the
+ * right eigenvectors (columns) are the acoustic waves (1, .., H -+ vn c)
+ * with vn -+ c in the normal momentum slot, the entropy wave
+ * (1, u, v, q^2/2) and the shear wave with a 1 in the tangential momentum
+ * slot and vt in the energy slot; the left ones are their inverse's rows:
+ * ((b2 + vn/c)/2, -(b1 vn + 1/c)/2, -b1 vt/2, b1/2), (1 - b2, b1 vn, b1 vt,
+ * -b1), (-vt, 0, 1, 0), ((b2 - vn/c)/2, -(b1 vn - 1/c)/2, -b1 vt/2, b1/2),
+ * entries listed in the order (rho, normal momentum, tangential momentum,
+ * E).  Everything that belongs to direction D takes set D: the fluxes on
+ * the faces normal to D, the volume integral of the flux in D, and in the
+ * KXRCF test the jumps and the normal velocity on those faces; the KXRCF
+ * norm is the maximum |rho| over both sets. */
+struct mr_char2 {
+  double vn, vt, c, rc, H, b1, b2, q2h;   /* q2h = q^2/2 */
+};
+
+template <int D>
+MR_INL mr_char2 mr_char2_state(const double* u, double gam) {
+  mr_char2 e;
+  const double r = mr_rcp(u[0]);
+  const double vx = u[1] * r, vy = u[2] * r;
+  e.q2h = 0.5 * (vx * vx + vy * vy);
+  const double p = (gam - 1.0) * (u[3] - u[0] * e.q2h);
+  const double c2 = gam * p * r;
+  e.c = mr_sqrtp(c2);
+  e.rc = mr_rcp(e.c);
+  e.H = (u[3] + p) * r;
+  e.b1 = (gam - 1.0) * mr_rcp(c2);
+  e.b2 = e.b1 * e.q2h;
+  e.vn = D == 0 ? vx : vy;
+  e.vt = D == 0 ? vy : vx;
+  return e;
+}
+
+/* row k of L in conserved order (rho, rho u, rho v, E) */
+template <int D>
+MR_INL void mr_char2_left(const mr_char2& e, int k, double l[4]) {
+  constexpr int N = 1 + D, T = 2 - D;
+  double a0, an, at, ae;
+  if (k == 0) { a0 = 0.5 * (e.b2 + e.vn * e.rc); an = -0.5 * (e.b1 * e.vn + e.rc); at = -0.5 * e.b1 * e.vt; ae = 0.5 * e.b1; }
+  else if (k == 1) { a0 = 1.0 - e.b2; an = e.b1 * e.vn; at = e.b1 * e.vt; ae = -e.b1; }
+  else if (k == 2) { a0 = -e.vt; an = 0.0; at = 1.0; ae = 0.0; }
+  else { a0 = 0.5 * (e.b2 - e.vn * e.rc); an = -0.5 * (e.b1 * e.vn - e.rc); at = -0.5 * e.b1 * e.vt; ae = 0.5 * e.b1; }
+  l[0] = a0; l[N] = an; l[T] = at; l[3] = ae;
+}
+
+/* conserved values from the four field values w (R w) */
+template <int D>
+MR_INL void mr_char2_right(const mr_char2& e, const double w[4], double out[4]) {
+  constexpr int N = 1 + D, T = 2 - D;
+  const double s = w[0] + w[1] + w[3];
+  out[0] = s;
+  out[N] = e.vn * s + e.c * (w[3] - w[0]);
+  out[T] = e.vt * s + w[2];
+  out[3] = e.H * (w[0] + w[3]) + e.vn * e.c * (w[3] - w[0]) + e.q2h * w[1] + e.vt * w[2];
+}
+
 /* flag of cell (i, j) from an extended plane with halo h (clamped) */
 template <class P>
 MR_INL int mr_flag(P fl, int ex, int ey, int h, int i, int j) {
@@ -260,6 +321,51 @@ MR_INL void mr2_cell_values(const mr_grid& g, const mr_inst& I, const MR_GLB uns
   *ve = v[4];
   *we = w[4];
   mr_recon2d<BP>(u, v, w, I.W, out);
+}
+
+/* Final Gauss-Lobatto values of all four components of cell (x, y), set D
+ * of the characteristic-wise Step 1 (see mr_char2): each field is
+ * projected from the stencil (with the troubled cells' first moments
+ * modified if the cell is troubled), reconstructed, and mapped back. */
+template <bool BP, int D>
+MR_INL void mr2_cell_values_ch(const mr_grid& g, const mr_inst& I, const MR_GLB unsigned char* fl, int x, int y,
+                               double out[4][16]) {
+  int fs[9];
+#pragma unroll
+  for (int l = 0; l < 9; ++l) fs[l] = mr_flag(fl, I.fex, I.fey, I.fhalo, x + l % 3 - 1, y + l / 3 - 1);
+  double u0[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) u0[c] = mr_ld(g, c, 0, x, y);
+  const mr_char2 e = mr_char2_state<D>(u0, I.gam);
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) out[c][q] = 0.0;
+  double w[4][16];
+#pragma unroll 1
+  for (int k = 0; k < 4; ++k) {
+    double lk[4];
+    mr_char2_left<D>(e, k, lk);
+    double fu[9], fv[9], fw[9];
+    for (int l = 0; l < 9; ++l) { fu[l] = 0.0; fv[l] = 0.0; fw[l] = 0.0; }
+    for (int c = 0; c < 4; ++c) {
+      double u[9], v[9], ww[9];
+      for (int l = 0; l < 9; ++l) {
+        u[l] = mr_ld(g, c, 0, x + l % 3 - 1, y + l / 3 - 1);
+        v[l] = mr_ld(g, c, 1, x + l % 3 - 1, y + l / 3 - 1);
+        ww[l] = mr_ld(g, c, 2, x + l % 3 - 1, y + l / 3 - 1);
+      }
+      if (fs[4]) mr2_modify_stencil(g, c, x, y, fs, v, ww);
+      for (int l = 0; l < 9; ++l) { fu[l] += lk[c] * u[l]; fv[l] += lk[c] * v[l]; fw[l] += lk[c] * ww[l]; }
+    }
+    mr_recon2d<BP>(fu, fv, fw, I.W, w[k]);
+  }
+  for (int q = 0; q < 16; ++q) {
+    const double wq[4] = {w[0][q], w[1][q], w[2][q], w[3][q]};
+    double o[4];
+    mr_char2_right<D>(e, wq, o);
+    for (int c = 0; c < 4; ++c) out[c][q] = o[c];
+  }
 }
 
 /* KXRCF face data of cell (i, j) from its Step-1 values, eqs. (KXRCF_),

@@ -451,6 +451,14 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_values(mr_inst* insts, con
     if (e >= tl.start + tl.count) continue;
     const int x = e % I.nx, y = e / I.nx;
     const mr_grid g{mr_gp(I.p_in[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, &I, mr_stage_time(I, 3)};
+    if (NC == 4 && I.charwise) {
+      /* characteristic-wise: the set of the x direction */
+      double val[4][16];
+      mr2_cell_values_ch<BP, 0>(g, I, mr_gp(I.flags[0]), x, y, val);
+      for (int c = 0; c < 4; ++c)
+        for (int p = 0; p < 16; ++p) gl[(long long)(c * 16 + p) * I.plane + e] = val[c][p];
+      continue;
+    }
     for (int c = 0; c < NC; ++c) {
       double val[16], a, b, d;
       mr2_cell_values<BP>(g, I, mr_gp(I.flags[0]), c, x, y, val, &a, &b, &d);

@@ -87,9 +87,77 @@ MR_INL void kx_face_data(const double (*mom)[3 * NK * KX_XW], int s0, int s1, in
   f[8] = nrm;
 }
 
+/* face data of one direction D of the characteristic-wise Step 1 (2D
+   Euler, four components staged; see mr_char2): each field projected from
+   the stencil, reconstructed, and mapped back at the points the indicator
+   reads -- the density at all sixteen points (its norm), the density and
+   the normal momentum at the points of the two faces normal to D.
+   f[0..1] / f[4..5] (D = 0: left, right) or f[2..3] / f[6..7] (D = 1:
+   bottom, top) as kx_face_data; *nrm is raised to max |rho|. */
+template <bool BP, int D>
+MR_INL void kx_face_data_ch(const double (*mom)[3 * 4 * KX_XW], int s0, int s1, int s2, int col,
+                            const mr_wconst& W, double gam, double f[9], double* nrm) {
+  double u0[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) u0[c] = mom[s1][(3 * c + 0) * KX_XW + col];
+  const mr_char2 e = mr_char2_state<D>(u0, gam);
+  double rho[16], mn[8];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) rho[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) mn[q] = 0.0;
+#pragma unroll 1
+  for (int k = 0; k < 4; ++k) {
+    __asm__ volatile("" ::: "memory");   /* keep the constant table in LDS (see kx_face_data) */
+    double lk[4];
+    mr_char2_left<D>(e, k, lk);
+    double u[9], v[9], w[9], q[16];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) {
+      const int dx = l % 3 - 1, slot = l < 3 ? s0 : (l < 6 ? s1 : s2);
+      u[l] = v[l] = w[l] = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        u[l] += lk[c] * mom[slot][(3 * c + 0) * KX_XW + col + dx];
+        v[l] += lk[c] * mom[slot][(3 * c + 1) * KX_XW + col + dx];
+        w[l] += lk[c] * mom[slot][(3 * c + 2) * KX_XW + col + dx];
+      }
+    }
+    mr_recon2d<BP>(u, v, w, W, q);
+    /* column k of R: density entry 1, 1, 0, 1; normal momentum vn - c, vn, 0, vn + c */
+    const double rr = k == 2 ? 0.0 : 1.0;
+    const double rn = k == 0 ? e.vn - e.c : (k == 1 ? e.vn : (k == 2 ? 0.0 : e.vn + e.c));
+#pragma unroll
+    for (int p = 0; p < 16; ++p) rho[p] += rr * q[p];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int pa = D == 0 ? 4 * m : m, pb = D == 0 ? 3 + 4 * m : 12 + m;
+      mn[m] += rn * q[pa];
+      mn[4 + m] += rn * q[pb];
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 16; ++p) *nrm = fmax(*nrm, fabs(rho[p]));
+  double sa = 0.0, sb = 0.0, va = 0.0, vb = 0.0;
+  double ia[4], ib[4];
+  if (D == 0) { mr_recip4(rho[0], rho[4], rho[8], rho[12], ia); mr_recip4(rho[3], rho[7], rho[11], rho[15], ib); }
+  else { mr_recip4(rho[0], rho[1], rho[2], rho[3], ia); mr_recip4(rho[12], rho[13], rho[14], rho[15], ib); }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int pa = D == 0 ? 4 * m : m, pb = D == 0 ? 3 + 4 * m : 12 + m;
+    sa += glw(m) * rho[pa];
+    sb += glw(m) * rho[pb];
+    va += glw(m) * (mn[m] * ia[m]);
+    vb += glw(m) * (mn[4 + m] * ib[m]);
+  }
+  f[2 * D] = sa; f[2 * D + 1] = sb;
+  f[4 + 2 * D] = va; f[5 + 2 * D] = vb;
+}
+
 /* NK: components the indicator reads (1 Burgers, 3 Euler: rho and the
-   momenta; 1 for the TVB minmod test, which reads the indicator variable
-   only and decides each cell from its own face averages).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
+   momenta; 4 Euler with the characteristic-wise Step 1, whose fields mix
+   all components; 1 for the TVB minmod test, which reads the indicator
+   variable only and decides each cell from its own face averages).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
    of the extended flag range [-2, n+2)^2 (y0 >= -2). */
 template <int NK, bool BP, bool GB>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, const mr_tile2* tiles, int ntiles, int stage) {
@@ -174,8 +242,17 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
       const int r = r0 + ry;
       if (r <= ylast) {
         double f[9];
-        kx_face_data<NK, BP>(mom, kx_slot(r - 1, KX_MR), kx_slot(r, KX_MR), kx_slot(r + 1, KX_MR), cx + 1, I.W,
-                             I.tc == 4 ? I.tvb_mh2 : -1.0, f);
+        if constexpr (NK == 4) {
+          /* characteristic-wise Step 1: x faces from the x set, y faces from the y set */
+          f[8] = 0.0;
+          kx_face_data_ch<BP, 0>(mom, kx_slot(r - 1, KX_MR), kx_slot(r, KX_MR), kx_slot(r + 1, KX_MR), cx + 1, I.W,
+                                 I.gam, f, &f[8]);
+          kx_face_data_ch<BP, 1>(mom, kx_slot(r - 1, KX_MR), kx_slot(r, KX_MR), kx_slot(r + 1, KX_MR), cx + 1, I.W,
+                                 I.gam, f, &f[8]);
+        } else {
+          kx_face_data<NK, BP>(mom, kx_slot(r - 1, KX_MR), kx_slot(r, KX_MR), kx_slot(r + 1, KX_MR), cx + 1, I.W,
+                               I.tc == 4 ? I.tvb_mh2 : -1.0, f);
+        }
         const int sf = kx_slot(r, KX_FR);
 #pragma unroll
         for (int k = 0; k < 9; ++k) fd[sf][k][cx] = f[k];
@@ -236,6 +313,7 @@ extern "C" hipError_t mr_launch_kxrcf2(hipStream_t s, int nk, int bp, int gb, mr
   } while (0)
   if (nk == 1) { if (bp) MR_LK(1, true); else MR_LK(1, false); }
   else if (nk == 3) { if (bp) MR_LK(3, true); else MR_LK(3, false); }
+  else if (nk == 4) { if (bp) MR_LK(4, true); else MR_LK(4, false); }   /* characteristic-wise */
   else return hipErrorInvalidValue;
 #undef MR_LK
   return hipGetLastError();

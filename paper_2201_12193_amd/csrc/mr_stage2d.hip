@@ -24,7 +24,15 @@
  * Gauss-Lobatto grid for the volume integrals, the left-face flux at eta_r
  * and the bottom-face flux at xi_r.  The top-face flux of a row is the
  * bottom-face flux of the next one, so the residual of row j is completed
- * while row j+1 is processed.  mode 0..2 = RK stage, 3 = write L(U). */
+ * while row j+1 is processed.  mode 0..2 = RK stage, 3 = write L(U).
+ *
+ * CH (characteristic-wise Step 1, NC = 4): lane k reconstructs field k of
+ * the x set into the value slots, maps row eta_k of the cell back to the
+ * conserved variables (R), takes the x-flux volume integral of that row
+ * and the left-face flux; then the same with the y set for the y-flux
+ * volume integral and the bottom-face flux, whose top traces the ring
+ * keeps.  The moment rows of the next step are stored once both sets have
+ * read the stencil. */
 template <int NC>
 struct mr2_lds {
   static constexpr int CW = MR_BLOCK / NC;   /* strip cells incl. ring */
@@ -58,7 +66,52 @@ MR_INL double mr2_stage_ld(const mr_grid& g, int e, int xs0, int y) {
   return mr_ld(g, pl - 2 * NC, 1, xs0 + col, y);
 }
 
-template <int NC, bool BP, bool GB>
+/* Characteristic-wise Step 1 (see mr_char2): field k of direction D of the
+   cell at staged column c0, projected from the stencil in the LDS rings
+   (the troubled cells' first moments modified when the cell is troubled)
+   and reconstructed. */
+template <bool BP, int D>
+MR_INL void mr2_stage_field(const mr2_lds<4>& sh, const int* ra, const int* rb, const int* fs, int c0, int k,
+                            const mr_char2& e, const mr_wconst& W, double val[16]) {
+  double lk[4];
+  mr_char2_left<D>(e, k, lk);
+  double u[9], v[9], w[9];
+#pragma unroll
+  for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int l = dx + 3 * dy, cc = c0 + dx - 1;
+      double a = 0.0, b = 0.0, d = 0.0;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        a += lk[c] * sh.mA[ra[dy + 1]][2 * c][cc];
+        b += lk[c] * sh.mB[rb[dy]][c][cc];
+        d += lk[c] * sh.mA[ra[dy + 1]][2 * c + 1][cc];
+      }
+      u[l] = a; v[l] = b; w[l] = d;
+    }
+  if (fs[4]) {
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int l = dx + 3 * dy, cc = c0 + dx - 1;
+        if (!fs[l]) continue;
+        double b = 0.0, d = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          b += lk[c] * mr_modified_moment(sh.mA[ra[dy + 1]][2 * c][cc - 1], sh.mA[ra[dy + 1]][2 * c][cc + 1],
+                                          sh.mB[rb[dy]][c][cc - 1], sh.mB[rb[dy]][c][cc + 1]);
+          d += lk[c] * mr_modified_moment(sh.mA[ra[dy]][2 * c][cc], sh.mA[ra[dy + 2]][2 * c][cc],
+                                          sh.mA[ra[dy]][2 * c + 1][cc], sh.mA[ra[dy + 2]][2 * c + 1][cc]);
+        }
+        v[l] = b; w[l] = d;
+      }
+  }
+  mr_recon2d<BP>(u, v, w, W, val);
+}
+
+template <int NC, bool BP, bool GB, bool CH>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, const mr_tile2* tiles, int ntiles, int mode) {
   mr_kt_fill();
   using S = mr2_lds<NC>;
@@ -161,7 +214,33 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
       if (tid < XW) pref = (unsigned char)mr_flag(fl, I.fex, I.fey, I.fhalo, xs0 + tid, y + 2);
       /* ---- Steps 1, 2.2, 2.3 for component `comp` of cell (x, y) ---- */
       double cu, cv, cw;
-      {
+      /* characteristic-wise: the stencil rows, flags and the cell's state */
+      int cra[5], crb[3], cfs[9];
+      mr_char2 ex{}, ey{};
+      if constexpr (CH) {
+        const int c0 = cs + 2;
+        for (int q = 0; q < 5; ++q) cra[q] = mr_mod5(y - 2 + q);
+        for (int q = 0; q < 3; ++q) crb[q] = mr_mod3(y - 1 + q);
+#pragma unroll
+        for (int l = 0; l < 9; ++l) cfs[l] = sh.flg[crb[l / 3]][c0 + l % 3 - 1];
+        double u0[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) u0[c] = sh.mA[cra[2]][2 * c][c0];
+        ex = mr_char2_state<0>(u0, gam);
+        ey = mr_char2_state<1>(u0, gam);
+        cu = u0[comp];
+        const bool md = cfs[4] && I.mod != 1;
+        cv = md ? mr_modified_moment(sh.mA[cra[2]][2 * comp][c0 - 1], sh.mA[cra[2]][2 * comp][c0 + 1],
+                                     sh.mB[crb[1]][comp][c0 - 1], sh.mB[crb[1]][comp][c0 + 1])
+                : sh.mB[crb[1]][comp][c0];
+        cw = md ? mr_modified_moment(sh.mA[cra[1]][2 * comp][c0], sh.mA[cra[3]][2 * comp][c0],
+                                     sh.mA[cra[1]][2 * comp + 1][c0], sh.mA[cra[3]][2 * comp + 1][c0])
+                : sh.mA[cra[2]][2 * comp + 1][c0];
+        double val[16];
+        mr2_stage_field<BP, 0>(sh, cra, crb, cfs, c0, comp, ex, I.W, val);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) VAL(q, comp, cs) = val[q];
+      } else {
         const int ra[5] = {mr_mod5(y - 2), mr_mod5(y - 1), mr_mod5(y), mr_mod5(y + 1), mr_mod5(y + 2)};
         const int rb[3] = {mr_mod3(y - 1), mr_mod3(y), mr_mod3(y + 1)};
         const int c0 = cs + 2;                    /* staged column of cell x */
@@ -206,7 +285,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
       __syncthreads();
       /* the slots of A row y-2 and of B/flag row y-1 are consumed: store
          A row y+3 and B/flag row y+2 */
-      {
+      auto store_rows = [&]() {
         const int sa = mr_mod5(y + 3), sb = mr_mod3(y + 2);
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
@@ -236,12 +315,93 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
             }
           }
         }
-      }
+      };
       /* ---- volume integrals and the fluxes this lane owns ---- */
       double F[NC], G[NC], XL0[NC], XL1[NC], YB0[NC], YB1[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) F[c] = G[c] = XL0[c] = XL1[c] = YB0[c] = YB1[c] = 0.0;
       const bool body = jr >= 0 && jr < tl.rows;
+      if constexpr (CH) {
+        /* lane k = row eta_k of the cell: x set back to conserved variables */
+        const int r = k;
+        const double wr = glw(r), er = gln(r);
+        double pts[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double wq[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) wq[j] = VAL(q + 4 * r, j, cs);
+          mr_char2_right<0>(ex, wq, pts[q]);
+        }
+        /* row eta_k of the cell is read and written by lane k only */
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) VAL(q + 4 * r, c, cs) = pts[q][c];
+        if (body) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double f[4];
+            mr_euler_flux<4, 0>(pts[q], gam, f);
+            const double wq = glw(q) * wr;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) F[c] += wq * f[c];
+          }
+        }
+        __syncthreads();
+        if (body && cs >= 1) {
+          double a[4], fh[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) a[c] = VAL(3 + 4 * r, c, cs - 1);
+          mr_numflux<4, 0>(a, pts[0], gam, alpha, fh);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) { XL0[c] += wr * fh[c]; XL1[c] += wr * er * fh[c]; }
+        }
+        __syncthreads();
+        /* field k of the y set (the stencil rows are still in place) */
+        {
+          double val[16];
+          mr2_stage_field<BP, 1>(sh, cra, crb, cfs, cs + 2, comp, ey, I.W, val);
+#pragma unroll
+          for (int q = 0; q < 16; ++q) VAL(q, comp, cs) = val[q];
+        }
+        __syncthreads();
+        store_rows();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double wq[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) wq[j] = VAL(q + 4 * r, j, cs);
+          mr_char2_right<1>(ey, wq, pts[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) VAL(q + 4 * r, c, cs) = pts[q][c];
+        if (body) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            double g4[4];
+            mr_euler_flux<4, 1>(pts[q], gam, g4);
+            const double wq = glw(q) * wr;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) G[c] += wq * g4[c];
+          }
+        }
+        __syncthreads();
+        if (jr >= 0) {
+          double a[4], b[4], gh[4];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            a[c] = TOP(r, c, cs);
+            b[c] = VAL(r, c, cs);
+          }
+          mr_numflux<4, 1>(a, b, gam, alpha, gh);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) { YB0[c] += wr * gh[c]; YB1[c] += wr * er * gh[c]; }
+        }
+      } else {
+      store_rows();
 #pragma unroll
       for (int rr = 0; rr < 4 / NC; ++rr) {
         const int r = (NC == 1) ? rr : k;
@@ -285,6 +445,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
 #pragma unroll
           for (int c = 0; c < NC; ++c) { YB0[c] += wr * gh[c]; YB1[c] += wr * er * gh[c]; }
         }
+      }
       }
       /* lane k collects component k's sums */
       const double fF = mr_rs<NC>(F, k), fG = mr_rs<NC>(G, k);
@@ -345,18 +506,20 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
 }
 
 /* gb: some instance of the list has ghosts that hold a prescribed state
-   (the variant without that code runs everything else) */
-extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, int gb, mr_inst* d, const mr_tile2* t, int nt,
-                                       int mode, int grid) {
+   (the variant without that code runs everything else); ch: the
+   characteristic-wise Step 1 (nc = 4) */
+extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, int gb, int ch, mr_inst* d, const mr_tile2* t,
+                                       int nt, int mode, int grid) {
   if (nt <= 0) return hipSuccess;
   const dim3 G(grid > 0 && grid < nt ? grid : nt), B(MR_BLOCK);
-#define MR_L2(NC_, BP_)                                                                  \
-  do {                                                                                   \
-    if (gb) hipLaunchKernelGGL((k2_stage<NC_, BP_, true>), G, B, 0, s, d, t, nt, mode);  \
-    else hipLaunchKernelGGL((k2_stage<NC_, BP_, false>), G, B, 0, s, d, t, nt, mode);    \
+#define MR_L2(NC_, BP_, CH_)                                                                  \
+  do {                                                                                        \
+    if (gb) hipLaunchKernelGGL((k2_stage<NC_, BP_, true, CH_>), G, B, 0, s, d, t, nt, mode);  \
+    else hipLaunchKernelGGL((k2_stage<NC_, BP_, false, CH_>), G, B, 0, s, d, t, nt, mode);    \
   } while (0)
-  if (nc == 1) { if (bp) MR_L2(1, true); else MR_L2(1, false); }
-  else if (nc == 4) { if (bp) MR_L2(4, true); else MR_L2(4, false); }
+  if (nc == 1) { if (bp) MR_L2(1, true, false); else MR_L2(1, false, false); }
+  else if (nc == 4 && !ch) { if (bp) MR_L2(4, true, false); else MR_L2(4, false, false); }
+  else if (nc == 4) { if (bp) MR_L2(4, true, true); else MR_L2(4, false, true); }
   else return hipErrorInvalidValue;
 #undef MR_L2
   return hipGetLastError();

@@ -38,7 +38,8 @@ def test_workspace_bytes_validates_problems():
            good.replace(cfl=0.0), good.replace(gbar=(1, -1, 1, 1)), good.replace(eps=0.0),
            good.replace(tc_mode=7), I.Problem(dim=1, nx=64, gamma=1.0),
            good.replace(modification=3), good.replace(tvb_m=-1.0), good.replace(tvb_m=float("nan")),
-           good.replace(charwise=1),                                  # characteristic-wise: 1D Euler only
+           good.replace(charwise=1, tc_mode=I.TC_TVB),                 # 2D characteristic-wise: KXRCF/all/none
+           good.replace(charwise=1, tc_mode=I.TC_LEARNED),
            I.Problem(dim=1, nx=64, system=I.BURGERS, charwise=1), I.Problem(dim=1, nx=64, charwise=2),
            I.Problem(dim=1, nx=64, system=I.BURGERS, bc_x=I.REFLECTIVE), good.replace(bc_y=4),
            good.replace(bc_y=I.SIDES),                                  # side kinds left unset
@@ -50,6 +51,7 @@ def test_workspace_bytes_validates_problems():
            I.Problem(dim=1, nx=64, system=I.BURGERS, bc_x=I.SIDES,
                      sides=(I.Side(kind=I.REFLECTIVE), I.Side(), None, None))]
     assert M.workspace_bytes([dmr]) > 0
+    assert M.workspace_bytes([good.replace(charwise=1)]) > 0                  # 2D Euler, KXRCF
     for b in bad:
         assert M.workspace_bytes([b]) == 0, b
     assert M.workspace_bytes([good, bad[0]]) == 0

@@ -217,6 +217,51 @@ def test_charwise_1d_parity(tc):
     s.close()
 
 
+CHAR2D = [("quadrants_70_periodic", I.PERIODIC), ("quadrants_70_walls", I.REFLECTIVE),
+          ("quadrants_70_transmissive", I.TRANSMISSIVE)]
+
+
+@pytest.mark.parametrize("name,bc", CHAR2D, ids=[c[0] for c in CHAR2D])
+@pytest.mark.parametrize("tc", [I.TC_KXRCF, I.TC_ALL, I.TC_NONE])
+def test_charwise_2d_parity(name, bc, tc):
+    """Characteristic-wise Step 1 in 2D (one set of values per direction):
+    the x set's values, the flags, the residual and steps against the
+    oracle."""
+    import torch
+    prob, U, _ = I.euler_quadrants_2d(seed=7, n=70, nq=2)
+    prob = prob.replace(charwise=1, tc_mode=tc, bc_x=bc, bc_y=bc)
+    U = _advance_oracle(prob, U, 3)
+    s, Ut = _solver(prob, U)
+    Uin = torch.from_numpy(U).to(_dev())
+    R, fl = s.residual(0, Uin)
+    gl, fl2 = s.reconstruct(0, Uin)
+    R, fl, gl, fl2 = R.cpu().numpy(), fl.cpu().numpy(), gl.cpu().numpy(), fl2.cpu().numpy()
+    Lref, flref = oracle.residual(prob, U)
+    glref, _, num, den = oracle.reconstruct(prob, U)
+    sc = comp_scale(prob, U)
+    dt = oracle.dt(prob, U)
+    tag = f"charwise2d/{name}/tc{tc}"
+    n, out = kxrcf_flags(tag, prob, fl, flref, num, den, sc[0])
+    assert out == 0 and n <= MISMATCHES_ALLOWED.get(tag, 0), (n, out)
+    assert np.array_equal(fl, fl2)
+    if tc == I.TC_KXRCF:
+        assert flref.sum() > 0
+    dgl = np.abs(gl - glref).reshape(prob.ncomp, -1).max(axis=1) / sc
+    assert dgl.max() <= TOL, dgl
+    dR = np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)
+    assert dR.max() <= TOL, dR
+    prev = U.copy()
+    for k in range(3):
+        s.step(1)
+        d = s.last_dt()[0]
+        s.sync()
+        got = Ut.cpu().numpy()
+        e = rel_state_err(prob, got, oracle.rk3_step(prob, prev, d), sc)
+        assert e <= TOL, (k, e)
+        prev = got
+    s.close()
+
+
 def _reflective_cases():
     out = []
     n = 400
