@@ -76,7 +76,8 @@ def parse():
                     help="skip the batched configuration's throughput (extra key of the default run)")
     ap.add_argument("--batched-steps", type=int, default=100)
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration for profiles)")
+                    help="also run a 1 GiB fill, copy, read-only sum and an element-wise FP64 product of "
+                         "2^27 elements (counter calibration for profiles)")
     return ap.parse_args()
 
 
@@ -442,7 +443,9 @@ def main():
         torch.cuda.synchronize()
         a.sum()                      # read-only pass over 1 GiB
         torch.cuda.synchronize()
-        del a, b
+        c = a * b                    # 2^27 FP64 multiplies: one FLOP each (FP64 counter calibration)
+        torch.cuda.synchronize()
+        del a, b, c
     if not args.no_batched:
         bv, bwall, binfo = batched_measure(args.seed, args.batched_steps, args.warmup)
         out["batched"] = dict({"value": bv, "unit": "cell-updates/s", "steps": args.batched_steps,
