@@ -138,7 +138,7 @@ def embed_1d(prob1, U1, ny: int = 8, rotate: bool = False):
 
 
 def collect_1d(runs: Sequence[Tuple[int, int, int]], neg_ratio: float = 1.0, seed: int = 0, log=print,
-               soft_k: Optional[float] = None):
+               soft_k: Optional[float] = None, modification: int = I.MOD_PERSIST):
     """Features and labels from 1D Euler Riemann runs (seed, steps, every)
     at N = 4096, embedded in 2D both ways (embed_1d)."""
     import torch
@@ -147,7 +147,7 @@ def collect_1d(runs: Sequence[Tuple[int, int, int]], neg_ratio: float = 1.0, see
     stats = {"runs_1d": [], "cells_labelled": 0, "positives": 0}
     for (s, steps, every) in runs:
         prob1, U0, _ = I.euler_riemann_1d(seed=s, n=4096)
-        prob1 = prob1.replace(t_final=float("inf"))
+        prob1 = prob1.replace(t_final=float("inf"), modification=modification)
         U = torch.from_numpy(U0).cuda()
         solver = Solver([prob1], [U])
         done, pos_run, stopped = 0, 0, None
@@ -178,14 +178,14 @@ def collect_1d(runs: Sequence[Tuple[int, int, int]], neg_ratio: float = 1.0, see
 
 
 def collect_batch(seed: int, steps: int, every: int, neg_ratio: float = 1.0, log=print,
-                  soft_k: Optional[float] = None):
+                  soft_k: Optional[float] = None, modification: int = I.MOD_PERSIST):
     """Features and labels from a batch of uneven 1D and 2D instances
     (inputs.batched_instances with 48 1D and 16 2D instances) advanced in
     one context; 1D instances embedded as in collect_1d."""
     import torch
     rng = np.random.default_rng(seed)
     pairs = I.batched_instances(seed, n1d=48, n2d=16)
-    probs = [p.replace(t_final=float("inf")) for p, _ in pairs]
+    probs = [p.replace(t_final=float("inf"), modification=modification) for p, _ in pairs]
     Us = [torch.from_numpy(U).cuda() for _, U in pairs]
     solver = Solver(probs, Us)
     Xs, ys = [], []
@@ -225,10 +225,12 @@ def collect_batch(seed: int, steps: int, every: int, neg_ratio: float = 1.0, log
 
 def collect(runs: Sequence[Tuple[int, int, int, int]], neg_ratio: float = 1.0, seed: int = 0,
             log=print, soft_k: Optional[float] = None, runs_1d: Sequence[Tuple[int, int, int]] = (),
-            batch: Optional[Tuple[int, int, int]] = None) -> Tuple["object", "object", Dict]:
+            batch: Optional[Tuple[int, int, int]] = None,
+            modification: int = I.MOD_PERSIST) -> Tuple["object", "object", Dict]:
     """Features and KXRCF labels from the 2D quadrant runs (seed, n, steps,
     every), the 1D runs (seed, steps, every) and the batch (seed, steps,
-    every).  Returns (X bf16 [N][320] CUDA, labels f32 [N][2] CUDA: column 0
+    every), all advanced with the given placement of the modified first
+    moments (by default persisted, as the benchmark runs).  Returns (X bf16 [N][320] CUDA, labels f32 [N][2] CUDA: column 0
     the KXRCF flag, column 1 the training target, summary)."""
     import torch
     rng = np.random.default_rng(seed)
@@ -236,7 +238,7 @@ def collect(runs: Sequence[Tuple[int, int, int, int]], neg_ratio: float = 1.0, s
     stats = {"runs": [], "cells_labelled": 0, "positives": 0, "samples": 0}
     for (s, n, steps, every) in runs:
         prob, U0, _ = I.euler_quadrants_2d(seed=s, n=n, nq=2)
-        prob = prob.replace(t_final=float("inf"))
+        prob = prob.replace(t_final=float("inf"), modification=modification)
         U = torch.from_numpy(U0).cuda()
         solver = Solver([prob], [U])
         pos_run = 0
@@ -260,14 +262,14 @@ def collect(runs: Sequence[Tuple[int, int, int, int]], neg_ratio: float = 1.0, s
                               "stopped_at": stopped})
         log(f"collect: seed {s} n {n} steps {steps}: {pos_run} flagged cells", flush=True)
     if runs_1d:
-        X1, y1, st1 = collect_1d(runs_1d, neg_ratio, seed + 1000, log, soft_k)
+        X1, y1, st1 = collect_1d(runs_1d, neg_ratio, seed + 1000, log, soft_k, modification)
         Xs += X1
         ys += y1
         stats["runs_1d"] = st1["runs_1d"]
         stats["cells_labelled"] += st1["cells_labelled"]
         stats["positives"] += st1["positives"]
     if batch is not None:
-        Xb, yb, stb = collect_batch(batch[0], batch[1], batch[2], neg_ratio, log, soft_k)
+        Xb, yb, stb = collect_batch(batch[0], batch[1], batch[2], neg_ratio, log, soft_k, modification)
         Xs += Xb
         ys += yb
         stats["batch"] = stb["batch"]
@@ -361,7 +363,7 @@ def evaluate_run(P: np.ndarray, seed: int, n: int, steps: int, every: int, lo: f
     per snapshot (snapshot_steps), the KXRCF false-negative rate of the
     learned run's decisions and the band fraction."""
     import torch
-    prob, U0, _ = I.euler_quadrants_2d(seed=seed, n=n, nq=2)
+    prob, U0, _ = I.euler_quadrants_2d(seed=seed, n=n, nq=2, modification=I.MOD_PERSIST)
     U = torch.from_numpy(U0).cuda()
     s = Solver([prob.replace(tc_mode=I.TC_LEARNED, t_final=float("inf"))], [U])
     s.set_indicator(torch.from_numpy(P).cuda().to(torch.bfloat16), lo, hi)

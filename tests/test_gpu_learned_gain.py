@@ -53,7 +53,7 @@ def _timed(prob, U0, W=None):
 def test_trained_indicator_gain_over_kxrcf():
     from paper_2201_12193_amd.mrhweno import Solver
     from paper_2201_12193_amd.indicator import load_weights
-    prob, U0, _ = I.euler_quadrants_2d(seed=SEED, n=N, nq=2, modification=I.MOD_INTERNAL)
+    prob, U0, _ = I.euler_quadrants_2d(seed=SEED, n=N, nq=2, modification=I.MOD_PERSIST)
     prob = prob.replace(t_final=float("inf"))
     W = load_weights()
     ms, nl, T, Uk = _timed(prob, U0)
