@@ -45,7 +45,9 @@ STAGE_BYTES_PER_CELL = (2 * 96 + 3 * 96 + 3 * 96) / 3.0
 STAGE_FLOP_PER_CELL = 5900.0
 STAGE_KERNEL = "k2_stage<4,false,false>"
 COUNTERS = os.path.join(ROOT, "profiles", "k2_stage_euler2d_2048_counters.json")
-STAGE_SOURCES = ["mr_stage2d.hip", "mr_common.h", "mr_device.h", "mr_types.h", "recon_gen.h"]
+# the kernel and the host code that builds its work lists (their order sets
+# the halo re-reads)
+STAGE_SOURCES = ["mr_stage2d.hip", "mr_common.h", "mr_device.h", "mr_types.h", "recon_gen.h", "mr_api.hip"]
 BATCHED_DESC = ("256 Euler instances in one launch per kernel class (192 1D, N log-uniform 128..16384; "
                 "64 2D, side log-uniform 64..1024), HLLC, KXRCF, CFL 0.6")
 EQUAL_L1_STEPS = 200   # the learned-vs-plain comparison runs the configured 200 steps
@@ -156,13 +158,14 @@ def timed_run(prob, U0, steps, warmup, rows=0, grid=0, weights=None, band=None, 
     if weights is not None:
         s.set_indicator(weights, *band)
     if shape is not None:
-        s.set_launch(*shape)
+        s.set_launch(*shape[:2])
+        s.set_indicator_launch(shape[2])
     elif rows:
         s.set_launch(rows, grid)
-        shape = (rows, grid)
+        shape = (rows, grid, 0)
     else:
-        r, g, _ = autotune.tune(s, use_cache=False, reps=5)
-        shape = (r, g)
+        r, g, _, kr = autotune.tune(s, use_cache=False, reps=5)
+        shape = (r, g, kr)
     s.step(warmup)
     s.sync()
     Ut.copy_(U_init)
@@ -185,7 +188,8 @@ def plain_reference(prob, U0, steps, shape):
     from paper_2201_12193_amd.mrhweno import Solver
     U = torch.from_numpy(U0).cuda()
     s = Solver([prob], [U])
-    s.set_launch(*shape)
+    s.set_launch(*shape[:2])
+    s.set_indicator_launch(shape[2])
     s.step(steps)
     t, _, _ = s.sync()
     s.close()
@@ -254,7 +258,7 @@ def batched_measure(seed, steps, warmup):
     probs = [p.replace(t_final=float("inf")) for p, _ in pairs]
     Us = [torch.from_numpy(U).cuda() for _, U in pairs]
     s = Solver(probs, Us)
-    shape = autotune.tune(s, use_cache=False, reps=3)[:2]
+    shape = autotune.tune(s, use_cache=False, reps=3)
     s.step(warmup)
     _, st0, _ = s.sync(raise_on_error=False)
     torch.cuda.synchronize()
@@ -270,7 +274,8 @@ def batched_measure(seed, steps, warmup):
     info = {"instances": len(probs), "instances_1d": sum(1 for p in probs if p.dim == 1),
             "instances_2d": sum(1 for p in probs if p.dim == 2), "cells": sum(p.ncell for p in probs),
             "seed": seed, "instances_stopped_nonphysical": stopped,
-            "launch": {"rows_per_strip": shape[0], "grid": shape[1], "chosen_by": "autotuner"},
+            "launch": {"rows_per_strip": shape[0], "grid": shape[1], "kxrcf_rows": shape.kx_rows,
+                                 "chosen_by": "autotuner"},
             "kernels_ms_per_step": {"reduce_dt": ms[0] / prof_steps, "kxrcf": (ms[1] + ms[2]) / prof_steps,
                                     "stage": ms[3] / prof_steps}}
     return updates / wall, wall, info
@@ -332,7 +337,7 @@ def dmr_workload(args):
     prob, U0 = I.double_mach_2d(ny=400)
     Ut = torch.from_numpy(U0).cuda()
     s = Solver([prob], [Ut])
-    shape = autotune.tune(s, use_cache=False, reps=3)[:2]
+    shape = autotune.tune(s, use_cache=False, reps=3)
     s.step(args.warmup)                   # warm-up, then back to the initial state
     s.sync(raise_on_error=False)
     Ut.copy_(torch.from_numpy(U0))
@@ -354,7 +359,8 @@ def dmr_workload(args):
            "config": {"workload": "double Mach reflection (Example 3.9), 1600 x 400, HLLC, KXRCF (M5-I), "
                                   "CFL 0.6, to T = 0.2", "cells": prob.ncell, "t_reached": t[0],
                       "status": status, "rho_max": float(rho.max().item()),
-                      "launch": {"rows_per_strip": shape[0], "grid": shape[1], "chosen_by": "autotuner"}}}
+                      "launch": {"rows_per_strip": shape[0], "grid": shape[1], "kxrcf_rows": shape.kx_rows,
+                                 "chosen_by": "autotuner"}}}
     s.close()
     print(json.dumps(out), flush=True)
 
@@ -410,7 +416,7 @@ def main():
                                f"CFL 0.6, {args.steps} SSP-RK3 steps",
                    "modification": "persisted (modified first moments replace those of the stage inputs and U^n)",
                    "cells": ncell, "rk_stages_per_step": 3, "seed": args.seed, "sim_time": T,
-                   "launch": {"rows_per_strip": shape[0], "grid": shape[1],
+                   "launch": {"rows_per_strip": shape[0], "grid": shape[1], "kxrcf_rows": shape[2],
                               "chosen_by": "given" if args.rows else "autotuner"}},
         "kernels_ms": {"reduce_dt": ms[0], "kxrcf_summary": ms[1], "flags": ms[2], "stage": ms[3],
                        "launches": nl},

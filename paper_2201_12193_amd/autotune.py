@@ -1,20 +1,29 @@
 """Launch-shape autotuning with a persistent cache.
 
-The C ABI's mrhweno_autotune times candidate 2D launch shapes on the
-instances' current states (without advancing them) and applies the fastest.
-This module remembers the choice per (GPU architecture, dimension, number of
-components, problem-size bucket) in a JSON file, so later contexts of the
-same kind apply it without re-timing."""
+The C ABI's mrhweno_autotune times candidate 2D launch shapes of the stage
+kernel on the instances' current states (without advancing them) and applies
+the fastest; mrhweno_autotune_indicator does the same for the strip height of
+the 2D KXRCF pass.  This module remembers the choices per (GPU architecture,
+dimension, number of components, problem-size bucket) in a JSON file, so
+later contexts of the same kind apply them without re-timing."""
 from __future__ import annotations
 
 import json
 import math
 import os
-from typing import Optional, Tuple
+from typing import NamedTuple, Optional
 
 CACHE = os.path.join(os.path.expanduser(os.environ.get("MRHWENO_CACHE_DIR", "~/.cache/mrhweno")),
                      "autotune.json")
 ROWS = (16, 24, 32, 40, 48, 64, 96)
+KX_ROWS = (8, 12, 16, 24, 32, 46)
+
+
+class Launch(NamedTuple):
+    rows: int          # rows per work item of the 2D stage kernel
+    grid: int          # its grid (0: one work group per work item)
+    ms: Optional[float]
+    kx_rows: int       # flag rows per work item of the 2D KXRCF pass (0: per problem)
 
 
 def _arch() -> str:
@@ -47,21 +56,24 @@ def resident_grid() -> int:
     return 2 * torch.cuda.get_device_properties(0).multi_processor_count
 
 
-def tune(solver, use_cache: bool = True, grids=None, reps: int = 3) -> Tuple[int, int, Optional[float]]:
-    """Apply the cached launch shape for this kind of problem, or time the
-    candidates (strip heights ROWS; grids: one work group per work item and
-    a persistent grid of resident size, unless given), apply the fastest and
-    cache it.  Returns (rows, grid, ms) (ms is None for a cache hit)."""
+def tune(solver, use_cache: bool = True, grids=None, reps: int = 3) -> Launch:
+    """Apply the cached launch shapes for this kind of problem, or time the
+    candidates (stage kernel: strip heights ROWS and grids, one work group
+    per work item and a persistent grid of resident size unless given;
+    KXRCF pass: strip heights KX_ROWS), apply the fastest and cache them.
+    ms is the stage kernel's mean launch time (None for a cache hit)."""
     if grids is None:
         grids = (0, resident_grid())
     k = key(solver)
     db = _load()
-    if use_cache and k in db:
-        rows, grid = db[k]["rows"], db[k]["grid"]
-        solver.set_launch(rows, grid)
-        return rows, grid, None
+    if use_cache and k in db and "kx_rows" in db[k]:
+        e = db[k]
+        solver.set_launch(e["rows"], e["grid"])
+        solver.set_indicator_launch(e["kx_rows"])
+        return Launch(e["rows"], e["grid"], None, e["kx_rows"])
     rows, grid, ms = solver.autotune(rows=ROWS, grids=grids, reps=reps)
-    db[k] = {"rows": rows, "grid": grid, "ms": ms}
+    kx_rows, kx_ms = solver.autotune_indicator(rows=KX_ROWS, reps=reps)
+    db[k] = {"rows": rows, "grid": grid, "ms": ms, "kx_rows": kx_rows, "kx_ms": kx_ms}
     try:
         os.makedirs(os.path.dirname(CACHE), exist_ok=True)
         tmp = CACHE + ".tmp"
@@ -70,4 +82,4 @@ def tune(solver, use_cache: bool = True, grids=None, reps: int = 3) -> Tuple[int
         os.replace(tmp, CACHE)
     except OSError:
         pass
-    return rows, grid, ms
+    return Launch(rows, grid, ms, kx_rows)

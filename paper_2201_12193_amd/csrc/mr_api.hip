@@ -99,9 +99,12 @@ int kx_rows(const mrhweno_problem& p) {
   }
   return best;
 }
-/* 2D KXRCF work items: strips over [-2, n+2)^2 */
-int kx_tiles(const mrhweno_problem& p) {
-  return p.dim == 2 && indicator_pass(p) ? ceil_div_i(ext(p.nx, kFHalo), kKxW) * ceil_div_i(ext(p.ny, kFHalo), kx_rows(p)) : 0;
+/* 2D KXRCF work items: strips over [-2, n+2)^2, `rows` rows each (0: the
+   height of kx_rows) */
+int kx_tiles(const mrhweno_problem& p, int rows = 0) {
+  return p.dim == 2 && indicator_pass(p)
+             ? ceil_div_i(ext(p.nx, kFHalo), kKxW) * ceil_div_i(ext(p.ny, kFHalo), rows > 0 ? rows : kx_rows(p))
+             : 0;
 }
 
 std::string validate(const mrhweno_problem& p) {
@@ -184,7 +187,7 @@ Layout layout(const mrhweno_problem* P, int n) {
     size_t a = ceil_div(plane_of(p), kBlock) + ceil_div((long long)sex(p) * sey(p), kBlock) +
                ceil_div((long long)fex(p) * fey(p), kBlock) + ceil_div(plane_of(p), kBlock);
     if (p.dim == 1) a += ceil_div(p.nx, kBlock - 2);
-    else t2 += (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) + kx_tiles(p);
+    else t2 += (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) + kx_tiles(p, kKxMinRows);
     t1 += a;
     tmax = std::max(tmax, a + learn_tiles(p) + kx_tiles(p) +
                               (p.dim == 2 ? (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) : 0));
@@ -237,11 +240,32 @@ struct Group {
 };
 
 /* learned-indicator work items of one instance (instance id `slot`) */
-void add_kx_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p) {
-  const int rows = kx_rows(p);
+void add_kx_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p, int rows_set = 0) {
+  const int rows = rows_set > 0 ? rows_set : kx_rows(p);
   for (int y0 = -kFHalo; y0 < p.ny + kFHalo; y0 += rows)
     for (int x0 = -kFHalo; x0 < p.nx + kFHalo; x0 += kKxW)
       v.push_back(mr_tile2{slot, x0, y0, std::min(rows, p.ny + kFHalo - y0)});
+}
+
+/* XCD-aware order of the work items v[begin, end) of one launch.  The
+   hardware hands work group i of a launch to XCD i % nxcd (round robin over
+   the XCDs, each with its own L2), and a work group of a persistent grid
+   whose size is a multiple of nxcd keeps that XCD for its later items.  The
+   natural order (row of strips after row of strips) is cut into nxcd
+   contiguous runs, run j going to the slots i with i % nxcd == j, so the
+   strips one XCD works on at a time are neighbours and their shared halo
+   columns are read into the same L2.  Results do not depend on the order. */
+void xcd_order(std::vector<mr_tile2>& v, size_t begin, int nxcd) {
+  const size_t n = v.size() - begin;
+  if (nxcd <= 1 || n <= (size_t)nxcd) return;
+  std::vector<mr_tile2> nat(v.begin() + begin, v.end());
+  const size_t base = n / nxcd, extra = n % nxcd;   /* runs 0..extra-1 hold one more */
+  size_t start = 0;
+  for (int j = 0; j < nxcd; ++j) {
+    const size_t len = base + ((size_t)j < extra ? 1 : 0);
+    for (size_t i = 0; i < len; ++i) v[begin + i * nxcd + j] = nat[start + i];
+    start += len;
+  }
 }
 
 void add_learn_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p) {
@@ -267,6 +291,8 @@ struct mrhweno_ctx {
   std::vector<mr_tile1> h_t1;
   std::vector<mr_tile2> h_t2;
   int rows2 = 32, grid2 = 0;
+  int kx_rows2 = 0;   /* rows of a 2D KXRCF work item (0: chosen per problem) */
+  int nxcd = 1;       /* XCDs of the device (work-list order) */
   /* learned indicator */
   bool any_learned = false, weights_set = false;
   mr_learn_w* lw = nullptr;
@@ -350,8 +376,8 @@ static void add_cells(std::vector<mr_tile1>& v, int inst, long long count) {
     v.push_back(mr_tile1{inst, (int)s, (int)std::min<long long>(kBlock, count - s), 0});
 }
 
-static void add_kx_tiles_if(std::vector<mr_tile2>& v, int q, const mrhweno_problem& p, bool want_tvb) {
-  if (kx_tiles(p) > 0 && tvb(p) == want_tvb) add_kx_tiles(v, q, p);
+static void add_kx_tiles_if(std::vector<mr_tile2>& v, int q, const mrhweno_problem& p, bool want_tvb, int rows) {
+  if (kx_tiles(p) > 0 && tvb(p) == want_tvb) add_kx_tiles(v, q, p, rows);
 }
 
 static void build_lists(mrhweno_ctx* c) {
@@ -404,12 +430,15 @@ static void build_lists(mrhweno_ctx* c) {
         }
       }
     }
+    xcd_order(c->h_t2, g.t_st2, c->nxcd);
     g.n_st2 = (int)c->h_t2.size() - g.t_st2;
     g.t_kx = (int)c->h_t2.size();
-    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], false);
+    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], false, c->kx_rows2);
+    xcd_order(c->h_t2, g.t_kx, c->nxcd);
     g.n_kx = (int)c->h_t2.size() - g.t_kx;
     g.t_tvb = (int)c->h_t2.size();
-    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], true);
+    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], true, c->kx_rows2);
+    xcd_order(c->h_t2, g.t_tvb, c->nxcd);
     g.n_tvb = (int)c->h_t2.size() - g.t_tvb;
   }
 }
@@ -559,6 +588,12 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     if (p.flux == MRHWENO_BURGERS_LF) c->any_lf = true;
   }
   std::memset(&c->h[n], 0, sizeof(mr_inst));
+  {
+    int dev = 0, nx = 1;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess &&
+        nx >= 1 && nx <= 64)
+      c->nxcd = nx;
+  }
   /* learned indicator: work items, band list, counters */
   if (c->L.n_tilesl) {
     c->any_learned = true;
@@ -722,6 +757,79 @@ mrhweno_status mrhweno_autotune(mrhweno_ctx* c, const int* rows_cand, int n_rows
   if (st == MRHWENO_OK) st = rebuild_graph(c);
   if (best_rows) *best_rows = c->rows2;
   if (best_grid) *best_grid = c->grid2;
+  if (best_ms) *best_ms = best;
+  return st;
+}
+
+mrhweno_status mrhweno_set_indicator_launch(mrhweno_ctx* c, int rows) {
+  if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
+  if (rows != 0 && (rows < kKxMinRows || rows > kKxRows))
+    return fail(c, MRHWENO_ERR_INVALID_ARG, "indicator rows must be 0 or in [8, 46]");
+  MR_CHECK(c, hipStreamSynchronize(c->stream));
+  c->kx_rows2 = rows;
+  build_lists(c);
+  mrhweno_status st = upload_lists(c);
+  if (st != MRHWENO_OK) return st;
+  return rebuild_graph(c);
+}
+
+mrhweno_status mrhweno_autotune_indicator(mrhweno_ctx* c, const int* rows_cand, int n_rows, int reps,
+                                          int* best_rows, float* best_ms) {
+  if (!c || !rows_cand || n_rows <= 0 || reps <= 0) return fail(c, MRHWENO_ERR_INVALID_ARG, "bad autotune arguments");
+  for (int a = 0; a < n_rows; ++a)
+    if (rows_cand[a] < kKxMinRows || rows_cand[a] > kKxRows)
+      return fail(c, MRHWENO_ERR_INVALID_ARG, "indicator rows candidate out of [8, 46]");
+  MR_CHECK(c, hipStreamSynchronize(c->stream));
+  mrhweno_status st = MRHWENO_OK;
+  if (st != MRHWENO_OK) return st;
+  bool any = false;
+  for (auto& g : c->groups) any |= g.n_kx > 0;
+  if (!any) {
+    if (best_rows) *best_rows = c->kx_rows2;
+    if (best_ms) *best_ms = 0.0f;
+    return MRHWENO_OK;
+  }
+  hipEvent_t e0, e1;
+  MR_CHECK(c, hipEventCreate(&e0));
+  MR_CHECK(c, hipEventCreate(&e1));
+  const int saved = c->kx_rows2;
+  float best = 1e30f;
+  int br = saved;
+  for (int a = 0; a < n_rows && st == MRHWENO_OK; ++a) {
+    c->kx_rows2 = rows_cand[a];
+    build_lists(c);
+    if ((st = upload_lists(c)) != MRHWENO_OK) break;
+    /* one-off evaluations (stage 3) of the KXRCF pass on rotation buffer 0,
+       which always holds a state of the instance; they write the first
+       flag plane only, which every step rewrites before reading it */
+    auto launch = [&]() -> hipError_t {
+      for (auto& g : c->groups)
+        if (g.n_kx > 0) {
+          hipError_t e = mr_launch_kxrcf2(c->stream, g.nc == 4 ? (g.ch ? 4 : 3) : 1, g.bp, g.gb, c->d, c->t2 + g.t_kx,
+                                          g.n_kx, 3);
+          if (e != hipSuccess) return e;
+        }
+      return hipSuccess;
+    };
+    if (launch() != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, "autotune launch"); break; }
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps; ++r)
+      if (launch() != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, "autotune launch"); break; }
+    (void)hipEventRecord(e1, c->stream);
+    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(c, MRHWENO_ERR_DEVICE, "autotune sync"); break; }
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ms /= reps;
+    if (ms < best) { best = ms; br = c->kx_rows2; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->kx_rows2 = st == MRHWENO_OK ? br : saved;
+  build_lists(c);
+  mrhweno_status s2 = upload_lists(c);
+  if (st == MRHWENO_OK) st = s2;
+  if (st == MRHWENO_OK) st = rebuild_graph(c);
+  if (best_rows) *best_rows = c->kx_rows2;
   if (best_ms) *best_ms = best;
   return st;
 }

@@ -424,13 +424,13 @@ MR_INL void mr2_face_summary(const mr_grid& g, const mr_inst& I, int i, int j, d
 
 template <int NC, int D>
 MR_INL void mr_numflux(const double* a, const double* b, double gam, double alpha, double* f) {
-  if (NC == 1) f[0] = mr_lf(a[0], b[0], alpha);
+  if constexpr (NC == 1) f[0] = mr_lf(a[0], b[0], alpha);
   else mr_hllc<NC, D>(a, b, gam, f);
 }
 
 template <int NC, int D>
 MR_INL void mr_physflux(const double* u, double gam, double* f) {
-  if (NC == 1) f[0] = 0.5 * u[0] * u[0];
+  if constexpr (NC == 1) f[0] = 0.5 * u[0] * u[0];
   else mr_euler_flux<NC, D>(u, gam, f);
 }
 

@@ -28,7 +28,8 @@ MLP_PARAMS = 24776
 
 EXPORTS = ["mrhweno_workspace_bytes", "mrhweno_create", "mrhweno_step", "mrhweno_sync",
            "mrhweno_set_time", "mrhweno_last_dt", "mrhweno_reconstruct", "mrhweno_flag",
-           "mrhweno_residual", "mrhweno_residual_noalloc", "mrhweno_set_launch", "mrhweno_autotune", "mrhweno_profile",
+           "mrhweno_residual", "mrhweno_residual_noalloc", "mrhweno_set_launch", "mrhweno_autotune",
+           "mrhweno_set_indicator_launch", "mrhweno_autotune_indicator", "mrhweno_profile",
            "mrhweno_set_indicator", "mrhweno_indicator", "mrhweno_features",
            "mrhweno_mlp_param_count", "mrhweno_mlp_feature_count", "mrhweno_mlp_cache_bytes",
            "mrhweno_mlp_gemm", "mrhweno_mlp_forward", "mrhweno_mlp_backward", "mrhweno_mlp_adam",
@@ -109,6 +110,8 @@ def lib():
         L.mrhweno_profile.argtypes = [vp, C.c_int, C.POINTER(C.c_float), C.POINTER(C.c_int)]
         IP = C.POINTER(C.c_int)
         L.mrhweno_autotune.argtypes = [vp, IP, C.c_int, IP, C.c_int, C.c_int, IP, IP, C.POINTER(C.c_float)]
+        L.mrhweno_set_indicator_launch.argtypes = [vp, C.c_int]
+        L.mrhweno_autotune_indicator.argtypes = [vp, IP, C.c_int, C.c_int, IP, C.POINTER(C.c_float)]
         L.mrhweno_set_indicator.argtypes = [vp, vp, C.c_double, C.c_double]
         L.mrhweno_indicator.argtypes = [vp, C.c_int, vp, vp, vp]
         L.mrhweno_features.argtypes = [vp, C.c_int, vp, vp, C.c_int, vp]
@@ -228,6 +231,18 @@ class Solver:
         _check(self.ctx, lib().mrhweno_autotune(self.ctx, r, len(rows), g, len(grids), int(reps),
                                                 C.byref(br), C.byref(bg), C.byref(bm)))
         return br.value, bg.value, bm.value
+
+    def set_indicator_launch(self, rows: int) -> None:
+        """Flag rows per work item of the 2D KXRCF pass (0: chosen per problem)."""
+        _check(self.ctx, lib().mrhweno_set_indicator_launch(self.ctx, int(rows)))
+
+    def autotune_indicator(self, rows=(8, 12, 16, 24, 32, 46), reps: int = 3):
+        """Time the candidate KXRCF strip heights (state untouched) and apply
+        the fastest; returns (rows, ms)."""
+        r = (C.c_int * len(rows))(*rows)
+        br, bm = C.c_int(), C.c_float()
+        _check(self.ctx, lib().mrhweno_autotune_indicator(self.ctx, r, len(rows), int(reps), C.byref(br), C.byref(bm)))
+        return br.value, bm.value
 
     def profile(self, nsteps: int):
         """Advance nsteps with per-kernel-class HIP event timing.  Returns

@@ -117,6 +117,38 @@ def test_autotune_keeps_state_and_results():
     sb.close()
 
 
+def test_indicator_strip_height_keeps_results():
+    """The KXRCF pass's strip height (set, or tuned on the current states)
+    changes neither the state nor any step's result: a batch of a walled
+    and a periodic instance steps bit for bit alike at heights 8, 46 and
+    the tuned one, and as with the per-problem default."""
+    from paper_2201_12193_amd.mrhweno import Solver
+    p1, U1, _ = I.euler_quadrants_2d(seed=25, n=300, nq=2)
+    p2, U2, _ = I.euler_quadrants_2d(seed=26, n=130, nq=2)
+    p2 = p2.replace(bc_x=I.REFLECTIVE, bc_y=I.TRANSMISSIVE)
+    ref = [_t(U1), _t(U2)]
+    s0 = Solver([p1, p2], ref)
+    s0.step(3)
+    s0.sync()
+    want = [x.cpu().numpy() for x in ref]
+    s0.close()
+    for rows in (8, 46, None):
+        A = [_t(U1), _t(U2)]
+        s = Solver([p1, p2], A)
+        if rows is None:
+            r, ms = s.autotune_indicator(rows=(8, 20, 46), reps=2)
+            assert r in (8, 20, 46) and ms > 0
+            s.sync()
+            assert np.array_equal(A[0].cpu().numpy(), U1) and np.array_equal(A[1].cpu().numpy(), U2)
+        else:
+            s.set_indicator_launch(rows)
+        s.step(3)
+        s.sync()
+        for a, w in zip(A, want):
+            assert np.array_equal(a.cpu().numpy(), w), rows
+        s.close()
+
+
 def test_nonphysical_state_is_latched():
     """A negative density (forced from the host) is reported by sync, no step
     is taken and the state is left as it was; other instances go on."""
