@@ -267,14 +267,15 @@ mrhweno_status mrhweno_autotune(mrhweno_ctx* ctx, const int* rows_cand, int n_ro
 
 /* Flag rows per work item of the 2D KXRCF pass (eq. (KXRCF_), Step 2.1):
  * 0 = the height chosen per problem from its size (the default), else a
- * value in [8, 46]; each work item covers 62 flag columns.  The flags do
+ * value in [8, 256]; each work item covers 62 flag columns.  The flags do
  * not depend on it.  Synchronises the context's stream. */
 mrhweno_status mrhweno_set_indicator_launch(mrhweno_ctx* ctx, int rows);
 
 /* Autotuner of the 2D KXRCF pass: time the pass alone (one-off
  * evaluations that rewrite the first flag plane only, which every step
  * recomputes before it reads it; the state is untouched) for every
- * candidate height in rows_cand (n_rows entries, each in [8, 46]) with
+ * candidate height in rows_cand (n_rows entries, each 0 -- the height
+ * chosen per problem -- or in [8, 256]) with
  * `reps` timed launches each, and apply the fastest.  Instances without a
  * KXRCF pass make it a no-op that keeps the current setting.
  * best_rows/best_ms (host, may be NULL) receive the choice and its mean

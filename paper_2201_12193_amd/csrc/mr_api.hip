@@ -47,6 +47,7 @@ constexpr int kMinRows = 8; /* smallest 2D strip height the work lists are sized
 constexpr int kKxW = 62;    /* 2D KXRCF work item: 62 flag columns ...                */
 constexpr int kKxRows = 46; /* ... x up to 46 flag rows of the extended flag range    */
 constexpr int kKxMinRows = 8;
+constexpr int kKxMaxRows = 256; /* tallest height a caller may set */
 constexpr int kKxFill = 512; /* work groups that fill the GPU (256 CUs x 2 resident)    */
 constexpr int kLearnW = 64;     /* learned-indicator work item: 64 columns ...       */
 constexpr int kLearnRows = 32;  /* ... x 32 rows of the extended flag range          */
@@ -247,14 +248,18 @@ void add_kx_tiles(std::vector<mr_tile2>& v, int slot, const mrhweno_problem& p, 
       v.push_back(mr_tile2{slot, x0, y0, std::min(rows, p.ny + kFHalo - y0)});
 }
 
-/* XCD-aware order of the work items v[begin, end) of one launch.  The
+/* XCD-aware order of the work items v[begin, end) of one instance.  The
    hardware hands work group i of a launch to XCD i % nxcd (round robin over
    the XCDs, each with its own L2), and a work group of a persistent grid
    whose size is a multiple of nxcd keeps that XCD for its later items.  The
-   natural order (row of strips after row of strips) is cut into nxcd
-   contiguous runs, run j going to the slots i with i % nxcd == j, so the
-   strips one XCD works on at a time are neighbours and their shared halo
-   columns are read into the same L2.  Results do not depend on the order. */
+   instance's natural order (row of strips after row of strips) is cut into
+   nxcd contiguous runs of equal length, run j going to the slots
+   begin + i nxcd + j, so the strips one XCD works on at a time are
+   neighbours and their shared halo columns are read into the same L2.  It
+   is done per instance: the items of one instance cost about the same, so
+   every XCD gets an equal share, and the order of the instances in a batch
+   (largest first, for a short tail) stays.  Results do not depend on the
+   order. */
 void xcd_order(std::vector<mr_tile2>& v, size_t begin, int nxcd) {
   const size_t n = v.size() - begin;
   if (nxcd <= 1 || n <= (size_t)nxcd) return;
@@ -376,8 +381,13 @@ static void add_cells(std::vector<mr_tile1>& v, int inst, long long count) {
     v.push_back(mr_tile1{inst, (int)s, (int)std::min<long long>(kBlock, count - s), 0});
 }
 
-static void add_kx_tiles_if(std::vector<mr_tile2>& v, int q, const mrhweno_problem& p, bool want_tvb, int rows) {
-  if (kx_tiles(p) > 0 && tvb(p) == want_tvb) add_kx_tiles(v, q, p, rows);
+static void add_kx_tiles_if(std::vector<mr_tile2>& v, int q, const mrhweno_problem& p, bool want_tvb, int rows,
+                            int nxcd) {
+  if (kx_tiles(p) > 0 && tvb(p) == want_tvb) {
+    const size_t first = v.size();
+    add_kx_tiles(v, q, p, rows);
+    xcd_order(v, first, nxcd);
+  }
 }
 
 static void build_lists(mrhweno_ctx* c) {
@@ -411,6 +421,7 @@ static void build_lists(mrhweno_ctx* c) {
         return plane_of(c->probs[a]) > plane_of(c->probs[b]); });
       for (int q : order) {
         const auto& p = c->probs[q];
+        const size_t first = c->h_t2.size();
         const int w = strip_cells(p) - 2;
         const int rows = std::max(kMinRows, c->rows2);
         const bool lx = side_data(p, 0), rx = side_data(p, 1);
@@ -418,6 +429,7 @@ static void build_lists(mrhweno_ctx* c) {
           for (int y0 = 0; y0 < p.ny; y0 += rows)
             for (int x0 = 0; x0 < p.nx; x0 += w)
               c->h_t2.push_back(mr_tile2{q, x0, y0, std::min(rows, p.ny - y0)});
+          xcd_order(c->h_t2, first, c->nxcd);
           continue;
         }
         /* strips whose staged columns (x0-3 .. x0+w+2) reach a left or right
@@ -428,17 +440,15 @@ static void build_lists(mrhweno_ctx* c) {
           const int r = edge ? std::max(kMinRows, rows / 2) : rows;
           for (int y0 = 0; y0 < p.ny; y0 += r) c->h_t2.push_back(mr_tile2{q, x0, y0, std::min(r, p.ny - y0)});
         }
+        xcd_order(c->h_t2, first, c->nxcd);
       }
     }
-    xcd_order(c->h_t2, g.t_st2, c->nxcd);
     g.n_st2 = (int)c->h_t2.size() - g.t_st2;
     g.t_kx = (int)c->h_t2.size();
-    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], false, c->kx_rows2);
-    xcd_order(c->h_t2, g.t_kx, c->nxcd);
+    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], false, c->kx_rows2, c->nxcd);
     g.n_kx = (int)c->h_t2.size() - g.t_kx;
     g.t_tvb = (int)c->h_t2.size();
-    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], true, c->kx_rows2);
-    xcd_order(c->h_t2, g.t_tvb, c->nxcd);
+    for (int q : g.insts) add_kx_tiles_if(c->h_t2, q, c->probs[q], true, c->kx_rows2, c->nxcd);
     g.n_tvb = (int)c->h_t2.size() - g.t_tvb;
   }
 }
@@ -763,8 +773,8 @@ mrhweno_status mrhweno_autotune(mrhweno_ctx* c, const int* rows_cand, int n_rows
 
 mrhweno_status mrhweno_set_indicator_launch(mrhweno_ctx* c, int rows) {
   if (!c) return fail(nullptr, MRHWENO_ERR_INVALID_ARG, "NULL context");
-  if (rows != 0 && (rows < kKxMinRows || rows > kKxRows))
-    return fail(c, MRHWENO_ERR_INVALID_ARG, "indicator rows must be 0 or in [8, 46]");
+  if (rows != 0 && (rows < kKxMinRows || rows > kKxMaxRows))
+    return fail(c, MRHWENO_ERR_INVALID_ARG, "indicator rows must be 0 or in [8, 256]");
   MR_CHECK(c, hipStreamSynchronize(c->stream));
   c->kx_rows2 = rows;
   build_lists(c);
@@ -777,8 +787,8 @@ mrhweno_status mrhweno_autotune_indicator(mrhweno_ctx* c, const int* rows_cand, 
                                           int* best_rows, float* best_ms) {
   if (!c || !rows_cand || n_rows <= 0 || reps <= 0) return fail(c, MRHWENO_ERR_INVALID_ARG, "bad autotune arguments");
   for (int a = 0; a < n_rows; ++a)
-    if (rows_cand[a] < kKxMinRows || rows_cand[a] > kKxRows)
-      return fail(c, MRHWENO_ERR_INVALID_ARG, "indicator rows candidate out of [8, 46]");
+    if (rows_cand[a] != 0 && (rows_cand[a] < kKxMinRows || rows_cand[a] > kKxMaxRows))
+      return fail(c, MRHWENO_ERR_INVALID_ARG, "indicator rows candidate neither 0 nor in [8, 256]");
   MR_CHECK(c, hipStreamSynchronize(c->stream));
   mrhweno_status st = MRHWENO_OK;
   if (st != MRHWENO_OK) return st;

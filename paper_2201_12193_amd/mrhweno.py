@@ -236,9 +236,9 @@ class Solver:
         """Flag rows per work item of the 2D KXRCF pass (0: chosen per problem)."""
         _check(self.ctx, lib().mrhweno_set_indicator_launch(self.ctx, int(rows)))
 
-    def autotune_indicator(self, rows=(8, 12, 16, 24, 32, 46), reps: int = 3):
-        """Time the candidate KXRCF strip heights (state untouched) and apply
-        the fastest; returns (rows, ms)."""
+    def autotune_indicator(self, rows=(0, 8, 16, 24, 32, 46, 64, 96, 140), reps: int = 3):
+        """Time the candidate KXRCF strip heights (0: the height chosen per
+        problem; state untouched) and apply the fastest; returns (rows, ms)."""
         r = (C.c_int * len(rows))(*rows)
         br, bm = C.c_int(), C.c_float()
         _check(self.ctx, lib().mrhweno_autotune_indicator(self.ctx, r, len(rows), int(reps), C.byref(br), C.byref(bm)))

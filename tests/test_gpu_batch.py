@@ -120,7 +120,7 @@ def test_autotune_keeps_state_and_results():
 def test_indicator_strip_height_keeps_results():
     """The KXRCF pass's strip height (set, or tuned on the current states)
     changes neither the state nor any step's result: a batch of a walled
-    and a periodic instance steps bit for bit alike at heights 8, 46 and
+    and a periodic instance steps bit for bit alike at heights 8, 46, 200 and
     the tuned one, and as with the per-problem default."""
     from paper_2201_12193_amd.mrhweno import Solver
     p1, U1, _ = I.euler_quadrants_2d(seed=25, n=300, nq=2)
@@ -132,7 +132,7 @@ def test_indicator_strip_height_keeps_results():
     s0.sync()
     want = [x.cpu().numpy() for x in ref]
     s0.close()
-    for rows in (8, 46, None):
+    for rows in (8, 46, 200, None):
         A = [_t(U1), _t(U2)]
         s = Solver([p1, p2], A)
         if rows is None:
