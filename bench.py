@@ -43,7 +43,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2
 # at their minimal operation counts: 5.9 kFLOP
 STAGE_BYTES_PER_CELL = (2 * 96 + 3 * 96 + 3 * 96) / 3.0
 STAGE_FLOP_PER_CELL = 5900.0
-STAGE_KERNEL = "k2_stage<4,false,false>"
+STAGE_KERNEL = "k2_stage<4,false,false,false>"
 COUNTERS = os.path.join(ROOT, "profiles", "k2_stage_euler2d_2048_counters.json")
 # the kernel and the host code that builds its work lists (their order sets
 # the halo re-reads)
@@ -91,9 +91,10 @@ def stage_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(ncell: int):
-    """HBM bytes per launch of the stage kernel from the committed counter
-    profile, if it was taken on the current kernel source."""
+def measured_counters(ncell: int):
+    """The committed counter profile of the stage kernel (calibrated HBM
+    bytes and counted FP64 FLOPs per launch), if it was taken on the current
+    kernel and work-list source at this grid size."""
     try:
         with open(COUNTERS) as f:
             c = json.load(f)
@@ -101,7 +102,7 @@ def measured_traffic(ncell: int):
         return None
     if c.get("source_hash") != stage_source_hash() or c.get("cells") != ncell:
         return None
-    return c.get("hbm_bytes_per_launch")
+    return c
 
 
 def cpu_model() -> str:
@@ -390,7 +391,8 @@ def main():
     stage_ms = ms[3] / max(nl[3], 1)
     achieved_tflops = STAGE_FLOP_PER_CELL * ncell / (stage_ms * 1e-3) / 1e12
     achieved_gbs = STAGE_BYTES_PER_CELL * ncell / (stage_ms * 1e-3) / 1e9
-    traffic = measured_traffic(ncell)
+    cnt = measured_counters(ncell)
+    traffic = cnt.get("hbm_bytes_per_launch") if cnt else None
     roofline = {"bound": "alu", "achieved": achieved_tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved_tflops / FP64_PEAK_TFLOPS, "traffic": traffic,
                 "kernel": STAGE_KERNEL, "kernel_avg_ms": stage_ms,
@@ -399,6 +401,18 @@ def main():
                 "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved_gbs / HBM_PEAK_GBS,
                         "algorithmic_bytes_per_cell": STAGE_BYTES_PER_CELL}}
+    if cnt:
+        # the same kernel's counters (profiles/): executed FP64 FLOPs, which
+        # include the strips' halo rows and columns, and calibrated HBM bytes
+        fl = cnt["fp64_flop_per_launch"]
+        roofline["counted"] = {
+            "fp64_flop_per_cell": cnt["fp64_flop_per_cell"],
+            "achieved": fl / (stage_ms * 1e-3) / 1e12,
+            "frac": fl / (stage_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "hbm_bytes_per_launch": traffic,
+            "traffic_over_algorithmic": traffic / (STAGE_BYTES_PER_CELL * ncell),
+            "taken_at_launch": cnt.get("launch"),
+            "profile": os.path.relpath(COUNTERS, ROOT)}
     out = {
         "metric": "2D Euler MR-HWENO cell-updates/s (FP64), plain vs learned-indicator at equal L1",
         "value": value,
