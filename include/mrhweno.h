@@ -167,6 +167,27 @@ typedef struct {
                               mode); 0 = component by component, as the paper
                               does                                           */
   mrhweno_side side[4];    /* per-side data of an axis whose bc is SIDES       */
+  int step_i, step_j;      /* 2D Euler: a solid step, the cells i >= step_i,
+                              j < step_j (the forward step of Example 3.10;
+                              step_j = 0: none; 0 < step_j <= step_i < nx,
+                              2 step_j <= ny).  Its cells carry no state (the
+                              steps write zeros there); read as ghosts they
+                              are mirror images of fluid cells across the
+                              step's nearest face (across the vertical face
+                              when fewer columns into the step than rows
+                              below its top, across the top in the opposite
+                              case, through the corner when equal), with the
+                              flips of a reflective wall; its faces are
+                              walls.  KXRCF, all-cells or no troubled cells. */
+  int wall_flux;           /* 2D Euler: 0 = the printed HLLC on the mirror
+                              state at wall faces; 1 = the Godunov flux of
+                              the mirror-image Riemann problem (star state
+                              at rest: mass and energy flux 0, normal
+                              momentum flux the exact star pressure of the
+                              reflected shock or rarefaction).  The printed
+                              HLLC lets a stream of normal Mach number above
+                              about 2 through a wall (its linearised star
+                              pressure puts s_L > 0).                     */
 } mrhweno_problem;
 
 /* Device workspace needed for n instances (bytes, 256-byte aligned pieces).

@@ -33,6 +33,10 @@ ORACLE_PINS = {
              "2D: denominator on uniform flows, face-length scaling on non-square cells, two inflow faces, "
              "x and y faces of a raised cell, norm over all sixteen points",
     "hllc": "consistency, supersonic branches, stationary contact",
+    "wall_flux": "gas at rest keeps its pressure; star pressure of the reflected shock against the Rankine-Hugoniot "
+                 "relations and the shock speed; isentropic rarefaction and vacuum; mirror-direction symmetry",
+    "step": "gas at rest in a tunnel with a step stays at rest; mirror images of the step cells (depth rule, "
+            "corner); uniform flow along the step top is preserved; step faces are walls in the KXRCF test",
     "residual": "conservation; free-stream preservation; convergence orders; Lax problem vs exact Riemann solution",
     "rk3": "third-order temporal convergence",
 }
@@ -56,7 +60,8 @@ class _Prob(C.Structure):
                 ("charwise", C.c_int),
                 ("x0", C.c_double), ("y0", C.c_double), ("t", C.c_double),
                 ("side_kind", C.c_int * 4), ("side_state", C.c_double * 16),
-                ("side_pre", C.c_double * 16), ("side_split", C.c_double * 12)]
+                ("side_pre", C.c_double * 16), ("side_split", C.c_double * 12),
+                ("step_i", C.c_int), ("step_j", C.c_int), ("wall_flux", C.c_int)]
 
 
 _lib = None
@@ -78,6 +83,7 @@ def lib():
         L.orc_qcoef_2d.argtypes = [C.c_int, D, D, D, D]
         L.orc_monomials_2d.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_hllc.argtypes = [D, D, C.c_int, C.c_int, C.c_double, D]
+        L.orc_wall_flux.argtypes = [D, C.c_int, C.c_int, C.c_int, C.c_double, D]
         L.orc_residual.argtypes = [P, D, D, B]
         L.orc_residual_given.argtypes = [P, D, B, D]
         L.orc_reconstruct.argtypes = [P, D, D, B, D, D]
@@ -124,6 +130,8 @@ def cprob(prob, t: float = 0.0) -> _Prob:
     p.tvb_m = getattr(prob, "tvb_m", 0.0)
     p.charwise = getattr(prob, "charwise", 0)
     p.x0, p.y0, p.t = prob.x0, prob.y0, float(t)
+    p.step_i, p.step_j = getattr(prob, "step_i", 0), getattr(prob, "step_j", 0)
+    p.wall_flux = getattr(prob, "wall_flux", 0)
     for k in range(4):
         p.side_split[3 * k] = -math.inf
     sides = getattr(prob, "sides", None)
@@ -231,6 +239,15 @@ def hllc(uL, uR, gamma: float, direction: int = 0) -> np.ndarray:
     uL, uR = _arr(uL), _arr(uR)
     f = np.zeros(len(uL))
     lib().orc_hllc(_dp(uL), _dp(uR), len(uL), direction, gamma, _dp(f))
+    return f
+
+
+def wall_flux(u, gamma: float, direction: int = 0, sgn: int = 1) -> np.ndarray:
+    """Flux through a wall face normal to `direction` of the fluid trace u,
+    the wall on the side sgn (+1: towards +direction) (reading R20)."""
+    u = _arr(u)
+    f = np.zeros(len(u))
+    lib().orc_wall_flux(_dp(u), len(u), direction, sgn, gamma, _dp(f))
     return f
 
 

@@ -92,6 +92,38 @@
  *       is the maximum of |rho| over both sets' sixteen values.  Step 2.3
  *       re-reconstructs both sets of a troubled cell from its modified
  *       stencil.  With charwise = 0 the two sets coincide (R2).
+ *   R19 the forward step of Example 3.10: a solid block of the cells
+ *       i >= step_i, j < step_j at the bottom right of the tunnel.  Its
+ *       cells carry no state (zero moments, zero residual); read as ghosts
+ *       (their Gauss-Lobatto values and KXRCF flags included, as for the
+ *       ghosts of R16), they are the mirror images of fluid cells across
+ *       the step's nearest face -- across the vertical face when the cell
+ *       lies fewer columns right of it than rows below the top face,
+ *       across the top face in the opposite case, across both (through
+ *       the corner) when the two depths are equal -- with the flips of
+ *       R16.  A domain ghost that folds onto a step cell takes that cell's
+ *       mirror image.  The step's faces are walls (never KXRCF inflow),
+ *       continued through the ghost cells: the vertical face x = step_i
+ *       for every row below the step's top (ghost rows below the tunnel
+ *       included) and the top y = step_j for every column from step_i on
+ *       (ghost columns beyond the exit included).  There the ghost field is
+ *       the mirror image across the face too, the two traces' normal
+ *       velocities cancel and only a rounding residue of either sign would
+ *       decide the inflow test.
+ *   R20 wall flux (wall_flux = 1): on a wall face the numerical flux is
+ *       the Godunov flux of the mirror-image Riemann problem, whose star
+ *       state is at rest: mass and energy flux zero, normal momentum flux
+ *       the star pressure p*.  With u_n the fluid trace's velocity into
+ *       the wall, p* solves the shock relation
+ *         (p* - p) sqrt(A / (p* + B)) = u_n,  A = 2/((g+1) rho),
+ *         B = (g-1)/(g+1) p
+ *       for u_n > 0 (the positive root q = p* - p of the quadratic
+ *       A q^2 - u_n^2 q - u_n^2 (p + B) = 0 it squares to), the
+ *       rarefaction relation p* = p (1 + (g-1) u_n / (2 c))^(2g/(g-1)) for
+ *       u_n < 0 (0 at vacuum), and p* = p for u_n = 0.  The printed HLLC
+ *       on the mirror state (R16, wall_flux = 0) passes a stream of normal
+ *       Mach number above about 2 through the wall: the linearised star
+ *       pressure puts s_L > 0, so it returns the upwind flux.
  *   R14 the TVB minmod indicator (tc_mode 4, one of Remark 2's
  *       alternatives, defined in its reference rather than the paper) acts
  *       on the indicator variable (density; u for Burgers) with h = dx; in
@@ -140,6 +172,9 @@ typedef struct {
   double side_state[4][4];  /* inflow state (conserved variables)           */
   double side_pre[4][4];    /* state of the ghosts before the split         */
   double side_split[4][3];  /* s0, st, sn of the split (bottom and top)     */
+  int step_i, step_j;       /* solid cells i >= step_i, j < step_j (R19);
+                               step_j = 0: none                            */
+  int wall_flux;            /* 1: exact mirror-problem flux on walls (R20)  */
 } orc_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -800,11 +835,16 @@ static int prescribed(const orc_problem* P, int c, int m, int i, int j, double* 
   return 0;
 }
 
+/* cell (i, j) of the grid lies in the step (R19) */
+static int solid(const orc_problem* P, int i, int j) {
+  return P->dim == 2 && P->step_j > 0 && i >= P->step_i && i < P->nx && j >= 0 && j < P->step_j;
+}
+
 /* Moment m of component c at cell (i, j), any integer (i, j).  A
    reflective ghost is the mirror image of the interior cell across the
    wall: the momentum normal to the wall and the first moment along the
    normal change sign, so a moment flips when exactly one of the two holds
-   (R16). */
+   (R16).  A cell of the step is the mirror image of a fluid cell (R19). */
 static double mom(const grid_t* G, int c, int m, int i, int j) {
   const orc_problem* P = G->P;
   int zero = 0, flip = 0;
@@ -832,6 +872,11 @@ static double mom(const grid_t* G, int c, int m, int i, int j) {
     }
   }
   if (P->dim == 1) j = 0;
+  if (solid(P, i, j)) {
+    const int dx = i - P->step_i, dy = P->step_j - 1 - j;
+    if (dx <= dy) { i = 2 * P->step_i - 1 - i; flip ^= (c == 1) ^ (m == 1); }
+    if (dy <= dx) { j = 2 * P->step_j - 1 - j; flip ^= (c == 2) ^ (m == 2); }
+  }
   if (zero && m > 0) return 0.0;
   const double v = G->U[((size_t)(c * G->nm + m) * P->ny + j) * P->nx + i];
   return flip ? -v : v;
@@ -853,13 +898,41 @@ static double modified_v1(const grid_t* G, int c, int i) {
    f of column i, is a reflective wall (R16, R17) */
 static int wall_x(const orc_problem* P, int f, int j) {
   double pv;
+  if (P->dim == 2 && P->step_j > 0 && f == P->step_i && j < P->step_j) return 1;   /* R19 */
   if (f != 0 && f != P->nx) return 0;
   return side_kind(P, f == 0 ? 0 : 1) == 2 && !prescribed(P, 0, 0, f == 0 ? -1 : P->nx, j, &pv);
 }
 static int wall_y(const orc_problem* P, int i, int f) {
   double pv;
+  if (P->dim == 2 && P->step_j > 0 && f == P->step_j && i >= P->step_i) return 1;   /* R19 */
   if (P->dim != 2 || (f != 0 && f != P->ny)) return 0;
   return side_kind(P, f == 0 ? 2 : 3) == 2 && !prescribed(P, 0, 0, i, f == 0 ? -1 : P->ny, &pv);
+}
+
+/* Star pressure of the mirror-image Riemann problem of a gas state
+   (rho, u_n, p) against a wall, u_n its velocity into the wall (R20). */
+static double wall_pstar(double rho, double un, double p, double gam) {
+  if (un > 0.0) {
+    /* (p* - p)^2 A = un^2 (p* + B) is a quadratic in q = p* - p:
+       A q^2 - un^2 q - un^2 (p + B) = 0, whose positive root is taken */
+    const double A = 2.0 / ((gam + 1.0) * rho), B = (gam - 1.0) / (gam + 1.0) * p;
+    return p + un * (un + sqrt(un * un + 4.0 * A * (p + B))) / (2.0 * A);
+  }
+  if (un < 0.0) {
+    const double c = sqrt(gam * p / rho);
+    const double base = 1.0 + 0.5 * (gam - 1.0) * un / c;
+    return base > 0.0 ? p * pow(base, 2.0 * gam / (gam - 1.0)) : 0.0;
+  }
+  return p;
+}
+
+/* Flux through a wall face normal to direction dir of the fluid trace u,
+   the wall on the side sgn (+1: towards +dir) (R20). */
+void orc_wall_flux(const double* u, int nc, int dir, int sgn, double gam, double* f) {
+  const double p = pressure(u, nc, gam);
+  const double un = sgn * u[1 + dir] / u[0];
+  for (int c = 0; c < nc; ++c) f[c] = 0.0;
+  f[1 + dir] = wall_pstar(u[0], un, p, gam);
 }
 
 /* velocity used by the KXRCF indicator at a point (Remark 2) */
@@ -1322,6 +1395,22 @@ static void num_flux(const orc_problem* P, const double* uL, const double* uR, i
   orc_hllc(uL, uR, ncomp_of(P), dir, P->gamma, f);
 }
 
+/* flux at a point of face f (an x face of row `other`, dir 0, or a y face
+   of column `other`, dir 1): the wall flux of R20 on a wall face when
+   wall_flux is set -- the fluid is on the low side of the high wall of
+   the domain and of the step's vertical face, on the high side of the low
+   wall and of the step's top -- else num_flux on the two traces */
+static void face_flux(const orc_problem* P, const double* uL, const double* uR, int dir, int f, int other,
+                      double alpha, double* out) {
+  if (P->wall_flux && P->system == 1 && (dir == 0 ? wall_x(P, f, other) : wall_y(P, other, f))) {
+    const int fluid_low = dir == 0 ? f != 0 : f == P->ny;
+    if (fluid_low) orc_wall_flux(uL, ncomp_of(P), dir, 1, P->gamma, out);
+    else orc_wall_flux(uR, ncomp_of(P), dir, -1, P->gamma, out);
+    return;
+  }
+  num_flux(P, uL, uR, dir, alpha, out);
+}
+
 /* L(U) of eq. (2D-equ-int-approximation) with the quadratures of eqs.
    (integral1)-(integral3). */
 static void residual_2d(const orc_problem* P, const double* U, double* L, unsigned char* flags,
@@ -1350,19 +1439,19 @@ static void residual_2d(const orc_problem* P, const double* U, double* L, unsign
         double wm = gl_weight(m), xm = gl_node(m);
         /* left face x_{i-1/2}, eta_m: left state from cell i-1 (xi = 1/2) */
         for (int c = 0; c < nc; ++c) { a[c] = lef[c * 16 + 3 + 4 * m]; b[c] = own[c * 16 + 0 + 4 * m]; }
-        num_flux(P, a, b, 0, alpha, f);
+        face_flux(P, a, b, 0, i, j, alpha, f);
         for (int c = 0; c < nc; ++c) { XL0[c] += wm * f[c]; XL1[c] += wm * xm * f[c]; }
         /* right face x_{i+1/2} */
         for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + 3 + 4 * m]; b[c] = rig[c * 16 + 0 + 4 * m]; }
-        num_flux(P, a, b, 0, alpha, f);
+        face_flux(P, a, b, 0, i + 1, j, alpha, f);
         for (int c = 0; c < nc; ++c) { XR0[c] += wm * f[c]; XR1[c] += wm * xm * f[c]; }
         /* bottom face y_{j-1/2}, xi_m */
         for (int c = 0; c < nc; ++c) { a[c] = bot[c * 16 + m + 12]; b[c] = owy[c * 16 + m]; }
-        num_flux(P, a, b, 1, alpha, f);
+        face_flux(P, a, b, 1, j, i, alpha, f);
         for (int c = 0; c < nc; ++c) { YB0[c] += wm * f[c]; YB1[c] += wm * xm * f[c]; }
         /* top face y_{j+1/2} */
         for (int c = 0; c < nc; ++c) { a[c] = owy[c * 16 + m + 12]; b[c] = top[c * 16 + m]; }
-        num_flux(P, a, b, 1, alpha, f);
+        face_flux(P, a, b, 1, j + 1, i, alpha, f);
         for (int c = 0; c < nc; ++c) { YT0[c] += wm * f[c]; YT1[c] += wm * xm * f[c]; }
       }
       /* volume terms F_ij, G_ij, eq. (integral1) */
@@ -1379,7 +1468,12 @@ static void residual_2d(const orc_problem* P, const double* U, double* L, unsign
           }
         }
       size_t plane = (size_t)nx * ny, cell = (size_t)j * nx + i;
+      const int sol = solid(P, i, j);   /* R19: no state in the step */
       for (int c = 0; c < nc; ++c) {
+        if (sol) {
+          for (int m = 0; m < 3; ++m) L[(c * 3 + m) * plane + cell] = 0.0;
+          continue;
+        }
         double du = -(XR0[c] - XL0[c]) / P->dx - (YT0[c] - YB0[c]) / P->dy;
         double dv = -(XR0[c] + XL0[c]) / (2.0 * P->dx) + F[c] / P->dx - (YT1[c] - YB1[c]) / P->dy;
         double dw = -(XR1[c] - XL1[c]) / P->dx - (YT0[c] + YB0[c]) / (2.0 * P->dy) + Gv[c] / P->dy;
@@ -1466,6 +1560,7 @@ int orc_wave_speeds(const orc_problem* P, const double* U, double* out) {
   size_t plane = (size_t)P->nx * P->ny;
   double ax = 0.0, ay = 0.0;
   for (size_t k = 0; k < plane; ++k) {
+    if (solid(P, (int)(k % P->nx), (int)(k / P->nx))) continue;   /* R19 */
     if (P->system == 0) {
       double a = fabs(U[k]);
       if (a > ax) ax = a;
@@ -1526,6 +1621,16 @@ int orc_modify(const orc_problem* P, const double* U, const unsigned char* flags
      0: not at all (the modification is internal to L);
      1: every stage input, U^n included, is replaced by its modified state;
      2: stage inputs are replaced, U^n in the later stages is the original. */
+/* the step's cells carry no state (R19) */
+static void zero_solid(const orc_problem* P, double* U) {
+  if (P->dim != 2 || P->step_j <= 0) return;
+  size_t plane = (size_t)P->nx * P->ny;
+  int nq = ncomp_of(P) * 3;
+  for (int j = 0; j < P->step_j; ++j)
+    for (int i = P->step_i; i < P->nx; ++i)
+      for (int q = 0; q < nq; ++q) U[q * plane + (size_t)j * P->nx + i] = 0.0;
+}
+
 int orc_rk3_step_p(const orc_problem* P, double* U, double dt, unsigned char* flags, int persist) {
   size_t n = (size_t)ncomp_of(P) * (P->dim + 1) * P->nx * P->ny;
   size_t cells = (size_t)P->nx * P->ny;
@@ -1545,16 +1650,19 @@ int orc_rk3_step_p(const orc_problem* P, double* U, double dt, unsigned char* fl
   if (persist) orc_modify(P, U, fl, Ut); else memcpy(Ut, U, n * sizeof(double));
   if (persist == 1) memcpy(Un, Ut, n * sizeof(double)); else memcpy(Un, U, n * sizeof(double));
   for (size_t k = 0; k < n; ++k) U1[k] = Ut[k] + dt * L[k];
+  zero_solid(P, U1);
   P = &S1;
   orc_residual(P, U1, L, fl);
   if (flags) memcpy(flags + cells, fl, cells);
   if (persist) orc_modify(P, U1, fl, Ut); else memcpy(Ut, U1, n * sizeof(double));
   for (size_t k = 0; k < n; ++k) U2[k] = 3.0 / 4.0 * Un[k] + 1.0 / 4.0 * Ut[k] + 1.0 / 4.0 * dt * L[k];
+  zero_solid(P, U2);
   P = &S2;
   orc_residual(P, U2, L, fl);
   if (flags) memcpy(flags + 2 * cells, fl, cells);
   if (persist) orc_modify(P, U2, fl, Ut); else memcpy(Ut, U2, n * sizeof(double));
   for (size_t k = 0; k < n; ++k) U[k] = 1.0 / 3.0 * Un[k] + 2.0 / 3.0 * Ut[k] + 2.0 / 3.0 * dt * L[k];
+  zero_solid(P, U);
   free(U1); free(U2); free(L); free(Ut); free(Un); free(fl);
   return 0;
 }
@@ -1640,16 +1748,16 @@ int orc_residual_cell_2d(const orc_problem* P, const double* U, double alpha, in
     double a[4], b[4], f[4];
     double wm = gl_weight(m), xm = gl_node(m);
     for (int c = 0; c < nc; ++c) { a[c] = lef[c * 16 + 3 + 4 * m]; b[c] = own[c * 16 + 0 + 4 * m]; }
-    num_flux(P, a, b, 0, alpha, f);
+    face_flux(P, a, b, 0, i, j, alpha, f);
     for (int c = 0; c < nc; ++c) { XL0[c] += wm * f[c]; XL1[c] += wm * xm * f[c]; }
     for (int c = 0; c < nc; ++c) { a[c] = own[c * 16 + 3 + 4 * m]; b[c] = rig[c * 16 + 0 + 4 * m]; }
-    num_flux(P, a, b, 0, alpha, f);
+    face_flux(P, a, b, 0, i + 1, j, alpha, f);
     for (int c = 0; c < nc; ++c) { XR0[c] += wm * f[c]; XR1[c] += wm * xm * f[c]; }
     for (int c = 0; c < nc; ++c) { a[c] = bot[c * 16 + m + 12]; b[c] = owy[c * 16 + m]; }
-    num_flux(P, a, b, 1, alpha, f);
+    face_flux(P, a, b, 1, j, i, alpha, f);
     for (int c = 0; c < nc; ++c) { YB0[c] += wm * f[c]; YB1[c] += wm * xm * f[c]; }
     for (int c = 0; c < nc; ++c) { a[c] = owy[c * 16 + m + 12]; b[c] = top[c * 16 + m]; }
-    num_flux(P, a, b, 1, alpha, f);
+    face_flux(P, a, b, 1, j + 1, i, alpha, f);
     for (int c = 0; c < nc; ++c) { YT0[c] += wm * f[c]; YT1[c] += wm * xm * f[c]; }
   }
   double F[4] = {0}, Gv[4] = {0};
@@ -1665,6 +1773,7 @@ int orc_residual_cell_2d(const orc_problem* P, const double* U, double alpha, in
       }
     }
   for (int c = 0; c < nc; ++c) {
+    if (solid(P, i, j)) { out[c * 3 + 0] = out[c * 3 + 1] = out[c * 3 + 2] = 0.0; continue; }
     out[c * 3 + 0] = -(XR0[c] - XL0[c]) / P->dx - (YT0[c] - YB0[c]) / P->dy;
     out[c * 3 + 1] = -(XR0[c] + XL0[c]) / (2.0 * P->dx) + F[c] / P->dx - (YT1[c] - YB1[c]) / P->dy;
     out[c * 3 + 2] = -(XR1[c] - XL1[c]) / P->dx - (YT0[c] + YB0[c]) / (2.0 * P->dy) + Gv[c] / P->dy;

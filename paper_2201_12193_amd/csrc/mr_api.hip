@@ -159,6 +159,15 @@ std::string validate(const mrhweno_problem& p) {
     const double dx = (p.x1 - p.x0) / p.nx, dy = (p.y1 - p.y0) / p.ny;
     if (std::fabs(dx - dy) > 1e-12 * std::max(dx, dy)) return "2D cells must be square (dx == dy)";
   }
+  if (p.wall_flux != 0 && p.wall_flux != 1) return "wall_flux must be 0 or 1";
+  if (p.wall_flux && (p.dim != 2 || p.flux != MRHWENO_EULER_HLLC)) return "wall_flux is for 2D Euler";
+  if (p.step_j != 0) {
+    if (p.dim != 2 || p.flux != MRHWENO_EULER_HLLC) return "a step is for 2D Euler";
+    if (p.step_j < 0 || p.step_i < 1 || p.step_i >= p.nx || p.step_j > p.step_i || 2 * p.step_j > p.ny)
+      return "the step needs 0 < step_j <= step_i < nx and 2 step_j <= ny (its mirror images lie in the grid)";
+    if (p.tc_mode != MRHWENO_TC_NONE && p.tc_mode != MRHWENO_TC_KXRCF && p.tc_mode != MRHWENO_TC_ALL)
+      return "a step takes the KXRCF, all-cells or no troubled-cell mode";
+  }
   if (plane_of(p) > (1ll << 31) - 1) return "grid too large";
   /* the 2D stage kernel addresses a moment plane and row as a 30-bit offset */
   if (p.dim == 2 && 13ll * plane_of(p) >= (1ll << 30)) return "2D grid too large (at most 2^30/13 cells)";
@@ -232,7 +241,7 @@ Layout layout(const mrhweno_problem* P, int n) {
 /* host-side description of one launch group (instances sharing a kernel) */
 struct Group {
   int dim, nc, bp;
-  int gb;           /* instances with ghosts that hold a prescribed state */
+  int gb;           /* boundary-data kernel variant (gb_of) */
   int ch;           /* 2D characteristic-wise Step 1 */
   bool any_summ = false, any_lf = false;
   std::vector<int> insts;
@@ -337,6 +346,10 @@ static void fill_wconst(const mrhweno_problem& p, mr_wconst& W) {
 
 /* the static part of an instance descriptor (grid, boundary data, flux,
    variants, weights); buffers and the dynamic part are left zero */
+/* kernel variant for the instance's boundary data: 0 none, 1 ghosts that
+   hold a prescribed state, 2 also a step or the wall flux */
+static int gb_of(const mr_inst& I) { return (I.stepj > 0 || I.wallflux != 0) ? 2 : (I.pres != 0 ? 1 : 0); }
+
 static void fill_inst(const mrhweno_problem& p, mr_inst& I) {
   std::memset(&I, 0, sizeof I);
   I.dim = p.dim; I.nx = p.nx; I.ny = p.dim == 2 ? p.ny : 1; I.nc = ncomp_of(p);
@@ -361,6 +374,9 @@ static void fill_inst(const mrhweno_problem& p, mr_inst& I) {
   }
   I.bcx = fold[0] | (fold[1] << 2);
   I.bcy = fold[2] | (fold[3] << 2);
+  I.stepi = p.dim == 2 && p.step_j > 0 ? p.step_i : 0;
+  I.stepj = p.dim == 2 ? p.step_j : 0;
+  I.wallflux = p.wall_flux;
   I.tc = p.tc_mode; I.beta_on = p.beta_on; I.mod = p.modification; I.charwise = p.charwise;
   I.fhalo = kFHalo; I.shalo = kSHalo;
   I.fex = fex(p); I.fey = fey(p); I.sex = sex(p); I.sey = sey(p);
@@ -637,8 +653,8 @@ mrhweno_status mrhweno_create(const mrhweno_problem* probs, int n, void* const* 
     Group* gp = nullptr;
     const int ch = p.dim == 2 && p.charwise;
     for (auto& g : c->groups)
-      if (g.dim == p.dim && g.nc == nc && g.bp == p.beta_on && g.gb == (c->h[q].pres != 0) && g.ch == ch) gp = &g;
-    if (!gp) { c->groups.push_back(Group{p.dim, nc, p.beta_on, c->h[q].pres != 0, ch}); gp = &c->groups.back(); }
+      if (g.dim == p.dim && g.nc == nc && g.bp == p.beta_on && g.gb == gb_of(c->h[q]) && g.ch == ch) gp = &g;
+    if (!gp) { c->groups.push_back(Group{p.dim, nc, p.beta_on, gb_of(c->h[q]), ch}); gp = &c->groups.back(); }
     gp->insts.push_back(q);
     gp->any_summ |= needs_summ(p);
   }
@@ -977,18 +993,18 @@ static hipError_t probe_kernels(hipStream_t s, const mrhweno_problem& p, const m
   mr_tile2* t3 = const_cast<mr_tile2*>(d3);
   if ((e = mr_launch_reduce(s, d, t1, L.n_red, 0)) != hipSuccess) return e;
   if ((e = mr_launch_finalize(s, d + slot, 1, 1)) != hipSuccess) return e;
-  if ((e = mr_launch_summary(s, p.dim, p.beta_on, I.pres != 0, d, t1 + L.t_sum, L.n_sum, 3)) != hipSuccess) return e;
+  if ((e = mr_launch_summary(s, p.dim, p.beta_on, gb_of(I), d, t1 + L.t_sum, L.n_sum, 3)) != hipSuccess) return e;
   if ((e = mr_launch_flags(s, p.dim, d, t1 + L.t_flg, L.n_flg, 3)) != hipSuccess) return e;
   const int ch = p.dim == 2 && p.charwise;
-  if (L.kx2 && (e = mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? (ch ? 4 : 3) : 1, p.beta_on, I.pres != 0, d,
+  if (L.kx2 && (e = mr_launch_kxrcf2(s, ncomp_of(p) == 4 && !tvb(p) ? (ch ? 4 : 3) : 1, p.beta_on, gb_of(I), d,
                                      t3, (int)L.t3.size(), 3)) != hipSuccess)
     return e;
   const int nc = ncomp_of(p);
   if (kind == 0 && (e = mr_launch_values(s, p.dim, nc, p.beta_on, d, t1 + L.t_val, L.n_val, (double*)out)) != hipSuccess)
     return e;
   if (kind == 2) {
-    if (p.dim == 1) e = mr_launch_stage1(s, nc, p.beta_on, I.pres != 0, d, t1 + L.t_st, L.n_st, 3, 0);
-    else e = mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, ch, d, t2, (int)L.t2.size(), 3, 0);
+    if (p.dim == 1) e = mr_launch_stage1(s, nc, p.beta_on, gb_of(I), d, t1 + L.t_st, L.n_st, 3, 0);
+    else e = mr_launch_stage2(s, nc, p.beta_on, gb_of(I), ch, d, t2, (int)L.t2.size(), 3, 0);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -1048,7 +1064,7 @@ static mrhweno_status probe(mrhweno_ctx* c, int q, const void* U, void* out, voi
     MR_CHECK(c, mr_launch_fallback(s, c->d, c->band, c->cnt, 3, c->grid_fb, p.beta_on));
     const int nc = ncomp_of(p);
     if (kind == 0) MR_CHECK(c, mr_launch_values(s, p.dim, nc, p.beta_on, c->d, d1 + PL.t_val, PL.n_val, (double*)out));
-    if (kind == 2) MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, I.pres != 0, 0, c->d, d2, (int)PL.t2.size(), 3, 0));
+    if (kind == 2) MR_CHECK(c, mr_launch_stage2(s, nc, p.beta_on, gb_of(I), 0, c->d, d2, (int)PL.t2.size(), 3, 0));
   } else {
     MR_CHECK(c, probe_kernels(s, p, I, c->d, slot, PL, d1, d2, d3, kind, out));
   }

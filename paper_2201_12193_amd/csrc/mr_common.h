@@ -86,13 +86,52 @@ MR_INL bool mr_presc_any(const mr_inst& I, int i, int j, double t) {
 }
 
 /* whether any cell of columns x0 .. x0+w-1 and rows y0 .. y0+nr-1 can hold
-   prescribed data: a row outside [0, ny) with data on the bottom or top
-   side, or a column outside [0, nx) with data on the left or right side
+   prescribed data or read a cell of the step: a row outside [0, ny) with
+   data on the bottom or top side, a column outside [0, nx) with data on the
+   left or right side, or a block that reaches the step's rows and columns
    (uniform over a work group: the rows and columns of its strip) */
 MR_INL bool mr_presc_rows(const mr_inst& I, int x0, int w, int y0, int nr) {
-  if (!I.pres || nr <= 0) return false;
+  if (nr <= 0) return false;
+  if (I.stepj > 0 && y0 < I.stepj && x0 + w > I.stepi) return true;
+  if (!I.pres) return false;
   if ((I.pres & 12) && (y0 < 0 || y0 + nr > I.ny)) return true;
   return (I.pres & 3) && (x0 < 0 || x0 + w > I.nx);
+}
+
+/* cell (i, j) of the grid lies in the step */
+MR_INL bool mr_solid(const mr_inst& I, int i, int j) {
+  return I.stepj > 0 && i >= I.stepi && i < I.nx && j >= 0 && j < I.stepj;
+}
+
+/* A cell of the step read as a ghost is the mirror image of a fluid cell
+ * across the step's nearest face: across the vertical face x = stepi when
+ * the cell lies fewer columns into the step than rows below its top,
+ * across the top y = stepj in the opposite case, across both (through the
+ * corner) when the two depths are equal.  (*i, *j) become the fluid cell;
+ * *fx, *fy say which mirrors apply (each flips the moments mr_refl_flip
+ * names for its axis). */
+MR_INL void mr_step_mirror(const mr_inst& I, int* i, int* j, bool* fx, bool* fy) {
+  const int dx = *i - I.stepi, dy = I.stepj - 1 - *j;
+  *fx = dx <= dy;
+  *fy = dy <= dx;
+  if (*fx) *i = 2 * I.stepi - 1 - *i;
+  if (*fy) *j = 2 * I.stepj - 1 - *j;
+}
+
+/* moment m of component c of the cell (i, j) of the extended grid if,
+   after the domain's fold, it reads a cell of the step: the mirror image,
+   loaded from the state U (planes of I.plane); false otherwise */
+MR_INL bool mr_step_val(const mr_inst& I, const MR_GLB double* U, int c, int m, int i, int j, double* val) {
+  if (I.stepj <= 0) return false;
+  int kx = 0, ky = 0;
+  int ii = mr_fold(i, I.nx, I.bcx, &kx), jj = mr_fold(j, I.ny, I.bcy, &ky);
+  if (!mr_solid(I, ii, jj)) return false;
+  bool sx, sy;
+  mr_step_mirror(I, &ii, &jj, &sx, &sy);
+  double v = U[(long long)(c * 3 + m) * I.plane + (long long)jj * I.nx + ii];
+  v = ((((kx == 2) != sx) && mr_refl_flip(c, m, 0)) != (((ky == 2) != sy) && mr_refl_flip(c, m, 1))) ? -v : v;
+  *val = ((kx == 1 || ky == 1) && m > 0) ? 0.0 : v;
+  return true;
 }
 
 /* moment m of component c of a ghost cell with prescribed data (see
@@ -130,13 +169,18 @@ MR_INL bool mr_presc(const mr_inst& I, int c, int m, int i, int j, double t, dou
 }
 
 /* The x face f of row j (between cells (f-1, j) and (f, j)), or the y face
- * f of column i, is a reflective wall at time t: the side is reflective and
- * the ghost across the face holds no prescribed state. */
+ * f of column i, is a reflective wall at time t: a face of the step --
+ * continued through the ghost cells below the tunnel and beyond the exit,
+ * where the ghost field is the mirror image across it as well -- or the
+ * side is reflective and the ghost across the face holds no prescribed
+ * state. */
 MR_INL bool mr_wall_x(const mr_inst& I, int f, int j, double t) {
+  if (I.stepj > 0 && f == I.stepi && j < I.stepj) return true;   /* the step's vertical face (and below) */
   if (!mr_wall(f, I.nx, I.bcx)) return false;
   return !((I.pres >> (f == 0 ? 0 : 1)) & 1) || !mr_presc_any(I, f == 0 ? -1 : I.nx, j, t);
 }
 MR_INL bool mr_wall_y(const mr_inst& I, int i, int f, double t) {
+  if (I.stepj > 0 && f == I.stepj && i >= I.stepi) return true;   /* the step's top (and beyond the exit) */
   if (!mr_wall(f, I.ny, I.bcy)) return false;
   return !((I.pres >> (f == 0 ? 2 : 3)) & 1) || !mr_presc_any(I, i, f == 0 ? -1 : I.ny, t);
 }
@@ -156,10 +200,12 @@ struct mr_grid {
    prescribed data of an inflow side or front, rare, replace it last */
 MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
   int kx = 0, ky = 0;
-  const int ii = mr_fold(i, g.nx, g.bcx, &kx);
-  const int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &ky) : 0;
+  int ii = mr_fold(i, g.nx, g.bcx, &kx);
+  int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &ky) : 0;
+  bool sx = false, sy = false;   /* a cell of the step: its mirror image */
+  if (g.I && g.I->stepj > 0 && mr_solid(*g.I, ii, jj)) mr_step_mirror(*g.I, &ii, &jj, &sx, &sy);
   double v = g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
-  v = ((kx == 2 && mr_refl_flip(c, m, 0)) != (ky == 2 && mr_refl_flip(c, m, 1))) ? -v : v;
+  v = ((((kx == 2) != sx) && mr_refl_flip(c, m, 0)) != (((ky == 2) != sy) && mr_refl_flip(c, m, 1))) ? -v : v;
   v = ((kx == 1 || ky == 1) && m > 0) ? 0.0 : v;
   if (g.I && (kx | ky) && g.I->pres) {
     double pv;
@@ -426,6 +472,55 @@ template <int NC, int D>
 MR_INL void mr_numflux(const double* a, const double* b, double gam, double alpha, double* f) {
   if constexpr (NC == 1) f[0] = mr_lf(a[0], b[0], alpha);
   else mr_hllc<NC, D>(a, b, gam, f);
+}
+
+/* Flux through a wall face normal to direction D of the fluid trace u,
+ * the wall on side sgn (+1: towards +D): the Godunov flux of the
+ * mirror-image Riemann problem, whose star state is at rest -- mass and
+ * energy flux zero, normal momentum flux the star pressure p*.  With u_n
+ * the velocity into the wall, p* solves the shock relation
+ * (p* - p) sqrt(A / (p* + B)) = u_n (A = 2/((g+1) rho), B = (g-1)/(g+1) p)
+ * for u_n > 0, taken as the positive root q = p* - p of
+ * A q^2 - u_n^2 q - u_n^2 (p + B) = 0; the isentropic rarefaction
+ * p* = p (1 + (g-1) u_n/(2c))^(2g/(g-1)) for u_n < 0 (0 at vacuum);
+ * p* = p for u_n = 0. */
+template <int D>
+MR_INL void mr_wall_flux(const double* u, int sgn, double gam, double* f) {
+  const double p = mr_pressure<4>(u, gam);
+  const double un = sgn * (u[1 + D] / u[0]);
+  double ps = p;
+  if (un > 0.0) {
+    const double A = 2.0 / ((gam + 1.0) * u[0]), B = (gam - 1.0) / (gam + 1.0) * p;
+    ps = p + un * (un + sqrt(un * un + 4.0 * A * (p + B))) / (2.0 * A);
+  } else if (un < 0.0) {
+    const double c = sqrt(gam * p / u[0]);
+    const double base = 1.0 + 0.5 * (gam - 1.0) * un / c;
+    ps = base > 0.0 ? p * pow(base, 2.0 * gam / (gam - 1.0)) : 0.0;
+  }
+  f[0] = 0.0;
+  f[1] = 0.0;
+  f[2] = 0.0;
+  f[3] = 0.0;
+  f[1 + D] = ps;
+}
+
+/* numerical flux at a point of face f (D = 0: the x face f of row `other`;
+ * D = 1: the y face f of column `other`) from the traces a (low side) and
+ * b (high side): on a wall face of an instance with wallflux set, the wall
+ * flux of the fluid trace -- the fluid lies on the low side of the
+ * domain's high walls and of the step's vertical face, on the high side of
+ * the low walls and of the step's top -- else mr_numflux */
+template <int NC, int D, bool GB>
+MR_INL void mr_face_flux(const mr_inst& I, const double* a, const double* b, double gam, double alpha, int f,
+                         int other, double tb, double* out) {
+  if constexpr (GB && NC == 4) {
+    if (I.wallflux && (D == 0 ? mr_wall_x(I, f, other, tb) : mr_wall_y(I, other, f, tb))) {
+      const bool low = D == 0 ? f != 0 : f == I.ny;
+      mr_wall_flux<D>(low ? a : b, low ? 1 : -1, gam, out);
+      return;
+    }
+  }
+  mr_numflux<NC, D>(a, b, gam, alpha, out);
 }
 
 template <int NC, int D>

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
 #pragma clang fp contract(off)
   __shared__ double sh[2 * (MR_BLOCK / 64)];
   __shared__ unsigned long long s_base[MR_BLOCK];   /* data of the item (0: skipped) */
-  __shared__ int s_inst[MR_BLOCK], s_cnt[MR_BLOCK];
+  __shared__ int s_inst[MR_BLOCK], s_cnt[MR_BLOCK], s_start[MR_BLOCK];
   const int t0 = blockIdx.x * chunk, t1 = min(ntiles, t0 + chunk);
   int cur = -1;
   double ax = 0.0, ay = 0.0;
@@ -91,6 +91,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
       s_base[threadIdx.x] = U ? (unsigned long long)(U + tl.start) : 0ull;
       s_inst[threadIdx.x] = tl.inst;
       s_cnt[threadIdx.x] = tl.count;
+      s_start[threadIdx.x] = tl.start;
     }
     __syncthreads();
     for (int g0 = 0; g0 < nb; g0 += MR_RED_ITEMS) {
@@ -106,6 +107,10 @@ __global__ __launch_bounds__(MR_BLOCK) void k_reduce(mr_inst* insts, const mr_ti
         const unsigned long long base = s_base[t];
         if (!base || (int)threadIdx.x >= s_cnt[t]) continue;
         const mr_inst& I = insts[inst[q]];
+        if (I.stepj > 0) {   /* the step's cells carry no state */
+          const int cell = s_start[t] + (int)threadIdx.x;
+          if (mr_solid(I, cell % I.nx, cell / I.nx)) continue;
+        }
         const MR_GLB double* U = mr_gp((const double*)base) + threadIdx.x;
         use[q] = 1;
         const long long P = I.plane;

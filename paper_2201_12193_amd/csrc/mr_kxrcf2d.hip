@@ -159,7 +159,7 @@ MR_INL void kx_face_data_ch(const double (*mom)[3 * 4 * KX_XW], int s0, int s1, 
    all components; 1 for the TVB minmod test, which reads the indicator
    variable only and decides each cell from its own face averages).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
    of the extended flag range [-2, n+2)^2 (y0 >= -2). */
-template <int NK, bool BP, bool GB>
+template <int NK, bool BP, int GB>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, const mr_tile2* tiles, int ntiles, int stage) {
   mr_kt_fill();
   constexpr int NPL = 3 * NK;
@@ -222,7 +222,9 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
         for (int k = tid; k < NROW; k += MR_BLOCK) {
           const int pl = k / KX_XW;
           double v;
-          if (mr_presc(I, pl / 3, pl % 3, xs + k % KX_XW, r, tb, &v)) mom[kx_slot(r, KX_MR)][k] = v;
+          if (mr_presc(I, pl / 3, pl % 3, xs + k % KX_XW, r, tb, &v) ||
+              (GB == 2 && mr_step_val(I, U, pl / 3, pl % 3, xs + k % KX_XW, r, &v)))
+            mom[kx_slot(r, KX_MR)][k] = v;
         }
     };
     /* prologue: moment rows y0-2 .. y0+3 */
@@ -301,15 +303,17 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
   }
 }
 
-/* gb: some instance of the list has ghosts that hold a prescribed state */
+/* gb: 0 no per-side boundary data in the list, 1 ghosts that hold a
+   prescribed state, 2 also a step (NK = 3, 4) */
 extern "C" hipError_t mr_launch_kxrcf2(hipStream_t s, int nk, int bp, int gb, mr_inst* d, const mr_tile2* t, int nt,
                                        int stage) {
   if (nt <= 0) return hipSuccess;
   const dim3 G(nt), B(MR_BLOCK);
-#define MR_LK(NK_, BP_)                                                                   \
-  do {                                                                                    \
-    if (gb) hipLaunchKernelGGL((k2_kxrcf<NK_, BP_, true>), G, B, 0, s, d, t, nt, stage);  \
-    else hipLaunchKernelGGL((k2_kxrcf<NK_, BP_, false>), G, B, 0, s, d, t, nt, stage);    \
+#define MR_LK(NK_, BP_)                                                                                   \
+  do {                                                                                                    \
+    if (gb == 2 && NK_ > 1) hipLaunchKernelGGL((k2_kxrcf<NK_, BP_, 2>), G, B, 0, s, d, t, nt, stage);      \
+    else if (gb) hipLaunchKernelGGL((k2_kxrcf<NK_, BP_, 1>), G, B, 0, s, d, t, nt, stage);                \
+    else hipLaunchKernelGGL((k2_kxrcf<NK_, BP_, 0>), G, B, 0, s, d, t, nt, stage);                        \
   } while (0)
   if (nk == 1) { if (bp) MR_LK(1, true); else MR_LK(1, false); }
   else if (nk == 3) { if (bp) MR_LK(3, true); else MR_LK(3, false); }

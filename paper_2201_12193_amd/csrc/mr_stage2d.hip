@@ -111,7 +111,7 @@ MR_INL void mr2_stage_field(const mr2_lds<4>& sh, const int* ra, const int* rb, 
   mr_recon2d<BP>(u, v, w, W, val);
 }
 
-template <int NC, bool BP, bool GB, bool CH>
+template <int NC, bool BP, int GB, bool CH>
 __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, const mr_tile2* tiles, int ntiles, int mode) {
   mr_kt_fill();
   using S = mr2_lds<NC>;
@@ -308,7 +308,8 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
               const bool isA = pl < 2 * NC;
               const int c = isA ? pl / 2 : pl - 2 * NC, m = isA ? (pl % 2) * 2 : 1;
               double v;
-              if (mr_presc(I, c, m, xs0 + col, isA ? y + 3 : y + 2, tb, &v)) {
+              if (mr_presc(I, c, m, xs0 + col, isA ? y + 3 : y + 2, tb, &v) ||
+                  (GB == 2 && mr_step_val(I, g.U, c, m, xs0 + col, isA ? y + 3 : y + 2, &v))) {
                 if (isA) sh.mA[sa][pl][col] = v;
                 else sh.mB[sb][pl - 2 * NC][col] = v;
               }
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
           double a[4], fh[4];
 #pragma unroll
           for (int c = 0; c < 4; ++c) a[c] = VAL(3 + 4 * r, c, cs - 1);
-          mr_numflux<4, 0>(a, pts[0], gam, alpha, fh);
+          mr_face_flux<4, 0, GB == 2>(I, a, pts[0], gam, alpha, x, y, mr_stage_time(I, mode), fh);
 #pragma unroll
           for (int c = 0; c < 4; ++c) { XL0[c] += wr * fh[c]; XL1[c] += wr * er * fh[c]; }
         }
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
             a[c] = TOP(r, c, cs);
             b[c] = VAL(r, c, cs);
           }
-          mr_numflux<4, 1>(a, b, gam, alpha, gh);
+          mr_face_flux<4, 1, GB == 2>(I, a, b, gam, alpha, y, x, mr_stage_time(I, mode), gh);
 #pragma unroll
           for (int c = 0; c < 4; ++c) { YB0[c] += wr * gh[c]; YB1[c] += wr * er * gh[c]; }
         }
@@ -429,7 +430,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
               a[c] = VAL(3 + 4 * r, c, cs - 1);
               b[c] = VAL(4 * r, c, cs);
             }
-            mr_numflux<NC, 0>(a, b, gam, alpha, fh);
+            mr_face_flux<NC, 0, GB == 2>(I, a, b, gam, alpha, x, y, mr_stage_time(I, mode), fh);
 #pragma unroll
             for (int c = 0; c < NC; ++c) { XL0[c] += wr * fh[c]; XL1[c] += wr * er * fh[c]; }
           }
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
             a[c] = TOP(r, c, cs);
             b[c] = VAL(r, c, cs);
           }
-          mr_numflux<NC, 1>(a, b, gam, alpha, gh);
+          mr_face_flux<NC, 1, GB == 2>(I, a, b, gam, alpha, y, x, mr_stage_time(I, mode), gh);
 #pragma unroll
           for (int c = 0; c < NC; ++c) { YB0[c] += wr * gh[c]; YB1[c] += wr * er * gh[c]; }
         }
@@ -470,8 +471,9 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
           r0 = pU + dt * Lu; r1 = pV + dt * Lv; r2 = pW + dt * Lw;
           /* U^n after Step 2.2 (its first moments) for stages 2 and 3 */
           if (I.mod == 0) {
-            unm[(long long)(comp * 2 + 0) * P + cell] = pV;
-            unm[(long long)(comp * 2 + 1) * P + cell] = pW;
+            const bool sol = GB == 2 && mr_solid(I, x, yp);
+            unm[(long long)(comp * 2 + 0) * P + cell] = sol ? 0.0 : pV;
+            unm[(long long)(comp * 2 + 1) * P + cell] = sol ? 0.0 : pW;
           }
         } else {
           const double a = mode == 1 ? 0.75 : 1.0 / 3.0, b = mode == 1 ? 0.25 : 2.0 / 3.0;
@@ -480,6 +482,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
           r1 = a * vn + b * pV + b * dt * Lv;
           r2 = a * wn + b * pW + b * dt * Lw;
         }
+        if (GB == 2 && mr_solid(I, x, yp)) r0 = r1 = r2 = 0.0;   /* the step's cells carry no state */
         O[(long long)(comp * 3 + 0) * P + cell] = r0;
         O[(long long)(comp * 3 + 1) * P + cell] = r1;
         O[(long long)(comp * 3 + 2) * P + cell] = r2;
@@ -505,17 +508,19 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
 #undef FSM
 }
 
-/* gb: some instance of the list has ghosts that hold a prescribed state
-   (the variant without that code runs everything else); ch: the
+/* gb: 0 no instance of the list has per-side boundary data (the variant
+   without that code), 1 some have ghosts that hold a prescribed state, 2
+   some also have a step or the wall flux (Euler); ch: the
    characteristic-wise Step 1 (nc = 4) */
 extern "C" hipError_t mr_launch_stage2(hipStream_t s, int nc, int bp, int gb, int ch, mr_inst* d, const mr_tile2* t,
                                        int nt, int mode, int grid) {
   if (nt <= 0) return hipSuccess;
   const dim3 G(grid > 0 && grid < nt ? grid : nt), B(MR_BLOCK);
-#define MR_L2(NC_, BP_, CH_)                                                                  \
-  do {                                                                                        \
-    if (gb) hipLaunchKernelGGL((k2_stage<NC_, BP_, true, CH_>), G, B, 0, s, d, t, nt, mode);  \
-    else hipLaunchKernelGGL((k2_stage<NC_, BP_, false, CH_>), G, B, 0, s, d, t, nt, mode);    \
+#define MR_L2(NC_, BP_, CH_)                                                                           \
+  do {                                                                                                 \
+    if (gb == 2 && NC_ == 4) hipLaunchKernelGGL((k2_stage<NC_, BP_, 2, CH_>), G, B, 0, s, d, t, nt, mode); \
+    else if (gb) hipLaunchKernelGGL((k2_stage<NC_, BP_, 1, CH_>), G, B, 0, s, d, t, nt, mode);         \
+    else hipLaunchKernelGGL((k2_stage<NC_, BP_, 0, CH_>), G, B, 0, s, d, t, nt, mode);                 \
   } while (0)
   if (nc == 1) { if (bp) MR_L2(1, true, false); else MR_L2(1, false, false); }
   else if (nc == 4 && !ch) { if (bp) MR_L2(4, true, false); else MR_L2(4, false, false); }

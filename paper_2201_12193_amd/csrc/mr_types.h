@@ -30,6 +30,9 @@ struct mr_inst {
   int pres;         /* bit s: side s (0 left, 1 right, 2 bottom, 3 top) has
                        ghosts that hold a prescribed state                     */
   int skind[4];     /* side kinds: 1 transmissive, 2 reflective, 3 inflow      */
+  int stepi, stepj; /* 2D: a solid step of the cells i >= stepi, j < stepj
+                       (stepj = 0: none); read as ghosts, mirror images      */
+  int wallflux;     /* 1: exact mirror-problem flux on wall faces            */
   int tc;           /* 0 none, 1 KXRCF, 2 all cells, 3 learned, 4 TVB minmod    */
   int beta_on;      /* 0 = q_l, 1 = p_l                                        */
   int charwise;     /* 1D Euler: Step 1 on characteristic fields               */

@@ -81,6 +81,9 @@ class Problem:
     tvb_m: float = 0.0   # TVB constant M of the minmod indicator (TC_TVB)
     charwise: int = 0    # 1D Euler: Step 1 on characteristic fields (0: component-wise)
     sides: Optional[Tuple[Side, Side, Side, Side]] = None   # left, right, bottom, top (SIDES)
+    step_i: int = 0      # 2D Euler: a solid step of the cells i >= step_i, j < step_j
+    step_j: int = 0      # (Example 3.10's forward step); step_j = 0: none
+    wall_flux: int = 0   # 1: exact mirror-problem flux on wall faces (0: HLLC on the mirror state)
 
     @property
     def dx(self) -> float:
@@ -502,4 +505,30 @@ def double_mach_2d(ny: int = 400, tc_mode: int = TC_KXRCF, t_final: float = 0.2,
             U[:, 0, j, i] = post_a * a + pre_a * (1.0 - a)
             U[:, 1, j, i] = (post_a - pre_a) * mx
             U[:, 2, j, i] = (post_a - pre_a) * my
+    return prob, U
+
+
+def forward_step(ny: int = 200, tc_mode: int = TC_KXRCF, t_final: float = 4.0,
+                 modification: int = MOD_INTERNAL, wall_flux: int = 1, **kw):
+    """Example 3.10: a tunnel [0, 3] x [0, 1] of 3*ny x ny cells with a step
+    of height 0.2 from x = 0.6 to the exit (the cells i >= 0.6 ny,
+    j < 0.2 ny), filled at t = 0 with a right-going Mach 3 flow (gamma 1.4,
+    rho = 1.4, u = 3, p = 1, so c = 1).  Left: inflow of that state; right:
+    transmissive; the tunnel's top and bottom and the step are reflective
+    walls, with the exact mirror-problem flux on the wall faces by default
+    (wall_flux = 1: the printed HLLC on the mirror state lets a stream of
+    normal Mach 3 through the step's face).  The step's cells hold zeros.
+    Returns (problem, U)."""
+    if ny % 5:
+        raise ValueError("ny must be a multiple of 5 (step at 0.6, height 0.2)")
+    gamma = 1.4
+    state = tuple(float(z) for z in euler2d_cons(np.array(1.4), np.array(3.0), np.array(0.0), np.array(1.0), gamma))
+    sides = (Side(kind=INFLOW, state=state), Side(kind=TRANSMISSIVE), Side(kind=REFLECTIVE), Side(kind=REFLECTIVE))
+    prob = Problem(dim=2, nx=3 * ny, ny=ny, x0=0.0, x1=3.0, y0=0.0, y1=1.0, system=EULER,
+                   bc_x=SIDES, bc_y=REFLECTIVE, gamma=gamma, t_final=t_final, tc_mode=tc_mode,
+                   modification=modification, sides=sides, step_i=3 * ny // 5, step_j=ny // 5,
+                   wall_flux=wall_flux, **kw)
+    U = np.zeros(prob.shape())
+    U[:, 0] = np.array(state)[:, None, None]
+    U[:, :, :prob.step_j, prob.step_i:] = 0.0
     return prob, U

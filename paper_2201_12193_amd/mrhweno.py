@@ -48,7 +48,8 @@ class MrProblem(C.Structure):
                 ("gamma_gas", C.c_double), ("cfl", C.c_double), ("t_final", C.c_double),
                 ("gamma_bar", C.c_double * 4), ("eps", C.c_double),
                 ("tc_mode", C.c_int), ("beta_on", C.c_int), ("modification", C.c_int),
-                ("tvb_m", C.c_double), ("charwise", C.c_int), ("side", MrSide * 4)]
+                ("tvb_m", C.c_double), ("charwise", C.c_int), ("side", MrSide * 4),
+                ("step_i", C.c_int), ("step_j", C.c_int), ("wall_flux", C.c_int)]
 
 
 def to_c(p: Problem) -> MrProblem:
@@ -63,6 +64,7 @@ def to_c(p: Problem) -> MrProblem:
     c.eps, c.tc_mode, c.beta_on, c.modification = p.eps, p.tc_mode, p.beta_on, p.modification
     c.tvb_m = p.tvb_m
     c.charwise = p.charwise
+    c.step_i, c.step_j, c.wall_flux = p.step_i, p.step_j, p.wall_flux
     if p.sides is not None:
         for k, sd in enumerate(p.sides):
             if sd is None:

@@ -49,9 +49,22 @@ def test_workspace_bytes_validates_problems():
                        + dmr.sides[3:]),
            dmr.replace(tc_mode=I.TC_LEARNED),                           # no per-side data with it
            I.Problem(dim=1, nx=64, system=I.BURGERS, bc_x=I.SIDES,
-                     sides=(I.Side(kind=I.REFLECTIVE), I.Side(), None, None))]
+                     sides=(I.Side(kind=I.REFLECTIVE), I.Side(), None, None)),
+           I.Problem(dim=1, nx=64, step_i=8, step_j=4),                    # a step is 2D Euler
+           good.replace(system=I.BURGERS, step_i=20, step_j=8),
+           good.replace(step_i=20, step_j=24),                             # step_j > step_i
+           good.replace(step_i=40, step_j=33),                             # mirror rows leave the grid
+           good.replace(step_i=64, step_j=8),                              # step_i < nx
+           good.replace(step_i=0, step_j=8), good.replace(step_i=20, step_j=-2),
+           good.replace(step_i=20, step_j=8, tc_mode=I.TC_TVB),
+           good.replace(step_i=20, step_j=8, tc_mode=I.TC_LEARNED),
+           good.replace(wall_flux=2), I.Problem(dim=1, nx=64, wall_flux=1),
+           good.replace(system=I.BURGERS, wall_flux=1)]
     assert M.workspace_bytes([dmr]) > 0
     assert M.workspace_bytes([good.replace(charwise=1)]) > 0                  # 2D Euler, KXRCF
+    step, _ = I.forward_step(ny=20)
+    assert M.workspace_bytes([step]) > 0 and M.workspace_bytes([step.replace(charwise=1, tc_mode=I.TC_ALL)]) > 0
+    assert M.workspace_bytes([good.replace(step_i=32, step_j=32)]) > 0       # step_j = step_i, 2 step_j = ny
     for b in bad:
         assert M.workspace_bytes([b]) == 0, b
     assert M.workspace_bytes([good, bad[0]]) == 0
