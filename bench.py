@@ -67,12 +67,13 @@ def parse():
                     help="learned-indicator uncertainty band (KXRCF inside)")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--workload", default="quadrants2d",
-                    choices=("quadrants2d", "batched", "riemann1d", "burgers1d", "dmr2d"),
+                    choices=("quadrants2d", "batched", "riemann1d", "burgers1d", "dmr2d", "fstep2d"),
                     help="quadrants2d: the benchmark above; batched, riemann1d, burgers1d time the "
                          "batched and 1D configurations (256 instances of uneven sizes in one launch "
                          "per kernel class; 1D Euler N = 4096; 1D Burgers N = 200) with every "
                          "instance kept advancing; dmr2d times the whole double Mach reflection "
-                         "(Example 3.9, 1600 x 400) to T = 0.2")
+                         "(Example 3.9, 1600 x 400) to T = 0.2, fstep2d the whole forward step "
+                         "(Example 3.10, 600 x 200, characteristic-wise) to T = 4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched configuration's throughput (extra key of the default run)")
@@ -328,14 +329,25 @@ def other_workload(args):
     print(json.dumps(out), flush=True)
 
 
-def dmr_workload(args):
-    """The double Mach reflection of Example 3.9 at 1600 x 400 (HWENO6-M5-I,
-    CFL 0.6, modification internal to L), the whole run to T = 0.2 timed."""
+def whole_run_workload(args):
+    """A whole run of one of the paper's 2D examples timed from t = 0 to its
+    final time: the double Mach reflection of Example 3.9 at 1600 x 400
+    (HWENO6-M5-I, modification internal to L) or the forward step of
+    Example 3.10 at 600 x 200 (HWENO6-M5-I characteristic-wise, the exact
+    wall flux; the component-wise scheme breaks down at the step's corner).
+    CFL 0.6; the cell count is the whole grid, which the kernels sweep."""
     import torch
     from paper_2201_12193_amd import inputs as I
     from paper_2201_12193_amd.mrhweno import Solver
     from paper_2201_12193_amd import autotune
-    prob, U0 = I.double_mach_2d(ny=400)
+    if args.workload == "dmr2d":
+        prob, U0 = I.double_mach_2d(ny=400)
+        desc = "double Mach reflection (Example 3.9), 1600 x 400, HLLC, KXRCF (M5-I), CFL 0.6, to T = 0.2"
+    else:
+        prob, U0 = I.forward_step(ny=200)
+        prob = prob.replace(charwise=1)
+        desc = ("forward step (Example 3.10), 600 x 200, HLLC, KXRCF (M5-I), characteristic-wise, "
+                "exact wall flux, CFL 0.6, to T = 4")
     Ut = torch.from_numpy(U0).cuda()
     s = Solver([prob], [Ut])
     shape = autotune.tune(s, use_cache=False, reps=3)
@@ -357,9 +369,9 @@ def dmr_workload(args):
            "unit": "cell-updates/s", "n_gpus": 1, "steps": steps[0], "warmup": args.warmup,
            "ms_per_step": wall / max(steps[0], 1) * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "double Mach reflection (Example 3.9), 1600 x 400, HLLC, KXRCF (M5-I), "
-                                  "CFL 0.6, to T = 0.2", "cells": prob.ncell, "t_reached": t[0],
-                      "status": status, "rho_max": float(rho.max().item()),
+           "config": {"workload": desc, "cells": prob.ncell,
+                      "fluid_cells": prob.ncell - (prob.nx - prob.step_i) * prob.step_j if prob.step_j else prob.ncell,
+                      "t_reached": t[0], "status": status, "rho_max": float(rho.max().item()),
                       "launch": {"rows_per_strip": shape[0], "grid": shape[1], "kxrcf_rows": shape.kx_rows,
                                  "chosen_by": "autotuner"}}}
     s.close()
@@ -372,8 +384,8 @@ def main():
         print(f"bench.py: the library runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU domain decomposition is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
-    if args.workload == "dmr2d":
-        return dmr_workload(args)
+    if args.workload in ("dmr2d", "fstep2d"):
+        return whole_run_workload(args)
     if args.workload != "quadrants2d":
         return other_workload(args)
     import torch

@@ -15,7 +15,7 @@ from typing import NamedTuple, Optional
 
 CACHE = os.path.join(os.path.expanduser(os.environ.get("MRHWENO_CACHE_DIR", "~/.cache/mrhweno")),
                      "autotune.json")
-ROWS = (16, 24, 32, 40, 48, 56, 64, 72, 96)
+ROWS = (8, 16, 24, 32, 40, 48, 56, 64, 72, 96)
 KX_ROWS = (0, 8, 16, 24, 32, 46, 64, 96, 140)   # 0: the height chosen per problem
 
 

@@ -89,10 +89,12 @@ MR_INL bool mr_presc_any(const mr_inst& I, int i, int j, double t) {
    prescribed data or read a cell of the step: a row outside [0, ny) with
    data on the bottom or top side, a column outside [0, nx) with data on the
    left or right side, or a block that reaches the step's rows and columns
-   (uniform over a work group: the rows and columns of its strip) */
+   (uniform over a work group: the rows and columns of its strip; STEP =
+   false: kernel variants for instances without a step) */
+template <bool STEP = true>
 MR_INL bool mr_presc_rows(const mr_inst& I, int x0, int w, int y0, int nr) {
   if (nr <= 0) return false;
-  if (I.stepj > 0 && y0 < I.stepj && x0 + w > I.stepi) return true;
+  if (STEP && I.stepj > 0 && y0 < I.stepj && x0 + w > I.stepi) return true;
   if (!I.pres) return false;
   if ((I.pres & 12) && (y0 < 0 || y0 + nr > I.ny)) return true;
   return (I.pres & 3) && (x0 < 0 || x0 + w > I.nx);
@@ -173,14 +175,16 @@ MR_INL bool mr_presc(const mr_inst& I, int c, int m, int i, int j, double t, dou
  * continued through the ghost cells below the tunnel and beyond the exit,
  * where the ghost field is the mirror image across it as well -- or the
  * side is reflective and the ghost across the face holds no prescribed
- * state. */
+ * state.  STEP = false: kernel variants for instances without a step. */
+template <bool STEP = true>
 MR_INL bool mr_wall_x(const mr_inst& I, int f, int j, double t) {
-  if (I.stepj > 0 && f == I.stepi && j < I.stepj) return true;   /* the step's vertical face (and below) */
+  if (STEP && I.stepj > 0 && f == I.stepi && j < I.stepj) return true;   /* the step's vertical face (and below) */
   if (!mr_wall(f, I.nx, I.bcx)) return false;
   return !((I.pres >> (f == 0 ? 0 : 1)) & 1) || !mr_presc_any(I, f == 0 ? -1 : I.nx, j, t);
 }
+template <bool STEP = true>
 MR_INL bool mr_wall_y(const mr_inst& I, int i, int f, double t) {
-  if (I.stepj > 0 && f == I.stepj && i >= I.stepi) return true;   /* the step's top (and beyond the exit) */
+  if (STEP && I.stepj > 0 && f == I.stepj && i >= I.stepi) return true;   /* the step's top (and beyond the exit) */
   if (!mr_wall(f, I.ny, I.bcy)) return false;
   return !((I.pres >> (f == 0 ? 2 : 3)) & 1) || !mr_presc_any(I, i, f == 0 ? -1 : I.ny, t);
 }
@@ -198,12 +202,13 @@ struct mr_grid {
    cell is always loaded (it lies in the grid) and the ghost rules applied
    to the value, so that a run of these loads issues without branches; the
    prescribed data of an inflow side or front, rare, replace it last */
+template <bool STEP = true>
 MR_INL double mr_ld(const mr_grid& g, int c, int m, int i, int j) {
   int kx = 0, ky = 0;
   int ii = mr_fold(i, g.nx, g.bcx, &kx);
   int jj = (g.nm == 3) ? mr_fold(j, g.ny, g.bcy, &ky) : 0;
   bool sx = false, sy = false;   /* a cell of the step: its mirror image */
-  if (g.I && g.I->stepj > 0 && mr_solid(*g.I, ii, jj)) mr_step_mirror(*g.I, &ii, &jj, &sx, &sy);
+  if (STEP && g.I && g.I->stepj > 0 && mr_solid(*g.I, ii, jj)) mr_step_mirror(*g.I, &ii, &jj, &sx, &sy);
   double v = g.U[(long long)(c * g.nm + m) * g.P + (long long)jj * g.nx + ii];
   v = ((((kx == 2) != sx) && mr_refl_flip(c, m, 0)) != (((ky == 2) != sy) && mr_refl_flip(c, m, 1))) ? -v : v;
   v = ((kx == 1 || ky == 1) && m > 0) ? 0.0 : v;

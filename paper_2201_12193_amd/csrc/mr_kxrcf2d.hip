@@ -237,7 +237,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
       store(y, a, za);
       store(y + 1, b, zb);
     }
-    if (GB && mr_presc_rows(I, xs, KX_XW, tl.y0 - 2, 6)) prescribe(tl.y0 - 2, 6);
+    if (GB && mr_presc_rows<GB == 2>(I, xs, KX_XW, tl.y0 - 2, 6)) prescribe(tl.y0 - 2, 6);
     __syncthreads();
     for (int s = 0; 4 * s <= tl.rows + 1; ++s) {
       const int r0 = tl.y0 - 1 + 4 * s;    /* rows r0 .. r0+3 are reconstructed */
@@ -277,13 +277,13 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
         } else {
           double J = 0.0, len = 0.0;
           const double vl = 0.5 * (fd[a][4][cx] + fd[a][5][cx - 1]);
-          if (vl > 0.0 && !(GB ? mr_wall_x(I, x, rf, tb) : mr_wall(x, I.nx, I.bcx))) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
+          if (vl > 0.0 && !(GB ? mr_wall_x<GB == 2>(I, x, rf, tb) : mr_wall(x, I.nx, I.bcx))) { J += I.dy * (fd[a][0][cx] - fd[a][1][cx - 1]); len += I.dy; }
           const double vr = 0.5 * (fd[a][5][cx] + fd[a][4][cx + 1]);
-          if (-vr > 0.0 && !(GB ? mr_wall_x(I, x + 1, rf, tb) : mr_wall(x + 1, I.nx, I.bcx))) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
+          if (-vr > 0.0 && !(GB ? mr_wall_x<GB == 2>(I, x + 1, rf, tb) : mr_wall(x + 1, I.nx, I.bcx))) { J += I.dy * (fd[a][1][cx] - fd[a][0][cx + 1]); len += I.dy; }
           const double vb = 0.5 * (fd[a][6][cx] + fd[b][7][cx]);
-          if (vb > 0.0 && !(GB ? mr_wall_y(I, x, rf, tb) : mr_wall(rf, I.ny, I.bcy))) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
+          if (vb > 0.0 && !(GB ? mr_wall_y<GB == 2>(I, x, rf, tb) : mr_wall(rf, I.ny, I.bcy))) { J += I.dx * (fd[a][2][cx] - fd[b][3][cx]); len += I.dx; }
           const double vt = 0.5 * (fd[a][7][cx] + fd[u][6][cx]);
-          if (-vt > 0.0 && !(GB ? mr_wall_y(I, x, rf + 1, tb) : mr_wall(rf + 1, I.ny, I.bcy))) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
+          if (-vt > 0.0 && !(GB ? mr_wall_y<GB == 2>(I, x, rf + 1, tb) : mr_wall(rf + 1, I.ny, I.bcy))) { J += I.dx * (fd[a][3][cx] - fd[u][2][cx]); len += I.dx; }
           const double num = fabs(J);
           const double den = I.dx * I.dx * len * fd[a][8][cx];
           fl[(long long)(rf + I.fhalo) * I.fex + (x + I.fhalo)] = (unsigned char)(num > den);
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, cons
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (r0 + 5 + k <= ylast + 1) store(r0 + 5 + k, v[k], z[k]);
-      if (GB && mr_presc_rows(I, xs, KX_XW, r0 + 5, min(4, ylast - r0 - 3))) prescribe(r0 + 5, min(4, ylast - r0 - 3));
+      if (GB && mr_presc_rows<GB == 2>(I, xs, KX_XW, r0 + 5, min(4, ylast - r0 - 3))) prescribe(r0 + 5, min(4, ylast - r0 - 3));
       __syncthreads();
     }
   }

@@ -59,11 +59,11 @@ MR_INL int mr_mod5(int y) { return ((y % 5) + 5) % 5; }
 
 /* staged element e of a row step at row y (A planes at row y+1, B planes
    at row y): plane pl < 2 NC is A plane pl, else B plane pl - 2 NC */
-template <int NC, int XW>
+template <int NC, int XW, bool STEP>
 MR_INL double mr2_stage_ld(const mr_grid& g, int e, int xs0, int y) {
   const int pl = e / XW, col = e % XW;
-  if (pl < 2 * NC) return mr_ld(g, pl / 2, (pl % 2) * 2, xs0 + col, y + 1);
-  return mr_ld(g, pl - 2 * NC, 1, xs0 + col, y);
+  if (pl < 2 * NC) return mr_ld<STEP>(g, pl / 2, (pl % 2) * 2, xs0 + col, y + 1);
+  return mr_ld<STEP>(g, pl - 2 * NC, 1, xs0 + col, y);
 }
 
 /* Characteristic-wise Step 1 (see mr_char2): field k of direction D of the
@@ -164,10 +164,10 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
     /* ---- prologue: A rows y0-3 .. y0+1, B and flag rows y0-2 .. y0 ---- */
     for (int r = tl.y0 - 3; r <= tl.y0 - 2; ++r)
       for (int e = tid; e < 2 * NC * XW; e += MR_BLOCK)
-        sh.mA[mr_mod5(r)][e / XW][e % XW] = mr_ld(g, (e / XW) / 2, ((e / XW) % 2) * 2, xs0 + e % XW, r);
+        sh.mA[mr_mod5(r)][e / XW][e % XW] = mr_ld<GB == 2>(g, (e / XW) / 2, ((e / XW) % 2) * 2, xs0 + e % XW, r);
     for (int r = tl.y0 - 2; r <= tl.y0; ++r) {
       for (int e = tid; e < NP * XW; e += MR_BLOCK) {
-        const double v = mr2_stage_ld<NC, XW>(g, e, xs0, r);
+        const double v = mr2_stage_ld<NC, XW, GB == 2>(g, e, xs0, r);
         if (e / XW < 2 * NC) sh.mA[mr_mod5(r + 1)][e / XW][e % XW] = v;
         else sh.mB[mr_mod3(r)][e / XW - 2 * NC][e % XW] = v;
       }
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, cons
           }
         }
         if (tid < XW) sh.flg[sb][tid] = pref;
-        if (GB && mr_presc_rows(I, xs0, XW, y + 2, 2)) {
+        if (GB && mr_presc_rows<GB == 2>(I, xs0, XW, y + 2, 2)) {
           /* ghosts that hold prescribed data */
           const double tb = mr_stage_time(I, mode);
 #pragma unroll 1
