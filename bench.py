@@ -212,7 +212,7 @@ def learned_compare(prob, U0, Uk, T, weights, band, steps):
     U = torch.from_numpy(U0).cuda()
     s = Solver([pl], [U])
     s.set_indicator(weights, *band)
-    judge = Solver([prob], [torch.from_numpy(U0).cuda()])
+    kx_ref = Solver([prob], [torch.from_numpy(U0).cuda()])
     fn = tp = fp = nband = ncell = 0
     snaps = []
     every = max(steps // 5, 1)
@@ -223,7 +223,7 @@ def learned_compare(prob, U0, Uk, T, weights, band, steps):
         s.step(k - done)
         done = k
         dec, fl = s.indicator(0, U)
-        fk, _ = judge.flag(0, U)
+        fk, _ = kx_ref.flag(0, U)
         dec, fl, fk = dec.cpu().numpy(), fl.cpu().numpy().astype(bool), fk.cpu().numpy().astype(bool)
         a, b, c = int((fk & ~fl).sum()), int((fk & fl).sum()), int((~fk & fl).sum())
         fn, tp, fp = fn + a, tp + b, fp + c
@@ -237,7 +237,7 @@ def learned_compare(prob, U0, Uk, T, weights, band, steps):
         done += 10
         t, _, _ = s.sync()
     s.close()
-    judge.close()
+    kx_ref.close()
     a = U.cpu().numpy()
     b = Uk.cpu().numpy()
     l1 = [float(np.abs(a[c, 0] - b[c, 0]).sum() / np.abs(b[c, 0]).sum()) for c in range(prob.ncomp)]

@@ -367,20 +367,20 @@ def evaluate_run(P: np.ndarray, seed: int, n: int, steps: int, every: int, lo: f
     U = torch.from_numpy(U0).cuda()
     s = Solver([prob.replace(tc_mode=I.TC_LEARNED, t_final=float("inf"))], [U])
     s.set_indicator(torch.from_numpy(P).cuda().to(torch.bfloat16), lo, hi)
-    judge = Solver([prob], [torch.from_numpy(U0).cuda()])
+    kx_ref = Solver([prob], [torch.from_numpy(U0).cuda()])
     out, done = [], 0
     for k in snapshot_steps(steps, every):
         if k > done:
             s.step(k - done)
             done = k
         dec, fl = s.indicator(0, U)
-        fk, _ = judge.flag(0, U)
+        fk, _ = kx_ref.flag(0, U)
         dec, fl, fk = dec.cpu().numpy(), fl.cpu().numpy().astype(bool), fk.cpu().numpy().astype(bool)
         a, b = int((fk & ~fl).sum()), int((fk & fl).sum())
         out.append({"step": k, "kxrcf_flags": a + b, "false_negative_rate": a / max(a + b, 1),
                     "band_fraction": float((dec == 2).mean())})
     s.close()
-    judge.close()
+    kx_ref.close()
     return out
 
 

@@ -69,7 +69,7 @@ def test_trained_indicator_gain_over_kxrcf():
     Ul = _t(U0)
     s = Solver([prob.replace(tc_mode=I.TC_LEARNED, t_final=T)], [Ul])
     s.set_indicator(W, *DEFAULT_BAND)
-    judge = Solver([prob], [_t(U0)])
+    kx_ref = Solver([prob], [_t(U0)])
     nband = ncell = 0
     rates = []
     done = 0
@@ -77,7 +77,7 @@ def test_trained_indicator_gain_over_kxrcf():
         s.step(k - done)
         done = k
         dec, fl = s.indicator(0, Ul)
-        fk, _ = judge.flag(0, Ul)
+        fk, _ = kx_ref.flag(0, Ul)
         dec = dec.cpu().numpy()
         fl, fk = fl.cpu().numpy().astype(bool), fk.cpu().numpy().astype(bool)
         fn, tp = int((fk & ~fl).sum()), int((fk & fl).sum())
@@ -92,7 +92,7 @@ def test_trained_indicator_gain_over_kxrcf():
         s.step(5)          # steps past the final time do nothing
         t, _, st = s.sync()
     s.close()
-    judge.close()
+    kx_ref.close()
     assert st == 0 and t[0] == T
     a, b = Ul.cpu().numpy(), Uk.cpu().numpy()
     l1 = [float(np.abs(a[c, 0] - b[c, 0]).sum() / np.abs(b[c, 0]).sum()) for c in range(prob.ncomp)]
