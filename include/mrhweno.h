@@ -140,8 +140,9 @@ typedef enum { MRHWENO_MOD_PERSIST = 0, MRHWENO_MOD_INTERNAL = 1, MRHWENO_MOD_ST
 /* A problem posed as the paper poses it (Secs. 2.1, 2.2, 3). */
 typedef struct {
   int dim;                 /* 1 or 2                                              */
-  int nx, ny;              /* cells (ny ignored in 1D); each >= 8; 2D: nx*ny
-                              below 2^30/13                                       */
+  int nx, ny;              /* cells (ny ignored in 1D); each >= 8; 1D: nx below
+                              2^30; 2D: nx*ny below 2^30/13 (82,595,524 cells,
+                              e.g. 9088 x 9088); larger grids are rejected     */
   double x0, x1, y0, y1;   /* domain; 2D requires square cells (dx == dy)        */
   int bc_x, bc_y;          /* mrhweno_bc                                         */
   int flux;                /* mrhweno_flux; ncomp = 1 (Burgers), 3 (1D Euler),

@@ -168,6 +168,9 @@ std::string validate(const mrhweno_problem& p) {
     if (p.tc_mode != MRHWENO_TC_NONE && p.tc_mode != MRHWENO_TC_KXRCF && p.tc_mode != MRHWENO_TC_ALL)
       return "a step takes the KXRCF, all-cells or no troubled-cell mode";
   }
+  /* 1D: cell, summary and flag indices (the grid plus its halos, a block
+     of threads past the last cell) stay in 32 bits */
+  if (p.dim == 1 && p.nx >= (1 << 30)) return "1D grid too large (at most 2^30 - 1 cells)";
   if (plane_of(p) > (1ll << 31) - 1) return "grid too large";
   /* the 2D stage kernel addresses a moment plane and row as a 30-bit offset */
   if (p.dim == 2 && 13ll * plane_of(p) >= (1ll << 30)) return "2D grid too large (at most 2^30/13 cells)";

@@ -397,6 +397,45 @@ def euler_quadrants_2d(seed: int, n: int = 2048, nq: int = 4, **kw):
     return prob, U, {"rho": rho, "p": p, "u": u, "v": v, "modes": modes}
 
 
+def contact_wave_2d(seed: int, nx: int, ny: int, amp: float = 0.2, jump: float = 0.5, **kw):
+    """2D Euler (gamma 1.4), periodic [0, nx/ny] x [0, 1]: a density field
+    rho = 1 + amp sin(2 pi (x + phx)) sin(2 pi (y + phy)) + jump [x > X/2]
+    carried by a constant velocity (u, v) ~ U(-0.5, 0.5)^2 at constant
+    pressure p ~ U(0.8, 1.2), phases from the seed (a contact discontinuity
+    on a cell face for even nx, smooth elsewhere).  Its moments are separable
+    products of 1D cell moments (Gauss quadrature per column and row), so a
+    grid of tens of millions of cells takes seconds: the generator of the
+    largest grids."""
+    rng = np.random.default_rng(seed)
+    gamma = 1.4
+    phx, phy = rng.uniform(0.0, 1.0, 2)
+    u0, v0 = rng.uniform(-0.5, 0.5, 2)
+    p0 = rng.uniform(0.8, 1.2)
+    prob = Problem(dim=2, nx=nx, ny=ny, x0=0.0, x1=nx / ny, y0=0.0, y1=1.0, system=EULER, gamma=gamma,
+                   tc_mode=kw.pop("tc_mode", TC_KXRCF), **kw)
+    xs, ws = _gauss(8)
+
+    def moments_1d(n, d, ph):
+        c = (np.arange(n) + 0.5) * d
+        s = np.sin(2.0 * math.pi * (c[:, None] + xs[None, :] * d + ph))
+        return (s * ws).sum(-1), (s * ws * xs).sum(-1)   # average, first moment
+    ax, mx = moments_1d(nx, prob.dx, phx)
+    ay, my = moments_1d(ny, prob.dy, phy)
+    hx = ((np.arange(nx) + 0.5) * prob.dx > 0.5 * (nx / ny)).astype(np.float64)
+    # moments of rho: average, x moment, y moment
+    r = [1.0 + amp * np.multiply.outer(ay, ax) + jump * hx[None, :],
+         amp * np.multiply.outer(ay, mx), amp * np.multiply.outer(my, ax)]
+    U = np.empty(prob.shape())
+    ke = 0.5 * (u0 * u0 + v0 * v0)
+    for m in range(3):
+        U[0, m] = r[m]
+        np.multiply(r[m], u0, out=U[1, m])
+        np.multiply(r[m], v0, out=U[2, m])
+        np.multiply(r[m], ke, out=U[3, m])
+    U[3, 0] += p0 / (gamma - 1.0)
+    return prob, U, {"u": u0, "v": v0, "p": p0}
+
+
 def batched_instances(seed: int, n1d: int = 192, n2d: int = 64,
                       n1_range=(128, 16384), n2_range=(64, 1024)):
     """Batched workload: n1d 1D Euler Riemann instances with N log-uniform in
