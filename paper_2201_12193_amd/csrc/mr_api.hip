@@ -22,6 +22,7 @@ hipError_t mr_launch_finalize(hipStream_t, mr_inst*, int, int);
 hipError_t mr_launch_summary(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_flags(hipStream_t, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_stage1(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, int, int);
+hipError_t mr_launch_fused1(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, int);
 hipError_t mr_launch_stage2(hipStream_t, int, int, int, int, mr_inst*, const mr_tile2*, int, int, int);
 hipError_t mr_launch_kxrcf2(hipStream_t, int, int, int, mr_inst*, const mr_tile2*, int, int);
 hipError_t mr_launch_values(hipStream_t, int, int, int, mr_inst*, const mr_tile1*, int, double*);
@@ -41,6 +42,7 @@ hipError_t mr_mlp_adam(hipStream_t, void*, void*, const void*, void*, void*, int
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kFused1 = kBlock - 6;   /* cells of a tile of the step's 1D kernel (three ring cells each side) */
 constexpr int kFHalo = 2;   /* flags: final values of cells -1..n need flags -2..n+1 */
 constexpr int kSHalo = 3;   /* summaries: flags of cells -2..n+1 need summaries -3..n+2 */
 constexpr int kMinRows = 8; /* smallest 2D strip height the work lists are sized for */
@@ -199,7 +201,7 @@ Layout layout(const mrhweno_problem* P, int n) {
     const auto& p = P[q];
     size_t a = ceil_div(plane_of(p), kBlock) + ceil_div((long long)sex(p) * sey(p), kBlock) +
                ceil_div((long long)fex(p) * fey(p), kBlock) + ceil_div(plane_of(p), kBlock);
-    if (p.dim == 1) a += ceil_div(p.nx, kBlock - 2);
+    if (p.dim == 1) a += ceil_div(p.nx, kFused1);
     else t2 += (size_t)ceil_div(p.nx, strip_cells(p) - 2) * ceil_div(p.ny, kMinRows) + kx_tiles(p, kKxMinRows);
     t1 += a;
     tmax = std::max(tmax, a + learn_tiles(p) + kx_tiles(p) +
@@ -418,19 +420,19 @@ static void build_lists(mrhweno_ctx* c) {
   c->n_reduce = (int)c->h_t1.size();
   for (auto& g : c->groups) {
     g.t_summ = (int)c->h_t1.size();
-    for (int q : g.insts)
-      if (needs_summ(c->probs[q])) add_cells(c->h_t1, q, (long long)sex(c->probs[q]) * sey(c->probs[q]));
+    for (int q : g.insts)   /* 1D Step 2.1 runs inside the step's stage kernel (k1_fused) */
+      if (g.dim == 2 && needs_summ(c->probs[q])) add_cells(c->h_t1, q, (long long)sex(c->probs[q]) * sey(c->probs[q]));
     g.n_summ = (int)c->h_t1.size() - g.t_summ;
     g.t_flag = (int)c->h_t1.size();
     for (int q : g.insts)   /* 2D KXRCF and TVB flags come from the fused kernel */
-      if (!learned(c->probs[q]) && !(g.dim == 2 && indicator_pass(c->probs[q])))
+      if (g.dim == 2 && !learned(c->probs[q]) && !indicator_pass(c->probs[q]))
         add_cells(c->h_t1, q, (long long)fex(c->probs[q]) * fey(c->probs[q]));
     g.n_flag = (int)c->h_t1.size() - g.t_flag;
     g.t_st1 = (int)c->h_t1.size();
     if (g.dim == 1)
       for (int q : g.insts)
-        for (int s = 0; s < c->probs[q].nx; s += kBlock - 2)
-          c->h_t1.push_back(mr_tile1{q, s, std::min(kBlock - 2, c->probs[q].nx - s), 0});
+        for (int s = 0; s < c->probs[q].nx; s += kFused1)
+          c->h_t1.push_back(mr_tile1{q, s, std::min(kFused1, c->probs[q].nx - s), 0});
     g.n_st1 = (int)c->h_t1.size() - g.t_st1;
     g.t_st2 = (int)c->h_t2.size();
     if (g.dim == 2) {
@@ -542,7 +544,7 @@ static hipError_t enqueue_step(mrhweno_ctx* c, mr_prof* P = nullptr) {
       return e;
     if ((e = mark(c, P, 2)) != hipSuccess) return e;
     for (auto& g : c->groups) {
-      if (g.dim == 1) e = mr_launch_stage1(s, g.nc, g.bp, g.gb, c->d, c->t1 + g.t_st1, g.n_st1, st, 0);
+      if (g.dim == 1) e = mr_launch_fused1(s, g.nc, g.bp, g.gb, c->d, c->t1 + g.t_st1, g.n_st1, st);
       else e = mr_launch_stage2(s, g.nc, g.bp, g.gb, g.ch, c->d, c->t2 + g.t_st2, g.n_st2, st, c->grid2);
       if (e != hipSuccess) return e;
     }
