@@ -279,7 +279,7 @@ MR_INL bool mr1_flag(const mr_inst& I, const mr_grid& g, int i, double tb, doubl
 /* KXRCF face data per cell over the extended range [-3, nx+3) into the
  * summary planes (plane k = entry k of mr1_face_data). */
 template <bool BP, bool GB>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(const mr_inst* __restrict__ insts, const mr_tile1* __restrict__ tiles, int ntiles, int stage) {
   mr_kt_fill();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
@@ -302,10 +302,10 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_summary(mr_inst* insts, co
 
 /* Troubled-cell flags (mr1_flag) over [-2, nx+2); tc = 0 / 2 write
  * all-zero / all-one maps. */
-__global__ __launch_bounds__(MR_BLOCK) void k1_flags(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
+__global__ __launch_bounds__(MR_BLOCK) void k1_flags(const mr_inst* __restrict__ insts, const mr_tile1* __restrict__ tiles, int ntiles, int stage) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
-    mr_inst& I = insts[tl.inst];
+    const mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
@@ -416,7 +416,7 @@ MR_INL void mr1_stage_cell(const mr_inst& I, int mode, int x, bool out, int f0, 
  * (k1_flags).  mode 0..2 = RK stage, mode 3 = write L(U) (input p_in[0],
  * output p_out[0]). */
 template <int NC, bool BP, bool GB>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, const mr_tile1* tiles, int ntiles, int mode) {
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(const mr_inst* __restrict__ insts, const mr_tile1* __restrict__ tiles, int ntiles, int mode) {
   mr_kt_fill();
   __shared__ double s_tr[MR_BLOCK * NC];
   __shared__ double s_fl[MR_BLOCK * NC];
@@ -448,7 +448,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_stage(mr_inst* insts, cons
  * also go to the flag plane: stages 2 and 3 read back those of stage 1 for
  * U^n.  Same arithmetic as the three separate kernels. */
 template <int NC, bool BP, bool GB>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_fused(mr_inst* insts, const mr_tile1* tiles, int ntiles, int mode) {
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_fused(const mr_inst* __restrict__ insts, const mr_tile1* __restrict__ tiles, int ntiles, int mode) {
   mr_kt_fill();
   __shared__ double s_sd[5 * MR_BLOCK];
   __shared__ unsigned char s_flg[MR_BLOCK];
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_fused(mr_inst* insts, cons
   const int cs = threadIdx.x;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
-    mr_inst& I = insts[tl.inst];
+    const mr_inst& I = insts[tl.inst];
     if (!I.active) continue;
     const int x = tl.start - 3 + cs;
     const double tb = mr_stage_time(I, mode);
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_fused(mr_inst* insts, cons
 
 /* 1D final Gauss-Lobatto values of interior cells: gl[(c*4 + k)*nx + i]. */
 template <int NC, bool BP>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, const mr_tile1* tiles, int ntiles, double* gl) {
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(const mr_inst* __restrict__ insts, const mr_tile1* __restrict__ tiles, int ntiles, double* gl) {
   mr_kt_fill();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
@@ -525,10 +525,10 @@ __global__ __launch_bounds__(MR_BLOCK) MR_OCC void k1_values(mr_inst* insts, con
 /* Flags of the 2D instances without an indicator pass (no troubled cells,
  * or all cells troubled) over [-2, n+2)^2; the KXRCF flags of 2D instances
  * come from the fused kernel k2_kxrcf, the learned ones from k2_learned. */
-__global__ __launch_bounds__(MR_BLOCK) void k2_flags(mr_inst* insts, const mr_tile1* tiles, int ntiles, int stage) {
+__global__ __launch_bounds__(MR_BLOCK) void k2_flags(const mr_inst* __restrict__ insts, const mr_tile1* __restrict__ tiles, int ntiles, int stage) {
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];
-    mr_inst& I = insts[tl.inst];
+    const mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
     const int e = tl.start + (int)threadIdx.x;
     if (e >= tl.start + tl.count) continue;
@@ -538,7 +538,7 @@ __global__ __launch_bounds__(MR_BLOCK) void k2_flags(mr_inst* insts, const mr_ti
 }
 
 template <int NC, bool BP>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_values(mr_inst* insts, const mr_tile1* tiles, int ntiles, double* gl) {
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_values(const mr_inst* __restrict__ insts, const mr_tile1* __restrict__ tiles, int ntiles, double* gl) {
   mr_kt_fill();
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile1 tl = tiles[t];

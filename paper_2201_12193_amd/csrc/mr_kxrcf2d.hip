@@ -160,7 +160,7 @@ MR_INL void kx_face_data_ch(const double (*mom)[3 * 4 * KX_XW], int s0, int s1, 
    variable only and decides each cell from its own face averages).  Work item: flag columns x0 .. x0+61, flag rows y0 .. y0+rows-1
    of the extended flag range [-2, n+2)^2 (y0 >= -2). */
 template <int NK, bool BP, int GB>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(mr_inst* insts, const mr_tile2* tiles, int ntiles, int stage) {
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_kxrcf(const mr_inst* __restrict__ insts, const mr_tile2* __restrict__ tiles, int ntiles, int stage) {
   mr_kt_fill();
   constexpr int NPL = 3 * NK;
   constexpr int NROW = NPL * KX_XW;                       /* staged values per row */

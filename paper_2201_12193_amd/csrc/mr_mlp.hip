@@ -122,7 +122,7 @@ struct mr_learn_lds {
   float mom[12 * MR_LPL];
 };
 
-__global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const mr_tile2* tiles, int ntiles,
+__global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(const mr_inst* __restrict__ insts, const mr_tile2* __restrict__ tiles, int ntiles,
                                                          int stage, const mr_learn_w* wg, mr_band* band, int* cnt) {
   __shared__ mr_learn_lds sh;
   const int tid = threadIdx.x, lane = tid % 64, wv = tid / 64, r = lane % 16, g = lane / 16;
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
   const bool stager = tid < 3 * MR_LCOLS;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const mr_tile2 tl = tiles[t];
-    mr_inst& I = insts[tl.inst];
+    const mr_inst& I = insts[tl.inst];
     if (stage < 3 && !I.active) continue;
     if (I.tc != 3) continue;
     const mr_grid gr{mr_gp(stage < 3 ? I.p_in[stage] : I.buf[0]), I.plane, I.nx, I.ny, I.bcx, I.bcy, 3, nullptr, 0.0};
@@ -350,7 +350,7 @@ __global__ __launch_bounds__(MR_BLOCK, 2) void k2_learned(mr_inst* insts, const 
  * rejects the combination), so its grids carry no instance for prescribed
  * ghosts. */
 template <bool BP>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k_fb_direct(mr_inst* insts, const mr_band* band, const int* cnt,
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k_fb_direct(const mr_inst* __restrict__ insts, const mr_band* band, const int* cnt,
                                                               int stage) {
 #pragma clang fp contract(off)
   constexpr int PB = MR_BLOCK / 5;   /* band cells per block pass */

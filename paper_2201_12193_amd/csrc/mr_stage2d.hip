@@ -112,7 +112,7 @@ MR_INL void mr2_stage_field(const mr2_lds<4>& sh, const int* ra, const int* rb, 
 }
 
 template <int NC, bool BP, int GB, bool CH>
-__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(mr_inst* insts, const mr_tile2* tiles, int ntiles, int mode) {
+__global__ __launch_bounds__(MR_BLOCK) MR_OCC void k2_stage(const mr_inst* __restrict__ insts, const mr_tile2* __restrict__ tiles, int ntiles, int mode) {
   mr_kt_fill();
   using S = mr2_lds<NC>;
   constexpr int CW = S::CW, XW = S::XW, NP = S::NP, CS = S::CS, VS = S::VS, TS = S::TS, FS = S::FS;
