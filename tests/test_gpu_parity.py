@@ -366,3 +366,36 @@ def test_transmissive_2d():
         assert rel_state_err(prob, got, ref, sc) <= TOL
         prev = got
     s.close()
+
+
+@pytest.mark.parametrize("name,prob,U", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("beta_on", [0, 1])
+def test_other_linear_weights_parity(name, prob, U, beta_on):
+    """Linear weights other than the defaults (any positive weights are
+    allowed, Step 1) and another epsilon: residual, flags and three steps
+    against the oracle."""
+    prob = prob.replace(gbar=(1.0, 2.5, 7.0, 40.0), eps=1e-6, beta_on=beta_on)
+    U = _advance_oracle(prob, U, 2 if prob.dim == 2 else 6)
+    s, Ut = _solver(prob, U)
+    import torch
+    R, fl = s.residual(0, torch.from_numpy(U).to(_dev()))
+    R, fl = R.cpu().numpy(), fl.cpu().numpy()
+    Lref, flref = oracle.residual(prob, U)
+    _, _, num, den = oracle.reconstruct(prob, U)
+    sc = comp_scale(prob, U)
+    dt = oracle.dt(prob, U)
+    tag = f"weights/{name}/bp{beta_on}"
+    n, out = kxrcf_flags(tag, prob, fl, flref, num, den, sc[0])
+    assert out == 0 and n <= MISMATCHES_ALLOWED.get(tag, 0), (n, out)
+    dR = np.abs(R - Lref).reshape(prob.ncomp, -1).max(axis=1) / (sc / dt)
+    assert dR.max() <= TOL, dR
+    prev = U.copy()
+    for k in range(3):
+        s.step(1)
+        d = s.last_dt()[0]
+        s.sync()
+        got = Ut.cpu().numpy()
+        e = rel_state_err(prob, got, oracle.rk3_step(prob, prev, d), sc)
+        assert e <= TOL, (k, e)
+        prev = got
+    s.close()
